@@ -1,0 +1,235 @@
+"""FP64 CPU oracle for the COLATUS hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import this package.  It shares no code with the HIP
+library (``paper_1208_3444_amd``) and never imports it.
+
+Every function is a thin numpy wrapper over ``colatus_oracle.c``; the
+arithmetic, and the citation of the paper passage each function follows,
+lives there:
+
+* ``forces``           -- Eq. (1) pair sum, a^-3 G sum m_j (x_j - x_k) r^-3
+* ``potential``        -- softened potential whose gradient is that sum
+* ``force_vjp``        -- transpose Jacobian of the comoving pair sum
+* ``hubble``           -- Eq. (2)
+* ``time_integral``    -- the cosmic-time, kick and drift integrals of Eq. (9)
+* ``step_coefficients``-- the kick/drift/kick coefficients of one step
+* ``run``              -- kick-drift-kick run built from Eq. (9), diagnostics
+* ``adjoint``          -- discrete reverse mode of ``run``
+* ``ftle``             -- finite-time Lyapunov exponent of tracer particles
+
+Arrays are float64, positions and velocities structure-of-arrays ``(3, N)``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DIAG_FIELDS = ("a", "t", "K", "U", "LI", "Px", "Py", "Pz", "Lx", "Ly", "Lz")
+
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_p = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_hubble.restype = _d
+    lib.oracle_hubble.argtypes = [_d] * 6
+    lib.oracle_time_integral.restype = _d
+    lib.oracle_time_integral.argtypes = [ctypes.c_int] + [_d] * 7
+    lib.oracle_step_coefficients.restype = None
+    lib.oracle_step_coefficients.argtypes = [_d] * 7 + [_i64, _i64, _p]
+    lib.oracle_forces.restype = None
+    lib.oracle_forces.argtypes = [_p, _p, _i64, _d, _d, _d, _p]
+    lib.oracle_forces_targets.restype = None
+    lib.oracle_forces_targets.argtypes = [_p, _p, _i64, _p, _i64, _d, _d, _d, _p]
+    lib.oracle_potential.restype = None
+    lib.oracle_potential.argtypes = [_p, _p, _i64, _d, _d, _p]
+    lib.oracle_force_vjp.restype = None
+    lib.oracle_force_vjp.argtypes = [_p, _p, _i64, _d, _d, _p, _p]
+    lib.oracle_run.restype = ctypes.c_int
+    lib.oracle_run.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
+        [_d, _d, _i64, _i64, _i64, _p]
+    lib.oracle_adjoint.restype = ctypes.c_int
+    lib.oracle_adjoint.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
+        [_d, _d, _i64, _i32, _p, _p, _p, _p, _p, _p]
+    _lib = lib
+    return lib
+
+
+def _c(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_p) if a is not None else None
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def hubble(a, H0, Om_R, Om_M, Om_K, Om_L):
+    return _load().oracle_hubble(a, H0, Om_R, Om_M, Om_K, Om_L)
+
+
+def time_integral(kind, a1, a2, H0, Om_R, Om_M, Om_K, Om_L):
+    """kind: 'time' -> int da/(aH), 'kick' -> int da/(a^2 H), 'drift' -> int da/(a^3 H)."""
+    k = {"time": 1, "kick": 2, "drift": 3}[kind]
+    return _load().oracle_time_integral(k, a1, a2, H0, Om_R, Om_M, Om_K, Om_L)
+
+
+def step_coefficients(cosmo, a_begin, a_end, n_steps, n):
+    """(k1, d, k2, dt) of step n of the global grid."""
+    out = np.zeros(4)
+    _load().oracle_step_coefficients(
+        cosmo["H0"], cosmo["Om_R"], cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"],
+        a_begin, a_end, n_steps, n, _ptr(out))
+    return tuple(out)
+
+
+def forces(x, m, eps, G=1.0, a=1.0):
+    x = _c(x)
+    m = _c(m)
+    N = m.shape[0]
+    assert x.shape == (3, N)
+    acc = np.empty((3, N))
+    _load().oracle_forces(_ptr(x), _ptr(m), N, eps, G, a, _ptr(acc))
+    return acc
+
+
+def forces_targets(x, m, targets, eps, G=1.0, a=1.0):
+    x = _c(x)
+    m = _c(m)
+    N = m.shape[0]
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    acc = np.empty((3, t.shape[0]))
+    _load().oracle_forces_targets(_ptr(x), _ptr(m), N, _ptr(t), t.shape[0],
+                                  eps, G, a, _ptr(acc))
+    return acc
+
+
+def potential(x, m, eps, G=1.0):
+    x = _c(x)
+    m = _c(m)
+    N = m.shape[0]
+    phi = np.empty(N)
+    _load().oracle_potential(_ptr(x), _ptr(m), N, eps, G, _ptr(phi))
+    return phi
+
+
+def force_vjp(x, m, lam, eps, G=1.0):
+    x = _c(x)
+    m = _c(m)
+    lam = _c(lam)
+    N = m.shape[0]
+    out = np.empty((3, N))
+    _load().oracle_force_vjp(_ptr(x), _ptr(m), N, eps, G, _ptr(lam), _ptr(out))
+    return out
+
+
+def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
+        last_step=None, diag=False):
+    """Kick-drift-kick run over steps first_step..last_step-1 of the grid.
+
+    Returns (x, v) at a_{last_step}, and the diagnostics rows (dict of arrays)
+    if diag is true.
+    """
+    if last_step is None:
+        last_step = n_steps
+    x = _c(x).copy()
+    v = _c(v).copy()
+    m = _c(m)
+    N = m.shape[0]
+    rows = np.zeros((last_step - first_step + 1, len(DIAG_FIELDS))) if diag else None
+    rc = _load().oracle_run(
+        _ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
+        cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
+        first_step, last_step, _ptr(rows))
+    if rc != 0:
+        raise ValueError("oracle_run: invalid arguments")
+    if diag:
+        return x, v, {f: rows[:, i].copy() for i, f in enumerate(DIAG_FIELDS)}
+    return x, v
+
+
+def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN):
+    """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x0, v0).
+
+    lam_xN, lam_vN: (C, 3, N) or (3, N).  Returns (grad_x0, grad_v0, xN, vN)
+    with the gradients shaped like the cotangents.
+    """
+    x0 = _c(x0)
+    v0 = _c(v0)
+    m = _c(m)
+    N = m.shape[0]
+    lx = _c(lam_xN)
+    lv = _c(lam_vN)
+    squeeze = lx.ndim == 2
+    lx = lx.reshape(-1, 3, N)
+    lv = lv.reshape(-1, 3, N)
+    C = lx.shape[0]
+    gx = np.empty_like(lx)
+    gv = np.empty_like(lv)
+    xN = np.empty((3, N))
+    vN = np.empty((3, N))
+    rc = _load().oracle_adjoint(
+        _ptr(x0), _ptr(v0), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
+        cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
+        C, _ptr(lx), _ptr(lv), _ptr(gx), _ptr(gv), _ptr(xN), _ptr(vN))
+    if rc != 0:
+        raise ValueError("oracle_adjoint: invalid arguments")
+    if squeeze:
+        gx, gv = gx[0], gv[0]
+    return gx, gv, xN, vN
+
+
+def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers):
+    """Finite-time Lyapunov exponent of each tracer particle.
+
+    The 3x3 block Phi_t = d x_t(a_end) / d x_t(a_begin) of the flow map is
+    read off three reverse sweeps seeded with the unit vectors on x_t(a_end);
+    lambda_t = ln sigma_max(Phi_t) / (t(a_end) - t(a_begin)), with the
+    cosmic time from the Friedmann integral (or the elapsed time in the
+    static limit).  Returns (lambda per unit cosmic time, lambda per unit
+    ln a, the blocks Phi).
+    """
+    m = _c(m)
+    N = m.shape[0]
+    tracers = np.asarray(tracers, dtype=np.int64)
+    T = tracers.shape[0]
+    lam_x = np.zeros((3 * T, 3, N))
+    for ti, t in enumerate(tracers):
+        for i in range(3):
+            lam_x[3 * ti + i, i, t] = 1.0
+    lam_v = np.zeros_like(lam_x)
+    gx, _, _, _ = adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps,
+                          lam_x, lam_v)
+    phi = np.empty((T, 3, 3))
+    for ti, t in enumerate(tracers):
+        for i in range(3):
+            phi[ti, i, :] = gx[3 * ti + i, :, t]
+    smax = np.linalg.svd(phi, compute_uv=False)[:, 0]
+    if cosmo["H0"] == 0.0:
+        span_t = a_end
+        span_lna = float("nan")
+    else:
+        span_t = time_integral("time", a_begin, a_end, cosmo["H0"], cosmo["Om_R"],
+                               cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"])
+        span_lna = np.log(a_end / a_begin)
+    lam = np.log(smax)
+    return lam / span_t, lam / span_lna, phi

@@ -1,0 +1,538 @@
+/*
+ * COLATUS plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP library.
+ * Only the test suite, the smoke entry point and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or helper with
+ * the HIP library, and the HIP library never calls it.
+ *
+ * Everything here is deliberately slow and literal: scalar loops in FP64,
+ * IEEE sqrt and divide, Neumaier-compensated sums in index order, adaptive
+ * Simpson quadrature in a.  The only parallelism is an OpenMP loop over
+ * independent target particles, which does not change any sum's order.
+ *
+ * Paper: Stalder et al., "A new gravitational N-body simulation algorithm
+ * for investigation of cosmological chaotic advection" (arXiv:1208.3444).
+ *
+ * Readings of the paper taken here (each is also listed in the design notes):
+ *  - Eq. (1) prints the pair term as m_j (x_k - x_j); that is repulsive.  The
+ *    attractive form m_j (x_j - x_k) is used.
+ *  - Eqs. (6)-(9): the canonical momentum is p = a^2 v (per unit mass), the
+ *    drift is dx/dt = p/a^2 and the kick is dp/dt = g/a, where
+ *    g = G sum_j m_j (x_j - x_k) r^-3 is the comoving pair sum without the
+ *    a^-3 factor.  This is Eq. (1) rewritten for p; the printed Eq. (8)
+ *    (p^2 in the drift, phi' instead of its gradient in the kick) is read as
+ *    a typesetting slip.
+ *  - The background term (a^2 a_ddot |x|^2 / 2) of Eq. (6) is not added:
+ *    the force is Eq. (1) exactly, in an open (non-periodic) box.
+ *  - The step is kick(half) - drift - kick(half) built from the drift and
+ *    kick operators of Eq. (9); steps are uniform in ln a and the half-step
+ *    point is the midpoint in ln a.
+ *  - Softening is Plummer, in comoving units, as written in Eq. (1).
+ *  - Static limit: H0 == 0 keeps a fixed at a_begin; then the "a_end"
+ *    argument of the run is the total elapsed time and dt = a_end/n_steps.
+ *
+ * Parity pins for every function live in the tests (closed forms,
+ * invariants, brute force, finite differences).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Compensated summation (Neumaier 1974).                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s, c; } ksum;
+
+static void ksum_add(ksum *k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v))
+        k->c += (k->s - t) + v;
+    else
+        k->c += (v - t) + k->s;
+    k->s = t;
+}
+
+static double ksum_value(const ksum *k) { return k->s + k->c; }
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Friedmann equation, Eq. (2):                                             */
+/*   H(a) = H0 sqrt(Om_R a^-4 + Om_M a^-3 + Om_K a^-2 + Om_L).              */
+/* No renormalisation of the density parameters.  Returns NaN if H^2 < 0.   */
+/* ------------------------------------------------------------------------ */
+typedef struct { double H0, OmR, OmM, OmK, OmL; } cosmo;
+
+double oracle_hubble(double a, double H0, double OmR, double OmM, double OmK,
+                     double OmL)
+{
+    double e2 = OmR / (a * a * a * a) + OmM / (a * a * a) + OmK / (a * a) + OmL;
+    if (e2 < 0.0)
+        return NAN;
+    return H0 * sqrt(e2);
+}
+
+/* Integrand 1/(a^k H(a)) of the three time integrals:
+ *   k = 1: cosmic time       dt       = da / (a H)
+ *   k = 2: kick factor       dt / a   = da / (a^2 H)   (Eq. (9), K)
+ *   k = 3: drift factor      dt / a^2 = da / (a^3 H)   (Eq. (9), D)      */
+static double integrand(const cosmo *c, int k, double a)
+{
+    double h = oracle_hubble(a, c->H0, c->OmR, c->OmM, c->OmK, c->OmL);
+    double ak = a;
+    for (int i = 1; i < k; ++i)
+        ak *= a;
+    return 1.0 / (ak * h);
+}
+
+static double simpson_rec(const cosmo *c, int k, double lo, double hi,
+                          double flo, double fmid, double fhi, double whole,
+                          double tol, int depth)
+{
+    double mid = 0.5 * (lo + hi);
+    double lm = 0.5 * (lo + mid), rm = 0.5 * (mid + hi);
+    double flm = integrand(c, k, lm), frm = integrand(c, k, rm);
+    double left = (mid - lo) / 6.0 * (flo + 4.0 * flm + fmid);
+    double right = (hi - mid) / 6.0 * (fmid + 4.0 * frm + fhi);
+    double delta = left + right - whole;
+    if (depth <= 0 || fabs(delta) <= 15.0 * tol)
+        return left + right + delta / 15.0;
+    return simpson_rec(c, k, lo, mid, flo, flm, fmid, left, 0.5 * tol, depth - 1) +
+           simpson_rec(c, k, mid, hi, fmid, frm, fhi, right, 0.5 * tol, depth - 1);
+}
+
+/* Adaptive Simpson in a of 1/(a^k H) from a1 to a2, to ~1e-14 relative.   */
+static double time_integral(const cosmo *c, int k, double a1, double a2)
+{
+    if (a1 == a2)
+        return 0.0;
+    double sign = 1.0;
+    if (a2 < a1) {
+        double t = a1;
+        a1 = a2;
+        a2 = t;
+        sign = -1.0;
+    }
+    /* Split into 64 equal panels first so the tolerance is relative to a
+     * sensible scale even for wide ranges; each panel is then refined.    */
+    const int panels = 64;
+    double h = (a2 - a1) / panels;
+    double rough = 0.0;
+    for (int i = 0; i < panels; ++i) {
+        double lo = a1 + i * h, hi = (i == panels - 1) ? a2 : a1 + (i + 1) * h;
+        double flo = integrand(c, k, lo), fhi = integrand(c, k, hi);
+        double fm = integrand(c, k, 0.5 * (lo + hi));
+        rough += (hi - lo) / 6.0 * (flo + 4.0 * fm + fhi);
+    }
+    double tol = 1e-15 * fabs(rough) / panels;
+    ksum total = {0.0, 0.0};
+    for (int i = 0; i < panels; ++i) {
+        double lo = a1 + i * h, hi = (i == panels - 1) ? a2 : a1 + (i + 1) * h;
+        double flo = integrand(c, k, lo), fhi = integrand(c, k, hi);
+        double fm = integrand(c, k, 0.5 * (lo + hi));
+        double whole = (hi - lo) / 6.0 * (flo + 4.0 * fm + fhi);
+        ksum_add(&total, simpson_rec(c, k, lo, hi, flo, fm, fhi, whole, tol, 48));
+    }
+    return sign * ksum_value(&total);
+}
+
+/* Public: kind 1 = cosmic time, 2 = kick factor, 3 = drift factor.        */
+double oracle_time_integral(int kind, double a1, double a2, double H0,
+                            double OmR, double OmM, double OmK, double OmL)
+{
+    cosmo c = {H0, OmR, OmM, OmK, OmL};
+    if (kind < 1 || kind > 3)
+        return NAN;
+    return time_integral(&c, kind, a1, a2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair sums of Eq. (1).                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* acc_k = a^-3 G sum_{j != k} m_j (x_j - x_k) / (|x_j - x_k|^2 + eps^2)^{3/2}
+ * x is SoA: x[0..N) = x-components, x[N..2N) = y, x[2N..3N) = z.
+ * The self pair j == k is excluded (the "k != j" of Eq. (1)).             */
+void oracle_forces(const double *x, const double *m, int64_t N, double eps,
+                   double G, double a, double *acc)
+{
+    const double *px = x, *py = x + N, *pz = x + 2 * N;
+    const double eps2 = eps * eps;
+    const double scale = G / (a * a * a);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < N; ++k) {
+        ksum sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == k)
+                continue;
+            double dx = px[j] - px[k];
+            double dy = py[j] - py[k];
+            double dz = pz[j] - pz[k];
+            double s = dx * dx + dy * dy + dz * dz + eps2;
+            double rinv = 1.0 / sqrt(s);
+            double r3 = rinv * rinv * rinv;
+            ksum_add(&sx, m[j] * dx * r3);
+            ksum_add(&sy, m[j] * dy * r3);
+            ksum_add(&sz, m[j] * dz * r3);
+        }
+        acc[k] = scale * ksum_value(&sx);
+        acc[N + k] = scale * ksum_value(&sy);
+        acc[2 * N + k] = scale * ksum_value(&sz);
+    }
+}
+
+/* Same sum for a subset of targets (index list), used to check a large
+ * force evaluation on sampled particles.  acc is [3][n_targets].          */
+void oracle_forces_targets(const double *x, const double *m, int64_t N,
+                           const int64_t *targets, int64_t n_targets,
+                           double eps, double G, double a, double *acc)
+{
+    const double *px = x, *py = x + N, *pz = x + 2 * N;
+    const double eps2 = eps * eps;
+    const double scale = G / (a * a * a);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < n_targets; ++t) {
+        int64_t k = targets[t];
+        ksum sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == k)
+                continue;
+            double dx = px[j] - px[k];
+            double dy = py[j] - py[k];
+            double dz = pz[j] - pz[k];
+            double s = dx * dx + dy * dy + dz * dz + eps2;
+            double rinv = 1.0 / sqrt(s);
+            double r3 = rinv * rinv * rinv;
+            ksum_add(&sx, m[j] * dx * r3);
+            ksum_add(&sy, m[j] * dy * r3);
+            ksum_add(&sz, m[j] * dz * r3);
+        }
+        acc[t] = scale * ksum_value(&sx);
+        acc[n_targets + t] = scale * ksum_value(&sy);
+        acc[2 * n_targets + t] = scale * ksum_value(&sz);
+    }
+}
+
+/* Softened comoving potential whose negative gradient is the Eq. (1) sum:
+ *   phi_k = -G sum_{j != k} m_j / sqrt(|x_j - x_k|^2 + eps^2).            */
+void oracle_potential(const double *x, const double *m, int64_t N, double eps,
+                      double G, double *phi)
+{
+    const double *px = x, *py = x + N, *pz = x + 2 * N;
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < N; ++k) {
+        ksum s = {0, 0};
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == k)
+                continue;
+            double dx = px[j] - px[k];
+            double dy = py[j] - py[k];
+            double dz = pz[j] - pz[k];
+            double r2 = dx * dx + dy * dy + dz * dz + eps2;
+            ksum_add(&s, m[j] / sqrt(r2));
+        }
+        phi[k] = -G * ksum_value(&s);
+    }
+}
+
+/* Vector-Jacobian product of the comoving pair sum g(x) (Eq. (1) without
+ * the a^-3 factor).  With d = x_j - x_k, s = |d|^2 + eps^2 and
+ *   M(d) = s^{-3/2} I - 3 s^{-5/2} d d^T,
+ * the derivative is dg_k/dx_j = G m_j M(d) for j != k and
+ * dg_k/dx_k = -G sum_j m_j M(d), so
+ *   (J^T lam)_k = G sum_{j != k} M(d_kj) (m_k lam_j - m_j lam_k).         */
+void oracle_force_vjp(const double *x, const double *m, int64_t N, double eps,
+                      double G, const double *lam, double *out)
+{
+    const double *px = x, *py = x + N, *pz = x + 2 * N;
+    const double *lx = lam, *ly = lam + N, *lz = lam + 2 * N;
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < N; ++k) {
+        ksum sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == k)
+                continue;
+            double dx = px[j] - px[k];
+            double dy = py[j] - py[k];
+            double dz = pz[j] - pz[k];
+            double s = dx * dx + dy * dy + dz * dz + eps2;
+            double rinv = 1.0 / sqrt(s);
+            double r3 = rinv * rinv * rinv;
+            double r5 = r3 * rinv * rinv;
+            double ux = m[k] * lx[j] - m[j] * lx[k];
+            double uy = m[k] * ly[j] - m[j] * ly[k];
+            double uz = m[k] * lz[j] - m[j] * lz[k];
+            double du = dx * ux + dy * uy + dz * uz;
+            ksum_add(&sx, r3 * ux - 3.0 * r5 * du * dx);
+            ksum_add(&sy, r3 * uy - 3.0 * r5 * du * dy);
+            ksum_add(&sz, r3 * uz - 3.0 * r5 * du * dz);
+        }
+        out[k] = G * ksum_value(&sx);
+        out[N + k] = G * ksum_value(&sy);
+        out[2 * N + k] = G * ksum_value(&sz);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time grid and step coefficients.                                         */
+/* ------------------------------------------------------------------------ */
+
+/* a_n = a_begin exp(n Delta), Delta = ln(a_end/a_begin)/n_steps, and
+ * a_{n_steps} is a_end exactly.  In the static limit a is constant.       */
+static double grid_a(const cosmo *c, double a_begin, double a_end,
+                     int64_t n_steps, double n)
+{
+    if (c->H0 == 0.0)
+        return a_begin;
+    if (n == (double)n_steps)
+        return a_end;
+    double delta = log(a_end / a_begin) / (double)n_steps;
+    return a_begin * exp(n * delta);
+}
+
+typedef struct { double k1, d, k2, dt; } step_coef;
+
+/* Kick-drift-kick coefficients of step n (Eq. (9)):
+ *   k1 = int_{a_n}^{a_n+1/2} dt/a,  d = int_{a_n}^{a_n+1} dt/a^2,
+ *   k2 = int_{a_n+1/2}^{a_n+1} dt/a,  dt = elapsed cosmic time.          */
+static step_coef step_coefficients(const cosmo *c, double a_begin, double a_end,
+                                   int64_t n_steps, int64_t n)
+{
+    step_coef s;
+    if (c->H0 == 0.0) {
+        double dt = a_end / (double)n_steps;
+        double a = a_begin;
+        s.k1 = 0.5 * dt / a;
+        s.k2 = 0.5 * dt / a;
+        s.d = dt / (a * a);
+        s.dt = dt;
+        return s;
+    }
+    double a0 = grid_a(c, a_begin, a_end, n_steps, (double)n);
+    double ah = grid_a(c, a_begin, a_end, n_steps, (double)n + 0.5);
+    double a1 = grid_a(c, a_begin, a_end, n_steps, (double)(n + 1));
+    s.k1 = time_integral(c, 2, a0, ah);
+    s.k2 = time_integral(c, 2, ah, a1);
+    s.d = time_integral(c, 3, a0, a1);
+    s.dt = time_integral(c, 1, a0, a1);
+    return s;
+}
+
+/* Public: the four coefficients of step n, for tests. out = {k1, d, k2, dt}. */
+void oracle_step_coefficients(double H0, double OmR, double OmM, double OmK,
+                              double OmL, double a_begin, double a_end,
+                              int64_t n_steps, int64_t n, double *out)
+{
+    cosmo c = {H0, OmR, OmM, OmK, OmL};
+    step_coef s = step_coefficients(&c, a_begin, a_end, n_steps, n);
+    out[0] = s.k1;
+    out[1] = s.d;
+    out[2] = s.k2;
+    out[3] = s.dt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics.                                                             */
+/* Row layout (11 doubles): a, t, K, U, LI, P[3], L[3].                     */
+/*   K = 1/2 sum m |p|^2 / a^2            (kinetic energy, p = a^2 v)       */
+/*   U = (1/(2a)) sum m_k phi_k           (potential energy)                */
+/*   LI = E - E_first + sum trapezoid(2K + U) d ln a  (Layzer-Irvine)       */
+/*   P = sum m p,  L = sum m x cross p.                                     */
+/* ------------------------------------------------------------------------ */
+#define DIAG_W 11
+
+static void energies(const double *x, const double *p, const double *m,
+                     int64_t N, double eps, double G, double a, double *K,
+                     double *U, double *P, double *L)
+{
+    double *phi = (double *)malloc(sizeof(double) * (size_t)N);
+    oracle_potential(x, m, N, eps, G, phi);
+    ksum kk = {0, 0}, uu = {0, 0};
+    ksum pp[3] = {{0, 0}, {0, 0}, {0, 0}}, ll[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t k = 0; k < N; ++k) {
+        double X = x[k], Y = x[N + k], Z = x[2 * N + k];
+        double px = p[k], py = p[N + k], pz = p[2 * N + k];
+        ksum_add(&kk, 0.5 * m[k] * (px * px + py * py + pz * pz));
+        ksum_add(&uu, m[k] * phi[k]);
+        ksum_add(&pp[0], m[k] * px);
+        ksum_add(&pp[1], m[k] * py);
+        ksum_add(&pp[2], m[k] * pz);
+        ksum_add(&ll[0], m[k] * (Y * pz - Z * py));
+        ksum_add(&ll[1], m[k] * (Z * px - X * pz));
+        ksum_add(&ll[2], m[k] * (X * py - Y * px));
+    }
+    *K = ksum_value(&kk) / (a * a);
+    *U = 0.5 * ksum_value(&uu) / a;
+    for (int i = 0; i < 3; ++i) {
+        P[i] = ksum_value(&pp[i]);
+        L[i] = ksum_value(&ll[i]);
+    }
+    free(phi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Run: kick-drift-kick steps first_step..last_step-1 of the global grid.   */
+/*   p = a_n^2 v;  p += k1 g(x_n);  x += d p;  p += k2 g(x_{n+1}).          */
+/* On return x, v hold the state at a_{last_step} (v = p/a^2).              */
+/* diag (optional) receives last-first+1 rows of DIAG_W doubles.            */
+/* ------------------------------------------------------------------------ */
+int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
+               double G, double H0, double OmR, double OmM, double OmK,
+               double OmL, double a_begin, double a_end, int64_t n_steps,
+               int64_t first_step, int64_t last_step, double *diag)
+{
+    cosmo c = {H0, OmR, OmM, OmK, OmL};
+    if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
+        last_step > n_steps)
+        return -1;
+    size_t n3 = 3 * (size_t)N;
+    double *p = (double *)malloc(sizeof(double) * n3);
+    double *g = (double *)malloc(sizeof(double) * n3);
+    double a = grid_a(&c, a_begin, a_end, n_steps, (double)first_step);
+    for (size_t i = 0; i < n3; ++i)
+        p[i] = a * a * v[i];
+    oracle_forces(x, m, N, eps, G, 1.0, g);
+
+    double t = 0.0, E0 = 0.0, li_int = 0.0, prev_src = 0.0;
+    if (diag) {
+        double K, U, P[3], L[3];
+        energies(x, p, m, N, eps, G, a, &K, &U, P, L);
+        E0 = K + U;
+        prev_src = 2.0 * K + U;
+        double *row = diag;
+        row[0] = a; row[1] = 0.0; row[2] = K; row[3] = U; row[4] = 0.0;
+        for (int i = 0; i < 3; ++i) { row[5 + i] = P[i]; row[8 + i] = L[i]; }
+    }
+    for (int64_t n = first_step; n < last_step; ++n) {
+        step_coef s = step_coefficients(&c, a_begin, a_end, n_steps, n);
+        for (size_t i = 0; i < n3; ++i)
+            p[i] += s.k1 * g[i];
+        for (size_t i = 0; i < n3; ++i)
+            x[i] += s.d * p[i];
+        oracle_forces(x, m, N, eps, G, 1.0, g);
+        for (size_t i = 0; i < n3; ++i)
+            p[i] += s.k2 * g[i];
+        double a_prev = a;
+        a = grid_a(&c, a_begin, a_end, n_steps, (double)(n + 1));
+        t += s.dt;
+        if (diag) {
+            double K, U, P[3], L[3];
+            energies(x, p, m, N, eps, G, a, &K, &U, P, L);
+            double src = 2.0 * K + U;
+            double dlna = (c.H0 == 0.0) ? 0.0 : log(a) - log(a_prev);
+            li_int += 0.5 * (prev_src + src) * dlna;
+            prev_src = src;
+            double *row = diag + (size_t)(n + 1 - first_step) * DIAG_W;
+            row[0] = a; row[1] = t; row[2] = K; row[3] = U;
+            row[4] = K + U - E0 + li_int;
+            for (int i = 0; i < 3; ++i) { row[5 + i] = P[i]; row[8 + i] = L[i]; }
+        }
+    }
+    for (size_t i = 0; i < n3; ++i)
+        v[i] = p[i] / (a * a);
+    free(p);
+    free(g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint (reverse mode of the run map, every state stored).      */
+/* Forward step n:  p' = p_n + k1 g(x_n);  x_{n+1} = x_n + d p';            */
+/*                  p_{n+1} = p' + k2 g(x_{n+1}).                           */
+/* Reverse step n:  lx += k2 J(x_{n+1})^T lp;  lp += d lx;                  */
+/*                  lx += k1 J(x_n)^T lp.                                   */
+/* Boundary maps: p_0 = a_0^2 v_0, v_N = p_N / a_N^2.                       */
+/* For each of n_cot cotangent pairs (lam_xN, lam_vN) [n_cot][3][N] the     */
+/* gradients with respect to x_0 and v_0 are written to grad_x0, grad_v0.   */
+/* xN, vN (optional) receive the forward end state.                         */
+/* ------------------------------------------------------------------------ */
+int oracle_adjoint(const double *x0, const double *v0, const double *m,
+                   int64_t N, double eps, double G, double H0, double OmR,
+                   double OmM, double OmK, double OmL, double a_begin,
+                   double a_end, int64_t n_steps, int32_t n_cot,
+                   const double *lam_xN, const double *lam_vN, double *grad_x0,
+                   double *grad_v0, double *xN, double *vN)
+{
+    cosmo c = {H0, OmR, OmM, OmK, OmL};
+    if (N < 1 || n_steps < 1 || n_cot < 1)
+        return -1;
+    size_t n3 = 3 * (size_t)N;
+    double *xs = (double *)malloc(sizeof(double) * n3 * (size_t)(n_steps + 1));
+    double *p = (double *)malloc(sizeof(double) * n3);
+    double *g = (double *)malloc(sizeof(double) * n3);
+    step_coef *coef = (step_coef *)malloc(sizeof(step_coef) * (size_t)n_steps);
+    double a0 = grid_a(&c, a_begin, a_end, n_steps, 0.0);
+    double aN = grid_a(&c, a_begin, a_end, n_steps, (double)n_steps);
+
+    memcpy(xs, x0, sizeof(double) * n3);
+    for (size_t i = 0; i < n3; ++i)
+        p[i] = a0 * a0 * v0[i];
+    oracle_forces(xs, m, N, eps, G, 1.0, g);
+    for (int64_t n = 0; n < n_steps; ++n) {
+        coef[n] = step_coefficients(&c, a_begin, a_end, n_steps, n);
+        double *xn = xs + (size_t)n * n3, *xn1 = xs + (size_t)(n + 1) * n3;
+        for (size_t i = 0; i < n3; ++i)
+            p[i] += coef[n].k1 * g[i];
+        for (size_t i = 0; i < n3; ++i)
+            xn1[i] = xn[i] + coef[n].d * p[i];
+        oracle_forces(xn1, m, N, eps, G, 1.0, g);
+        for (size_t i = 0; i < n3; ++i)
+            p[i] += coef[n].k2 * g[i];
+    }
+    if (xN)
+        memcpy(xN, xs + (size_t)n_steps * n3, sizeof(double) * n3);
+    if (vN)
+        for (size_t i = 0; i < n3; ++i)
+            vN[i] = p[i] / (aN * aN);
+
+    double *lx = (double *)malloc(sizeof(double) * n3);
+    double *lp = (double *)malloc(sizeof(double) * n3);
+    double *w = (double *)malloc(sizeof(double) * n3);
+    for (int32_t ci = 0; ci < n_cot; ++ci) {
+        const double *lxN = lam_xN + (size_t)ci * n3;
+        const double *lvN = lam_vN + (size_t)ci * n3;
+        for (size_t i = 0; i < n3; ++i) {
+            lx[i] = lxN[i];
+            lp[i] = lvN[i] / (aN * aN);
+        }
+        for (int64_t n = n_steps - 1; n >= 0; --n) {
+            double *xn = xs + (size_t)n * n3, *xn1 = xs + (size_t)(n + 1) * n3;
+            oracle_force_vjp(xn1, m, N, eps, G, lp, w);
+            for (size_t i = 0; i < n3; ++i)
+                lx[i] += coef[n].k2 * w[i];
+            for (size_t i = 0; i < n3; ++i)
+                lp[i] += coef[n].d * lx[i];
+            oracle_force_vjp(xn, m, N, eps, G, lp, w);
+            for (size_t i = 0; i < n3; ++i)
+                lx[i] += coef[n].k1 * w[i];
+        }
+        double *gx = grad_x0 + (size_t)ci * n3, *gv = grad_v0 + (size_t)ci * n3;
+        for (size_t i = 0; i < n3; ++i) {
+            gx[i] = lx[i];
+            gv[i] = a0 * a0 * lp[i];
+        }
+    }
+    free(lx);
+    free(lp);
+    free(w);
+    free(xs);
+    free(p);
+    free(g);
+    free(coef);
+    return 0;
+}
