@@ -1,0 +1,235 @@
+/*
+ * colatus.h -- C ABI of the MI355X (gfx950) COLATUS hot path.
+ *
+ * Paper: Stalder et al., "A new gravitational N-body simulation algorithm
+ * for investigation of cosmological chaotic advection" (arXiv:1208.3444).
+ *
+ * What the library computes
+ *   - the direct-summation (particle-particle) softened acceleration of
+ *     Eq. (1) in comoving coordinates, with the attractive sign,
+ *         acc_k = a^-3 G sum_{j != k} m_j (x_j - x_k) / (|x_j - x_k|^2 + eps^2)^{3/2}
+ *     (Section II; the GPU force loop of Appendix A);
+ *   - the expansion-aware kick-drift-kick step built from the drift and kick
+ *     operators of Eq. (9), with a(t) from the Friedmann equation, Eq. (2);
+ *   - the discrete adjoint (vector-Jacobian product) of that step, used for
+ *     trajectory sensitivities and finite-time Lyapunov exponents of the
+ *     chaotic-advection study the paper motivates (Sections I and IV).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays named x, v, acc, lam_*, grad_* are structure-of-arrays float64
+ *     planes of shape [3][N]: x[0..N) holds the x components, x[N..2N) the
+ *     y components, x[2N..3N) the z components.  m and phi are [N] float64.
+ *     All of them are DEVICE pointers on the current HIP device, contiguous,
+ *     owned by the caller; the library never frees or retains them beyond
+ *     the call's queued work.
+ *   - x is the comoving position, v = dx/dt the comoving velocity (Eq. (1)),
+ *     m the particle mass, eps the Plummer softening in comoving units, G the
+ *     gravitational constant, H0 and Om_R, Om_M, Om_K, Om_L the parameters
+ *     of Eq. (2) (no renormalisation of their sum), a the scale factor.
+ *   - stream is a hipStream_t (NULL = the default stream).  Work is queued
+ *     on it and the call returns without waiting, except where a host
+ *     output (diagnostics) is requested.
+ *   - Every argument check runs on the host before any HIP call; on an error
+ *     nothing has been queued.  Return value 0 on success, else one of the
+ *     negative COLATUS_E* codes; colatus_strerror() names it.
+ *   - Internal scratch (split-j partial sums, coefficient tables, work lists,
+ *     checkpoints) is allocated by the library per (device, stream), kept for
+ *     reuse and released by colatus_release() or at process exit.  Calls on
+ *     one stream are serialised by the stream; concurrent calls from
+ *     different host threads on the SAME stream are not supported.
+ *   - Results are deterministic: the split over source slices is summed in a
+ *     fixed order, with no atomics in any reduction, so a repeated call on the
+ *     same input gives bitwise the same output.
+ *   - Limits: 1 <= N <= 2^28 particles (per call, all boxes together).
+ *
+ * Readings of the paper taken by this library (see also the design notes)
+ *   - Eq. (1) prints the pair term as m_j (x_k - x_j), which is repulsive;
+ *     the attractive m_j (x_j - x_k) is used.  The self pair j == k is
+ *     excluded.  No background (a^2 a_ddot |x|^2 / 2) term: open box.
+ *   - The step is the symplectic kick-drift-kick of Eq. (9) with canonical
+ *     momentum p = a^2 v (per unit mass): kick p += g int dt/a, drift
+ *     x += p int dt/a^2, where g = G sum m_j (x_j - x_k) r^-3.  Steps are
+ *     uniform in ln a; the half-step point is the midpoint in ln a.
+ *   - Static limit: H0 == 0 holds a fixed; see colatus_step / colatus_run.
+ */
+#ifndef COLATUS_H
+#define COLATUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define COLATUS_OK          0
+#define COLATUS_EINVAL     -1  /* invalid argument (shape, range, NULL, non-finite scalar) */
+#define COLATUS_EFRIEDMANN -2  /* H^2(a) <= 0 somewhere on the requested range of a      */
+#define COLATUS_ENODEV     -3  /* no HIP device available                                 */
+#define COLATUS_ENOMEM     -4  /* device scratch allocation failed                        */
+#define COLATUS_EHIP       -5  /* a HIP runtime call failed                               */
+#define COLATUS_ENONFINITE -6  /* diagnostics found a NaN or Inf in the state             */
+
+/* ---- pair arithmetic --------------------------------------------------- */
+#define COLATUS_FP64         0  /* FP64 pairs, FP64 running sums                            */
+#define COLATUS_MIXED_TWOSUM 1  /* FP32 pairs on coordinates relative to the target block's
+                                   centre; per-tile FP32 partials folded by TwoSum into an
+                                   unevaluated (hi, lo) FP32 pair                          */
+#define COLATUS_MIXED_F64ACC 2  /* FP32 pairs as above; per-tile partials folded into FP64  */
+#define COLATUS_FP32         3  /* FP32 pairs as above, one FP32 running sum per target and
+                                   source slice (no compensation)                          */
+
+/* ---- ensembles of independent boxes ------------------------------------ */
+/* Particles of box b are [box_offsets[b], box_offsets[b+1]) of the [3][N]
+ * arrays; particles of different boxes do not interact, and box b uses
+ * softening eps[b] (the scalar eps argument is then ignored).  Both arrays
+ * are HOST pointers, read during the call only.  box_offsets[0] == 0,
+ * non-decreasing, box_offsets[n_boxes] == N, every box non-empty.
+ * A NULL batch pointer means one box holding all N particles.             */
+typedef struct {
+    int32_t n_boxes;
+    const int64_t *box_offsets; /* host, n_boxes + 1 */
+    const double *eps;          /* host, n_boxes     */
+} colatus_batch;
+
+/* ---- diagnostics row --------------------------------------------------- */
+/* One row per integer grid point a_n visited by a run (first row: the start
+ * state).  With p = a^2 v:
+ *   K  = 1/2 sum m |p|^2 / a^2            U = (1/(2a)) sum_k m_k phi_k
+ *   LI = K + U - (K + U)_first + sum of trapezoids of (2K + U) over ln a,
+ *        the residual of the Layzer-Irvine equation dE/d ln a = -(2K + U)
+ *        that this Hamiltonian system obeys (zero for exact integration);
+ *        in the static limit LI = E - E_first.
+ *   P  = sum m p,   L = sum m x cross p   (conserved by central forces)
+ *   t  = cosmic time elapsed since the run's first row.
+ * flags bit 0: a NaN or Inf was seen in this row's sums.                  */
+typedef struct {
+    double a, t, K, U, LI;
+    double P[3];
+    double L[3];
+    uint32_t flags;
+    uint32_t reserved;
+} colatus_diag;
+
+/* ---- entry points ------------------------------------------------------ */
+
+/* Pair sum of Eq. (1) (Section II) for every particle.
+ *   x    [3][N] device, m [N] device.
+ *   acc  [3][N] device, out: a^-3 G sum_{j != k} m_j (x_j - x_k) r^-3,
+ *        r = sqrt(|x_j - x_k|^2 + eps^2).
+ *   phi  [N] device, out, or NULL: phi_k = -G sum_{j != k} m_j / r (comoving,
+ *        no a factor); its negative gradient is the comoving pair sum.
+ *   precision: COLATUS_FP64 / _MIXED_TWOSUM / _MIXED_F64ACC / _FP32.
+ *   eps >= 0 (eps == 0 with two coincident particles gives Inf/NaN), G finite,
+ *   a > 0.  batch: see colatus_batch, or NULL.                            */
+int colatus_forces(const double *x, const double *m, int64_t N, double eps,
+                   double G, double a, int precision, double *acc, double *phi,
+                   const colatus_batch *batch, void *stream);
+
+/* One kick-drift-kick step (Eq. (9) operators, Section II) from a to a_next,
+ * in place on x and v (comoving position and dx/dt):
+ *   p = a^2 v;  p += K(a, a_h) g(x);  x += D(a, a_next) p;
+ *   p += K(a_h, a_next) g(x);  v = p / a_next^2,
+ * with a_h = sqrt(a a_next), K(a1,a2) = int_{a1}^{a2} da/(a^2 H),
+ * D(a1,a2) = int_{a1}^{a2} da/(a^3 H), H from Eq. (2).
+ * Static limit H0 == 0: a stays fixed and a_next is read as the time step
+ * dt (K = dt/(2a) each, D = dt/a^2).  Costs two force evaluations; use
+ * colatus_run for many steps (one evaluation per step).                    */
+int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
+                 double G, double H0, double Om_R, double Om_M, double Om_K,
+                 double Om_L, double a, double a_next, int precision,
+                 const colatus_batch *batch, void *stream);
+
+/* Steps first_step .. last_step-1 of the global grid a_n = a_begin
+ * exp(n ln(a_end/a_begin)/n_steps), a_{n_steps} = a_end, in place on x, v.
+ * Running [0, k) then [k, n_steps) matches one [0, n_steps) run up to the
+ * rounding of the p <-> v conversion at the seam.
+ * Static limit H0 == 0: a stays at a_begin and a_end is read as the total
+ * elapsed time (dt = a_end / n_steps).
+ *   diag: HOST array of (last_step - first_step + 1) rows, or NULL.  When
+ *         non-NULL the call synchronises the stream and returns
+ *         COLATUS_ENONFINITE if any row saw a NaN/Inf.  With a batch, diag
+ *         holds n_boxes consecutive blocks of rows (box-major).
+ * Requires n_steps >= 1, 0 <= first_step < last_step <= n_steps, a_begin > 0,
+ * a_end > 0 (or > 0 elapsed time in the static limit), H^2 > 0 on the range
+ * (else COLATUS_EFRIEDMANN).                                              */
+int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
+                double G, double H0, double Om_R, double Om_M, double Om_K,
+                double Om_L, double a_begin, double a_end, int64_t n_steps,
+                int64_t first_step, int64_t last_step, int precision,
+                colatus_diag *diag, const colatus_batch *batch, void *stream);
+
+/* Reverse-mode derivative of the full run [0, n_steps) of colatus_run
+ * (discretise-then-differentiate: the exact gradient of the computed map).
+ * For each of n_cot cotangent pairs (lam_xN[c], lam_vN[c]), each [3][N],
+ * on the end state (x_N, v_N), writes grad_x0[c] = d<lam, state_N>/dx_0 and
+ * grad_v0[c] = d<lam, state_N>/dv_0, each [3][N]; arrays are [n_cot][3][N]
+ * device.  x0, v0 are not modified; xN, vN ([3][N] device, or NULL) receive
+ * the forward end state.  The forward run stores (x, p) every
+ * checkpoint_every steps and recomputes each segment, bitwise, during the
+ * reverse sweep; the transpose Jacobian of the pair sum,
+ *   (J^T lam)_k = G sum_{j != k} M(d)(m_k lam_j - m_j lam_k),
+ *   M(d) = r^-3 I - 3 r^-5 d d^T,  d = x_j - x_k,
+ * is evaluated by its own O(N^2) pair sweep in the given precision, once
+ * per step for all cotangents together.  1 <= n_cot <= 4096; batch must be
+ * NULL (single box).                                                        */
+int colatus_adjoint(const double *x0, const double *v0, const double *m,
+                    int64_t N, double eps, double G, double H0, double Om_R,
+                    double Om_M, double Om_K, double Om_L, double a_begin,
+                    double a_end, int64_t n_steps, int64_t checkpoint_every,
+                    int32_t n_cot, const double *lam_xN, const double *lam_vN,
+                    double *grad_x0, double *grad_v0, double *xN, double *vN,
+                    int precision, const colatus_batch *batch, void *stream);
+
+/* Transpose-Jacobian product of the comoving pair sum g (Eq. (1) without
+ * a^-3) alone: out[c] = J(x)^T lam[c] for n_cot cotangents, arrays
+ * [n_cot][3][N] device.  The building block of colatus_adjoint.           */
+int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps,
+                      double G, int32_t n_cot, const double *lam, double *out,
+                      int precision, void *stream);
+
+/* Hubble rate of Eq. (2) at scale factor a, on the host.  Returns
+ * COLATUS_EFRIEDMANN if H^2 < 0 there.                                    */
+int colatus_hubble(double a, double H0, double Om_R, double Om_M, double Om_K,
+                   double Om_L, double *H);
+
+/* Human-readable name of a return code (static string).                  */
+const char *colatus_strerror(int code);
+
+/* ---- tuning, timing and housekeeping ----------------------------------- */
+#define COLATUS_OPT_GRAPH      1  /* 1: capture the repeated step of colatus_run in a
+                                     hipGraph and replay it (default 1)              */
+#define COLATUS_OPT_TIMER      2  /* 1: bracket every pair-sweep launch with hipEvents
+                                     on its stream (default 0)                       */
+#define COLATUS_OPT_AUTOTUNE   3  /* 1: time candidate tile shapes on first use of an
+                                     (N bucket, precision) and keep the fastest
+                                     (default 0: built-in heuristic)                 */
+#define COLATUS_OPT_TILE_R     4  /* >0: force targets per lane (1, 2, 4); 0 = auto  */
+#define COLATUS_OPT_TILE_TPB   5  /* >0: force threads per block (128, 256); 0 = auto */
+#define COLATUS_OPT_TILE_SLICES 6 /* >0: force the number of source slices; 0 = auto  */
+#define COLATUS_OPT_PERSISTENT 7  /* 1: persistent pair-sweep grid pulling work items
+                                     from a device counter (default 1)               */
+int colatus_set_option(int key, int64_t value);
+int colatus_get_option(int key, int64_t *value);
+
+/* Pair-sweep timer: sum of hipEvent durations of the forward (kind 0) or
+ * adjoint (kind 1) pair-sweep launches recorded since the last reset, and
+ * their count.  Synchronises the recorded events.  reset != 0 clears.     */
+int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset);
+
+/* Tile shape the library would use (or has tuned) for N particles in one
+ * box at the given precision: out[0] = targets per lane R, out[1] = threads
+ * per block, out[2] = source slices.  kind 0 = forward, 1 = adjoint.      */
+int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[3]);
+
+/* Release all cached device scratch of all streams (synchronises them).  */
+int colatus_release(void);
+
+/* Library version, major*10000 + minor*100 + patch.                      */
+int colatus_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COLATUS_H */

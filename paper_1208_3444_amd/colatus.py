@@ -1,0 +1,372 @@
+"""Python binding of libcolatus (argument marshalling only).
+
+Every computation happens in the HIP library behind the C ABI declared in
+``include/colatus.h``; this module checks tensor placement, dtype and shape,
+passes device pointers and the current HIP stream, and turns negative return
+codes into exceptions.  There is no CPU fallback: if ``libcolatus.so`` has not
+been built, every call raises.
+
+Tensors are torch float64 on a HIP device, contiguous, positions and
+velocities shaped (3, N) (structure of arrays), masses (N,).
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcolatus.so")
+
+FP64 = 0
+MIXED_TWOSUM = 1
+MIXED_F64ACC = 2
+FP32 = 3
+PRECISIONS = {"fp64": FP64, "mixed_twosum": MIXED_TWOSUM, "mixed": MIXED_TWOSUM,
+              "mixed_f64acc": MIXED_F64ACC, "fp32": FP32}
+
+OPT_GRAPH = 1
+OPT_TIMER = 2
+OPT_AUTOTUNE = 3
+OPT_TILE_R = 4
+OPT_TILE_TPB = 5
+OPT_TILE_SLICES = 6
+OPT_PERSISTENT = 7
+
+ERRORS = {0: "OK", -1: "EINVAL", -2: "EFRIEDMANN", -3: "ENODEV", -4: "ENOMEM", -5: "EHIP",
+          -6: "ENONFINITE"}
+
+# Every symbol include/colatus.h declares, with its ctypes signature.
+_d, _i64, _i32, _i, _p = (ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                          ctypes.c_void_p)
+SIGNATURES = {
+    "colatus_forces": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p]),
+    "colatus_step": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i, _p, _p]),
+    "colatus_run": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
+                         _i64, _i, _p, _p, _p]),
+    "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
+                             _i32, _p, _p, _p, _p, _p, _p, _i, _p, _p]),
+    "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p]),
+    "colatus_hubble": (_i, [_d, _d, _d, _d, _d, _d, ctypes.POINTER(_d)]),
+    "colatus_strerror": (ctypes.c_char_p, [_i]),
+    "colatus_set_option": (_i, [_i, _i64]),
+    "colatus_get_option": (_i, [_i, ctypes.POINTER(_i64)]),
+    "colatus_timer_read": (_i, [_i, ctypes.POINTER(_d), ctypes.POINTER(_i64), _i]),
+    "colatus_tile_config": (_i, [_i64, _i, _i, ctypes.POINTER(_i32)]),
+    "colatus_release": (_i, []),
+    "colatus_version": (_i, []),
+}
+
+
+class ColatusError(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        msg = _lib_or_none().colatus_strerror(code).decode() if _lib_or_none() else ""
+        super().__init__(f"{fn} failed: {ERRORS.get(code, code)} ({msg})")
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int32), ("box_offsets", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("a", _d), ("t", _d), ("K", _d), ("U", _d), ("LI", _d), ("P", _d * 3),
+                ("L", _d * 3), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_LIB = None
+
+
+def _lib_or_none():
+    return _LIB
+
+
+def lib():
+    """The loaded libcolatus (ctypes.CDLL); raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"libcolatus.so not found at {LIB_PATH}: build it with "
+            "`python -m paper_1208_3444_amd.build` (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise ColatusError(fn, rc)
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _dev(t, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a HIP device (got {t.device})")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _batch(batch):
+    """batch = (box_offsets (B+1,) int64 array-like, eps (B,) array-like) or None."""
+    if batch is None:
+        return None, None
+    import numpy as np
+    off = np.ascontiguousarray(np.asarray(batch[0], dtype=np.int64))
+    eps = np.ascontiguousarray(np.asarray(batch[1], dtype=np.float64))
+    b = _Batch(int(eps.shape[0]), off.ctypes.data, eps.ctypes.data)
+    return b, (off, eps)
+
+
+def forces(x, m, eps, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False, batch=None):
+    """a^-3 G sum_{j != k} m_j (x_j - x_k) / (|x_j - x_k|^2 + eps^2)^{3/2}  (Eq. (1)).
+
+    Returns acc (3, N), and phi (N,) (-G sum m_j / r) if with_phi.
+    """
+    N = m.shape[0]
+    px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
+    acc = torch.empty_like(x)
+    phi = torch.empty_like(m) if with_phi else None
+    b, keep = _batch(batch)
+    rc = lib().colatus_forces(px, pm, N, float(eps) if batch is None else 0.0, float(G),
+                              float(a), _prec(precision), ctypes.c_void_p(acc.data_ptr()),
+                              ctypes.c_void_p(phi.data_ptr()) if with_phi else None,
+                              ctypes.byref(b) if b is not None else None, _stream(x))
+    del keep
+    _check("colatus_forces", rc)
+    return (acc, phi) if with_phi else acc
+
+
+def _cosmo(c):
+    return (float(c["H0"]), float(c["Om_R"]), float(c["Om_M"]), float(c["Om_K"]),
+            float(c["Om_L"]))
+
+
+def step(x, v, m, eps, G, cosmo, a, a_next, precision="mixed_twosum", batch=None):
+    """One kick-drift-kick step from a to a_next, in place on x and v."""
+    N = m.shape[0]
+    px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
+    b, keep = _batch(batch)
+    rc = lib().colatus_step(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
+                            *_cosmo(cosmo), float(a), float(a_next), _prec(precision),
+                            ctypes.byref(b) if b is not None else None, _stream(x))
+    del keep
+    _check("colatus_step", rc)
+
+
+DIAG_FIELDS = ("a", "t", "K", "U", "LI", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "flags")
+
+
+def _diag_dict(rows):
+    import numpy as np
+    out = {f: np.empty(len(rows)) for f in DIAG_FIELDS}
+    for i, r in enumerate(rows):
+        out["a"][i], out["t"][i], out["K"][i], out["U"][i], out["LI"][i] = r.a, r.t, r.K, r.U, r.LI
+        out["Px"][i], out["Py"][i], out["Pz"][i] = r.P[0], r.P[1], r.P[2]
+        out["Lx"][i], out["Ly"][i], out["Lz"][i] = r.L[0], r.L[1], r.L[2]
+        out["flags"][i] = r.flags
+    return out
+
+
+def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step=None,
+        precision="mixed_twosum", diag=False, batch=None):
+    """Kick-drift-kick steps [first_step, last_step) of the global ln-a grid, in place.
+
+    Returns the diagnostics (dict of numpy arrays, one entry per grid point;
+    with a batch, a list of such dicts, one per box) if diag, else None.
+    """
+    if last_step is None:
+        last_step = n_steps
+    N = m.shape[0]
+    px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
+    b, keep = _batch(batch)
+    n_boxes = 1 if batch is None else len(keep[1])
+    rows = (Diag * (n_boxes * (last_step - first_step + 1)))() if diag else None
+    rc = lib().colatus_run(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
+                           *_cosmo(cosmo), float(a_begin), float(a_end), int(n_steps),
+                           int(first_step), int(last_step), _prec(precision),
+                           ctypes.cast(rows, ctypes.c_void_p) if diag else None,
+                           ctypes.byref(b) if b is not None else None, _stream(x))
+    del keep
+    _check("colatus_run", rc)
+    if not diag:
+        return None
+    nr = last_step - first_step + 1
+    per_box = [_diag_dict(rows[k * nr:(k + 1) * nr]) for k in range(n_boxes)]
+    return per_box[0] if batch is None else per_box
+
+
+def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum"):
+    """J(x)^T lam for the comoving pair sum; lam (3, N) or (C, 3, N)."""
+    N = m.shape[0]
+    px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
+    C = 1 if lam.dim() == 2 else lam.shape[0]
+    pl = _dev(lam, "lam", (3, N) if lam.dim() == 2 else (C, 3, N))
+    out = torch.empty_like(lam)
+    rc = lib().colatus_force_vjp(px, pm, N, float(eps), float(G), C, pl,
+                                 ctypes.c_void_p(out.data_ptr()), _prec(precision), _stream(x))
+    _check("colatus_force_vjp", rc)
+    return out
+
+
+def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
+            checkpoint_every=20, precision="mixed_twosum", return_state=False):
+    """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x_0, v_0).
+
+    lam_xN, lam_vN: (3, N) or (C, 3, N).  Returns (grad_x0, grad_v0) shaped
+    like the cotangents, plus (x_N, v_N) if return_state.
+    """
+    N = m.shape[0]
+    px, pv, pm = _dev(x0, "x0", (3, N)), _dev(v0, "v0", (3, N)), _dev(m, "m", (N,))
+    C = 1 if lam_xN.dim() == 2 else lam_xN.shape[0]
+    shp = (3, N) if lam_xN.dim() == 2 else (C, 3, N)
+    plx, plv = _dev(lam_xN, "lam_xN", shp), _dev(lam_vN, "lam_vN", shp)
+    gx, gv = torch.empty_like(lam_xN), torch.empty_like(lam_vN)
+    xN = torch.empty_like(x0) if return_state else None
+    vN = torch.empty_like(v0) if return_state else None
+    rc = lib().colatus_adjoint(
+        px, pv, pm, N, float(eps), float(G), *_cosmo(cosmo), float(a_begin), float(a_end),
+        int(n_steps), int(checkpoint_every), C, plx, plv, ctypes.c_void_p(gx.data_ptr()),
+        ctypes.c_void_p(gv.data_ptr()),
+        ctypes.c_void_p(xN.data_ptr()) if return_state else None,
+        ctypes.c_void_p(vN.data_ptr()) if return_state else None,
+        _prec(precision), None, _stream(x0))
+    _check("colatus_adjoint", rc)
+    if return_state:
+        return gx, gv, xN, vN
+    return gx, gv
+
+
+class ColatusRun(torch.autograd.Function):
+    """(x_0, v_0) -> (x_N, v_N) of a full run, differentiable by the discrete adjoint.
+
+    ``ColatusRun.apply(x0, v0, m, params)`` with params a dict holding eps, G,
+    cosmo, a_begin, a_end, n_steps and optionally checkpoint_every and
+    precision.  The backward pass calls colatus_adjoint, which re-runs the
+    forward with checkpoints and returns gradients for x0 and v0.
+    """
+
+    @staticmethod
+    def forward(ctx, x0, v0, m, params):
+        x = x0.detach().clone()
+        v = v0.detach().clone()
+        run(x, v, m, params["eps"], params["G"], params["cosmo"], params["a_begin"],
+            params["a_end"], params["n_steps"], precision=params.get("precision", "mixed_twosum"))
+        ctx.save_for_backward(x0.detach(), v0.detach(), m)
+        ctx.params = params
+        return x, v
+
+    @staticmethod
+    def backward(ctx, gx, gv):
+        x0, v0, m = ctx.saved_tensors
+        P = ctx.params
+        gx = torch.zeros_like(x0) if gx is None else gx.contiguous()
+        gv = torch.zeros_like(v0) if gv is None else gv.contiguous()
+        dx, dv = adjoint(x0, v0, m, P["eps"], P["G"], P["cosmo"], P["a_begin"], P["a_end"],
+                         P["n_steps"], gx, gv, checkpoint_every=P.get("checkpoint_every", 20),
+                         precision=P.get("precision", "mixed_twosum"))
+        return dx, dv, None, None
+
+
+def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_every=20,
+         precision="mixed_twosum"):
+    """Finite-time Lyapunov exponents of tracer particles.
+
+    The 3x3 block d x_t(a_end) / d x_t(a_begin) of each tracer is read off
+    3 reverse sweeps (cotangents e_i on x_t(a_end)), all tracers batched in
+    one adjoint call; lambda_t = ln sigma_max / elapsed cosmic time, with the
+    elapsed time from the library's coefficient integrals.  Returns
+    (lambda per unit cosmic time, lambda per unit ln a, blocks (T, 3, 3)).
+    """
+    import math
+    import numpy as np
+    N = m.shape[0]
+    T = len(tracers)
+    lam_x = torch.zeros((3 * T, 3, N), dtype=torch.float64, device=x0.device)
+    for ti, t in enumerate(tracers):
+        for i in range(3):
+            lam_x[3 * ti + i, i, int(t)] = 1.0
+    lam_v = torch.zeros_like(lam_x)
+    gx, _ = adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_x, lam_v,
+                    checkpoint_every=checkpoint_every, precision=precision)
+    g = gx.cpu().numpy()
+    phi = np.empty((T, 3, 3))
+    for ti, t in enumerate(tracers):
+        for i in range(3):
+            phi[ti, i, :] = g[3 * ti + i, :, int(t)]
+    smax = np.linalg.svd(phi, compute_uv=False)[:, 0]
+    span_t = elapsed_time(cosmo, a_begin, a_end, n_steps, x0.device)
+    span_lna = math.log(a_end / a_begin) if cosmo["H0"] != 0 else float("nan")
+    lam = np.log(smax)
+    return lam / span_t, lam / span_lna, phi
+
+
+def elapsed_time(cosmo, a_begin, a_end, n_steps, device):
+    """Cosmic time from a_begin to a_end, from a 2-particle diagnostic run."""
+    x = torch.tensor([[0.0, 100.0], [0.0, 0.0], [0.0, 0.0]], dtype=torch.float64, device=device)
+    v = torch.zeros_like(x)
+    m = torch.zeros(2, dtype=torch.float64, device=device)
+    d = run(x, v, m, 1.0, 0.0, cosmo, a_begin, a_end, n_steps, precision="fp64", diag=True)
+    return float(d["t"][-1])
+
+
+def hubble(a, cosmo):
+    """H(a) of Eq. (2), computed by the library on the host."""
+    out = ctypes.c_double()
+    _check("colatus_hubble", lib().colatus_hubble(float(a), *_cosmo(cosmo), ctypes.byref(out)))
+    return out.value
+
+
+def set_option(key, value):
+    _check("colatus_set_option", lib().colatus_set_option(int(key), int(value)))
+
+
+def get_option(key):
+    out = ctypes.c_int64()
+    _check("colatus_get_option", lib().colatus_get_option(int(key), ctypes.byref(out)))
+    return out.value
+
+
+def timer_read(kind=0, reset=True):
+    """(total ms, launches) of the pair sweeps timed since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check("colatus_timer_read", lib().colatus_timer_read(int(kind), ctypes.byref(ms),
+                                                          ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
+
+
+def tile_config(N, precision="mixed_twosum", kind=0):
+    out = (ctypes.c_int32 * 3)()
+    _check("colatus_tile_config", lib().colatus_tile_config(int(N), _prec(precision), int(kind),
+                                                            out))
+    return tuple(out)
+
+
+def release():
+    _check("colatus_release", lib().colatus_release())
+
+
+def version():
+    return lib().colatus_version()

@@ -1,0 +1,1114 @@
+// C ABI of libcolatus: argument validation, scratch management, work lists,
+// tile-shape selection (heuristic or autotuned), hipGraph replay of the run's
+// repeated step, pair-sweep timers, and the drivers of colatus_forces,
+// colatus_step, colatus_run, colatus_adjoint and colatus_force_vjp.
+#include "colatus.h"
+#include "colatus_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+using namespace colatus;
+
+namespace {
+
+constexpr int64_t kMaxN = (int64_t)1 << 28;
+constexpr int kMaxCot = 4096;
+
+// ---------------------------------------------------------------------------
+// Options.
+// ---------------------------------------------------------------------------
+struct Options {
+    int64_t graph = 1;
+    int64_t timer = 0;
+    int64_t autotune = 0;
+    int64_t tile_r = 0;
+    int64_t tile_tpb = 0;
+    int64_t tile_slices = 0;
+    int64_t persistent = 1;
+};
+Options g_opt;
+std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
+
+// ---------------------------------------------------------------------------
+// Validation helpers (host only; nothing touches HIP before they pass).
+// ---------------------------------------------------------------------------
+bool is_fin(double v) { return std::isfinite(v); }
+
+struct Boxes {
+    std::vector<int64_t> off;  // n_boxes + 1
+    std::vector<double> eps;   // n_boxes
+    int64_t max_n = 0;
+};
+
+int resolve_boxes(int64_t N, double eps, const colatus_batch *batch, Boxes &b)
+{
+    if (!batch) {
+        if (!is_fin(eps) || eps < 0.0)
+            return COLATUS_EINVAL;
+        b.off = {0, N};
+        b.eps = {eps};
+        b.max_n = N;
+        return COLATUS_OK;
+    }
+    if (batch->n_boxes < 1 || !batch->box_offsets || !batch->eps)
+        return COLATUS_EINVAL;
+    b.off.assign(batch->box_offsets, batch->box_offsets + batch->n_boxes + 1);
+    b.eps.assign(batch->eps, batch->eps + batch->n_boxes);
+    if (b.off[0] != 0 || b.off.back() != N)
+        return COLATUS_EINVAL;
+    for (int i = 0; i < batch->n_boxes; ++i) {
+        if (b.off[i + 1] <= b.off[i])
+            return COLATUS_EINVAL;
+        if (!is_fin(b.eps[i]) || b.eps[i] < 0.0)
+            return COLATUS_EINVAL;
+        b.max_n = std::max(b.max_n, b.off[i + 1] - b.off[i]);
+    }
+    return COLATUS_OK;
+}
+
+bool valid_precision(int p) { return p >= COLATUS_FP64 && p <= COLATUS_FP32; }
+
+// a^4 H^2 / H0^2 = Om_R + Om_M a + Om_K a^2 + Om_L a^4 must stay > 0 on
+// [lo, hi].  Checked at 4096 points and at the critical points of the
+// quartic located by bisection between sign changes of its derivative.
+bool friedmann_positive(double OmR, double OmM, double OmK, double OmL, double lo, double hi)
+{
+    auto f = [&](double a) { return OmR + a * (OmM + a * (OmK + a * a * OmL)); };
+    auto df = [&](double a) { return OmM + a * (2.0 * OmK + 4.0 * OmL * a * a); };
+    const int n = 4096;
+    double prev_a = lo, prev_d = df(lo);
+    if (!(f(lo) > 0.0) || !(f(hi) > 0.0))
+        return false;
+    for (int i = 1; i <= n; ++i) {
+        const double a = lo + (hi - lo) * i / n;
+        if (!(f(a) > 0.0))
+            return false;
+        const double d = df(a);
+        if ((prev_d < 0.0) != (d < 0.0)) {
+            double l = prev_a, r = a;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (l + r);
+                if ((df(mid) < 0.0) == (prev_d < 0.0))
+                    l = mid;
+                else
+                    r = mid;
+            }
+            if (!(f(0.5 * (l + r)) > 0.0))
+                return false;
+        }
+        prev_a = a;
+        prev_d = d;
+    }
+    return true;
+}
+
+int validate_cosmology(double H0, double OmR, double OmM, double OmK, double OmL,
+                       double a_begin, double a_end)
+{
+    if (!is_fin(H0) || H0 < 0.0 || !is_fin(OmR) || !is_fin(OmM) || !is_fin(OmK) || !is_fin(OmL))
+        return COLATUS_EINVAL;
+    if (!is_fin(a_begin) || !is_fin(a_end) || a_begin <= 0.0 || a_end <= 0.0)
+        return COLATUS_EINVAL;
+    if (H0 == 0.0)
+        return COLATUS_OK;
+    if (a_begin == a_end)
+        return COLATUS_EINVAL;
+    const double lo = std::min(a_begin, a_end), hi = std::max(a_begin, a_end);
+    if (!friedmann_positive(OmR, OmM, OmK, OmL, lo, hi))
+        return COLATUS_EFRIEDMANN;
+    return COLATUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch, one workspace per (device, stream).
+// ---------------------------------------------------------------------------
+struct Buffer {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct WorkList {
+    // key
+    int64_t N = -1;
+    std::vector<int64_t> off;
+    std::vector<double> eps;
+    TileCfg cfg{0, 0, 0};
+    // content
+    std::vector<WorkItem> items;
+    std::vector<IntBlock> blocks;
+    std::vector<int32_t> box_first_block;
+    int max_slices = 0;
+    Buffer d_items, d_blocks, d_box_first;
+};
+
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg;
+    WorkList fwd, adj;
+};
+
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+
+int hip_err(hipError_t e)
+{
+    if (e == hipSuccess)
+        return COLATUS_OK;
+    if (e == hipErrorOutOfMemory)
+        return COLATUS_ENOMEM;
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice)
+        return COLATUS_ENODEV;
+    return COLATUS_EHIP;
+}
+
+#define CHECK_HIP(expr)                                                                       \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            return hip_err(_e);                                                               \
+    } while (0)
+
+#define CHECK_RC(expr)                                                                        \
+    do {                                                                                      \
+        int _rc = (expr);                                                                     \
+        if (_rc != COLATUS_OK)                                                                \
+            return _rc;                                                                       \
+    } while (0)
+
+int ensure(Buffer &b, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 256;
+    if (b.cap >= bytes)
+        return COLATUS_OK;
+    if (b.ptr) {
+        CHECK_HIP(hipDeviceSynchronize());
+        CHECK_HIP(hipFree(b.ptr));
+        b.ptr = nullptr;
+        b.cap = 0;
+    }
+    const size_t rounded = (bytes + 4095) & ~(size_t)4095;
+    CHECK_HIP(hipMalloc(&b.ptr, rounded));
+    b.cap = rounded;
+    return COLATUS_OK;
+}
+
+int device_ready(int &dev)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        return COLATUS_ENODEV;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return COLATUS_ENODEV;
+    return COLATUS_OK;
+}
+
+int get_workspace(hipStream_t stream, Workspace *&ws)
+{
+    int dev = 0;
+    CHECK_RC(device_ready(dev));
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        ws = it->second;
+        return COLATUS_OK;
+    }
+    ws = new Workspace();
+    ws->device = dev;
+    ws->stream = stream;
+    g_ws[key] = ws;
+    // counters: [0] work-item counter (int), [8..16) step counter (int64)
+    CHECK_RC(ensure(ws->counters, 256));
+    CHECK_HIP(launch_zero_counter(static_cast<int *>(ws->counters.ptr), stream));
+    return COLATUS_OK;
+}
+
+int *work_counter(Workspace *ws) { return static_cast<int *>(ws->counters.ptr); }
+int64_t *step_counter(Workspace *ws)
+{
+    return reinterpret_cast<int64_t *>(static_cast<char *>(ws->counters.ptr) + 64);
+}
+
+__global__ void set_step_kernel(int64_t *step, int64_t value, int *counter)
+{
+    *step = value;
+    *counter = 0;
+}
+
+int set_step(Workspace *ws, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(1), 0, s, step_counter(ws), value,
+                       work_counter(ws));
+    CHECK_HIP(hipGetLastError());
+    return COLATUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int64_t nbucket;
+    int nboxes_bucket;
+    int precision;
+    int kind;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(nbucket, nboxes_bucket, precision, kind) <
+               std::tie(o.nbucket, o.nboxes_bucket, o.precision, o.kind);
+    }
+};
+std::map<TuneKey, TileCfg> g_tuned;
+
+int64_t pow2_ceil(int64_t n)
+{
+    int64_t p = 1;
+    while (p < n)
+        p <<= 1;
+    return p;
+}
+
+int cu_count(int dev)
+{
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        n = 256;
+    return n;
+}
+
+int n_target_blocks(const Boxes &b, int ti)
+{
+    int64_t t = 0;
+    for (size_t i = 0; i + 1 < b.off.size(); ++i)
+        t += (b.off[i + 1] - b.off[i] + ti - 1) / ti;
+    return (int)t;
+}
+
+// Built-in heuristic: enough (target block, source slice) items to give
+// every CU several resident workgroups, with at least two source tiles
+// per slice so the LDS staging stays amortised.
+TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu)
+{
+    TileCfg c;
+    if (kind == 0) {
+        if (precision == COLATUS_FP64) {
+            c.R = 2;
+            c.tpb = 256;
+        } else if (b.max_n >= 16384) {
+            c.R = 4;
+            c.tpb = 256;
+        } else if (b.max_n >= 4096) {
+            c.R = 2;
+            c.tpb = 256;
+        } else {
+            c.R = 2;
+            c.tpb = 128;
+        }
+    } else {
+        c.R = 1;
+        c.tpb = 256;
+    }
+    const int tb = n_target_blocks(b, c.R * c.tpb);
+    const int want = 4 * n_cu;
+    int s = (want + tb - 1) / tb;
+    const int64_t max_s = std::max<int64_t>(1, b.max_n / (2 * c.tpb));
+    s = (int)std::max<int64_t>(1, std::min<int64_t>(s, max_s));
+    c.slices = s;
+    return c;
+}
+
+TileCfg apply_overrides(TileCfg c, int kind)
+{
+    if (g_opt.tile_r > 0 && kind == 0)
+        c.R = (int)g_opt.tile_r;
+    if (g_opt.tile_tpb > 0 && kind == 0)
+        c.tpb = (int)g_opt.tile_tpb;
+    if (g_opt.tile_slices > 0)
+        c.slices = (int)g_opt.tile_slices;
+    return c;
+}
+
+bool cfg_supported(const TileCfg &c, int kind)
+{
+    if (kind == 0)
+        return (c.R == 1 || c.R == 2 || c.R == 4) && (c.tpb == 128 || c.tpb == 256) &&
+               c.slices >= 1;
+    return (c.R == 1 || c.R == 2) && c.tpb == 256 && c.slices >= 1;
+}
+
+// ---------------------------------------------------------------------------
+// Work lists.
+// ---------------------------------------------------------------------------
+void build_worklist(const Boxes &b, int64_t N, const TileCfg &cfg, WorkList &wl)
+{
+    wl.items.clear();
+    wl.blocks.clear();
+    wl.box_first_block.clear();
+    wl.max_slices = 0;
+    const int ti = cfg.R * cfg.tpb;
+    const int nb = (int)b.eps.size();
+    for (int box = 0; box < nb; ++box) {
+        const int64_t o0 = b.off[box], o1 = b.off[box + 1], nbx = o1 - o0;
+        const int64_t tiles = (nbx + cfg.tpb - 1) / cfg.tpb;
+        int64_t s = std::min<int64_t>(cfg.slices, tiles);
+        const int64_t tiles_per_slice = (tiles + s - 1) / s;
+        const int64_t js = tiles_per_slice * cfg.tpb;
+        s = (nbx + js - 1) / js;
+        wl.max_slices = std::max<int>(wl.max_slices, (int)s);
+        const double eps2 = b.eps[box] * b.eps[box];
+        for (int64_t i0 = o0; i0 < o1; i0 += ti) {
+            const int64_t i1 = std::min(i0 + ti, o1);
+            for (int64_t q = 0; q < s; ++q) {
+                WorkItem w;
+                w.i0 = i0;
+                w.i1 = i1;
+                w.j0 = o0 + q * js;
+                w.j1 = std::min(o0 + (q + 1) * js, o1);
+                w.eps2 = eps2;
+                w.slice = (int32_t)q;
+                w.box = box;
+                wl.items.push_back(w);
+            }
+        }
+        wl.box_first_block.push_back((int32_t)wl.blocks.size());
+        for (int64_t i0 = o0; i0 < o1; i0 += kIntBlock) {
+            IntBlock ib;
+            ib.i0 = i0;
+            ib.i1 = std::min<int64_t>(i0 + kIntBlock, o1);
+            ib.eps = b.eps[box];
+            ib.box = box;
+            ib.n_slices = (int32_t)s;
+            wl.blocks.push_back(ib);
+        }
+    }
+    wl.box_first_block.push_back((int32_t)wl.blocks.size());
+    // Longest-processing-time-first order for the persistent grid: an item's
+    // cost is its source count (every lane of the block runs).
+    std::stable_sort(wl.items.begin(), wl.items.end(), [](const WorkItem &a, const WorkItem &c) {
+        return (a.j1 - a.j0) > (c.j1 - c.j0);
+    });
+}
+
+int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, const TileCfg &cfg,
+                    hipStream_t s)
+{
+    if (wl.N == N && wl.off == b.off && wl.eps == b.eps && wl.cfg.R == cfg.R &&
+        wl.cfg.tpb == cfg.tpb && wl.cfg.slices == cfg.slices)
+        return COLATUS_OK;
+    // the previous list may still be read by queued work
+    CHECK_HIP(hipStreamSynchronize(s));
+    build_worklist(b, N, cfg, wl);
+    wl.N = N;
+    wl.off = b.off;
+    wl.eps = b.eps;
+    wl.cfg = cfg;
+    CHECK_RC(ensure(wl.d_items, wl.items.size() * sizeof(WorkItem)));
+    CHECK_RC(ensure(wl.d_blocks, wl.blocks.size() * sizeof(IntBlock)));
+    CHECK_RC(ensure(wl.d_box_first, wl.box_first_block.size() * sizeof(int32_t)));
+    CHECK_HIP(hipMemcpyAsync(wl.d_items.ptr, wl.items.data(), wl.items.size() * sizeof(WorkItem),
+                             hipMemcpyHostToDevice, s));
+    CHECK_HIP(hipMemcpyAsync(wl.d_blocks.ptr, wl.blocks.data(),
+                             wl.blocks.size() * sizeof(IntBlock), hipMemcpyHostToDevice, s));
+    CHECK_HIP(hipMemcpyAsync(wl.d_box_first.ptr, wl.box_first_block.data(),
+                             wl.box_first_block.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    (void)ws;
+    return COLATUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pair-sweep timers (hipEvents around each launch on its stream).
+// ---------------------------------------------------------------------------
+struct TimerRec {
+    hipEvent_t start, stop;
+};
+std::vector<TimerRec> g_timer[2];
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Forward pair sweep on the workspace's buffers, with the timer if enabled.
+int run_forward_sweep(Workspace *ws, const WorkList &wl, int precision, bool phi,
+                      bool mask, const double *x, const double *m, int64_t N, hipStream_t s,
+                      bool zero_counter)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_opt.timer) {
+        e0 = take_event();
+        e1 = take_event();
+    }
+    if (zero_counter && g_opt.persistent)
+        CHECK_HIP(launch_zero_counter(work_counter(ws), s));
+    if (e0)
+        CHECK_HIP(hipEventRecord(e0, s));
+    CHECK_HIP(launch_pair_sweep(precision, wl.cfg, phi, mask, x, m, N,
+                                static_cast<const WorkItem *>(wl.d_items.ptr),
+                                (int)wl.items.size(), work_counter(ws), g_opt.persistent != 0,
+                                static_cast<double *>(ws->part.ptr),
+                                phi ? static_cast<double *>(ws->part_phi.ptr) : nullptr, s));
+    if (e1) {
+        CHECK_HIP(hipEventRecord(e1, s));
+        g_timer[0].push_back({e0, e1});
+    }
+    return COLATUS_OK;
+}
+
+int run_adjoint_sweep(Workspace *ws, const WorkList &wl, int precision, bool mask,
+                      const double *x, const double *m, int64_t N, int n_cot,
+                      const double *lam, hipStream_t s)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_opt.timer) {
+        e0 = take_event();
+        e1 = take_event();
+    }
+    if (g_opt.persistent)
+        CHECK_HIP(launch_zero_counter(work_counter(ws), s));
+    if (e0)
+        CHECK_HIP(hipEventRecord(e0, s));
+    CHECK_HIP(launch_adjoint_sweep(precision, wl.cfg, mask, x, m, N, n_cot, lam,
+                                   static_cast<const WorkItem *>(wl.d_items.ptr),
+                                   (int)wl.items.size(), work_counter(ws),
+                                   g_opt.persistent != 0, static_cast<double *>(ws->part.ptr),
+                                   s));
+    if (e1) {
+        CHECK_HIP(hipEventRecord(e1, s));
+        g_timer[1].push_back({e0, e1});
+    }
+    return COLATUS_OK;
+}
+
+// Choose (and if asked, autotune) the tile shape, then make the work list.
+int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int precision,
+                     const double *x, const double *m, int n_cot, hipStream_t s)
+{
+    const int n_cu = cu_count(ws->device);
+    TuneKey key{pow2_ceil(b.max_n), (int)std::min<size_t>(pow2_ceil(b.eps.size()), 1 << 20),
+                precision, kind};
+    TileCfg cfg;
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        cfg = it->second;
+    } else {
+        cfg = heuristic_cfg(b, precision, kind, n_cu);
+        if (g_opt.autotune && x && m) {
+            // time candidates on the live data; scratch outputs only
+            std::vector<TileCfg> cand;
+            const int rs_f[3] = {1, 2, 4};
+            const int tp_f[2] = {128, 256};
+            if (kind == 0) {
+                for (int r : rs_f)
+                    for (int t : tp_f) {
+                        TileCfg c{r, t, 1};
+                        TileCfg h = heuristic_cfg(b, precision, kind, n_cu);
+                        const int tb = n_target_blocks(b, r * t);
+                        const int base = std::max(1, (4 * n_cu + tb - 1) / tb);
+                        for (int mult : {1, 2}) {
+                            c.slices = (int)std::max<int64_t>(
+                                1, std::min<int64_t>(base * mult, std::max<int64_t>(1, b.max_n / (2 * t))));
+                            cand.push_back(c);
+                        }
+                        (void)h;
+                    }
+            } else {
+                for (int r : {1, 2}) {
+                    TileCfg c{r, 256, 1};
+                    const int tb = n_target_blocks(b, r * 256);
+                    const int base = std::max(1, (4 * n_cu + tb - 1) / tb);
+                    for (int mult : {1, 2}) {
+                        c.slices = (int)std::max<int64_t>(
+                            1, std::min<int64_t>(base * mult, std::max<int64_t>(1, b.max_n / 512)));
+                        cand.push_back(c);
+                    }
+                }
+            }
+            hipEvent_t e0 = take_event(), e1 = take_event();
+            float best = 1e30f;
+            for (const TileCfg &c : cand) {
+                WorkList tmp;
+                CHECK_RC(ensure_worklist(ws, tmp, b, N, c, s));
+                const size_t need = (size_t)tmp.max_slices * 3 * (size_t)N * sizeof(double) *
+                                    (kind == 0 ? 1 : (size_t)std::max(1, n_cot));
+                CHECK_RC(ensure(ws->part, need));
+                CHECK_RC(ensure(ws->part_phi, (size_t)tmp.max_slices * N * sizeof(double)));
+                float ms_total = 0.0f;
+                for (int rep = 0; rep < 4; ++rep) {
+                    CHECK_HIP(launch_zero_counter(work_counter(ws), s));
+                    CHECK_HIP(hipEventRecord(e0, s));
+                    if (kind == 0)
+                        CHECK_HIP(launch_pair_sweep(
+                            precision, c, false, false, x, m, N,
+                            static_cast<const WorkItem *>(tmp.d_items.ptr), (int)tmp.items.size(),
+                            work_counter(ws), g_opt.persistent != 0,
+                            static_cast<double *>(ws->part.ptr), nullptr, s));
+                    else
+                        CHECK_HIP(launch_adjoint_sweep(
+                            precision, c, false, x, m, N, 1, x,
+                            static_cast<const WorkItem *>(tmp.d_items.ptr), (int)tmp.items.size(),
+                            work_counter(ws), g_opt.persistent != 0,
+                            static_cast<double *>(ws->part.ptr), s));
+                    CHECK_HIP(hipEventRecord(e1, s));
+                    CHECK_HIP(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep > 0)
+                        ms_total += ms;
+                }
+                for (Buffer *bb : {&tmp.d_items, &tmp.d_blocks, &tmp.d_box_first})
+                    if (bb->ptr)
+                        hipFree(bb->ptr);
+                if (ms_total < best) {
+                    best = ms_total;
+                    cfg = c;
+                }
+            }
+            g_event_pool.push_back(e0);
+            g_event_pool.push_back(e1);
+            g_tuned[key] = cfg;
+        }
+    }
+    cfg = apply_overrides(cfg, kind);
+    if (!cfg_supported(cfg, kind))
+        return COLATUS_EINVAL;
+    WorkList &wl = kind == 0 ? ws->fwd : ws->adj;
+    CHECK_RC(ensure_worklist(ws, wl, b, N, cfg, s));
+    return COLATUS_OK;
+}
+
+int check_ptrs(std::initializer_list<const void *> ps)
+{
+    for (const void *p : ps)
+        if (!p)
+            return COLATUS_EINVAL;
+    return COLATUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The run driver (shared by colatus_step and colatus_run).
+// ---------------------------------------------------------------------------
+struct RunParams {
+    double *x, *v;
+    const double *m;
+    int64_t N;
+    double G, H0, OmR, OmM, OmK, OmL, a_begin, a_end;
+    int64_t n_steps, first, last;
+    int precision;
+    colatus_diag *diag;
+    hipStream_t stream;
+};
+
+int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, bool mask,
+                  int64_t n_iter)
+{
+    // one iteration: integrate(n) -> tick -> sweep(x_{n+1})
+    hipStream_t s = P.stream;
+    const bool phi = P.diag != nullptr;
+    auto body = [&](hipStream_t st) -> int {
+        CHECK_HIP(launch_integrate(base, st));
+        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), st));
+        CHECK_RC(run_forward_sweep(ws, ws->fwd, P.precision, phi, mask, P.x, P.m, P.N, st,
+                                   false));
+        return COLATUS_OK;
+    };
+    const bool use_graph = g_opt.graph && !g_opt.timer && n_iter >= 8;
+    if (!use_graph) {
+        for (int64_t k = 0; k < n_iter; ++k)
+            CHECK_RC(body(s));
+        return COLATUS_OK;
+    }
+    if (!ws->cap_stream)
+        CHECK_HIP(hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking));
+    const int64_t per_graph = std::min<int64_t>(n_iter, 32);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    CHECK_HIP(hipStreamBeginCapture(ws->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = COLATUS_OK;
+    for (int64_t k = 0; k < per_graph && rc == COLATUS_OK; ++k)
+        rc = body(ws->cap_stream);
+    hipError_t ec = hipStreamEndCapture(ws->cap_stream, &graph);
+    if (rc != COLATUS_OK) {
+        if (graph)
+            hipGraphDestroy(graph);
+        return rc;
+    }
+    CHECK_HIP(ec);
+    hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    CHECK_HIP(ei);
+    int64_t done = 0;
+    while (done + per_graph <= n_iter) {
+        hipError_t el = hipGraphLaunch(exec, s);
+        if (el != hipSuccess) {
+            hipGraphExecDestroy(exec);
+            return hip_err(el);
+        }
+        done += per_graph;
+    }
+    // the graph is released after the queued replays have been consumed
+    for (; done < n_iter; ++done) {
+        rc = body(s);
+        if (rc != COLATUS_OK)
+            break;
+    }
+    hipError_t es = hipStreamSynchronize(s);
+    hipGraphExecDestroy(exec);
+    CHECK_HIP(es);
+    return rc;
+}
+
+int run_impl(const RunParams &P, const Boxes &b)
+{
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(P.stream, ws));
+    hipStream_t s = P.stream;
+    CHECK_RC(prepare_worklist(ws, 0, b, P.N, P.precision, P.x, P.m, 1, s));
+    const WorkList &wl = ws->fwd;
+    const int64_t nsteps = P.last - P.first;
+    const int64_t rows = nsteps + 1;
+    const int n_boxes = (int)b.eps.size();
+    const size_t n3 = 3 * (size_t)P.N;
+    CHECK_RC(ensure(ws->coef, (size_t)nsteps * sizeof(StepCoef)));
+    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n3 * sizeof(double)));
+    const bool diag = P.diag != nullptr;
+    if (diag) {
+        CHECK_RC(ensure(ws->part_phi, (size_t)wl.max_slices * P.N * sizeof(double)));
+        CHECK_RC(ensure(ws->diag_part, (size_t)rows * wl.blocks.size() * kDiagW * sizeof(double)));
+        CHECK_RC(ensure(ws->diag_out, (size_t)n_boxes * rows * sizeof(colatus_diag)));
+    }
+    bool mask = false;
+    for (double e : b.eps)
+        mask = mask || e == 0.0;
+
+    StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
+    double *p = static_cast<double *>(ws->p.ptr);
+    CHECK_HIP(launch_coefficients(P.H0, P.OmR, P.OmM, P.OmK, P.OmL, P.a_begin, P.a_end,
+                                  P.n_steps, P.first, P.last, coef, s));
+    CHECK_HIP(launch_convert(0, P.v, p, P.N, coef, 0, s));
+    CHECK_RC(set_step(ws, P.first, s));
+    CHECK_RC(run_forward_sweep(ws, wl, P.precision, diag, mask, P.x, P.m, P.N, s, false));
+
+    IntegrateArgs A;
+    A.x = P.x;
+    A.p = p;
+    A.m = P.m;
+    A.part = static_cast<const double *>(ws->part.ptr);
+    A.part_phi = diag ? static_cast<const double *>(ws->part_phi.ptr) : nullptr;
+    A.blocks = static_cast<const IntBlock *>(wl.d_blocks.ptr);
+    A.n_blocks = (int)wl.blocks.size();
+    A.N = P.N;
+    A.G = P.G;
+    A.coef = coef;
+    A.step = step_counter(ws);
+    A.first = P.first;
+    A.last = P.last;
+    A.diag_part = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
+
+    CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
+    CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
+    CHECK_HIP(launch_convert(1, p, P.v, P.N, coef, nsteps - 1, s));
+    if (diag) {
+        CHECK_HIP(launch_diag_reduce(static_cast<const double *>(ws->diag_part.ptr), (int)rows,
+                                     A.blocks, A.n_blocks, n_boxes,
+                                     static_cast<const int32_t *>(wl.d_box_first.ptr), coef,
+                                     P.H0, static_cast<double *>(ws->diag_out.ptr), s));
+        CHECK_HIP(hipMemcpyAsync(P.diag, ws->diag_out.ptr,
+                                 (size_t)n_boxes * rows * sizeof(colatus_diag),
+                                 hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        for (int64_t r = 0; r < (int64_t)n_boxes * rows; ++r)
+            if (P.diag[r].flags & 1u)
+                return COLATUS_ENONFINITE;
+    }
+    return COLATUS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Exported entry points.
+// ===========================================================================
+extern "C" {
+
+int colatus_version(void) { return 10000; }
+
+const char *colatus_strerror(int code)
+{
+    switch (code) {
+    case COLATUS_OK: return "success";
+    case COLATUS_EINVAL: return "invalid argument";
+    case COLATUS_EFRIEDMANN: return "H^2(a) <= 0 on the requested range of a";
+    case COLATUS_ENODEV: return "no HIP device available";
+    case COLATUS_ENOMEM: return "device memory allocation failed";
+    case COLATUS_EHIP: return "HIP runtime error";
+    case COLATUS_ENONFINITE: return "non-finite value in the state";
+    default: return "unknown error code";
+    }
+}
+
+int colatus_hubble(double a, double H0, double Om_R, double Om_M, double Om_K, double Om_L,
+                   double *H)
+{
+    if (!H || !is_fin(a) || a <= 0.0 || !is_fin(H0) || H0 < 0.0 || !is_fin(Om_R) ||
+        !is_fin(Om_M) || !is_fin(Om_K) || !is_fin(Om_L))
+        return COLATUS_EINVAL;
+    const double e2 = Om_R / (a * a * a * a) + Om_M / (a * a * a) + Om_K / (a * a) + Om_L;
+    if (e2 < 0.0)
+        return COLATUS_EFRIEDMANN;
+    *H = H0 * std::sqrt(e2);
+    return COLATUS_OK;
+}
+
+int colatus_set_option(int key, int64_t value)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    switch (key) {
+    case COLATUS_OPT_GRAPH: g_opt.graph = value != 0; return COLATUS_OK;
+    case COLATUS_OPT_TIMER: g_opt.timer = value != 0; return COLATUS_OK;
+    case COLATUS_OPT_AUTOTUNE: g_opt.autotune = value != 0; return COLATUS_OK;
+    case COLATUS_OPT_TILE_R:
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return COLATUS_EINVAL;
+        g_opt.tile_r = value;
+        return COLATUS_OK;
+    case COLATUS_OPT_TILE_TPB:
+        if (value != 0 && value != 128 && value != 256)
+            return COLATUS_EINVAL;
+        g_opt.tile_tpb = value;
+        return COLATUS_OK;
+    case COLATUS_OPT_TILE_SLICES:
+        if (value < 0 || value > 4096)
+            return COLATUS_EINVAL;
+        g_opt.tile_slices = value;
+        return COLATUS_OK;
+    case COLATUS_OPT_PERSISTENT: g_opt.persistent = value != 0; return COLATUS_OK;
+    }
+    return COLATUS_EINVAL;
+}
+
+int colatus_get_option(int key, int64_t *value)
+{
+    if (!value)
+        return COLATUS_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mu);
+    switch (key) {
+    case COLATUS_OPT_GRAPH: *value = g_opt.graph; return COLATUS_OK;
+    case COLATUS_OPT_TIMER: *value = g_opt.timer; return COLATUS_OK;
+    case COLATUS_OPT_AUTOTUNE: *value = g_opt.autotune; return COLATUS_OK;
+    case COLATUS_OPT_TILE_R: *value = g_opt.tile_r; return COLATUS_OK;
+    case COLATUS_OPT_TILE_TPB: *value = g_opt.tile_tpb; return COLATUS_OK;
+    case COLATUS_OPT_TILE_SLICES: *value = g_opt.tile_slices; return COLATUS_OK;
+    case COLATUS_OPT_PERSISTENT: *value = g_opt.persistent; return COLATUS_OK;
+    }
+    return COLATUS_EINVAL;
+}
+
+int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset)
+{
+    if (kind < 0 || kind > 1 || !total_ms || !launches)
+        return COLATUS_EINVAL;
+    std::lock_guard<std::mutex> lock(g_mu);
+    double tot = 0.0;
+    for (const TimerRec &r : g_timer[kind]) {
+        CHECK_HIP(hipEventSynchronize(r.stop));
+        float ms = 0.0f;
+        CHECK_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)g_timer[kind].size();
+    if (reset) {
+        for (const TimerRec &r : g_timer[kind]) {
+            g_event_pool.push_back(r.start);
+            g_event_pool.push_back(r.stop);
+        }
+        g_timer[kind].clear();
+    }
+    return COLATUS_OK;
+}
+
+int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[3])
+{
+    if (!out || N < 1 || N > kMaxN || !valid_precision(precision) || kind < 0 || kind > 1)
+        return COLATUS_EINVAL;
+    int dev = 0;
+    int n_cu = 256;
+    if (device_ready(dev) == COLATUS_OK)
+        n_cu = cu_count(dev);
+    Boxes b;
+    b.off = {0, N};
+    b.eps = {0.0};
+    b.max_n = N;
+    std::lock_guard<std::mutex> lock(g_mu);
+    TuneKey key{pow2_ceil(N), 1, precision, kind};
+    auto it = g_tuned.find(key);
+    TileCfg c = it != g_tuned.end() ? it->second : heuristic_cfg(b, precision, kind, n_cu);
+    c = apply_overrides(c, kind);
+    out[0] = c.R;
+    out[1] = c.tpb;
+    out[2] = c.slices;
+    return COLATUS_OK;
+}
+
+int colatus_release(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        return COLATUS_OK;
+    for (auto &kv : g_ws) {
+        Workspace *ws = kv.second;
+        hipSetDevice(ws->device);
+        hipStreamSynchronize(ws->stream);
+        for (Buffer *bb : {&ws->part, &ws->part_phi, &ws->coef, &ws->p, &ws->diag_part,
+                           &ws->diag_out, &ws->counters, &ws->lam_x, &ws->lam_p, &ws->ckpt,
+                           &ws->seg, &ws->fwd.d_items, &ws->fwd.d_blocks, &ws->fwd.d_box_first,
+                           &ws->adj.d_items, &ws->adj.d_blocks, &ws->adj.d_box_first})
+            if (bb->ptr)
+                hipFree(bb->ptr);
+        if (ws->cap_stream)
+            hipStreamDestroy(ws->cap_stream);
+        delete ws;
+    }
+    g_ws.clear();
+    return COLATUS_OK;
+}
+
+int colatus_forces(const double *x, const double *m, int64_t N, double eps, double G, double a,
+                   int precision, double *acc, double *phi, const colatus_batch *batch,
+                   void *stream)
+{
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || !is_fin(a) || a <= 0.0)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, m, acc}));
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, batch, b));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(prepare_worklist(ws, 0, b, N, precision, x, m, 1, s));
+    const WorkList &wl = ws->fwd;
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * 3 * N * sizeof(double)));
+    if (phi)
+        CHECK_RC(ensure(ws->part_phi, (size_t)wl.max_slices * N * sizeof(double)));
+    bool mask = false;
+    for (double e : b.eps)
+        mask = mask || e == 0.0;
+    CHECK_RC(run_forward_sweep(ws, wl, precision, phi != nullptr, mask, x, m, N, s, true));
+    CHECK_HIP(launch_forces_finalize(precision, static_cast<const IntBlock *>(wl.d_blocks.ptr),
+                                     (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
+                                     phi ? static_cast<const double *>(ws->part_phi.ptr) : nullptr,
+                                     m, N, G, G / (a * a * a), acc, phi, s));
+    return COLATUS_OK;
+}
+
+int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, double G,
+                double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a_begin,
+                double a_end, int64_t n_steps, int64_t first_step, int64_t last_step,
+                int precision, colatus_diag *diag, const colatus_batch *batch, void *stream)
+{
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
+        return COLATUS_EINVAL;
+    if (n_steps < 1 || first_step < 0 || last_step <= first_step || last_step > n_steps)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, v, m}));
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, batch, b));
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream)};
+    return run_impl(P, b);
+}
+
+int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, double G,
+                 double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a,
+                 double a_next, int precision, const colatus_batch *batch, void *stream)
+{
+    return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
+                       precision, nullptr, batch, stream);
+}
+
+int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, double G,
+                      int32_t n_cot, const double *lam, double *out, int precision,
+                      void *stream)
+{
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_cot < 1 ||
+        n_cot > kMaxCot)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, m, lam, out}));
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, nullptr, b));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(prepare_worklist(ws, 1, b, N, precision, x, m, n_cot, s));
+    const WorkList &wl = ws->adj;
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n_cot * 3 * N * sizeof(double)));
+    const bool mask = eps == 0.0;
+    CHECK_RC(run_adjoint_sweep(ws, wl, precision, mask, x, m, N, n_cot, lam, s));
+    CHECK_HIP(launch_vjp_finalize(precision, static_cast<const IntBlock *>(wl.d_blocks.ptr),
+                                  (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
+                                  N, n_cot, wl.max_slices, G, out, s));
+    return COLATUS_OK;
+}
+
+int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t N, double eps,
+                    double G, double H0, double Om_R, double Om_M, double Om_K, double Om_L,
+                    double a_begin, double a_end, int64_t n_steps, int64_t checkpoint_every,
+                    int32_t n_cot, const double *lam_xN, const double *lam_vN, double *grad_x0,
+                    double *grad_v0, double *xN, double *vN, int precision,
+                    const colatus_batch *batch, void *stream)
+{
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
+        checkpoint_every < 1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x0, v0, m, lam_xN, lam_vN, grad_x0, grad_v0}));
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, nullptr, b));
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(prepare_worklist(ws, 0, b, N, precision, x0, m, 1, s));
+    CHECK_RC(prepare_worklist(ws, 1, b, N, precision, x0, m, n_cot, s));
+    const WorkList &wf = ws->fwd;
+    const WorkList &wa = ws->adj;
+    const size_t n3 = 3 * (size_t)N;
+    const int64_t K = checkpoint_every;
+    const int64_t n_seg = (n_steps + K - 1) / K;
+    CHECK_RC(ensure(ws->coef, (size_t)n_steps * sizeof(StepCoef)));
+    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
+    const size_t part_fwd = (size_t)wf.max_slices * n3;
+    const size_t part_adj = (size_t)wa.max_slices * n3 * (size_t)n_cot;
+    CHECK_RC(ensure(ws->part, std::max(part_fwd, part_adj) * sizeof(double)));
+    CHECK_RC(ensure(ws->lam_x, (size_t)n_cot * n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->lam_p, (size_t)n_cot * n3 * sizeof(double)));
+    // checkpoints: (x, p) at n = 0, K, 2K, ... ; segment states: K + 1 positions
+    CHECK_RC(ensure(ws->ckpt, (size_t)n_seg * 2 * n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->seg, (size_t)(K + 1) * n3 * sizeof(double)));
+    const bool mask = eps == 0.0;
+
+    StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
+    double *p = static_cast<double *>(ws->p.ptr);
+    double *ck = static_cast<double *>(ws->ckpt.ptr);
+    double *seg = static_cast<double *>(ws->seg.ptr);
+    double *lx = static_cast<double *>(ws->lam_x.ptr);
+    double *lp = static_cast<double *>(ws->lam_p.ptr);
+    // the working position buffer is the first segment slot
+    double *xw = seg;
+
+    CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps, 0,
+                                  n_steps, coef, s));
+    std::vector<StepCoef> hc((size_t)n_steps);
+    CHECK_HIP(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(StepCoef), hipMemcpyDeviceToHost,
+                             s));
+    CHECK_HIP(hipStreamSynchronize(s));
+
+    IntegrateArgs A;
+    A.p = p;
+    A.m = m;
+    A.part = static_cast<const double *>(ws->part.ptr);
+    A.part_phi = nullptr;
+    A.blocks = static_cast<const IntBlock *>(wf.d_blocks.ptr);
+    A.n_blocks = (int)wf.blocks.size();
+    A.N = N;
+    A.G = G;
+    A.coef = coef;
+    A.step = step_counter(ws);
+    A.first = 0;
+    A.last = n_steps;
+    A.diag_part = nullptr;
+
+    // ---- forward with checkpoints --------------------------------------
+    CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CHECK_HIP(launch_convert(0, v0, p, N, coef, 0, s));
+    CHECK_RC(set_step(ws, 0, s));
+    A.x = xw;
+    for (int64_t n = 0; n < n_steps; ++n) {
+        CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
+        if (n % K == 0) {
+            double *cx = ck + (size_t)(n / K) * 2 * n3;
+            CHECK_HIP(hipMemcpyAsync(cx, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            CHECK_HIP(hipMemcpyAsync(cx + n3, p, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        CHECK_HIP(launch_integrate(A, s));
+        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+    }
+    if (xN || vN) {
+        CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
+        CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_end
+        if (xN)
+            CHECK_HIP(hipMemcpyAsync(xN, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (vN)
+            CHECK_HIP(launch_convert(1, p, vN, N, coef, n_steps - 1, s));
+    }
+
+    // ---- reverse sweep ---------------------------------------------------
+    const double aN = hc[(size_t)n_steps - 1].a1, a0 = hc[0].a0;
+    CHECK_HIP(hipMemcpyAsync(lx, lam_xN, (size_t)n_cot * n3 * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    CHECK_HIP(launch_scale(lam_vN, lp, (int64_t)n_cot * (int64_t)n3, 1.0 / (aN * aN), s));
+    for (int64_t sg = n_seg - 1; sg >= 0; --sg) {
+        const int64_t lo = sg * K, hi = std::min(lo + K, n_steps);
+        // recompute positions x_lo .. x_hi from the checkpoint (bitwise: same kernels)
+        const double *cx = ck + (size_t)sg * 2 * n3;
+        CHECK_HIP(hipMemcpyAsync(seg, cx, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        CHECK_HIP(hipMemcpyAsync(p, cx + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        CHECK_RC(set_step(ws, lo, s));
+        for (int64_t n = lo; n < hi; ++n) {
+            double *xs = seg + (size_t)(n - lo) * n3;
+            double *xn = seg + (size_t)(n - lo + 1) * n3;
+            CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
+            CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            IntegrateArgs B = A;
+            B.x = xn;
+            CHECK_HIP(launch_integrate(B, s));
+            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+        }
+        // visit x_n for n = hi (only in the top segment) .. lo+1, and lo in segment 0
+        const int64_t top = (sg == n_seg - 1) ? hi : hi - 1;
+        const int64_t bottom = (sg == 0) ? lo : lo + 1;
+        for (int64_t n = top; n >= bottom; --n) {
+            const double *xs = seg + (size_t)(n - lo) * n3;
+            CHECK_RC(run_adjoint_sweep(ws, wa, precision, mask, xs, m, N, n_cot, lp, s));
+            const double cw = (n < n_steps ? hc[(size_t)n].k1 : 0.0) +
+                              (n > 0 ? hc[(size_t)n - 1].k2 : 0.0);
+            const double dnext = n > 0 ? hc[(size_t)n - 1].d : 0.0;
+            CHECK_HIP(launch_adjoint_update(static_cast<const IntBlock *>(wa.d_blocks.ptr),
+                                            (int)wa.blocks.size(),
+                                            static_cast<const double *>(ws->part.ptr),
+                                            wa.max_slices, N, n_cot, G, cw, lx, lp, n > 0 ? 1 : 0,
+                                            dnext, s));
+        }
+    }
+    CHECK_HIP(hipMemcpyAsync(grad_x0, lx, (size_t)n_cot * n3 * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    CHECK_HIP(launch_scale(lp, grad_v0, (int64_t)n_cot * (int64_t)n3, a0 * a0, s));
+    return COLATUS_OK;
+}
+
+}  // extern "C"

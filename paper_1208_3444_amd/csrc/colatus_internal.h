@@ -1,0 +1,136 @@
+// Internal declarations shared by the HIP translation units of libcolatus.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace colatus {
+
+// One unit of the O(N^2) pair sweep: a block of target particles of one box
+// against a contiguous slice of that box's source particles.  The sweep
+// writes its partial sums into slot `slice` of the partial-sum buffer.
+struct WorkItem {
+    int64_t i0, i1;   // targets [i0, i1)
+    int64_t j0, j1;   // sources [j0, j1)
+    double eps2;      // squared softening of the box
+    int32_t slice;    // partial-sum slot
+    int32_t box;
+};
+
+// Up to kIntBlock particles of one box, for the O(N) kernels (finalise,
+// kick/drift, diagnostics).  Blocks never straddle a box boundary.
+constexpr int kIntBlock = 256;
+struct IntBlock {
+    int64_t i0, i1;
+    double eps;       // softening of the box (self-term of the potential)
+    int32_t box;
+    int32_t n_slices; // partial-sum slots written for this box
+};
+
+// Coefficients of step n of a run (Eq. (9) integrals).
+struct StepCoef {
+    double k1;   // int_{a_n}^{a_n+1/2} dt / a
+    double d;    // int_{a_n}^{a_n+1} dt / a^2
+    double k2;   // int_{a_n+1/2}^{a_n+1} dt / a
+    double dt;   // cosmic time of the step
+    double a0;   // a_n
+    double a1;   // a_{n+1}
+};
+
+enum Precision { kFP64 = 0, kMixedTwoSum = 1, kMixedF64Acc = 2, kFP32 = 3 };
+
+// Shape of one pair-sweep launch.
+struct TileCfg {
+    int R;        // targets per lane
+    int tpb;      // threads per block (= sources per LDS tile)
+    int slices;   // source slices per box
+};
+
+// Diagnostics partial row written per IntBlock: K*a^2*2, sum m phi, P[3], L[3],
+// non-finite flag (as a double), padding.
+constexpr int kDiagW = 10;
+
+// ---- launchers (each returns the launch's hipError_t) -------------------
+
+// Forward pair sweep: part[s][3][N] = sum over the item's sources of
+// m_j (x_j - x_k) r^-3, and part_phi[s][N] = sum m_j / r when with_phi.
+hipError_t launch_pair_sweep(int precision, const TileCfg &cfg, bool with_phi,
+                             bool mask_self, const double *x, const double *m,
+                             int64_t N, const WorkItem *items, int n_items,
+                             int *counter, bool persistent, double *part,
+                             double *part_phi, hipStream_t stream);
+
+// Adjoint pair sweep for n_cot cotangents lam [n_cot][3][N]:
+// part[s][c][3][N] = sum over the item's sources of M(d)(m_k lam_j - m_j lam_k).
+hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_self,
+                                const double *x, const double *m, int64_t N,
+                                int n_cot, const double *lam,
+                                const WorkItem *items, int n_items, int *counter,
+                                bool persistent, double *part, hipStream_t stream);
+
+// Sets *counter = 0 (graph-safe replacement for a memset node).
+hipError_t launch_zero_counter(int *counter, hipStream_t stream);
+
+// acc = scale * sum_s part[s], phi = -G (sum_s part_phi[s] - m/eps).
+hipError_t launch_forces_finalize(int precision, const IntBlock *blocks, int n_blocks,
+                                  const double *part, const double *part_phi,
+                                  const double *m, int64_t N, double G, double scale,
+                                  double *acc, double *phi, hipStream_t stream);
+
+// out = G * sum_s part[s] for n_cot cotangents ([n_cot][3][N]).
+hipError_t launch_vjp_finalize(int precision, const IntBlock *blocks, int n_blocks,
+                               const double *part, int64_t N, int n_cot, int n_slices,
+                               double G, double *out, hipStream_t stream);
+
+// Step coefficients of steps [first, last) of the global grid.
+hipError_t launch_coefficients(double H0, double OmR, double OmM, double OmK, double OmL,
+                               double a_begin, double a_end, int64_t n_steps,
+                               int64_t first, int64_t last, StepCoef *coef,
+                               hipStream_t stream);
+
+// p = a_first^2 v (mode 0) or v = p / a^2 (mode 1) over all particles.
+hipError_t launch_convert(int mode, const double *src, double *dst, int64_t N,
+                          const StepCoef *coef, int64_t idx, hipStream_t stream);
+
+struct IntegrateArgs {
+    double *x;             // [3][N], in/out
+    double *p;             // [3][N], in/out (canonical momentum a^2 v)
+    const double *m;
+    const double *part;    // [S][3][N]
+    const double *part_phi;// [S][N] or null
+    const IntBlock *blocks;
+    int n_blocks;
+    int64_t N;
+    double G;
+    const StepCoef *coef;  // indexed by (n - first)
+    const int64_t *step;   // device step counter n (absolute)
+    int64_t first, last;
+    double *diag_part;     // [rows][n_blocks][kDiagW] or null
+};
+// Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
+// record diagnostics of the state at a_n, and (n < last) kick by k1_n and
+// drift by d_n.  Reads n from *step.
+hipError_t launch_integrate(const IntegrateArgs &args, hipStream_t stream);
+
+// *step += 1; *counter = 0.
+hipError_t launch_tick(int64_t *step, int *counter, hipStream_t stream);
+
+// Reduce per-block diagnostics rows per box and accumulate LI / t.
+// out: [n_boxes][rows] rows of colatus_diag layout (as doubles, 14 each).
+hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock *blocks,
+                              int n_blocks, int n_boxes, const int32_t *box_first_block,
+                              const StepCoef *coef, double H0, double *out,
+                              hipStream_t stream);
+
+// Adjoint update after a VJP sweep at x_n (all cotangents):
+//   w = G sum_s part;  lam_x += cw * w;  then if do_drift: lam_p += dnext * lam_x.
+hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
+                                 int n_slices, int64_t N, int n_cot, double G, double cw,
+                                 double *lam_x, double *lam_p, int do_drift, double dnext,
+                                 hipStream_t stream);
+
+// lam_p = lam_v / aN^2 (mode 0) or grad_v = a0^2 lam_p (mode 1); n values.
+hipError_t launch_scale(const double *src, double *dst, int64_t n, double factor,
+                        hipStream_t stream);
+
+}  // namespace colatus

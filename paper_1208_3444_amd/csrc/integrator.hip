@@ -1,0 +1,448 @@
+// O(N) kernels around the pair sweep: Friedmann step coefficients, the
+// kick-drift-kick update in canonical momentum, diagnostics, and the
+// finalisation of split-source partial sums.  All of them are bound by HBM
+// traffic (or launch latency at small N): each reads and writes each
+// particle's FP64 state once, coalesced, in structure-of-arrays planes.
+#include "colatus_internal.h"
+
+#include "colatus.h"
+
+#include <math.h>
+
+namespace colatus {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Friedmann equation (Eq. (2)) and the time integrals of the kick and drift
+// operators (Eq. (9)), evaluated in s = ln a by composite 8-point
+// Gauss-Legendre quadrature (sub-intervals of at most 0.05 in ln a):
+//   cosmic time   int dt       = int ds / H
+//   kick          int dt / a   = int e^-s  ds / H
+//   drift         int dt / a^2 = int e^-2s ds / H
+// ---------------------------------------------------------------------------
+__constant__ double kGLx[4] = {0.18343464249564978, 0.52553240991632899, 0.79666647741362673,
+                               0.96028985649753618};
+__constant__ double kGLw[4] = {0.36268378337836177, 0.31370664587788705, 0.22238103445337434,
+                               0.10122853629037669};
+
+struct Cosmo {
+    double H0, OmR, OmM, OmK, OmL;
+};
+
+__device__ double hubble(const Cosmo &c, double a)
+{
+    const double ia = 1.0 / a;
+    const double ia2 = ia * ia;
+    const double e2 = c.OmR * ia2 * ia2 + c.OmM * ia2 * ia + c.OmK * ia2 + c.OmL;
+    return c.H0 * sqrt(e2);  // NaN when e2 < 0; the host rejects such ranges
+}
+
+// int_{s0}^{s1} e^{-q s} / H(e^s) ds for q = 0, 1, 2 at once.
+__device__ void time_integrals(const Cosmo &c, double s0, double s1, double out[3])
+{
+    const double span = s1 - s0;
+    int nsub = (int)ceil(fabs(span) / 0.05);
+    if (nsub < 1)
+        nsub = 1;
+    const double h = span / nsub;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < nsub; ++k) {
+        const double mid = s0 + (k + 0.5) * h;
+        for (int q = 0; q < 4; ++q) {
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double s = mid + sgn * 0.5 * h * kGLx[q];
+                const double a = exp(s);
+                const double wH = kGLw[q] / hubble(c, a);
+                const double ia = 1.0 / a;
+                acc[0] += wH;
+                acc[1] += wH * ia;
+                acc[2] += wH * ia * ia;
+            }
+        }
+    }
+    for (int q = 0; q < 3; ++q)
+        out[q] = 0.5 * h * acc[q];
+}
+
+__global__ void coefficients_kernel(Cosmo c, double a_begin, double a_end, int64_t n_steps,
+                                    int64_t first, int64_t last, StepCoef *coef)
+{
+    const int64_t n = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= last)
+        return;
+    StepCoef s;
+    if (c.H0 == 0.0) {
+        const double dt = a_end / (double)n_steps;
+        const double a = a_begin;
+        s.k1 = 0.5 * dt / a;
+        s.k2 = 0.5 * dt / a;
+        s.d = dt / (a * a);
+        s.dt = dt;
+        s.a0 = a;
+        s.a1 = a;
+    } else {
+        const double delta = log(a_end / a_begin) / (double)n_steps;
+        const double a0 = a_begin * exp((double)n * delta);
+        const double ah = a_begin * exp(((double)n + 0.5) * delta);
+        const double a1 = (n + 1 == n_steps) ? a_end : a_begin * exp((double)(n + 1) * delta);
+        const double s0 = log(a0), sh = log(ah), s1 = log(a1);
+        double lo[3], hi[3];
+        time_integrals(c, s0, sh, lo);
+        time_integrals(c, sh, s1, hi);
+        s.k1 = lo[1];
+        s.k2 = hi[1];
+        s.d = lo[2] + hi[2];
+        s.dt = lo[0] + hi[0];
+        s.a0 = a0;
+        s.a1 = a1;
+    }
+    coef[n - first] = s;
+}
+
+__global__ void convert_kernel(int mode, const double *__restrict__ src, double *__restrict__ dst,
+                               int64_t n3, const StepCoef *__restrict__ coef, int64_t idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3)
+        return;
+    if (mode == 0) {
+        const double a = coef[idx].a0;
+        dst[i] = a * a * src[i];
+    } else {
+        const double a = coef[idx].a1;
+        dst[i] = src[i] / (a * a);
+    }
+}
+
+// Deterministic tree sum of kDiagW values over a 256-thread block.
+__device__ void block_sum_rows(double (&v)[kDiagW], double (*sh)[kIntBlock])
+{
+    const int tid = threadIdx.x;
+    for (int q = 0; q < kDiagW; ++q)
+        sh[q][tid] = v[q];
+    __syncthreads();
+    for (int w = kIntBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            for (int q = 0; q < kDiagW; ++q) {
+                if (q == kDiagW - 1)
+                    sh[q][tid] = fmax(sh[q][tid], sh[q][tid + w]);
+                else
+                    sh[q][tid] += sh[q][tid + w];
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < kDiagW; ++q)
+        v[q] = sh[q][0];
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c)
+{
+    return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// Kick-drift-kick in canonical momentum p = a^2 v (Eq. (9) with the kick
+// factor int dt/a acting on g = G sum m_j (x_j - x_k) r^-3 and the drift
+// factor int dt/a^2 acting on p).  One launch per grid point n:
+//   g = G sum_s part[s]                       (finalise split partials)
+//   p += k2_{n-1} g                           (closing half kick, n > first)
+//   diagnostics of (x_n, p_n)                 (optional)
+//   p += k1_n g;  x += d_n p                  (opening half kick + drift, n < last)
+__global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
+{
+    __shared__ double sh[kDiagW][kIntBlock];
+    const IntBlock blk = A.blocks[blockIdx.x];
+    const int64_t i = blk.i0 + threadIdx.x;
+    const bool valid = i < blk.i1;
+    const int64_t n = *A.step;
+    const int64_t row = n - A.first;
+    const int64_t N = A.N;
+    const int S = blk.n_slices;
+
+    double v[kDiagW];
+    for (int q = 0; q < kDiagW; ++q)
+        v[q] = 0.0;
+    if (valid) {
+        double g[3];
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < S; ++k)
+                s += A.part[((int64_t)k * 3 + c) * N + i];
+            g[c] = A.G * s;
+        }
+        double p[3] = {A.p[i], A.p[N + i], A.p[2 * N + i]};
+        double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
+        if (n > A.first) {
+            const double k2 = A.coef[row - 1].k2;
+            for (int c = 0; c < 3; ++c)
+                p[c] += k2 * g[c];
+        }
+        if (A.diag_part) {
+            const double mi = A.m[i];
+            double phs = 0.0;
+            for (int k = 0; k < S; ++k)
+                phs += A.part_phi[(int64_t)k * N + i];
+            if (blk.eps > 0.0)
+                phs -= mi / blk.eps;  // the self pair's m_i / eps
+            const double phi = -A.G * phs;
+            v[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+            v[1] = mi * phi;
+            v[2] = mi * p[0];
+            v[3] = mi * p[1];
+            v[4] = mi * p[2];
+            v[5] = mi * (xx[1] * p[2] - xx[2] * p[1]);
+            v[6] = mi * (xx[2] * p[0] - xx[0] * p[2]);
+            v[7] = mi * (xx[0] * p[1] - xx[1] * p[0]);
+            v[8] = 0.0;
+            v[9] = (finite3(xx[0], xx[1], xx[2]) && finite3(p[0], p[1], p[2]) && isfinite(phi))
+                       ? 0.0
+                       : 1.0;
+        }
+        if (n < A.last) {
+            const StepCoef cf = A.coef[row];
+            for (int c = 0; c < 3; ++c) {
+                p[c] += cf.k1 * g[c];
+                xx[c] += cf.d * p[c];
+            }
+            A.x[i] = xx[0];
+            A.x[N + i] = xx[1];
+            A.x[2 * N + i] = xx[2];
+        }
+        A.p[i] = p[0];
+        A.p[N + i] = p[1];
+        A.p[2 * N + i] = p[2];
+    }
+    if (A.diag_part) {
+        block_sum_rows(v, sh);
+        if (threadIdx.x == 0) {
+            double *out = A.diag_part + (row * A.n_blocks + blockIdx.x) * kDiagW;
+            for (int q = 0; q < kDiagW; ++q)
+                out[q] = v[q];
+        }
+    }
+}
+
+__global__ void tick_kernel(int64_t *step, int *counter)
+{
+    *step += 1;
+    *counter = 0;
+}
+
+// One block per box: sum the per-block rows in block order, then the
+// Layzer-Irvine residual and elapsed time by a sequential pass.
+__global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int rows,
+                                   const IntBlock *__restrict__ blocks, int n_blocks,
+                                   const int32_t *__restrict__ box_first_block,
+                                   const StepCoef *__restrict__ coef, double H0,
+                                   colatus_diag *__restrict__ out)
+{
+    const int box = blockIdx.x;
+    const int b0 = box_first_block[box], b1 = box_first_block[box + 1];
+    colatus_diag *o = out + (int64_t)box * rows;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        double s[kDiagW];
+        for (int q = 0; q < kDiagW; ++q)
+            s[q] = 0.0;
+        for (int b = b0; b < b1; ++b) {
+            const double *d = diag_part + ((int64_t)r * n_blocks + b) * kDiagW;
+            for (int q = 0; q < kDiagW - 1; ++q)
+                s[q] += d[q];
+            s[kDiagW - 1] = fmax(s[kDiagW - 1], d[kDiagW - 1]);
+        }
+        const double a = (r < rows - 1) ? coef[r].a0 : coef[r - 1].a1;
+        colatus_diag row;
+        row.a = a;
+        row.t = 0.0;
+        row.K = 0.5 * s[0] / (a * a);
+        row.U = 0.5 * s[1] / a;
+        row.LI = 0.0;
+        row.P[0] = s[2];
+        row.P[1] = s[3];
+        row.P[2] = s[4];
+        row.L[0] = s[5];
+        row.L[1] = s[6];
+        row.L[2] = s[7];
+        const bool bad = s[kDiagW - 1] != 0.0 || !isfinite(row.K) || !isfinite(row.U);
+        row.flags = bad ? 1u : 0u;
+        row.reserved = 0u;
+        o[r] = row;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double E0 = o[0].K + o[0].U;
+        double t = 0.0, li = 0.0;
+        double prev = 2.0 * o[0].K + o[0].U;
+        for (int r = 1; r < rows; ++r) {
+            t += coef[r - 1].dt;
+            const double src = 2.0 * o[r].K + o[r].U;
+            const double dlna = (H0 == 0.0) ? 0.0 : log(o[r].a) - log(o[r - 1].a);
+            li += 0.5 * (prev + src) * dlna;
+            prev = src;
+            o[r].t = t;
+            o[r].LI = o[r].K + o[r].U - E0 + li;
+        }
+    }
+}
+
+// acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - m / eps).
+__global__ __launch_bounds__(kIntBlock) void forces_finalize_kernel(
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part,
+    const double *__restrict__ part_phi, const double *__restrict__ m, int64_t N, double G,
+    double scale, double *__restrict__ acc, double *__restrict__ phi)
+{
+    const IntBlock blk = blocks[blockIdx.x];
+    const int64_t i = blk.i0 + threadIdx.x;
+    if (i >= blk.i1)
+        return;
+    for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < blk.n_slices; ++k)
+            s += part[((int64_t)k * 3 + c) * N + i];
+        acc[(int64_t)c * N + i] = scale * s;
+    }
+    if (phi) {
+        double s = 0.0;
+        for (int k = 0; k < blk.n_slices; ++k)
+            s += part_phi[(int64_t)k * N + i];
+        if (blk.eps > 0.0)
+            s -= m[i] / blk.eps;
+        phi[i] = -G * s;
+    }
+}
+
+// out[c] = G * sum_s part[s][c]  (part [S][n_cot][3][N]).
+__global__ __launch_bounds__(kIntBlock) void vjp_finalize_kernel(
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int64_t N, int n_cot,
+    double G, double *__restrict__ out)
+{
+    const IntBlock blk = blocks[blockIdx.x];
+    const int64_t i = blk.i0 + threadIdx.x;
+    if (i >= blk.i1)
+        return;
+    for (int c = 0; c < n_cot; ++c)
+        for (int q = 0; q < 3; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < blk.n_slices; ++k)
+                s += part[(((int64_t)k * n_cot + c) * 3 + q) * N + i];
+            out[((int64_t)c * 3 + q) * N + i] = G * s;
+        }
+}
+
+// lam_x += cw * G sum_s part[s];  then (do_drift) lam_p += dnext * lam_x.
+__global__ __launch_bounds__(kIntBlock) void adjoint_update_kernel(
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int64_t N, int n_cot,
+    double G, double cw, double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift,
+    double dnext)
+{
+    const IntBlock blk = blocks[blockIdx.x];
+    const int64_t i = blk.i0 + threadIdx.x;
+    if (i >= blk.i1)
+        return;
+    for (int c = 0; c < n_cot; ++c)
+        for (int q = 0; q < 3; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < blk.n_slices; ++k)
+                s += part[(((int64_t)k * n_cot + c) * 3 + q) * N + i];
+            const int64_t o = ((int64_t)c * 3 + q) * N + i;
+            const double lx = lam_x[o] + cw * (G * s);
+            lam_x[o] = lx;
+            if (do_drift)
+                lam_p[o] += dnext * lx;
+        }
+}
+
+__global__ void scale_kernel(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
+                             double f)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = f * src[i];
+}
+
+inline unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+}  // namespace
+
+hipError_t launch_coefficients(double H0, double OmR, double OmM, double OmK, double OmL,
+                               double a_begin, double a_end, int64_t n_steps, int64_t first,
+                               int64_t last, StepCoef *coef, hipStream_t stream)
+{
+    Cosmo c{H0, OmR, OmM, OmK, OmL};
+    const int64_t n = last - first;
+    hipLaunchKernelGGL(coefficients_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, stream, c,
+                       a_begin, a_end, n_steps, first, last, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int mode, const double *src, double *dst, int64_t N,
+                          const StepCoef *coef, int64_t idx, hipStream_t stream)
+{
+    hipLaunchKernelGGL(convert_kernel, dim3(blocks_for(3 * N, 256)), dim3(256), 0, stream, mode,
+                       src, dst, 3 * N, coef, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(const IntegrateArgs &args, hipStream_t stream)
+{
+    hipLaunchKernelGGL(integrate_kernel, dim3(args.n_blocks), dim3(kIntBlock), 0, stream, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(int64_t *step, int *counter, hipStream_t stream)
+{
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, stream, step, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock *blocks,
+                              int n_blocks, int n_boxes, const int32_t *box_first_block,
+                              const StepCoef *coef, double H0, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(diag_reduce_kernel, dim3(n_boxes), dim3(256), 0, stream, diag_part, rows,
+                       blocks, n_blocks, box_first_block, coef, H0,
+                       reinterpret_cast<colatus_diag *>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_finalize(int precision, const IntBlock *blocks, int n_blocks,
+                                  const double *part, const double *part_phi, const double *m,
+                                  int64_t N, double G, double scale, double *acc, double *phi,
+                                  hipStream_t stream)
+{
+    (void)precision;
+    hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream,
+                       blocks, part, part_phi, m, N, G, scale, acc, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_finalize(int precision, const IntBlock *blocks, int n_blocks,
+                               const double *part, int64_t N, int n_cot, int n_slices, double G,
+                               double *out, hipStream_t stream)
+{
+    (void)precision;
+    (void)n_slices;
+    hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream, blocks,
+                       part, N, n_cot, G, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
+                                 int n_slices, int64_t N, int n_cot, double G, double cw,
+                                 double *lam_x, double *lam_p, int do_drift, double dnext,
+                                 hipStream_t stream)
+{
+    (void)n_slices;
+    hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream,
+                       blocks, part, N, n_cot, G, cw, lam_x, lam_p, do_drift, dnext);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const double *src, double *dst, int64_t n, double factor,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, src, dst, n,
+                       factor);
+    return hipGetLastError();
+}
+
+}  // namespace colatus

@@ -1,0 +1,640 @@
+// Pair sweeps of the direct-summation (particle-particle) scheme: the O(N^2)
+// hot loop of the method (Section II: the force computation dominates the
+// cost; Appendix A: one GPU thread per target particle looping over every
+// source).  Gfx950 design, not a translation of the paper's kernel:
+//
+//   * a work item is (block of target particles) x (slice of sources); the
+//     slices of one target block write separate partial sums that a later
+//     O(N) kernel adds in a fixed order, so results are deterministic and a
+//     32^3 problem still spreads over thousands of wave64s;
+//   * each lane keeps R targets in registers; sources are staged tile by tile
+//     into LDS (one source per thread) and read back as wave-uniform
+//     broadcasts, so one LDS read feeds R pair interactions;
+//   * mixed precision stores coordinates relative to the centre of the target
+//     block's bounding box (FP64 subtract, then round to FP32), so FP32 pair
+//     arithmetic keeps the relative accuracy of the separation itself;
+//   * per-tile FP32 partial sums are folded into FP64 or an unevaluated FP32
+//     (hi, lo) pair with TwoSum (Knuth), bounding the accumulation error;
+//   * rsqrt is the hardware v_rsq_f32 in FP32 and a Newton-refined rsqrt in
+//     FP64; no MFMA: the pair interaction is not a dense contraction.
+//
+// The persistent variant launches about one grid of resident workgroups and
+// pulls work items from a device counter until none are left (every
+// workgroup's last fetch sees the counter past the end and exits).
+#include "colatus_internal.h"
+
+#include <math.h>
+
+namespace colatus {
+namespace {
+
+enum AccMode { kDirect = 0, kTwoSum = 1, kFold64 = 2 };
+
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+__device__ __forceinline__ float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
+__device__ __forceinline__ double rsqrt_t(double s) { return rsqrt(s); }
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
+// hi + lo += v with the rounding error of hi + v carried into lo (TwoSum).
+__device__ __forceinline__ void two_sum_add(float &hi, float &lo, float v)
+{
+    float s = hi + v;
+    float bp = s - hi;
+    float err = (hi - (s - bp)) + (v - bp);
+    hi = s;
+    lo += err;
+}
+
+// Centre of the bounding box of the block's valid targets, for every thread.
+template <int TPB, int R>
+__device__ __forceinline__ void block_centre(const double (&tx)[R], const double (&ty)[R],
+                                             const double (&tz)[R], const bool (&valid)[R],
+                                             double (*red)[6], double &cx, double &cy,
+                                             double &cz)
+{
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (valid[r]) {
+            v[0] = fmin(v[0], tx[r]);
+            v[1] = fmin(v[1], ty[r]);
+            v[2] = fmin(v[2], tz[r]);
+            v[3] = fmax(v[3], tx[r]);
+            v[4] = fmax(v[4], ty[r]);
+            v[5] = fmax(v[5], tz[r]);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            v[q] = fmin(v[q], __shfl_xor(v[q], off, 64));
+            v[q + 3] = fmax(v[q + 3], __shfl_xor(v[q + 3], off, 64));
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            red[wave][q] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        v[q] = red[0][q];
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            v[q] = fmin(v[q], red[w][q]);
+            v[q + 3] = fmax(v[q + 3], red[w][q + 3]);
+        }
+    }
+    cx = 0.5 * (v[0] + v[3]);
+    cy = 0.5 * (v[1] + v[4]);
+    cz = 0.5 * (v[2] + v[5]);
+}
+
+// Fetch the next work item index (persistent) or this block's (one-shot).
+__device__ __forceinline__ int next_item(int persistent, int *counter, int *s_item, int iter)
+{
+    if (!persistent)
+        return iter == 0 ? (int)blockIdx.x : 0x7fffffff;
+    if (threadIdx.x == 0)
+        *s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    int it = *s_item;
+    __syncthreads();
+    return it;
+}
+
+// ---------------------------------------------------------------------------
+// Forward sweep: sum_j m_j (x_j - x_k) r^-3 (and sum_j m_j r^-1 with PHI).
+// ---------------------------------------------------------------------------
+template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK>
+__global__ __launch_bounds__(TPB) void pair_sweep_kernel(
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
+    const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
+    int persistent, double *__restrict__ part, double *__restrict__ part_phi)
+{
+    using V = typename V4<T>::type;
+    __shared__ V tile[TPB];
+    __shared__ double red[TPB / 64][6];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const double *X = x, *Y = x + N, *Z = x + 2 * N;
+
+    for (int iter = 0;; ++iter) {
+        const int it = next_item(persistent, counter, &s_item, iter);
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+
+        double tx[R], ty[R], tz[R];
+        bool valid[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = w.i0 + tid + (int64_t)r * TPB;
+            valid[r] = i < w.i1;
+            const int64_t ii = valid[r] ? i : w.i0;
+            tx[r] = X[ii];
+            ty[r] = Y[ii];
+            tz[r] = Z[ii];
+        }
+        double cx, cy, cz;
+        block_centre<TPB, R>(tx, ty, tz, valid, red, cx, cy, cz);
+
+        T xi[R], yi[R], zi[R];
+        T ax[R], ay[R], az[R], ph[R];
+        T hx[R], hy[R], hz[R], hp[R];      // TwoSum hi
+        T lx[R], ly[R], lz[R], lp[R];      // TwoSum lo
+        double bx[R], by[R], bz[R], bp[R]; // FP64 fold
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            xi[r] = (T)(tx[r] - cx);
+            yi[r] = (T)(ty[r] - cy);
+            zi[r] = (T)(tz[r] - cz);
+            ax[r] = ay[r] = az[r] = ph[r] = (T)0;
+            hx[r] = hy[r] = hz[r] = hp[r] = (T)0;
+            lx[r] = ly[r] = lz[r] = lp[r] = (T)0;
+            bx[r] = by[r] = bz[r] = bp[r] = 0.0;
+        }
+        const T eps2 = (T)w.eps2;
+
+        for (int64_t jt = w.j0; jt < w.j1; jt += TPB) {
+            const int64_t j = jt + tid;
+            V v;
+            if (j < w.j1) {
+                v.x = (T)(X[j] - cx);
+                v.y = (T)(Y[j] - cy);
+                v.z = (T)(Z[j] - cz);
+                v.w = (T)m[j];
+            } else {
+                v.x = v.y = v.z = v.w = (T)0;  // zero mass: contributes exactly 0
+            }
+            __syncthreads();
+            tile[tid] = v;
+            __syncthreads();
+            const int nt = (int)((w.j1 - jt) < TPB ? (w.j1 - jt) : TPB);
+            const int nt4 = (nt + 3) & ~3;
+            for (int jj = 0; jj < nt4; jj += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const V pj = tile[jj + u];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T dx = pj.x - xi[r];
+                        const T dy = pj.y - yi[r];
+                        const T dz = pj.z - zi[r];
+                        T s = fma_t(dx, dx, eps2);
+                        s = fma_t(dy, dy, s);
+                        s = fma_t(dz, dz, s);
+                        T rinv = rsqrt_t(s);
+                        if constexpr (MASK)
+                            rinv = s > (T)0 ? rinv : (T)0;
+                        const T mr = pj.w * rinv;
+                        const T w3 = mr * (rinv * rinv);
+                        ax[r] = fma_t(w3, dx, ax[r]);
+                        ay[r] = fma_t(w3, dy, ay[r]);
+                        az[r] = fma_t(w3, dz, az[r]);
+                        if constexpr (PHI)
+                            ph[r] += mr;
+                    }
+                }
+            }
+            if constexpr (ACC == kTwoSum) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    two_sum_add(hx[r], lx[r], (float)ax[r]);
+                    two_sum_add(hy[r], ly[r], (float)ay[r]);
+                    two_sum_add(hz[r], lz[r], (float)az[r]);
+                    if constexpr (PHI)
+                        two_sum_add(hp[r], lp[r], (float)ph[r]);
+                    ax[r] = ay[r] = az[r] = ph[r] = (T)0;
+                }
+            } else if constexpr (ACC == kFold64) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    bx[r] += (double)ax[r];
+                    by[r] += (double)ay[r];
+                    bz[r] += (double)az[r];
+                    if constexpr (PHI)
+                        bp[r] += (double)ph[r];
+                    ax[r] = ay[r] = az[r] = ph[r] = (T)0;
+                }
+            }
+        }
+
+        const int64_t slot = (int64_t)w.slice;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!valid[r])
+                continue;
+            const int64_t i = w.i0 + tid + (int64_t)r * TPB;
+            double ox, oy, oz, op;
+            if constexpr (ACC == kTwoSum) {
+                ox = (double)hx[r] + (double)lx[r];
+                oy = (double)hy[r] + (double)ly[r];
+                oz = (double)hz[r] + (double)lz[r];
+                op = (double)hp[r] + (double)lp[r];
+            } else if constexpr (ACC == kFold64) {
+                ox = bx[r];
+                oy = by[r];
+                oz = bz[r];
+                op = bp[r];
+            } else {
+                ox = (double)ax[r];
+                oy = (double)ay[r];
+                oz = (double)az[r];
+                op = (double)ph[r];
+            }
+            part[(slot * 3 + 0) * N + i] = ox;
+            part[(slot * 3 + 1) * N + i] = oy;
+            part[(slot * 3 + 2) * N + i] = oz;
+            if constexpr (PHI)
+                part_phi[slot * N + i] = op;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep: sum_j M(d)(m_k lam_j - m_j lam_k), M(d) = r^-3 I - 3 r^-5 d d^T,
+// for C cotangents sharing the geometry.  lam is [n_cot][3][N]; this launch
+// handles cotangents [c0, c0 + C).  part is [slices][n_cot][3][N].
+// ---------------------------------------------------------------------------
+template <typename T, int ACC, int R, int TPB, int C, bool MASK>
+__global__ __launch_bounds__(TPB) void adjoint_sweep_kernel(
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
+    const double *__restrict__ lam, int n_cot, int c0,
+    const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
+    int persistent, double *__restrict__ part)
+{
+    using V = typename V4<T>::type;
+    constexpr int LW = 3 * C;
+    __shared__ V tile[TPB];
+    __shared__ T ltile[TPB * LW];
+    __shared__ double red[TPB / 64][6];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const double *X = x, *Y = x + N, *Z = x + 2 * N;
+
+    for (int iter = 0;; ++iter) {
+        const int it = next_item(persistent, counter, &s_item, iter);
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+
+        double tx[R], ty[R], tz[R];
+        bool valid[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = w.i0 + tid + (int64_t)r * TPB;
+            valid[r] = i < w.i1;
+            const int64_t ii = valid[r] ? i : w.i0;
+            tx[r] = X[ii];
+            ty[r] = Y[ii];
+            tz[r] = Z[ii];
+        }
+        double cx, cy, cz;
+        block_centre<TPB, R>(tx, ty, tz, valid, red, cx, cy, cz);
+
+        T xi[R], yi[R], zi[R], mk[R];
+        T lk[R][LW];    // lam_k
+        T acc[R][LW];   // tile partial / direct sum
+        double fold[R][LW];
+        T hi[R][LW], lo[R][LW];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = w.i0 + tid + (int64_t)r * TPB;
+            const int64_t ii = valid[r] ? i : w.i0;
+            xi[r] = (T)(tx[r] - cx);
+            yi[r] = (T)(ty[r] - cy);
+            zi[r] = (T)(tz[r] - cz);
+            mk[r] = (T)m[ii];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    lk[r][3 * c + q] = (T)lam[((int64_t)(c0 + c) * 3 + q) * N + ii];
+                    acc[r][3 * c + q] = (T)0;
+                    fold[r][3 * c + q] = 0.0;
+                    hi[r][3 * c + q] = (T)0;
+                    lo[r][3 * c + q] = (T)0;
+                }
+        }
+        const T eps2 = (T)w.eps2;
+
+        for (int64_t jt = w.j0; jt < w.j1; jt += TPB) {
+            const int64_t j = jt + tid;
+            V v;
+            T lj[LW];
+            if (j < w.j1) {
+                v.x = (T)(X[j] - cx);
+                v.y = (T)(Y[j] - cy);
+                v.z = (T)(Z[j] - cz);
+                v.w = (T)m[j];
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        lj[3 * c + q] = (T)lam[((int64_t)(c0 + c) * 3 + q) * N + j];
+            } else {
+                v.x = v.y = v.z = v.w = (T)0;
+#pragma unroll
+                for (int q = 0; q < LW; ++q)
+                    lj[q] = (T)0;
+            }
+            __syncthreads();
+            tile[tid] = v;
+#pragma unroll
+            for (int q = 0; q < LW; ++q)
+                ltile[tid * LW + q] = lj[q];
+            __syncthreads();
+            const int nt = (int)((w.j1 - jt) < TPB ? (w.j1 - jt) : TPB);
+            for (int jj = 0; jj < nt; ++jj) {
+                const V pj = tile[jj];
+                T lt[LW];
+#pragma unroll
+                for (int q = 0; q < LW; ++q)
+                    lt[q] = ltile[jj * LW + q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T dx = pj.x - xi[r];
+                    const T dy = pj.y - yi[r];
+                    const T dz = pj.z - zi[r];
+                    T s = fma_t(dx, dx, eps2);
+                    s = fma_t(dy, dy, s);
+                    s = fma_t(dz, dz, s);
+                    T rinv = rsqrt_t(s);
+                    if constexpr (MASK)
+                        rinv = s > (T)0 ? rinv : (T)0;
+                    const T r2 = rinv * rinv;
+                    const T r3 = r2 * rinv;
+                    const T m3r5 = (T)(-3) * (r3 * r2);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const T ux = fma_t(mk[r], lt[3 * c + 0], -(pj.w * lk[r][3 * c + 0]));
+                        const T uy = fma_t(mk[r], lt[3 * c + 1], -(pj.w * lk[r][3 * c + 1]));
+                        const T uz = fma_t(mk[r], lt[3 * c + 2], -(pj.w * lk[r][3 * c + 2]));
+                        const T du = fma_t(dx, ux, fma_t(dy, uy, dz * uz));
+                        const T t = m3r5 * du;
+                        acc[r][3 * c + 0] = fma_t(t, dx, fma_t(r3, ux, acc[r][3 * c + 0]));
+                        acc[r][3 * c + 1] = fma_t(t, dy, fma_t(r3, uy, acc[r][3 * c + 1]));
+                        acc[r][3 * c + 2] = fma_t(t, dz, fma_t(r3, uz, acc[r][3 * c + 2]));
+                    }
+                }
+            }
+            if constexpr (ACC != kDirect) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int q = 0; q < LW; ++q) {
+                        if constexpr (ACC == kTwoSum)
+                            two_sum_add(hi[r][q], lo[r][q], (float)acc[r][q]);
+                        else
+                            fold[r][q] += (double)acc[r][q];
+                        acc[r][q] = (T)0;
+                    }
+            }
+        }
+
+        const int64_t slot = (int64_t)w.slice;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!valid[r])
+                continue;
+            const int64_t i = w.i0 + tid + (int64_t)r * TPB;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    double o;
+                    if constexpr (ACC == kTwoSum)
+                        o = (double)hi[r][3 * c + q] + (double)lo[r][3 * c + q];
+                    else if constexpr (ACC == kFold64)
+                        o = fold[r][3 * c + q];
+                    else
+                        o = (double)acc[r][3 * c + q];
+                    part[((slot * n_cot + (c0 + c)) * 3 + q) * N + i] = o;
+                }
+        }
+    }
+}
+
+__global__ void zero_counter_kernel(int *counter) { *counter = 0; }
+
+// ---------------------------------------------------------------------------
+// Host-side dispatch over the template instantiations.
+// ---------------------------------------------------------------------------
+struct LaunchShape {
+    int grid;
+};
+
+int device_cu_count()
+{
+    static int cached = -1;
+    if (cached > 0)
+        return cached;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        n = 256;
+    cached = n;
+    return n;
+}
+
+template <typename K>
+int persistent_grid(K kernel, int tpb, size_t dyn_lds, int n_items)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, tpb, dyn_lds) !=
+            hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    long g = (long)per_cu * device_cu_count();
+    return (int)(g < n_items ? g : n_items);
+}
+
+template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK>
+hipError_t launch_fwd(const double *x, const double *m, int64_t N, const WorkItem *items,
+                      int n_items, int *counter, bool persistent, double *part,
+                      double *part_phi, hipStream_t stream)
+{
+    auto k = pair_sweep_kernel<T, ACC, R, TPB, PHI, MASK>;
+    int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
+    if (grid <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, items, n_items, counter,
+                       persistent ? 1 : 0, part, part_phi);
+    return hipGetLastError();
+}
+
+template <typename T, int ACC, int R, int TPB>
+hipError_t dispatch_fwd_flags(bool phi, bool mask, const double *x, const double *m,
+                              int64_t N, const WorkItem *items, int n_items, int *counter,
+                              bool persistent, double *part, double *part_phi,
+                              hipStream_t s)
+{
+    if (phi) {
+        if (mask)
+            return launch_fwd<T, ACC, R, TPB, true, true>(x, m, N, items, n_items, counter,
+                                                          persistent, part, part_phi, s);
+        return launch_fwd<T, ACC, R, TPB, true, false>(x, m, N, items, n_items, counter,
+                                                       persistent, part, part_phi, s);
+    }
+    if (mask)
+        return launch_fwd<T, ACC, R, TPB, false, true>(x, m, N, items, n_items, counter,
+                                                       persistent, part, part_phi, s);
+    return launch_fwd<T, ACC, R, TPB, false, false>(x, m, N, items, n_items, counter,
+                                                    persistent, part, part_phi, s);
+}
+
+template <typename T, int ACC>
+hipError_t dispatch_fwd_shape(const TileCfg &cfg, bool phi, bool mask, const double *x,
+                              const double *m, int64_t N, const WorkItem *items, int n_items,
+                              int *counter, bool persistent, double *part, double *part_phi,
+                              hipStream_t s)
+{
+#define COLATUS_FWD(RR, TT)                                                                  \
+    if (cfg.R == RR && cfg.tpb == TT)                                                        \
+        return dispatch_fwd_flags<T, ACC, RR, TT>(phi, mask, x, m, N, items, n_items, counter, \
+                                                  persistent, part, part_phi, s);
+    COLATUS_FWD(1, 256)
+    COLATUS_FWD(2, 256)
+    COLATUS_FWD(4, 256)
+    COLATUS_FWD(1, 128)
+    COLATUS_FWD(2, 128)
+    COLATUS_FWD(4, 128)
+#undef COLATUS_FWD
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int ACC, int R, int TPB, int C>
+hipError_t launch_adj(bool mask, const double *x, const double *m, int64_t N, const double *lam,
+                      int n_cot, int c0, const WorkItem *items, int n_items, int *counter,
+                      bool persistent, double *part, hipStream_t stream)
+{
+    if (mask) {
+        auto k = adjoint_sweep_kernel<T, ACC, R, TPB, C, true>;
+        int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, lam, n_cot, c0, items,
+                           n_items, counter, persistent ? 1 : 0, part);
+    } else {
+        auto k = adjoint_sweep_kernel<T, ACC, R, TPB, C, false>;
+        int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, lam, n_cot, c0, items,
+                           n_items, counter, persistent ? 1 : 0, part);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int ACC>
+hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const double *m,
+                        int64_t N, int n_cot, const double *lam, const WorkItem *items,
+                        int n_items, int *counter, bool persistent, double *part,
+                        hipStream_t s)
+{
+    // Cotangents in chunks of 8, then 4, then 1; the work counter is re-armed
+    // before every chunk after the first.
+    int c0 = 0;
+    bool first = true;
+    while (c0 < n_cot) {
+        const int left = n_cot - c0;
+        if (!first && persistent) {
+            hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+        }
+        first = false;
+        hipError_t e;
+        const bool r2 = cfg.R >= 2;
+        if (left >= 8) {
+            // eight cotangents keep 24 accumulators per target: one target per lane
+            e = launch_adj<T, ACC, 1, 256, 8>(mask, x, m, N, lam, n_cot, c0, items, n_items,
+                                              counter, persistent, part, s);
+            c0 += 8;
+        } else if (left >= 4) {
+            e = r2 ? launch_adj<T, ACC, 2, 256, 4>(mask, x, m, N, lam, n_cot, c0, items, n_items,
+                                                    counter, persistent, part, s)
+                   : launch_adj<T, ACC, 1, 256, 4>(mask, x, m, N, lam, n_cot, c0, items, n_items,
+                                                    counter, persistent, part, s);
+            c0 += 4;
+        } else {
+            e = r2 ? launch_adj<T, ACC, 2, 256, 1>(mask, x, m, N, lam, n_cot, c0, items, n_items,
+                                                    counter, persistent, part, s)
+                   : launch_adj<T, ACC, 1, 256, 1>(mask, x, m, N, lam, n_cot, c0, items, n_items,
+                                                    counter, persistent, part, s);
+            c0 += 1;
+        }
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_zero_counter(int *counter, hipStream_t stream)
+{
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_sweep(int precision, const TileCfg &cfg, bool with_phi, bool mask_self,
+                             const double *x, const double *m, int64_t N,
+                             const WorkItem *items, int n_items, int *counter, bool persistent,
+                             double *part, double *part_phi, hipStream_t stream)
+{
+    if (n_items <= 0)
+        return hipSuccess;
+    switch (precision) {
+    case kFP64:
+        return dispatch_fwd_shape<double, kDirect>(cfg, with_phi, mask_self, x, m, N, items,
+                                                   n_items, counter, persistent, part,
+                                                   part_phi, stream);
+    case kMixedTwoSum:
+        return dispatch_fwd_shape<float, kTwoSum>(cfg, with_phi, mask_self, x, m, N, items,
+                                                  n_items, counter, persistent, part,
+                                                  part_phi, stream);
+    case kMixedF64Acc:
+        return dispatch_fwd_shape<float, kFold64>(cfg, with_phi, mask_self, x, m, N, items,
+                                                  n_items, counter, persistent, part,
+                                                  part_phi, stream);
+    case kFP32:
+        return dispatch_fwd_shape<float, kDirect>(cfg, with_phi, mask_self, x, m, N, items,
+                                                  n_items, counter, persistent, part,
+                                                  part_phi, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_self,
+                                const double *x, const double *m, int64_t N, int n_cot,
+                                const double *lam, const WorkItem *items, int n_items,
+                                int *counter, bool persistent, double *part,
+                                hipStream_t stream)
+{
+    if (n_items <= 0)
+        return hipSuccess;
+    switch (precision) {
+    case kFP64:
+        return dispatch_adj<double, kDirect>(cfg, mask_self, x, m, N, n_cot, lam, items,
+                                             n_items, counter, persistent, part, stream);
+    case kMixedTwoSum:
+        return dispatch_adj<float, kTwoSum>(cfg, mask_self, x, m, N, n_cot, lam, items,
+                                            n_items, counter, persistent, part, stream);
+    case kMixedF64Acc:
+        return dispatch_adj<float, kFold64>(cfg, mask_self, x, m, N, n_cot, lam, items,
+                                            n_items, counter, persistent, part, stream);
+    case kFP32:
+        return dispatch_adj<float, kDirect>(cfg, mask_self, x, m, N, n_cot, lam, items,
+                                            n_items, counter, persistent, part, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace colatus

@@ -1,0 +1,169 @@
+"""The C ABI on the host: every declared symbol is exported, and argument
+checks reject bad input before any HIP call (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_1208_3444_amd import colatus
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "colatus.h")
+
+EINVAL, EFRIEDMANN, ENODEV = -1, -2, -3
+FAKE = ctypes.c_void_p(4096)  # never dereferenced: checks fail first
+
+LCDM = (math.sqrt(8 * math.pi / 0.9), 0.0, 0.3, 0.0, 0.7)
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(colatus_[a-z0-9_]+)\s*\(", text)))
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+def test_every_declared_symbol_is_exported():
+    L = colatus.lib()
+    names = _declared()
+    assert "colatus_forces" in names and "colatus_adjoint" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(colatus.SIGNATURES), "binding signatures out of sync with header"
+
+
+def test_strerror_and_version():
+    L = colatus.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.colatus_strerror(code)
+    assert L.colatus_strerror(-99) == b"unknown error code"
+    assert L.colatus_version() == 10000
+
+
+def test_forces_rejects_bad_arguments():
+    L = colatus.lib()
+    f = L.colatus_forces
+    ok = dict(x=FAKE, m=FAKE, N=16, eps=0.01, G=1.0, a=1.0, prec=0, acc=FAKE, phi=None)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["x"], a["m"], a["N"], a["eps"], a["G"], a["a"], a["prec"], a["acc"],
+                 a["phi"], None, None)
+
+    assert call(N=0) == EINVAL
+    assert call(N=(1 << 28) + 1) == EINVAL
+    assert call(eps=-1e-3) == EINVAL
+    assert call(eps=float("nan")) == EINVAL
+    assert call(G=float("inf")) == EINVAL
+    assert call(a=0.0) == EINVAL
+    assert call(a=-1.0) == EINVAL
+    assert call(prec=4) == EINVAL
+    assert call(x=None) == EINVAL
+    assert call(acc=None) == EINVAL
+
+
+def test_batch_descriptor_checks():
+    L = colatus.lib()
+    import numpy as np
+    off = np.array([0, 10, 10, 30], dtype=np.int64)  # empty box
+    eps = np.array([0.1, 0.1, 0.1])
+    b = colatus._Batch(3, off.ctypes.data, eps.ctypes.data)
+    rc = L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b), None)
+    assert rc == EINVAL
+    off2 = np.array([0, 10, 25], dtype=np.int64)  # does not end at N
+    b2 = colatus._Batch(2, off2.ctypes.data, eps.ctypes.data)
+    assert L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b2),
+                            None) == EINVAL
+    eps3 = np.array([0.1, -0.1])
+    off3 = np.array([0, 10, 30], dtype=np.int64)
+    b3 = colatus._Batch(2, off3.ctypes.data, eps3.ctypes.data)
+    assert L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b3),
+                            None) == EINVAL
+
+
+def _run(**kw):
+    L = colatus.lib()
+    a = dict(x=FAKE, v=FAKE, m=FAKE, N=8, eps=0.01, G=1.0, cos=LCDM, a0=0.1, a1=1.0,
+             n=10, first=0, last=10, prec=1)
+    a.update(kw)
+    return L.colatus_run(a["x"], a["v"], a["m"], a["N"], a["eps"], a["G"], *a["cos"],
+                         a["a0"], a["a1"], a["n"], a["first"], a["last"], a["prec"], None, None,
+                         None)
+
+
+def test_run_rejects_bad_arguments():
+    assert _run(n=0, last=0) == EINVAL
+    assert _run(first=-1) == EINVAL
+    assert _run(first=5, last=5) == EINVAL
+    assert _run(last=11) == EINVAL
+    assert _run(a0=0.0) == EINVAL
+    assert _run(a1=-1.0) == EINVAL
+    assert _run(a1=0.1) == EINVAL  # zero span with H0 > 0
+    assert _run(cos=(-1.0, 0, 1, 0, 0)) == EINVAL
+    assert _run(cos=(1.0, 0, float("nan"), 0, 0)) == EINVAL
+    assert _run(v=None) == EINVAL
+    assert _run(prec=7) == EINVAL
+
+
+def test_run_rejects_unphysical_friedmann_range():
+    # closed matter universe: H^2 ~ a^-3 (1 - 2a) turns negative past a = 0.5
+    assert _run(cos=(1.0, 0.0, 1.0, -2.0, 0.0), a0=0.3, a1=0.9) == EFRIEDMANN
+    # a dip below zero strictly inside the range, positive at both ends:
+    # f(a) = 1 - 3a + 2.5 a^2 ... via Om_R + Om_M a + Om_K a^2 with a minimum < 0
+    assert _run(cos=(1.0, 1.0, -3.0, 2.2, 0.0), a0=0.2, a1=1.2) == EFRIEDMANN
+
+
+def test_adjoint_rejects_bad_arguments():
+    L = colatus.lib()
+
+    def call(**kw):
+        a = dict(N=8, K=5, C=1, batch=None, prec=1)
+        a.update(kw)
+        return L.colatus_adjoint(FAKE, FAKE, FAKE, a["N"], 0.01, 1.0, *LCDM, 0.2, 1.0, 10,
+                                 a["K"], a["C"], FAKE, FAKE, FAKE, FAKE, None, None, a["prec"],
+                                 a["batch"], None)
+
+    assert call(K=0) == EINVAL
+    assert call(C=0) == EINVAL
+    assert call(C=5000) == EINVAL
+    assert call(batch=FAKE) == EINVAL
+
+
+def test_hubble_host():
+    L = colatus.lib()
+    out = ctypes.c_double()
+    assert L.colatus_hubble(0.5, 2.0, 0.0, 1.0, 0.0, 0.0, ctypes.byref(out)) == 0
+    assert abs(out.value - 2.0 * 0.5 ** -1.5) < 1e-15 * out.value
+    assert L.colatus_hubble(0.9, 1.0, 0.0, 1.0, -2.0, 0.0, ctypes.byref(out)) == EFRIEDMANN
+    assert L.colatus_hubble(0.0, 1.0, 0.0, 1.0, 0.0, 0.0, ctypes.byref(out)) == EINVAL
+
+
+def test_options_and_tile_config():
+    L = colatus.lib()
+    v = ctypes.c_int64()
+    assert L.colatus_get_option(1, ctypes.byref(v)) == 0 and v.value == 1
+    assert L.colatus_set_option(4, 3) == EINVAL
+    assert L.colatus_set_option(99, 0) == EINVAL
+    assert colatus.tile_config(32768, "mixed") == (4, 256, 32)
+    assert colatus.tile_config(32768, "fp64")[0:2] == (2, 256)
+    colatus.set_option(colatus.OPT_TILE_SLICES, 3)
+    try:
+        assert colatus.tile_config(32768, "mixed")[2] == 3
+    finally:
+        colatus.set_option(colatus.OPT_TILE_SLICES, 0)
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_valid_call_without_device_is_enodev():
+    assert _run() == ENODEV
+    L = colatus.lib()
+    assert L.colatus_forces(FAKE, FAKE, 16, 0.01, 1.0, 1.0, 0, FAKE, None, None, None) == ENODEV

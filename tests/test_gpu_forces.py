@@ -1,0 +1,168 @@
+"""GPU parity of the pair sweep (Eq. (1)) against the FP64 oracle, through the C ABI.
+
+Tolerances (per-particle relative error e_k = |a_k - a_k^ref| / |a_k^ref|):
+  FP64 path           median and max <= 1e-12
+  MIXED_TWOSUM/F64ACC median <= 1e-6, max <= 1e-4
+  FP32 (no compensation, reported in the precision sweep) max <= 1e-3
+Random clouds with near-cancelling forces use the conditioned metric
+|a_k - a_k^ref| / sum_j |term_kj| instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1208_3444_amd import colatus, inputs
+from conftest import rel_err_per_particle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _term_scale(x, m, eps, G=1.0):
+    """sum_j |G m_j (x_j - x_k) r^-3| per target (conditioning of the sum)."""
+    d = x[:, None, :] - x[:, :, None]
+    s = (d ** 2).sum(axis=0) + eps * eps
+    w = G * m[None, :] * s ** -1.5
+    np.fill_diagonal(w, 0.0)
+    return (w * np.sqrt((d ** 2).sum(axis=0))).sum(axis=1)
+
+
+def _gpu_forces(x, m, eps, dev, prec, a=1.0, G=1.0, with_phi=False, batch=None):
+    xt, mt = to_dev(x, dev), to_dev(m, dev)
+    out = colatus.forces(xt, mt, eps, G=G, a=a, precision=prec, with_phi=with_phi, batch=batch)
+    torch.cuda.synchronize()
+    if with_phi:
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+def test_fp64_lattice_4096(dev):
+    w = inputs.eds_lattice(16)
+    ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
+    got, phi = _gpu_forces(w.x, w.m, w.eps, dev, "fp64", a=0.1, with_phi=True)
+    e = rel_err_per_particle(got, ref)
+    assert np.median(e) <= 1e-12 and e.max() <= 1e-12, (np.median(e), e.max())
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    phi_ref = oracle.potential(w.x, w.m, w.eps)
+    assert np.max(np.abs(phi - phi_ref) / np.abs(phi_ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 127, 255, 257, 1000, 1537])
+def test_fp64_ragged_sizes(dev, N):
+    x, m = inputs.random_cloud(N, 100 + N, scale=0.5)
+    eps = 0.01
+    got = _gpu_forces(x, m, eps, dev, "fp64", a=0.7, G=1.3)
+    ref = oracle.forces(x, m, eps, G=1.3, a=0.7)
+    if N == 1:
+        assert np.all(got == 0.0)
+        return
+    scale = _term_scale(x, m, eps, 1.3) / 0.7 ** 3
+    assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", ["mixed_twosum", "mixed_f64acc"])
+def test_mixed_lattice_4096(dev, prec):
+    w = inputs.eds_lattice(16)
+    ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
+    got = _gpu_forces(w.x, w.m, w.eps, dev, prec, a=0.1)
+    e = rel_err_per_particle(got, ref)
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4, (np.median(e), e.max())
+
+
+@pytest.mark.parametrize("prec,med,mx", [("fp64", 1e-12, 1e-12), ("mixed_twosum", 1e-6, 1e-4),
+                                         ("mixed_f64acc", 1e-6, 1e-4), ("fp32", 1e-5, 1e-3)])
+def test_paper_scale_32cubed_sampled(dev, prec, med, mx):
+    w = inputs.lcdm_grf(32)
+    targets = np.sort(np.random.Generator(np.random.PCG64(22)).choice(w.N, 1024, replace=False))
+    ref = oracle.forces_targets(w.x, w.m, targets, w.eps, a=w.a_begin)
+    got = _gpu_forces(w.x, w.m, w.eps, dev, prec, a=w.a_begin)[:, targets]
+    e = rel_err_per_particle(got, ref)
+    print(f"{prec}: median {np.median(e):.3e} max {e.max():.3e}")
+    assert np.median(e) <= med and e.max() <= mx
+
+
+def test_softening_zero_masks_self_pair(dev):
+    x, m = inputs.random_cloud(300, 7, scale=0.5)
+    ref = oracle.forces(x, m, 0.0)
+    scale = _term_scale(x, m, 0.0)
+    got = _gpu_forces(x, m, 0.0, dev, "fp64")
+    assert np.all(np.isfinite(got))
+    assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 1e-14
+    got32 = _gpu_forces(x, m, 0.0, dev, "mixed_twosum")
+    assert np.all(np.isfinite(got32))
+    assert np.max(np.linalg.norm(got32 - ref, axis=0) / scale) <= 1e-5
+
+
+def test_deterministic_and_translation_invariant(dev):
+    w = inputs.lcdm_grf(16, seed=9)
+    for prec in ("fp64", "mixed_twosum"):
+        a1 = _gpu_forces(w.x, w.m, w.eps, dev, prec)
+        a2 = _gpu_forces(w.x, w.m, w.eps, dev, prec)
+        assert np.array_equal(a1, a2), prec
+    shift = np.array([[0.37], [-0.21], [1.5]])
+    ref = oracle.forces(w.x, w.m, w.eps)
+    got = _gpu_forces(w.x + shift, w.m, w.eps, dev, "mixed_twosum")
+    e = rel_err_per_particle(got, ref)
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4
+
+
+@pytest.mark.parametrize("R,tpb,slices", [(1, 128, 1), (2, 256, 3), (4, 128, 7), (4, 256, 64)])
+def test_tile_shapes_agree(dev, R, tpb, slices):
+    x, m = inputs.random_cloud(2000, 3, scale=0.5)
+    eps = 0.02
+    ref = oracle.forces(x, m, eps)
+    scale = _term_scale(x, m, eps)
+    colatus.set_option(colatus.OPT_TILE_R, R)
+    colatus.set_option(colatus.OPT_TILE_TPB, tpb)
+    colatus.set_option(colatus.OPT_TILE_SLICES, slices)
+    try:
+        for persistent in (1, 0):
+            colatus.set_option(colatus.OPT_PERSISTENT, persistent)
+            got = _gpu_forces(x, m, eps, dev, "fp64")
+            assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 1e-14
+            got = _gpu_forces(x, m, eps, dev, "mixed_f64acc")
+            assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 1e-6
+    finally:
+        for k in (colatus.OPT_TILE_R, colatus.OPT_TILE_TPB, colatus.OPT_TILE_SLICES):
+            colatus.set_option(k, 0)
+        colatus.set_option(colatus.OPT_PERSISTENT, 1)
+
+
+def test_batch_boxes_do_not_interact(dev):
+    sizes = [1, 40, 513, 2, 1030]
+    xs, ms, epss = [], [], []
+    for i, n in enumerate(sizes):
+        x, m = inputs.random_cloud(n, 50 + i, scale=0.5)
+        xs.append(x + 0.1 * i)
+        ms.append(m)
+        epss.append(0.01 * (i + 1))
+    x = np.concatenate(xs, axis=1)
+    m = np.concatenate(ms)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for prec, tol in (("fp64", 1e-14), ("mixed_twosum", 1e-6)):
+        got, phi = _gpu_forces(x, m, 0.0, dev, prec, a=0.5, with_phi=True,
+                               batch=(off, np.array(epss)))
+        for b in range(len(sizes)):
+            sl = slice(off[b], off[b + 1])
+            ref = oracle.forces(xs[b], ms[b], epss[b], a=0.5)
+            if sizes[b] == 1:
+                assert np.all(got[:, sl] == 0.0)
+                continue
+            scale = _term_scale(xs[b], ms[b], epss[b]) / 0.5 ** 3
+            assert np.max(np.linalg.norm(got[:, sl] - ref, axis=0) / scale) <= tol
+            pref = oracle.potential(xs[b], ms[b], epss[b])
+            assert np.max(np.abs(phi[sl] - pref) / np.abs(pref)) <= (1e-13 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec,med,mx", [("fp64", 1e-12, 1e-12), ("mixed_twosum", 1e-6, 1e-4),
+                                         ("mixed_f64acc", 1e-6, 1e-4), ("fp32", 1e-5, 1e-3)])
+def test_precision_sweep_64cubed(dev, prec, med, mx):
+    """The single-evaluation precision sweep at N = 64^3, a = 0.5, on 512 of
+    the seeded targets (the full 4096 are timed by the benchmark script)."""
+    w = inputs.precision_sweep(64, n_targets=512)
+    t = w.extra["targets"]
+    ref = oracle.forces_targets(w.x, w.m, t, w.eps, a=0.5)
+    got = _gpu_forces(w.x, w.m, w.eps, dev, prec, a=0.5)[:, t]
+    e = rel_err_per_particle(got, ref)
+    print(f"{prec}: median {np.median(e):.3e} max {e.max():.3e}")
+    assert np.median(e) <= med and e.max() <= mx
