@@ -1,0 +1,252 @@
+"""Benchmark of the COLATUS hot path on one MI355X.
+
+One step = one kick-drift-kick step of the paper-scale LCDM run: N = 32^3
+particles, a from 1/51 to 1 in 1000 steps uniform in ln a, eps = 0.05 d,
+k^-2 displacement initial conditions (synthetic, seeded), FP32 pair
+arithmetic on tile-relative coordinates with TwoSum accumulation and FP64
+state.  Each step is one O(N^2) pair sweep plus the O(N) finalise/kick/drift
+kernel, replayed from a hipGraph.  ``value`` is pair interactions per second
+over the timed steps (N^2 per sweep; K steps run K + 1 sweeps).
+
+The same JSON line also carries, each measured in this process:
+  roofline      the pair sweep's FP32 VALU throughput (20 flops per pair)
+                against the MI355X FP32 vector peak, its average launch
+                duration timed with hipEvents on the launching stream
+  variants      the FP64 path, the run with per-step diagnostics (fused
+                potential, energies, Layzer-Irvine), forward + adjoint, the
+                ragged 256-box ensemble, and the O(N) integrator's bandwidth
+  cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G pair-interactions/s & % FP32 peak at N=32^3: mixed vs FP64, fwd vs fwd+adj"
+FLOPS_PER_PAIR = 20          # forward pair (rsqrt counted as 1)
+FLOPS_PER_PAIR_ADJ = 36      # adjoint pair per cotangent (equal-mass minimal count)
+PEAK_FP32 = 157.3e12         # MI355X FP32 vector peak (packed)
+PEAK_FP64 = 78.6e12          # MI355X FP64 vector peak
+PEAK_HBM = 8.0e12            # bytes/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=300)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--precision", default="mixed_twosum")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--cpu-sample-steps", type=int, default=2)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1208_3444_amd import colatus, inputs
+
+    dev = torch.device("cuda", 0)
+    w = inputs.lcdm_grf(32)
+    H_i = colatus.hubble(w.a_begin, w.cosmo)
+    v0 = w.velocities(H_i)
+    N = w.N
+    pairs = float(N) * N
+
+    def state():
+        return (torch.from_numpy(w.x.copy()).to(dev), torch.from_numpy(v0.copy()).to(dev),
+                torch.from_numpy(w.m.copy()).to(dev))
+
+    K, W = args.steps, args.warmup
+    if W + K > w.n_steps:
+        raise SystemExit(f"--warmup + --steps must be <= {w.n_steps}")
+
+    def timed_run(x, v, m, first, last, prec, diag=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
+                    first_step=first, last_step=last, precision=prec, diag=diag)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # ---- headline: mixed forward run steps -------------------------------
+    x, v, m = state()
+    timed_run(x, v, m, 0, W, args.precision)
+    print(f"[bench] warmup {W} steps done", file=sys.stderr, flush=True)
+    t = timed_run(x, v, m, W, W + K, args.precision)
+    value = (K + 1) * pairs / t / 1e9
+    ms_per_step = 1e3 * t / K
+    print(f"[bench] timed {K} steps: {ms_per_step:.3f} ms/step, {value:.1f} Gpairs/s",
+          file=sys.stderr, flush=True)
+
+    # ---- roofline: pair-sweep launches timed with hipEvents ---------------
+    colatus.set_option(colatus.OPT_TIMER, 1)
+    colatus.timer_read(0, reset=True)
+    timed_run(x, v, m, W + K, min(W + 2 * K, w.n_steps), args.precision)
+    ms_tot, launches = colatus.timer_read(0, reset=True)
+    colatus.set_option(colatus.OPT_TIMER, 0)
+    sweep_ms = ms_tot / launches
+    achieved = FLOPS_PER_PAIR * pairs / (sweep_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                "kernel": "pair_sweep_kernel<float,TwoSum>", "launch_ms": sweep_ms,
+                "launches": launches,
+                "flops_per_launch": FLOPS_PER_PAIR * pairs,
+                "note": "20 flops per ordered pair, N^2 pairs per launch; packed-FP32 "
+                        "instructions are disabled in this build, so the reachable VALU "
+                        "ceiling is half the listed peak"}
+    print(f"[bench] pair sweep {sweep_ms:.4f} ms/launch -> {achieved / 1e12:.2f} TFLOP/s",
+          file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "lcdm_grf_32^3", "N": N, "cosmology": "LCDM Om_M=0.3 Om_L=0.7",
+                   "a_begin": w.a_begin, "a_end": w.a_end, "n_steps_grid": w.n_steps,
+                   "eps": w.eps, "precision": args.precision,
+                   "pairs_per_step": pairs, "seed": w.seed},
+        "roofline": roofline,
+    }
+
+    if not args.no_variants:
+        line["variants"] = variants(w, v0, state, timed_run, args, colatus, inputs, np, torch,
+                                    dev)
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, v0, args)
+
+    print(json.dumps(line), flush=True)
+
+
+def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
+    out = {}
+    N = w.N
+    pairs = float(N) * N
+    # FP64 path, same workload
+    x, v, m = state()
+    Kd = 50
+    timed_run(x, v, m, 0, 5, "fp64")
+    t = timed_run(x, v, m, 5, 5 + Kd, "fp64")
+    colatus.set_option(colatus.OPT_TIMER, 1)
+    colatus.timer_read(0, reset=True)
+    timed_run(x, v, m, 5 + Kd, 5 + 2 * Kd, "fp64")
+    ms_tot, launches = colatus.timer_read(0, reset=True)
+    colatus.set_option(colatus.OPT_TIMER, 0)
+    fp64_rate = (Kd + 1) * pairs / t / 1e9
+    out["fp64_fwd"] = {"gpairs_s": fp64_rate, "ms_per_step": 1e3 * t / Kd,
+                       "sweep_ms": ms_tot / launches,
+                       "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms_tot / launches * 1e-3)
+                       / PEAK_FP64}
+    print(f"[bench] fp64: {fp64_rate:.1f} Gpairs/s", file=sys.stderr, flush=True)
+
+    # mixed with per-step diagnostics (fused potential + energies + LI)
+    x, v, m = state()
+    Kg = 100
+    timed_run(x, v, m, 0, 5, args.precision, diag=True)
+    t = timed_run(x, v, m, 5, 5 + Kg, args.precision, diag=True)
+    out["mixed_fwd_diag"] = {"gpairs_s": (Kg + 1) * pairs / t / 1e9,
+                             "ms_per_step": 1e3 * t / Kg}
+
+    # forward + adjoint (adjoint workload recipe, 200 steps from a = 0.2,
+    # checkpoints every 20), one cotangent: the tracers' |v|^2 loss
+    wa = inputs.adjoint_run(32)
+    va = wa.velocities(colatus.hubble(wa.a_begin, wa.cosmo))
+    xa, vat, ma = (torch.from_numpy(a.copy()).to(dev) for a in (wa.x, va, wa.m))
+    lx = torch.zeros_like(xa)
+    lv = torch.zeros_like(xa)
+    tr = torch.from_numpy(wa.extra["tracers"]).to(dev)
+    lv[:, tr] = 1.0
+    nA = 40
+    for prec in (args.precision, "fp64"):
+        colatus.adjoint(xa, vat, ma, wa.eps, wa.G, wa.cosmo, wa.a_begin, wa.a_end, 4, lx, lv,
+                        checkpoint_every=2, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        colatus.adjoint(xa, vat, ma, wa.eps, wa.G, wa.cosmo, wa.a_begin, wa.a_end, nA, lx, lv,
+                        checkpoint_every=wa.extra["checkpoint_every"], precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        fwd_sweeps = (nA + 1) + nA   # forward + recompute
+        adj_sweeps = nA + 1
+        flops = (FLOPS_PER_PAIR * fwd_sweeps + FLOPS_PER_PAIR_ADJ * adj_sweeps) * pairs
+        peak = PEAK_FP64 if prec == "fp64" else PEAK_FP32
+        key = "fp64_fwd_adj" if prec == "fp64" else "mixed_fwd_adj"
+        out[key] = {"gpairs_s": (fwd_sweeps + adj_sweeps) * pairs / t / 1e9,
+                    "ms_per_step": 1e3 * t / nA, "tflops": flops / t / 1e12,
+                    "frac_peak": flops / t / peak, "steps": nA,
+                    "flops_per_adjoint_pair": FLOPS_PER_PAIR_ADJ}
+        print(f"[bench] {key}: {out[key]['gpairs_s']:.1f} Gpairs/s", file=sys.stderr,
+              flush=True)
+
+    # ragged ensemble: 256 boxes, N log-uniform in [512, 8192], one launch per step
+    e = inputs.ragged_ensemble()
+    ve = e.velocities(colatus.hubble(e.a_begin, e.cosmo))
+    xe, vee, me = (torch.from_numpy(a.copy()).to(dev) for a in (e.x, ve, e.m))
+    sizes = np.diff(e.box_offsets)
+    pairs_e = float(np.sum(sizes.astype(np.float64) ** 2))
+    batch = (e.box_offsets, e.box_eps)
+
+    def erun(first, last):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        colatus.run(xe, vee, me, 0.0, e.G, e.cosmo, e.a_begin, e.a_end, e.n_steps,
+                    first_step=first, last_step=last, precision=args.precision, batch=batch)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    erun(0, 5)
+    Ke = 50
+    t = erun(5, 5 + Ke)
+    ens = {"boxes": int(len(sizes)), "particles": int(sizes.sum()),
+           "pairs_per_step": pairs_e, "gpairs_s": (Ke + 1) * pairs_e / t / 1e9,
+           "ms_per_step": 1e3 * t / Ke}
+    # the per-box loop: each box its own run call (the plain kernels, no batching)
+    xs = [(xe[:, o0:o1].contiguous(), vee[:, o0:o1].contiguous(), me[o0:o1].contiguous())
+          for o0, o1 in zip(e.box_offsets[:-1], e.box_offsets[1:])]
+    Kl = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, (xb, vb, mb) in enumerate(xs):
+        colatus.run(xb, vb, mb, float(e.box_eps[b]), e.G, e.cosmo, e.a_begin, e.a_end,
+                    e.n_steps, first_step=5 + Ke, last_step=5 + Ke + Kl,
+                    precision=args.precision)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ens["per_box_loop_gpairs_s"] = (Kl + 1) * pairs_e / t / 1e9
+    ens["speedup_vs_per_box_loop"] = ens["gpairs_s"] / ens["per_box_loop_gpairs_s"]
+    out["ensemble_256"] = ens
+    print(f"[bench] ensemble: {ens['gpairs_s']:.1f} Gpairs/s "
+          f"({ens['speedup_vs_per_box_loop']:.1f}x per-box loop)", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_baseline(w, v0, args):
+    import oracle
+    n = args.cpu_sample_steps
+    t0 = time.perf_counter()
+    oracle.run(w.x, v0, w.m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
+               first_step=0, last_step=n)
+    t = time.perf_counter() - t0
+    sweeps = n + 1
+    rate = sweeps * float(w.N) ** 2 / t / 1e9
+    print(f"[bench] cpu oracle: {rate:.3f} Gpairs/s in {t:.1f} s", file=sys.stderr, flush=True)
+    return {"value": rate, "unit": "Gpairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} kick-drift-kick steps ({sweeps} FP64 force sweeps) of the "
+                      f"same 32^3 LCDM run", "seconds": t}
+
+
+if __name__ == "__main__":
+    main()

@@ -724,6 +724,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.first = P.first;
     A.last = P.last;
     A.diag_part = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
+    A.precision = P.precision;
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
     CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
@@ -1042,6 +1043,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.first = 0;
     A.last = n_steps;
     A.diag_part = nullptr;
+    A.precision = precision;
 
     // ---- forward with checkpoints --------------------------------------
     CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1089,8 +1091,9 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
             CHECK_HIP(launch_integrate(B, s));
             CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
         }
-        // visit x_n for n = hi (only in the top segment) .. lo+1, and lo in segment 0
-        const int64_t top = (sg == n_seg - 1) ? hi : hi - 1;
+        // visit x_n for n = hi .. lo+1 (and lo itself in segment 0): every grid
+        // point is visited once, x_hi being the unvisited bottom of the segment above
+        const int64_t top = hi;
         const int64_t bottom = (sg == 0) ? lo : lo + 1;
         for (int64_t n = top; n >= bottom; --n) {
             const double *xs = seg + (size_t)(n - lo) * n3;

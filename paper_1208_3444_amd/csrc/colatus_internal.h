@@ -106,6 +106,7 @@ struct IntegrateArgs {
     const int64_t *step;   // device step counter n (absolute)
     int64_t first, last;
     double *diag_part;     // [rows][n_blocks][kDiagW] or null
+    int precision;         // pair arithmetic of the sweep that wrote part_phi
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and

@@ -141,6 +141,20 @@ __device__ __forceinline__ bool finite3(double a, double b, double c)
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// The potential sweep includes the self pair j == k, whose term is exactly
+// m_k * rsqrt(eps^2) as the sweep computed it (zero separation); subtract
+// that same value, rounded the same way, so no FP32-vs-FP64 residue of a
+// large self term is left in phi.  With eps == 0 the sweep masks it.
+__device__ __forceinline__ double self_potential(int precision, double m, double eps)
+{
+    if (!(eps > 0.0))
+        return 0.0;
+    const double eps2 = eps * eps;
+    if (precision == kFP64)
+        return m * rsqrt(eps2);
+    return (double)((float)m * __builtin_amdgcn_rsqf((float)eps2));
+}
+
 // Kick-drift-kick in canonical momentum p = a^2 v (Eq. (9) with the kick
 // factor int dt/a acting on g = G sum m_j (x_j - x_k) r^-3 and the drift
 // factor int dt/a^2 acting on p).  One launch per grid point n:
@@ -182,8 +196,7 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
             double phs = 0.0;
             for (int k = 0; k < S; ++k)
                 phs += A.part_phi[(int64_t)k * N + i];
-            if (blk.eps > 0.0)
-                phs -= mi / blk.eps;  // the self pair's m_i / eps
+            phs -= self_potential(A.precision, mi, blk.eps);
             const double phi = -A.G * phs;
             v[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
             v[1] = mi * phi;
@@ -286,7 +299,7 @@ __global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int row
 
 // acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - m / eps).
 __global__ __launch_bounds__(kIntBlock) void forces_finalize_kernel(
-    const IntBlock *__restrict__ blocks, const double *__restrict__ part,
+    int precision, const IntBlock *__restrict__ blocks, const double *__restrict__ part,
     const double *__restrict__ part_phi, const double *__restrict__ m, int64_t N, double G,
     double scale, double *__restrict__ acc, double *__restrict__ phi)
 {
@@ -304,8 +317,7 @@ __global__ __launch_bounds__(kIntBlock) void forces_finalize_kernel(
         double s = 0.0;
         for (int k = 0; k < blk.n_slices; ++k)
             s += part_phi[(int64_t)k * N + i];
-        if (blk.eps > 0.0)
-            s -= m[i] / blk.eps;
+        s -= self_potential(precision, m[i], blk.eps);
         phi[i] = -G * s;
     }
 }
@@ -409,9 +421,8 @@ hipError_t launch_forces_finalize(int precision, const IntBlock *blocks, int n_b
                                   int64_t N, double G, double scale, double *acc, double *phi,
                                   hipStream_t stream)
 {
-    (void)precision;
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream,
-                       blocks, part, part_phi, m, N, G, scale, acc, phi);
+                       precision, blocks, part, part_phi, m, N, G, scale, acc, phi);
     return hipGetLastError();
 }
 

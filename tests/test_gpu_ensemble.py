@@ -35,20 +35,43 @@ def test_ensemble_fp64_each_box_matches_oracle(dev):
 
 
 def test_ensemble_mixed_matches_single_box_runs(dev):
+    """With the same tile shape, each box of the batched launch is bitwise the
+    box run on its own: boxes share no arithmetic."""
     e, v0 = _ensemble(12, 512, 4096, 20)
+    colatus.set_option(colatus.OPT_TILE_R, 2)
+    colatus.set_option(colatus.OPT_TILE_TPB, 128)
+    colatus.set_option(colatus.OPT_TILE_SLICES, 3)
+    try:
+        xt, vt, mt = to_dev(e.x, dev), to_dev(v0, dev), to_dev(e.m, dev)
+        rows = colatus.run(xt, vt, mt, 0.0, e.G, e.cosmo, e.a_begin, e.a_end, e.n_steps,
+                           precision="mixed_twosum", diag=True,
+                           batch=(e.box_offsets, e.box_eps))
+        x, v = xt.cpu().numpy(), vt.cpu().numpy()
+        for b in (0, 5, 11):
+            sl = slice(e.box_offsets[b], e.box_offsets[b + 1])
+            xb, vb, mb = to_dev(e.x[:, sl], dev), to_dev(v0[:, sl], dev), to_dev(e.m[sl], dev)
+            d = colatus.run(xb, vb, mb, e.box_eps[b], e.G, e.cosmo, e.a_begin, e.a_end,
+                            e.n_steps, precision="mixed_twosum", diag=True)
+            assert np.array_equal(x[:, sl], xb.cpu().numpy())
+            assert np.array_equal(v[:, sl], vb.cpu().numpy())
+            for f in ("K", "U", "LI", "Px", "Lz"):
+                assert np.array_equal(rows[b][f], d[f]), f
+    finally:
+        for k in (colatus.OPT_TILE_R, colatus.OPT_TILE_TPB, colatus.OPT_TILE_SLICES):
+            colatus.set_option(k, 0)
+
+
+def test_ensemble_mixed_short_run_matches_oracle(dev):
+    e, v0 = _ensemble(8, 512, 2048, 100)
     xt, vt, mt = to_dev(e.x, dev), to_dev(v0, dev), to_dev(e.m, dev)
-    colatus.run(xt, vt, mt, 0.0, e.G, e.cosmo, e.a_begin, e.a_end, e.n_steps,
+    colatus.run(xt, vt, mt, 0.0, e.G, e.cosmo, e.a_begin, e.a_end, e.n_steps, last_step=3,
                 precision="mixed_twosum", batch=(e.box_offsets, e.box_eps))
     x = xt.cpu().numpy()
-    for b in (0, 5, 11):
+    for b in (0, 3, 7):
         sl = slice(e.box_offsets[b], e.box_offsets[b + 1])
-        xb, vb, mb = to_dev(e.x[:, sl], dev), to_dev(v0[:, sl], dev), to_dev(e.m[sl], dev)
-        colatus.run(xb, vb, mb, e.box_eps[b], e.G, e.cosmo, e.a_begin, e.a_end, e.n_steps,
-                    precision="fp64")
-        ref = xb.cpu().numpy()
-        d = e.box_offsets[b + 1] - e.box_offsets[b]
-        # positions agree far below the interparticle spacing N^(-1/3)
-        assert np.max(np.abs(x[:, sl] - ref)) <= 1e-6 * d ** (-1 / 3)
+        xr, _ = oracle.run(e.x[:, sl], v0[:, sl], e.m[sl], e.box_eps[b], e.G, e.cosmo,
+                           e.a_begin, e.a_end, e.n_steps, last_step=3)
+        assert np.max(np.abs(x[:, sl] - xr)) <= 1e-9
 
 
 def test_ensemble_forces_sampled_boxes_match_oracle(dev):
