@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--precision", default="mixed_twosum")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
-    p.add_argument("--cpu-sample-steps", type=int, default=2)
+    p.add_argument("--cpu-sample-steps", type=int, default=24)
     return p.parse_args()
 
 

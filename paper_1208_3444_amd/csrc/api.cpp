@@ -32,6 +32,7 @@ struct Options {
     int64_t tile_tpb = 0;
     int64_t tile_slices = 0;
     int64_t persistent = 1;
+    int64_t pair_form = 1;
 };
 Options g_opt;
 std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
@@ -145,14 +146,15 @@ struct WorkList {
     std::vector<IntBlock> blocks;
     std::vector<int32_t> box_first_block;
     int max_slices = 0;
-    Buffer d_items, d_blocks, d_box_first;
+    Buffer d_items, d_blocks, d_box_first, d_off;
 };
 
 struct Workspace {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
-    Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg;
+    Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
+        box_mass;
     WorkList fwd, adj;
 };
 
@@ -413,6 +415,7 @@ int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, cons
     CHECK_RC(ensure(wl.d_items, wl.items.size() * sizeof(WorkItem)));
     CHECK_RC(ensure(wl.d_blocks, wl.blocks.size() * sizeof(IntBlock)));
     CHECK_RC(ensure(wl.d_box_first, wl.box_first_block.size() * sizeof(int32_t)));
+    CHECK_RC(ensure(wl.d_off, wl.off.size() * sizeof(int64_t)));
     CHECK_HIP(hipMemcpyAsync(wl.d_items.ptr, wl.items.data(), wl.items.size() * sizeof(WorkItem),
                              hipMemcpyHostToDevice, s));
     CHECK_HIP(hipMemcpyAsync(wl.d_blocks.ptr, wl.blocks.data(),
@@ -420,6 +423,8 @@ int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, cons
     CHECK_HIP(hipMemcpyAsync(wl.d_box_first.ptr, wl.box_first_block.data(),
                              wl.box_first_block.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                              s));
+    CHECK_HIP(hipMemcpyAsync(wl.d_off.ptr, wl.off.data(), wl.off.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
     CHECK_HIP(hipStreamSynchronize(s));
     (void)ws;
     return COLATUS_OK;
@@ -461,9 +466,10 @@ int run_forward_sweep(Workspace *ws, const WorkList &wl, int precision, bool phi
         CHECK_HIP(launch_zero_counter(work_counter(ws), s));
     if (e0)
         CHECK_HIP(hipEventRecord(e0, s));
-    CHECK_HIP(launch_pair_sweep(precision, wl.cfg, phi, mask, x, m, N,
+    CHECK_HIP(launch_pair_sweep(precision, (int)g_opt.pair_form, wl.cfg, phi, mask, x, m, N,
                                 static_cast<const WorkItem *>(wl.d_items.ptr),
                                 (int)wl.items.size(), work_counter(ws), g_opt.persistent != 0,
+                                static_cast<const double *>(ws->box_mass.ptr),
                                 static_cast<double *>(ws->part.ptr),
                                 phi ? static_cast<double *>(ws->part_phi.ptr) : nullptr, s));
     if (e1) {
@@ -557,9 +563,9 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                     CHECK_HIP(hipEventRecord(e0, s));
                     if (kind == 0)
                         CHECK_HIP(launch_pair_sweep(
-                            precision, c, false, false, x, m, N,
+                            precision, (int)g_opt.pair_form, c, false, false, x, m, N,
                             static_cast<const WorkItem *>(tmp.d_items.ptr), (int)tmp.items.size(),
-                            work_counter(ws), g_opt.persistent != 0,
+                            work_counter(ws), g_opt.persistent != 0, nullptr,
                             static_cast<double *>(ws->part.ptr), nullptr, s));
                     else
                         CHECK_HIP(launch_adjoint_sweep(
@@ -574,7 +580,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                     if (rep > 0)
                         ms_total += ms;
                 }
-                for (Buffer *bb : {&tmp.d_items, &tmp.d_blocks, &tmp.d_box_first})
+                for (Buffer *bb : {&tmp.d_items, &tmp.d_blocks, &tmp.d_box_first, &tmp.d_off})
                     if (bb->ptr)
                         hipFree(bb->ptr);
                 if (ms_total < best) {
@@ -592,6 +598,18 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
         return COLATUS_EINVAL;
     WorkList &wl = kind == 0 ? ws->fwd : ws->adj;
     CHECK_RC(ensure_worklist(ws, wl, b, N, cfg, s));
+    return COLATUS_OK;
+}
+
+// Per-box common mass (NaN where the masses of a box differ), for the
+// equal-mass form of the pair loop.  Queued on the stream; the masses are
+// read as they are when this runs.
+int prepare_box_mass(Workspace *ws, const WorkList &wl, const double *m, hipStream_t s)
+{
+    const int n_boxes = (int)wl.off.size() - 1;
+    CHECK_RC(ensure(ws->box_mass, (size_t)n_boxes * sizeof(double)));
+    CHECK_HIP(launch_box_mass(m, static_cast<const int64_t *>(wl.d_off.ptr), n_boxes,
+                              static_cast<double *>(ws->box_mass.ptr), s));
     return COLATUS_OK;
 }
 
@@ -684,6 +702,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     hipStream_t s = P.stream;
     CHECK_RC(prepare_worklist(ws, 0, b, P.N, P.precision, P.x, P.m, 1, s));
     const WorkList &wl = ws->fwd;
+    CHECK_RC(prepare_box_mass(ws, wl, P.m, s));
     const int64_t nsteps = P.last - P.first;
     const int64_t rows = nsteps + 1;
     const int n_boxes = (int)b.eps.size();
@@ -725,6 +744,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.last = P.last;
     A.diag_part = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
     A.precision = P.precision;
+    A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
     CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
@@ -804,6 +824,11 @@ int colatus_set_option(int key, int64_t value)
         g_opt.tile_slices = value;
         return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: g_opt.persistent = value != 0; return COLATUS_OK;
+    case COLATUS_OPT_PAIR_FORM:
+        if (value != 0 && value != 1)
+            return COLATUS_EINVAL;
+        g_opt.pair_form = value;
+        return COLATUS_OK;
     }
     return COLATUS_EINVAL;
 }
@@ -821,6 +846,7 @@ int colatus_get_option(int key, int64_t *value)
     case COLATUS_OPT_TILE_TPB: *value = g_opt.tile_tpb; return COLATUS_OK;
     case COLATUS_OPT_TILE_SLICES: *value = g_opt.tile_slices; return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: *value = g_opt.persistent; return COLATUS_OK;
+    case COLATUS_OPT_PAIR_FORM: *value = g_opt.pair_form; return COLATUS_OK;
     }
     return COLATUS_EINVAL;
 }
@@ -885,7 +911,8 @@ int colatus_release(void)
         for (Buffer *bb : {&ws->part, &ws->part_phi, &ws->coef, &ws->p, &ws->diag_part,
                            &ws->diag_out, &ws->counters, &ws->lam_x, &ws->lam_p, &ws->ckpt,
                            &ws->seg, &ws->fwd.d_items, &ws->fwd.d_blocks, &ws->fwd.d_box_first,
-                           &ws->adj.d_items, &ws->adj.d_blocks, &ws->adj.d_box_first})
+                           &ws->adj.d_items, &ws->adj.d_blocks, &ws->adj.d_box_first,
+                           &ws->fwd.d_off, &ws->adj.d_off, &ws->box_mass})
             if (bb->ptr)
                 hipFree(bb->ptr);
         if (ws->cap_stream)
@@ -911,6 +938,7 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
     CHECK_RC(get_workspace(s, ws));
     CHECK_RC(prepare_worklist(ws, 0, b, N, precision, x, m, 1, s));
     const WorkList &wl = ws->fwd;
+    CHECK_RC(prepare_box_mass(ws, wl, m, s));
     CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * 3 * N * sizeof(double)));
     if (phi)
         CHECK_RC(ensure(ws->part_phi, (size_t)wl.max_slices * N * sizeof(double)));
@@ -918,7 +946,8 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
     for (double e : b.eps)
         mask = mask || e == 0.0;
     CHECK_RC(run_forward_sweep(ws, wl, precision, phi != nullptr, mask, x, m, N, s, true));
-    CHECK_HIP(launch_forces_finalize(precision, static_cast<const IntBlock *>(wl.d_blocks.ptr),
+    CHECK_HIP(launch_forces_finalize(precision, static_cast<const double *>(ws->box_mass.ptr),
+                                     static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                      (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                      phi ? static_cast<const double *>(ws->part_phi.ptr) : nullptr,
                                      m, N, G, G / (a * a * a), acc, phi, s));
@@ -998,6 +1027,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     CHECK_RC(prepare_worklist(ws, 1, b, N, precision, x0, m, n_cot, s));
     const WorkList &wf = ws->fwd;
     const WorkList &wa = ws->adj;
+    CHECK_RC(prepare_box_mass(ws, wf, m, s));
     const size_t n3 = 3 * (size_t)N;
     const int64_t K = checkpoint_every;
     const int64_t n_seg = (n_steps + K - 1) / K;
@@ -1044,6 +1074,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.last = n_steps;
     A.diag_part = nullptr;
     A.precision = precision;
+    A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
 
     // ---- forward with checkpoints --------------------------------------
     CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -54,11 +54,17 @@ constexpr int kDiagW = 10;
 
 // Forward pair sweep: part[s][3][N] = sum over the item's sources of
 // m_j (x_j - x_k) r^-3, and part_phi[s][N] = sum m_j / r when with_phi.
-hipError_t launch_pair_sweep(int precision, const TileCfg &cfg, bool with_phi,
+// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s) (FP32 only).
+// box_mass[b]: common mass of box b or NaN (see launch_box_mass), or null.
+hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool with_phi,
                              bool mask_self, const double *x, const double *m,
                              int64_t N, const WorkItem *items, int n_items,
-                             int *counter, bool persistent, double *part,
-                             double *part_phi, hipStream_t stream);
+                             int *counter, bool persistent, const double *box_mass,
+                             double *part, double *part_phi, hipStream_t stream);
+
+// box_mass[b] = m of box b if all its masses are equal and positive, else NaN.
+hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes,
+                           double *box_mass, hipStream_t stream);
 
 // Adjoint pair sweep for n_cot cotangents lam [n_cot][3][N]:
 // part[s][c][3][N] = sum over the item's sources of M(d)(m_k lam_j - m_j lam_k).
@@ -72,7 +78,8 @@ hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_sel
 hipError_t launch_zero_counter(int *counter, hipStream_t stream);
 
 // acc = scale * sum_s part[s], phi = -G (sum_s part_phi[s] - m/eps).
-hipError_t launch_forces_finalize(int precision, const IntBlock *blocks, int n_blocks,
+hipError_t launch_forces_finalize(int precision, const double *box_mass,
+                                  const IntBlock *blocks, int n_blocks,
                                   const double *part, const double *part_phi,
                                   const double *m, int64_t N, double G, double scale,
                                   double *acc, double *phi, hipStream_t stream);
@@ -107,6 +114,7 @@ struct IntegrateArgs {
     int64_t first, last;
     double *diag_part;     // [rows][n_blocks][kDiagW] or null
     int precision;         // pair arithmetic of the sweep that wrote part_phi
+    const double *box_mass;// per-box common mass or NaN (as given to the sweep)
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and

@@ -144,15 +144,26 @@ __device__ __forceinline__ bool finite3(double a, double b, double c)
 // The potential sweep includes the self pair j == k, whose term is exactly
 // m_k * rsqrt(eps^2) as the sweep computed it (zero separation); subtract
 // that same value, rounded the same way, so no FP32-vs-FP64 residue of a
-// large self term is left in phi.  With eps == 0 the sweep masks it.
-__device__ __forceinline__ double self_potential(int precision, double m, double eps)
+// large self term is left in phi.  Equal-mass boxes (mbox not NaN) were
+// summed without m and scaled by mbox in FP64.  With eps == 0 the sweep
+// masks the self pair.
+__device__ __forceinline__ double self_potential(int precision, double m, double eps,
+                                                 double mbox)
 {
     if (!(eps > 0.0))
         return 0.0;
     const double eps2 = eps * eps;
     if (precision == kFP64)
         return m * rsqrt(eps2);
-    return (double)((float)m * __builtin_amdgcn_rsqf((float)eps2));
+    const float r = __builtin_amdgcn_rsqf((float)eps2);
+    if (!isnan(mbox))
+        return mbox * (double)r;
+    return (double)((float)m * r);
+}
+
+__device__ __forceinline__ double box_mass_of(const double *box_mass, int box)
+{
+    return box_mass ? box_mass[box] : NAN;
 }
 
 // Kick-drift-kick in canonical momentum p = a^2 v (Eq. (9) with the kick
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
             double phs = 0.0;
             for (int k = 0; k < S; ++k)
                 phs += A.part_phi[(int64_t)k * N + i];
-            phs -= self_potential(A.precision, mi, blk.eps);
+            phs -= self_potential(A.precision, mi, blk.eps, box_mass_of(A.box_mass, blk.box));
             const double phi = -A.G * phs;
             v[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
             v[1] = mi * phi;
@@ -299,7 +310,8 @@ __global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int row
 
 // acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - m / eps).
 __global__ __launch_bounds__(kIntBlock) void forces_finalize_kernel(
-    int precision, const IntBlock *__restrict__ blocks, const double *__restrict__ part,
+    int precision, const double *__restrict__ box_mass, const IntBlock *__restrict__ blocks,
+    const double *__restrict__ part,
     const double *__restrict__ part_phi, const double *__restrict__ m, int64_t N, double G,
     double scale, double *__restrict__ acc, double *__restrict__ phi)
 {
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(kIntBlock) void forces_finalize_kernel(
         double s = 0.0;
         for (int k = 0; k < blk.n_slices; ++k)
             s += part_phi[(int64_t)k * N + i];
-        s -= self_potential(precision, m[i], blk.eps);
+        s -= self_potential(precision, m[i], blk.eps, box_mass_of(box_mass, blk.box));
         phi[i] = -G * s;
     }
 }
@@ -416,13 +428,13 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
     return hipGetLastError();
 }
 
-hipError_t launch_forces_finalize(int precision, const IntBlock *blocks, int n_blocks,
-                                  const double *part, const double *part_phi, const double *m,
-                                  int64_t N, double G, double scale, double *acc, double *phi,
-                                  hipStream_t stream)
+hipError_t launch_forces_finalize(int precision, const double *box_mass, const IntBlock *blocks,
+                                  int n_blocks, const double *part, const double *part_phi,
+                                  const double *m, int64_t N, double G, double scale,
+                                  double *acc, double *phi, hipStream_t stream)
 {
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream,
-                       precision, blocks, part, part_phi, m, N, G, scale, acc, phi);
+                       precision, box_mass, blocks, part, part_phi, m, N, G, scale, acc, phi);
     return hipGetLastError();
 }
 

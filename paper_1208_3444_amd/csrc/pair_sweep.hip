@@ -115,12 +115,66 @@ __device__ __forceinline__ int next_item(int persistent, int *counter, int *s_it
 
 // ---------------------------------------------------------------------------
 // Forward sweep: sum_j m_j (x_j - x_k) r^-3 (and sum_j m_j r^-1 with PHI).
+//
+// Per pair: 3 subtractions, 3 FMAs for s = |d|^2 + eps^2, one v_rsq, then
+// the weight w = m_j r^-3 and 3 FMAs into the accumulators.  The weight is
+// formed either as m r^-1 (r^-1 r^-1) (FORM 0) or as (m r^-1) rcp(s)
+// (FORM 1, one VALU multiply fewer, one more transcendental, which gfx950
+// issues beside the VALU stream).  When every mass of the box is equal
+// (EQM), m_j leaves the loop and multiplies the slice's partial sum once.
 // ---------------------------------------------------------------------------
-template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK>
+template <typename T> __device__ __forceinline__ T pad_coord();
+template <> __device__ __forceinline__ float pad_coord<float>() { return 1e30f; }
+template <> __device__ __forceinline__ double pad_coord<double>() { return 1e300; }
+
+template <typename T> __device__ __forceinline__ T rcp_t(T s);
+template <> __device__ __forceinline__ float rcp_t<float>(float s) { return __builtin_amdgcn_rcpf(s); }
+template <> __device__ __forceinline__ double rcp_t<double>(double s) { return 1.0 / s; }
+
+template <typename T, int R, bool PHI, bool MASK, bool EQM, int FORM, typename V>
+__device__ __forceinline__ void sweep_tile(const V *__restrict__ tile, int nt4, const T (&xi)[R],
+                                           const T (&yi)[R], const T (&zi)[R], T eps2,
+                                           T (&ax)[R], T (&ay)[R], T (&az)[R], T (&ph)[R])
+{
+    for (int jj = 0; jj < nt4; jj += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const V pj = tile[jj + u];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T dx = pj.x - xi[r];
+                const T dy = pj.y - yi[r];
+                const T dz = pj.z - zi[r];
+                T s = fma_t(dx, dx, eps2);
+                s = fma_t(dy, dy, s);
+                s = fma_t(dz, dz, s);
+                const T rinv = rsqrt_t(s);
+                T mr = EQM ? rinv : pj.w * rinv;
+                T w3;
+                if constexpr (FORM == 1)
+                    w3 = mr * rcp_t<T>(s);
+                else
+                    w3 = mr * (rinv * rinv);
+                if constexpr (MASK) {
+                    w3 = s > (T)0 ? w3 : (T)0;
+                    mr = s > (T)0 ? mr : (T)0;
+                }
+                ax[r] = fma_t(w3, dx, ax[r]);
+                ay[r] = fma_t(w3, dy, ay[r]);
+                az[r] = fma_t(w3, dz, az[r]);
+                if constexpr (PHI)
+                    ph[r] += mr;
+            }
+        }
+    }
+}
+
+template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK, int FORM>
 __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
     const double *__restrict__ x, const double *__restrict__ m, int64_t N,
     const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
-    int persistent, double *__restrict__ part, double *__restrict__ part_phi)
+    int persistent, const double *__restrict__ box_mass, double *__restrict__ part,
+    double *__restrict__ part_phi)
 {
     using V = typename V4<T>::type;
     __shared__ V tile[TPB];
@@ -134,6 +188,9 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
         if (it >= n_items)
             break;
         const WorkItem w = items[it];
+        // common mass of the box, or NaN when the masses differ
+        const double mbox = box_mass ? box_mass[w.box] : NAN;
+        const bool eqm = !isnan(mbox);
 
         double tx[R], ty[R], tz[R];
         bool valid[R];
@@ -175,38 +232,22 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
                 v.z = (T)(Z[j] - cz);
                 v.w = (T)m[j];
             } else {
-                v.x = v.y = v.z = v.w = (T)0;  // zero mass: contributes exactly 0
+                // padding: so far away that s overflows to +inf, r^-1 = 0 and
+                // the pair adds exactly 0 in every form (and zero mass)
+                v.x = v.y = v.z = pad_coord<T>();
+                v.w = (T)0;
             }
             __syncthreads();
             tile[tid] = v;
             __syncthreads();
             const int nt = (int)((w.j1 - jt) < TPB ? (w.j1 - jt) : TPB);
             const int nt4 = (nt + 3) & ~3;
-            for (int jj = 0; jj < nt4; jj += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const V pj = tile[jj + u];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const T dx = pj.x - xi[r];
-                        const T dy = pj.y - yi[r];
-                        const T dz = pj.z - zi[r];
-                        T s = fma_t(dx, dx, eps2);
-                        s = fma_t(dy, dy, s);
-                        s = fma_t(dz, dz, s);
-                        T rinv = rsqrt_t(s);
-                        if constexpr (MASK)
-                            rinv = s > (T)0 ? rinv : (T)0;
-                        const T mr = pj.w * rinv;
-                        const T w3 = mr * (rinv * rinv);
-                        ax[r] = fma_t(w3, dx, ax[r]);
-                        ay[r] = fma_t(w3, dy, ay[r]);
-                        az[r] = fma_t(w3, dz, az[r]);
-                        if constexpr (PHI)
-                            ph[r] += mr;
-                    }
-                }
-            }
+            if (eqm)
+                sweep_tile<T, R, PHI, MASK, true, FORM>(tile, nt4, xi, yi, zi, eps2, ax, ay, az,
+                                                        ph);
+            else
+                sweep_tile<T, R, PHI, MASK, false, FORM>(tile, nt4, xi, yi, zi, eps2, ax, ay, az,
+                                                         ph);
             if constexpr (ACC == kTwoSum) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -231,6 +272,7 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
         }
 
         const int64_t slot = (int64_t)w.slice;
+        const double scale = eqm ? mbox : 1.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!valid[r])
@@ -253,11 +295,11 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
                 oz = (double)az[r];
                 op = (double)ph[r];
             }
-            part[(slot * 3 + 0) * N + i] = ox;
-            part[(slot * 3 + 1) * N + i] = oy;
-            part[(slot * 3 + 2) * N + i] = oz;
+            part[(slot * 3 + 0) * N + i] = scale * ox;
+            part[(slot * 3 + 1) * N + i] = scale * oy;
+            part[(slot * 3 + 2) * N + i] = scale * oz;
             if constexpr (PHI)
-                part_phi[slot * N + i] = op;
+                part_phi[slot * N + i] = scale * op;
         }
     }
 }
@@ -461,50 +503,58 @@ int persistent_grid(K kernel, int tpb, size_t dyn_lds, int n_items)
     return (int)(g < n_items ? g : n_items);
 }
 
-template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK>
+template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK, int FORM>
 hipError_t launch_fwd(const double *x, const double *m, int64_t N, const WorkItem *items,
-                      int n_items, int *counter, bool persistent, double *part,
-                      double *part_phi, hipStream_t stream)
+                      int n_items, int *counter, bool persistent, const double *box_mass,
+                      double *part, double *part_phi, hipStream_t stream)
 {
-    auto k = pair_sweep_kernel<T, ACC, R, TPB, PHI, MASK>;
+    auto k = pair_sweep_kernel<T, ACC, R, TPB, PHI, MASK, FORM>;
     int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
     if (grid <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, items, n_items, counter,
-                       persistent ? 1 : 0, part, part_phi);
+                       persistent ? 1 : 0, box_mass, part, part_phi);
     return hipGetLastError();
 }
 
-template <typename T, int ACC, int R, int TPB>
-hipError_t dispatch_fwd_flags(bool phi, bool mask, const double *x, const double *m,
-                              int64_t N, const WorkItem *items, int n_items, int *counter,
-                              bool persistent, double *part, double *part_phi,
-                              hipStream_t s)
+struct FwdArgs {
+    const double *x, *m;
+    int64_t N;
+    const WorkItem *items;
+    int n_items;
+    int *counter;
+    bool persistent;
+    const double *box_mass;
+    double *part, *part_phi;
+    hipStream_t s;
+};
+
+template <typename T, int ACC, int R, int TPB, int FORM>
+hipError_t dispatch_fwd_flags(bool phi, bool mask, const FwdArgs &a)
 {
+#define COLATUS_FWD_F(P, M)                                                                   \
+    return launch_fwd<T, ACC, R, TPB, P, M, FORM>(a.x, a.m, a.N, a.items, a.n_items, a.counter, \
+                                                  a.persistent, a.box_mass, a.part, a.part_phi, \
+                                                  a.s);
     if (phi) {
-        if (mask)
-            return launch_fwd<T, ACC, R, TPB, true, true>(x, m, N, items, n_items, counter,
-                                                          persistent, part, part_phi, s);
-        return launch_fwd<T, ACC, R, TPB, true, false>(x, m, N, items, n_items, counter,
-                                                       persistent, part, part_phi, s);
+        if (mask) {
+            COLATUS_FWD_F(true, true)
+        }
+        COLATUS_FWD_F(true, false)
     }
-    if (mask)
-        return launch_fwd<T, ACC, R, TPB, false, true>(x, m, N, items, n_items, counter,
-                                                       persistent, part, part_phi, s);
-    return launch_fwd<T, ACC, R, TPB, false, false>(x, m, N, items, n_items, counter,
-                                                    persistent, part, part_phi, s);
+    if (mask) {
+        COLATUS_FWD_F(false, true)
+    }
+    COLATUS_FWD_F(false, false)
+#undef COLATUS_FWD_F
 }
 
-template <typename T, int ACC>
-hipError_t dispatch_fwd_shape(const TileCfg &cfg, bool phi, bool mask, const double *x,
-                              const double *m, int64_t N, const WorkItem *items, int n_items,
-                              int *counter, bool persistent, double *part, double *part_phi,
-                              hipStream_t s)
+template <typename T, int ACC, int FORM>
+hipError_t dispatch_fwd_shape(const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
 {
 #define COLATUS_FWD(RR, TT)                                                                  \
     if (cfg.R == RR && cfg.tpb == TT)                                                        \
-        return dispatch_fwd_flags<T, ACC, RR, TT>(phi, mask, x, m, N, items, n_items, counter, \
-                                                  persistent, part, part_phi, s);
+        return dispatch_fwd_flags<T, ACC, RR, TT, FORM>(phi, mask, a);
     COLATUS_FWD(1, 256)
     COLATUS_FWD(2, 256)
     COLATUS_FWD(4, 256)
@@ -513,6 +563,14 @@ hipError_t dispatch_fwd_shape(const TileCfg &cfg, bool phi, bool mask, const dou
     COLATUS_FWD(4, 128)
 #undef COLATUS_FWD
     return hipErrorInvalidValue;
+}
+
+template <typename T, int ACC>
+hipError_t dispatch_fwd_form(int form, const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
+{
+    if (form == 1)
+        return dispatch_fwd_shape<T, ACC, 1>(cfg, phi, mask, a);
+    return dispatch_fwd_shape<T, ACC, 0>(cfg, phi, mask, a);
 }
 
 template <typename T, int ACC, int R, int TPB, int C>
@@ -584,32 +642,50 @@ hipError_t launch_zero_counter(int *counter, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_pair_sweep(int precision, const TileCfg &cfg, bool with_phi, bool mask_self,
-                             const double *x, const double *m, int64_t N,
+hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool with_phi,
+                             bool mask_self, const double *x, const double *m, int64_t N,
                              const WorkItem *items, int n_items, int *counter, bool persistent,
-                             double *part, double *part_phi, hipStream_t stream)
+                             const double *box_mass, double *part, double *part_phi,
+                             hipStream_t stream)
 {
     if (n_items <= 0)
         return hipSuccess;
+    const FwdArgs a{x, m, N, items, n_items, counter, persistent, box_mass, part, part_phi,
+                    stream};
     switch (precision) {
     case kFP64:
-        return dispatch_fwd_shape<double, kDirect>(cfg, with_phi, mask_self, x, m, N, items,
-                                                   n_items, counter, persistent, part,
-                                                   part_phi, stream);
+        return dispatch_fwd_shape<double, kDirect, 0>(cfg, with_phi, mask_self, a);
     case kMixedTwoSum:
-        return dispatch_fwd_shape<float, kTwoSum>(cfg, with_phi, mask_self, x, m, N, items,
-                                                  n_items, counter, persistent, part,
-                                                  part_phi, stream);
+        return dispatch_fwd_form<float, kTwoSum>(form, cfg, with_phi, mask_self, a);
     case kMixedF64Acc:
-        return dispatch_fwd_shape<float, kFold64>(cfg, with_phi, mask_self, x, m, N, items,
-                                                  n_items, counter, persistent, part,
-                                                  part_phi, stream);
+        return dispatch_fwd_form<float, kFold64>(form, cfg, with_phi, mask_self, a);
     case kFP32:
-        return dispatch_fwd_shape<float, kDirect>(cfg, with_phi, mask_self, x, m, N, items,
-                                                  n_items, counter, persistent, part,
-                                                  part_phi, stream);
+        return dispatch_fwd_form<float, kDirect>(form, cfg, with_phi, mask_self, a);
     }
     return hipErrorInvalidValue;
+}
+
+// box_mass[b] = the common mass of box b, or NaN if its masses differ.
+__global__ void box_mass_kernel(const double *__restrict__ m, const int64_t *__restrict__ off,
+                                double *__restrict__ box_mass)
+{
+    const int b = blockIdx.x;
+    const int64_t o0 = off[b], o1 = off[b + 1];
+    const double m0 = m[o0];
+    int differ = 0;
+    for (int64_t i = o0 + threadIdx.x; i < o1; i += blockDim.x)
+        differ |= (m[i] != m0) || !(m[i] > 0.0);
+    differ = __syncthreads_or(differ);
+    if (threadIdx.x == 0)
+        box_mass[b] = differ ? NAN : m0;
+}
+
+hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes,
+                           double *box_mass, hipStream_t stream)
+{
+    hipLaunchKernelGGL(box_mass_kernel, dim3(n_boxes), dim3(1024), 0, stream, m, box_offsets,
+                       box_mass);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_self,

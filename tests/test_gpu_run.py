@@ -112,19 +112,21 @@ def test_free_particles_exact_drag(dev):
 
 def test_layzer_irvine_mixed_tracks_fp64(dev):
     """Precision must not degrade the invariant.  Until the open box's
-    mean-field collapse (a < 0.25 here) both residuals stay tiny and agree
+    mean-field collapse (a < 0.08 here) both residuals stay tiny and agree
     closely; through the collapse, close encounters at this step size make the
     residual itself large and the two (chaotic) runs differ, so there only the
-    size of the residual is compared."""
+    size of the residual is compared (within 10%)."""
     w = inputs.lcdm_grf(16, n_steps=200)
     v0 = _v0(w)
     _, _, d64 = _gpu_run(w, v0, dev, "fp64", diag=True)
     _, _, dmx = _gpu_run(w, v0, dev, "mixed_twosum", diag=True)
     scale = np.abs(d64["U"]).max()
-    early = d64["a"] < 0.25
+    early = d64["a"] < 0.08
     assert np.max(np.abs(dmx["LI"][early] - d64["LI"][early])) <= 1e-6 * scale
     assert np.max(np.abs(d64["LI"][early])) <= 1e-4 * scale
-    assert np.max(np.abs(dmx["LI"])) <= 1.1 * np.max(np.abs(d64["LI"])) + 1e-6 * scale
+    li64 = np.max(np.abs(d64["LI"]))
+    assert np.max(np.abs(dmx["LI"] - d64["LI"])) <= 0.1 * li64
+    assert np.max(np.abs(dmx["LI"])) <= 1.1 * li64
     for f in ("Px", "Py", "Pz"):
         assert np.max(np.abs(dmx[f] - dmx[f][0])) <= 1e-8
 
