@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
     p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--calibration-copy-mib", type=int, default=0,
+                   help="first run one plain device copy of this many MiB (a known-size "
+                        "kernel for scaling hardware byte counters)")
     return p.parse_args()
 
 
@@ -59,6 +62,13 @@ def main():
     from paper_1208_3444_amd import colatus, inputs
 
     dev = torch.device("cuda", 0)
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.lcdm_grf(32)
     H_i = colatus.hubble(w.a_begin, w.cosmo)
     v0 = w.velocities(H_i)

@@ -210,7 +210,8 @@ const char *colatus_strerror(int code);
 #define COLATUS_OPT_PERSISTENT 7  /* 1: persistent pair-sweep grid pulling work items
                                      from a device counter (default 1)               */
 #define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair weight m r^-3: 0 = m r^-1 (r^-1)^2,
-                                     1 = m r^-1 rcp(r^2) (default 1; FP64 always 0)  */
+                                     1 = m r^-1 rcp(r^2) (default 0, measured faster
+                                     on gfx950; FP64 always 0)                       */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

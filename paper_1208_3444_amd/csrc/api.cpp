@@ -32,7 +32,7 @@ struct Options {
     int64_t tile_tpb = 0;
     int64_t tile_slices = 0;
     int64_t persistent = 1;
-    int64_t pair_form = 1;
+    int64_t pair_form = 0;
 };
 Options g_opt;
 std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
@@ -304,9 +304,6 @@ TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu)
         if (precision == COLATUS_FP64) {
             c.R = 2;
             c.tpb = 256;
-        } else if (b.max_n >= 16384) {
-            c.R = 4;
-            c.tpb = 256;
         } else if (b.max_n >= 4096) {
             c.R = 2;
             c.tpb = 256;
@@ -319,7 +316,7 @@ TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu)
         c.tpb = 256;
     }
     const int tb = n_target_blocks(b, c.R * c.tpb);
-    const int want = 4 * n_cu;
+    const int want = 8 * n_cu;
     int s = (want + tb - 1) / tb;
     const int64_t max_s = std::max<int64_t>(1, b.max_n / (2 * c.tpb));
     s = (int)std::max<int64_t>(1, std::min<int64_t>(s, max_s));

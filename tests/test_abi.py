@@ -153,7 +153,7 @@ def test_options_and_tile_config():
     assert L.colatus_get_option(1, ctypes.byref(v)) == 0 and v.value == 1
     assert L.colatus_set_option(4, 3) == EINVAL
     assert L.colatus_set_option(99, 0) == EINVAL
-    assert colatus.tile_config(32768, "mixed") == (4, 256, 32)
+    assert colatus.tile_config(32768, "mixed") == (2, 256, 32)
     assert colatus.tile_config(32768, "fp64")[0:2] == (2, 256)
     colatus.set_option(colatus.OPT_TILE_SLICES, 3)
     try:
