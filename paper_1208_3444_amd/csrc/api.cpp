@@ -234,21 +234,26 @@ int get_workspace(hipStream_t stream, Workspace *&ws)
 }
 
 int *work_counter(Workspace *ws) { return static_cast<int *>(ws->counters.ptr); }
+int *done_counter(Workspace *ws)
+{
+    return reinterpret_cast<int *>(static_cast<char *>(ws->counters.ptr) + 128);
+}
 int64_t *step_counter(Workspace *ws)
 {
     return reinterpret_cast<int64_t *>(static_cast<char *>(ws->counters.ptr) + 64);
 }
 
-__global__ void set_step_kernel(int64_t *step, int64_t value, int *counter)
+__global__ void set_step_kernel(int64_t *step, int64_t value, int *counter, int *done)
 {
     *step = value;
     *counter = 0;
+    *done = 0;
 }
 
 int set_step(Workspace *ws, int64_t value, hipStream_t s)
 {
     hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(1), 0, s, step_counter(ws), value,
-                       work_counter(ws));
+                       work_counter(ws), done_counter(ws));
     CHECK_HIP(hipGetLastError());
     return COLATUS_OK;
 }
@@ -639,8 +644,7 @@ int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, 
     hipStream_t s = P.stream;
     const bool phi = P.diag != nullptr;
     auto body = [&](hipStream_t st) -> int {
-        CHECK_HIP(launch_integrate(base, st));
-        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), st));
+        CHECK_HIP(launch_integrate(base, st));  // advances the step counter
         CHECK_RC(run_forward_sweep(ws, ws->fwd, P.precision, phi, mask, P.x, P.m, P.N, st,
                                    false));
         return COLATUS_OK;
@@ -737,6 +741,9 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.G = P.G;
     A.coef = coef;
     A.step = step_counter(ws);
+    A.done = done_counter(ws);
+    A.work_counter = work_counter(ws);
+    A.tick = 1;
     A.first = P.first;
     A.last = P.last;
     A.diag_part = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
@@ -744,6 +751,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
+    A.tick = 0;
     CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
     CHECK_HIP(launch_convert(1, p, P.v, P.N, coef, nsteps - 1, s));
     if (diag) {
@@ -1067,6 +1075,9 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.G = G;
     A.coef = coef;
     A.step = step_counter(ws);
+    A.done = done_counter(ws);
+    A.work_counter = work_counter(ws);
+    A.tick = 1;
     A.first = 0;
     A.last = n_steps;
     A.diag_part = nullptr;
@@ -1085,12 +1096,13 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
             CHECK_HIP(hipMemcpyAsync(cx, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
             CHECK_HIP(hipMemcpyAsync(cx + n3, p, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
-        CHECK_HIP(launch_integrate(A, s));
-        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+        CHECK_HIP(launch_integrate(A, s));  // advances the step counter
     }
     if (xN || vN) {
         CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
-        CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_end
+        IntegrateArgs E = A;
+        E.tick = 0;
+        CHECK_HIP(launch_integrate(E, s));  // closing half kick at a_end
         if (xN)
             CHECK_HIP(hipMemcpyAsync(xN, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (vN)
@@ -1116,8 +1128,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
             CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
             IntegrateArgs B = A;
             B.x = xn;
-            CHECK_HIP(launch_integrate(B, s));
-            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+            CHECK_HIP(launch_integrate(B, s));  // advances the step counter
         }
         // visit x_n for n = hi .. lo+1 (and lo itself in segment 0): every grid
         // point is visited once, x_hi being the unvisited bottom of the segment above

@@ -19,7 +19,7 @@ struct WorkItem {
 
 // Up to kIntBlock particles of one box, for the O(N) kernels (finalise,
 // kick/drift, diagnostics).  Blocks never straddle a box boundary.
-constexpr int kIntBlock = 256;
+constexpr int kIntBlock = 64;
 struct IntBlock {
     int64_t i0, i1;
     double eps;       // softening of the box (self-term of the potential)
@@ -110,7 +110,11 @@ struct IntegrateArgs {
     int64_t N;
     double G;
     const StepCoef *coef;  // indexed by (n - first)
-    const int64_t *step;   // device step counter n (absolute)
+    int64_t *step;         // device step counter n (absolute); advanced by the
+                           // last block to finish (with tick != 0)
+    int *done;             // blocks finished in this launch (zero between launches)
+    int *work_counter;     // pair-sweep work counter, re-armed with the step
+    int tick;              // advance *step and re-arm the counters at the end
     int64_t first, last;
     double *diag_part;     // [rows][n_blocks][kDiagW] or null
     int precision;         // pair arithmetic of the sweep that wrote part_phi
@@ -118,7 +122,8 @@ struct IntegrateArgs {
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and
-// drift by d_n.  Reads n from *step.
+// drift by d_n.  Reads n from *step; with tick, the last block to finish
+// sets *step = n + 1 and zeroes the work counter (graph-safe, no memset).
 hipError_t launch_integrate(const IntegrateArgs &args, hipStream_t stream);
 
 // *step += 1; *counter = 0.

@@ -188,13 +188,18 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
     for (int q = 0; q < kDiagW; ++q)
         v[q] = 0.0;
     if (valid) {
-        double g[3];
-        for (int c = 0; c < 3; ++c) {
-            double s = 0.0;
-            for (int k = 0; k < S; ++k)
-                s += A.part[((int64_t)k * 3 + c) * N + i];
-            g[c] = A.G * s;
+        // fixed-order sum of the slice partials; the loads are independent,
+        // unrolled so that many are in flight per thread
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+        const double *pp = A.part + i;
+        const int64_t stride = 3 * N;
+#pragma unroll 8
+        for (int k = 0; k < S; ++k) {
+            g0 += pp[(int64_t)k * stride];
+            g1 += pp[(int64_t)k * stride + N];
+            g2 += pp[(int64_t)k * stride + 2 * N];
         }
+        const double g[3] = {A.G * g0, A.G * g1, A.G * g2};
         double p[3] = {A.p[i], A.p[N + i], A.p[2 * N + i]};
         double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
         if (n > A.first) {
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
         if (A.diag_part) {
             const double mi = A.m[i];
             double phs = 0.0;
+#pragma unroll 8
             for (int k = 0; k < S; ++k)
                 phs += A.part_phi[(int64_t)k * N + i];
             phs -= self_potential(A.precision, mi, blk.eps, box_mass_of(A.box_mass, blk.box));
@@ -242,6 +248,21 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
             double *out = A.diag_part + (row * A.n_blocks + blockIdx.x) * kDiagW;
             for (int q = 0; q < kDiagW; ++q)
                 out[q] = v[q];
+        }
+    }
+    if (A.tick) {
+        // every block has read *step before it arrives here; the last to
+        // arrive advances the step and re-arms the counters for the next one
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const int arrived = atomicAdd(A.done, 1);
+            if (arrived == A.n_blocks - 1) {
+                *A.step = n + 1;
+                *A.work_counter = 0;
+                *A.done = 0;
+                __threadfence();
+            }
         }
     }
 }

@@ -127,8 +127,13 @@ def test_layzer_irvine_mixed_tracks_fp64(dev):
     li64 = np.max(np.abs(d64["LI"]))
     assert np.max(np.abs(dmx["LI"] - d64["LI"])) <= 0.1 * li64
     assert np.max(np.abs(dmx["LI"])) <= 1.1 * li64
+    # total momentum: exactly antisymmetric pair forces conserve it to FP64
+    # roundoff; FP32 pairs break the antisymmetry at the FP32 rounding level.
+    # Scale: sum m |p| <= a sqrt(2 K) for unit total mass.
+    p_scale = np.max(d64["a"] * np.sqrt(2 * d64["K"]))
     for f in ("Px", "Py", "Pz"):
-        assert np.max(np.abs(dmx[f] - dmx[f][0])) <= 1e-8
+        assert np.max(np.abs(d64[f] - d64[f][0])) <= 1e-12 * p_scale
+        assert np.max(np.abs(dmx[f] - dmx[f][0])) <= 1e-6 * p_scale
 
 
 def test_layzer_irvine_second_order_on_gpu(dev):
