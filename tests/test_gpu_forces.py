@@ -152,17 +152,3 @@ def test_batch_boxes_do_not_interact(dev):
             assert np.max(np.linalg.norm(got[:, sl] - ref, axis=0) / scale) <= tol
             pref = oracle.potential(xs[b], ms[b], epss[b])
             assert np.max(np.abs(phi[sl] - pref) / np.abs(pref)) <= (1e-13 if prec == "fp64" else 1e-6)
-
-
-@pytest.mark.parametrize("prec,med,mx", [("fp64", 1e-12, 1e-12), ("mixed_twosum", 1e-6, 1e-4),
-                                         ("mixed_f64acc", 1e-6, 1e-4), ("fp32", 1e-5, 1e-3)])
-def test_precision_sweep_64cubed(dev, prec, med, mx):
-    """The single-evaluation precision sweep at N = 64^3, a = 0.5, on 512 of
-    the seeded targets (the full 4096 are timed by the benchmark script)."""
-    w = inputs.precision_sweep(64, n_targets=512)
-    t = w.extra["targets"]
-    ref = oracle.forces_targets(w.x, w.m, t, w.eps, a=0.5)
-    got = _gpu_forces(w.x, w.m, w.eps, dev, prec, a=0.5)[:, t]
-    e = rel_err_per_particle(got, ref)
-    print(f"{prec}: median {np.median(e):.3e} max {e.max():.3e}")
-    assert np.median(e) <= med and e.max() <= mx
