@@ -209,9 +209,11 @@ const char *colatus_strerror(int code);
 #define COLATUS_OPT_TILE_SLICES 6 /* >0: force the number of source slices; 0 = auto  */
 #define COLATUS_OPT_PERSISTENT 7  /* 1: persistent pair-sweep grid pulling work items
                                      from a device counter (default 1)               */
-#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair weight m r^-3: 0 = m r^-1 (r^-1)^2,
-                                     1 = m r^-1 rcp(r^2) (default 0, measured faster
-                                     on gfx950; FP64 always 0)                       */
+#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair loop: 0 = weight m r^-1 (r^-1)^2 and
+                                     VALU accumulation; 1 = weight m r^-1 rcp(r^2);
+                                     2 = weight r^-3 on the VALU, accumulation of
+                                     w (m x, m y, m z, m) on the matrix cores
+                                     (v_mfma_f32_4x4x1f32); FP64 always uses 0      */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

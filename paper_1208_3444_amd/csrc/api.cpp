@@ -830,7 +830,7 @@ int colatus_set_option(int key, int64_t value)
         return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: g_opt.persistent = value != 0; return COLATUS_OK;
     case COLATUS_OPT_PAIR_FORM:
-        if (value != 0 && value != 1)
+        if (value < 0 || value > 2)
             return COLATUS_EINVAL;
         g_opt.pair_form = value;
         return COLATUS_OK;

@@ -54,7 +54,8 @@ constexpr int kDiagW = 10;
 
 // Forward pair sweep: part[s][3][N] = sum over the item's sources of
 // m_j (x_j - x_k) r^-3, and part_phi[s][N] = sum m_j / r when with_phi.
-// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s) (FP32 only).
+// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s); form 2: w = r^-3 on
+// the VALU with the accumulation on the matrix cores (forms 1, 2: FP32 only).
 // box_mass[b]: common mass of box b or NaN (see launch_box_mass), or null.
 hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool with_phi,
                              bool mask_self, const double *x, const double *m,

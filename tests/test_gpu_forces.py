@@ -152,3 +152,50 @@ def test_batch_boxes_do_not_interact(dev):
             assert np.max(np.linalg.norm(got[:, sl] - ref, axis=0) / scale) <= tol
             pref = oracle.potential(xs[b], ms[b], epss[b])
             assert np.max(np.abs(phi[sl] - pref) / np.abs(pref)) <= (1e-13 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_alternative_pair_forms_match_oracle(dev, form):
+    """Form 1 (rcp-based weight) and form 2 (matrix-core accumulation) give
+    the same sums as the default loop, to the mixed-precision tolerance."""
+    colatus.set_option(colatus.OPT_PAIR_FORM, form)
+    try:
+        w = inputs.eds_lattice(16)
+        ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
+        for prec in ("mixed_twosum", "mixed_f64acc"):
+            got, phi = _gpu_forces(w.x, w.m, w.eps, dev, prec, a=0.1, with_phi=True)
+            e = rel_err_per_particle(got, ref)
+            print(f"form {form} {prec}: median {np.median(e):.3e} max {e.max():.3e}")
+            assert np.median(e) <= 1e-6 and e.max() <= 1e-4
+            pref = oracle.potential(w.x, w.m, w.eps)
+            assert np.max(np.abs(phi - pref) / np.abs(pref)) <= 1e-6
+        got = _gpu_forces(w.x, w.m, w.eps, dev, "fp32", a=0.1)
+        e = rel_err_per_particle(got, ref)
+        assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+        # unequal masses, ragged sizes, several tile shapes
+        for N, R, tpb in ((1000, 2, 256), (1537, 4, 128), (300, 1, 256)):
+            colatus.set_option(colatus.OPT_TILE_R, R)
+            colatus.set_option(colatus.OPT_TILE_TPB, tpb)
+            x, m = inputs.random_cloud(N, N, scale=0.5)
+            got = _gpu_forces(x, m, 0.01, dev, "mixed_twosum")
+            ref = oracle.forces(x, m, 0.01)
+            scale = _term_scale(x, m, 0.01)
+            assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 1e-6
+        # softening zero masks the self pair
+        x, m = inputs.random_cloud(300, 7, scale=0.5)
+        got = _gpu_forces(x, m, 0.0, dev, "mixed_twosum")
+        assert np.all(np.isfinite(got))
+        assert np.max(np.linalg.norm(got - oracle.forces(x, m, 0.0), axis=0)
+                      / _term_scale(x, m, 0.0)) <= 1e-5
+        # paper-scale sampled check
+        w = inputs.lcdm_grf(32)
+        t = np.arange(0, w.N, 37)
+        ref = oracle.forces_targets(w.x, w.m, t, w.eps, a=w.a_begin)
+        got = _gpu_forces(w.x, w.m, w.eps, dev, "mixed_twosum", a=w.a_begin)[:, t]
+        e = rel_err_per_particle(got, ref)
+        print(f"form {form} 32^3: median {np.median(e):.3e} max {e.max():.3e}")
+        assert np.median(e) <= 1e-6 and e.max() <= 1e-4
+    finally:
+        colatus.set_option(colatus.OPT_PAIR_FORM, 0)
+        colatus.set_option(colatus.OPT_TILE_R, 0)
+        colatus.set_option(colatus.OPT_TILE_TPB, 0)
