@@ -213,7 +213,9 @@ const char *colatus_strerror(int code);
                                      VALU accumulation; 1 = weight m r^-1 rcp(r^2);
                                      2 = weight r^-3 on the VALU, accumulation of
                                      w (m x, m y, m z, m) on the matrix cores
-                                     (v_mfma_f32_4x4x1f32); FP64 always uses 0      */
+                                     (v_mfma_f32_4x4x1f32); -1 (default) = the
+                                     heuristic's or the autotuner's choice.  FP64
+                                     always uses 0                                   */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 
@@ -224,8 +226,9 @@ int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset)
 
 /* Tile shape the library would use (or has tuned) for N particles in one
  * box at the given precision: out[0] = targets per lane R, out[1] = threads
- * per block, out[2] = source slices.  kind 0 = forward, 1 = adjoint.      */
-int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[3]);
+ * per block, out[2] = source slices, out[3] = pair-loop form (see
+ * COLATUS_OPT_PAIR_FORM).  kind 0 = forward, 1 = adjoint.                 */
+int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[4]);
 
 /* Release all cached device scratch of all streams (synchronises them).  */
 int colatus_release(void);

@@ -359,7 +359,8 @@ def timer_read(kind=0, reset=True):
 
 
 def tile_config(N, precision="mixed_twosum", kind=0):
-    out = (ctypes.c_int32 * 3)()
+    """(targets per lane, threads per block, source slices, pair-loop form)."""
+    out = (ctypes.c_int32 * 4)()
     _check("colatus_tile_config", lib().colatus_tile_config(int(N), _prec(precision), int(kind),
                                                             out))
     return tuple(out)

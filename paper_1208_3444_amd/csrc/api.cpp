@@ -32,7 +32,7 @@ struct Options {
     int64_t tile_tpb = 0;
     int64_t tile_slices = 0;
     int64_t persistent = 1;
-    int64_t pair_form = 0;
+    int64_t pair_form = -1;  // -1: heuristic or tuned
 };
 Options g_opt;
 std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
@@ -140,7 +140,7 @@ struct WorkList {
     int64_t N = -1;
     std::vector<int64_t> off;
     std::vector<double> eps;
-    TileCfg cfg{0, 0, 0};
+    TileCfg cfg{0, 0, 0, 0};
     // content
     std::vector<WorkItem> items;
     std::vector<IntBlock> blocks;
@@ -326,7 +326,17 @@ TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu)
     const int64_t max_s = std::max<int64_t>(1, b.max_n / (2 * c.tpb));
     s = (int)std::max<int64_t>(1, std::min<int64_t>(s, max_s));
     c.slices = s;
+    c.form = 0;
     return c;
+}
+
+// Number of source slices giving about `per_cu` work items per CU.
+int slices_for(const Boxes &b, int R, int tpb, int per_cu, int n_cu)
+{
+    const int tb = n_target_blocks(b, R * tpb);
+    const int s = (per_cu * n_cu + tb - 1) / tb;
+    const int64_t max_s = std::max<int64_t>(1, b.max_n / (2 * tpb));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(s, max_s));
 }
 
 TileCfg apply_overrides(TileCfg c, int kind)
@@ -337,6 +347,8 @@ TileCfg apply_overrides(TileCfg c, int kind)
         c.tpb = (int)g_opt.tile_tpb;
     if (g_opt.tile_slices > 0)
         c.slices = (int)g_opt.tile_slices;
+    if (g_opt.pair_form >= 0 && kind == 0)
+        c.form = (int)g_opt.pair_form;
     return c;
 }
 
@@ -405,7 +417,7 @@ int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, cons
                     hipStream_t s)
 {
     if (wl.N == N && wl.off == b.off && wl.eps == b.eps && wl.cfg.R == cfg.R &&
-        wl.cfg.tpb == cfg.tpb && wl.cfg.slices == cfg.slices)
+        wl.cfg.tpb == cfg.tpb && wl.cfg.slices == cfg.slices && wl.cfg.form == cfg.form)
         return COLATUS_OK;
     // the previous list may still be read by queued work
     CHECK_HIP(hipStreamSynchronize(s));
@@ -468,7 +480,7 @@ int run_forward_sweep(Workspace *ws, const WorkList &wl, int precision, bool phi
         CHECK_HIP(launch_zero_counter(work_counter(ws), s));
     if (e0)
         CHECK_HIP(hipEventRecord(e0, s));
-    CHECK_HIP(launch_pair_sweep(precision, (int)g_opt.pair_form, wl.cfg, phi, mask, x, m, N,
+    CHECK_HIP(launch_pair_sweep(precision, wl.cfg.form, wl.cfg, phi, mask, x, m, N,
                                 static_cast<const WorkItem *>(wl.d_items.ptr),
                                 (int)wl.items.size(), work_counter(ws), g_opt.persistent != 0,
                                 static_cast<const double *>(ws->box_mass.ptr),
@@ -506,6 +518,8 @@ int run_adjoint_sweep(Workspace *ws, const WorkList &wl, int precision, bool mas
     return COLATUS_OK;
 }
 
+int prepare_box_mass(Workspace *ws, const WorkList &wl, const double *m, hipStream_t s);
+
 // Choose (and if asked, autotune) the tile shape, then make the work list.
 int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int precision,
                      const double *x, const double *m, int n_cot, hipStream_t s)
@@ -522,39 +536,31 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
         if (g_opt.autotune && x && m) {
             // time candidates on the live data; scratch outputs only
             std::vector<TileCfg> cand;
-            const int rs_f[3] = {1, 2, 4};
-            const int tp_f[2] = {128, 256};
             if (kind == 0) {
-                for (int r : rs_f)
-                    for (int t : tp_f) {
-                        TileCfg c{r, t, 1};
-                        TileCfg h = heuristic_cfg(b, precision, kind, n_cu);
-                        const int tb = n_target_blocks(b, r * t);
-                        const int base = std::max(1, (4 * n_cu + tb - 1) / tb);
-                        for (int mult : {1, 2}) {
-                            c.slices = (int)std::max<int64_t>(
-                                1, std::min<int64_t>(base * mult, std::max<int64_t>(1, b.max_n / (2 * t))));
-                            cand.push_back(c);
-                        }
-                        (void)h;
-                    }
+                const bool fp32 = precision != COLATUS_FP64;
+                for (int form : {0, 2}) {
+                    if (form == 2 && !fp32)
+                        continue;
+                    for (int r : {1, 2, 4})
+                        for (int t : {128, 256})
+                            for (int per_cu : {4, 8, 16}) {
+                                TileCfg c{r, t, slices_for(b, r, t, per_cu, n_cu), form};
+                                cand.push_back(c);
+                            }
+                }
             } else {
-                for (int r : {1, 2}) {
-                    TileCfg c{r, 256, 1};
-                    const int tb = n_target_blocks(b, r * 256);
-                    const int base = std::max(1, (4 * n_cu + tb - 1) / tb);
-                    for (int mult : {1, 2}) {
-                        c.slices = (int)std::max<int64_t>(
-                            1, std::min<int64_t>(base * mult, std::max<int64_t>(1, b.max_n / 512)));
+                for (int r : {1, 2})
+                    for (int per_cu : {4, 8, 16}) {
+                        TileCfg c{r, 256, slices_for(b, r, 256, per_cu, n_cu), 0};
                         cand.push_back(c);
                     }
-                }
             }
             hipEvent_t e0 = take_event(), e1 = take_event();
             float best = 1e30f;
             for (const TileCfg &c : cand) {
                 WorkList tmp;
                 CHECK_RC(ensure_worklist(ws, tmp, b, N, c, s));
+                CHECK_RC(prepare_box_mass(ws, tmp, m, s));
                 const size_t need = (size_t)tmp.max_slices * 3 * (size_t)N * sizeof(double) *
                                     (kind == 0 ? 1 : (size_t)std::max(1, n_cot));
                 CHECK_RC(ensure(ws->part, need));
@@ -565,9 +571,10 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                     CHECK_HIP(hipEventRecord(e0, s));
                     if (kind == 0)
                         CHECK_HIP(launch_pair_sweep(
-                            precision, (int)g_opt.pair_form, c, false, false, x, m, N,
+                            precision, c.form, c, false, false, x, m, N,
                             static_cast<const WorkItem *>(tmp.d_items.ptr), (int)tmp.items.size(),
-                            work_counter(ws), g_opt.persistent != 0, nullptr,
+                            work_counter(ws), g_opt.persistent != 0,
+                            static_cast<const double *>(ws->box_mass.ptr),
                             static_cast<double *>(ws->part.ptr), nullptr, s));
                     else
                         CHECK_HIP(launch_adjoint_sweep(
@@ -830,7 +837,7 @@ int colatus_set_option(int key, int64_t value)
         return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: g_opt.persistent = value != 0; return COLATUS_OK;
     case COLATUS_OPT_PAIR_FORM:
-        if (value < 0 || value > 2)
+        if (value < -1 || value > 2)
             return COLATUS_EINVAL;
         g_opt.pair_form = value;
         return COLATUS_OK;
@@ -880,7 +887,7 @@ int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset)
     return COLATUS_OK;
 }
 
-int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[3])
+int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[4])
 {
     if (!out || N < 1 || N > kMaxN || !valid_precision(precision) || kind < 0 || kind > 1)
         return COLATUS_EINVAL;
@@ -900,6 +907,7 @@ int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[3])
     out[0] = c.R;
     out[1] = c.tpb;
     out[2] = c.slices;
+    out[3] = c.form;
     return COLATUS_OK;
 }
 

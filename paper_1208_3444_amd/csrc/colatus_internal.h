@@ -44,6 +44,7 @@ struct TileCfg {
     int R;        // targets per lane
     int tpb;      // threads per block (= sources per LDS tile)
     int slices;   // source slices per box
+    int form;     // FP32 pair-loop form (see launch_pair_sweep); 0 for FP64
 };
 
 // Diagnostics partial row written per IntBlock: K*a^2*2, sum m phi, P[3], L[3],

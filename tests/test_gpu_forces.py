@@ -196,6 +196,23 @@ def test_alternative_pair_forms_match_oracle(dev, form):
         print(f"form {form} 32^3: median {np.median(e):.3e} max {e.max():.3e}")
         assert np.median(e) <= 1e-6 and e.max() <= 1e-4
     finally:
-        colatus.set_option(colatus.OPT_PAIR_FORM, 0)
+        colatus.set_option(colatus.OPT_PAIR_FORM, -1)
         colatus.set_option(colatus.OPT_TILE_R, 0)
         colatus.set_option(colatus.OPT_TILE_TPB, 0)
+
+
+def test_autotuner_picks_a_working_shape(dev):
+    """The autotuner times candidate shapes (and pair-loop forms) on the live
+    data and keeps the fastest; results still match the oracle."""
+    w = inputs.eds_lattice(12)
+    colatus.set_option(colatus.OPT_AUTOTUNE, 1)
+    try:
+        got = _gpu_forces(w.x, w.m, w.eps, dev, "mixed_twosum", a=0.1)
+        cfg = colatus.tile_config(w.N, "mixed_twosum")
+    finally:
+        colatus.set_option(colatus.OPT_AUTOTUNE, 0)
+    print("tuned", cfg)
+    assert cfg[0] in (1, 2, 4) and cfg[1] in (128, 256) and cfg[2] >= 1 and cfg[3] in (0, 2)
+    ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
+    e = rel_err_per_particle(got, ref)
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4
