@@ -509,8 +509,9 @@ int run_adjoint_sweep(Workspace *ws, const WorkList &wl, int precision, bool mas
     CHECK_HIP(launch_adjoint_sweep(precision, wl.cfg, mask, x, m, N, n_cot, lam,
                                    static_cast<const WorkItem *>(wl.d_items.ptr),
                                    (int)wl.items.size(), work_counter(ws),
-                                   g_opt.persistent != 0, static_cast<double *>(ws->part.ptr),
-                                   s));
+                                   g_opt.persistent != 0,
+                                   static_cast<const double *>(ws->box_mass.ptr),
+                                   static_cast<double *>(ws->part.ptr), s));
     if (e1) {
         CHECK_HIP(hipEventRecord(e1, s));
         g_timer[1].push_back({e0, e1});
@@ -581,6 +582,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                             precision, c, false, x, m, N, 1, x,
                             static_cast<const WorkItem *>(tmp.d_items.ptr), (int)tmp.items.size(),
                             work_counter(ws), g_opt.persistent != 0,
+                            static_cast<const double *>(ws->box_mass.ptr),
                             static_cast<double *>(ws->part.ptr), s));
                     CHECK_HIP(hipEventRecord(e1, s));
                     CHECK_HIP(hipEventSynchronize(e1));
@@ -1009,6 +1011,7 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
     CHECK_RC(get_workspace(s, ws));
     CHECK_RC(prepare_worklist(ws, 1, b, N, precision, x, m, n_cot, s));
     const WorkList &wl = ws->adj;
+    CHECK_RC(prepare_box_mass(ws, wl, m, s));
     CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n_cot * 3 * N * sizeof(double)));
     const bool mask = eps == 0.0;
     CHECK_RC(run_adjoint_sweep(ws, wl, precision, mask, x, m, N, n_cot, lam, s));

@@ -74,7 +74,8 @@ hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_sel
                                 const double *x, const double *m, int64_t N,
                                 int n_cot, const double *lam,
                                 const WorkItem *items, int n_items, int *counter,
-                                bool persistent, double *part, hipStream_t stream);
+                                bool persistent, const double *box_mass, double *part,
+                                hipStream_t stream);
 
 // Sets *counter = 0 (graph-safe replacement for a memset node).
 hipError_t launch_zero_counter(int *counter, hipStream_t stream);

@@ -309,12 +309,66 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
 // for C cotangents sharing the geometry.  lam is [n_cot][3][N]; this launch
 // handles cotangents [c0, c0 + C).  part is [slices][n_cot][3][N].
 // ---------------------------------------------------------------------------
+// Pair loop of the adjoint sweep over one LDS tile.  With equal masses
+// (EQM) the bracket m_k lam_j - m_j lam_k is m (lam_j - lam_k); the common
+// m multiplies the slice's partial sum once instead.
+template <typename T, int R, int C, bool MASK, bool EQM, typename V>
+__device__ __forceinline__ void adjoint_tile(const V *__restrict__ tile,
+                                             const T *__restrict__ ltile, int nt,
+                                             const T (&xi)[R], const T (&yi)[R],
+                                             const T (&zi)[R], const T (&mk)[R],
+                                             const T (&lk)[R][3 * C], T eps2,
+                                             T (&acc)[R][3 * C])
+{
+    constexpr int LW = 3 * C;
+    for (int jj = 0; jj < nt; ++jj) {
+        const V pj = tile[jj];
+        T lt[LW];
+#pragma unroll
+        for (int q = 0; q < LW; ++q)
+            lt[q] = ltile[jj * LW + q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T dx = pj.x - xi[r];
+            const T dy = pj.y - yi[r];
+            const T dz = pj.z - zi[r];
+            T s = fma_t(dx, dx, eps2);
+            s = fma_t(dy, dy, s);
+            s = fma_t(dz, dz, s);
+            T rinv = rsqrt_t(s);
+            if constexpr (MASK)
+                rinv = s > (T)0 ? rinv : (T)0;
+            const T r2 = rinv * rinv;
+            const T r3 = r2 * rinv;
+            const T m3r5 = (T)(-3) * (r3 * r2);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                T ux, uy, uz;
+                if constexpr (EQM) {
+                    ux = lt[3 * c + 0] - lk[r][3 * c + 0];
+                    uy = lt[3 * c + 1] - lk[r][3 * c + 1];
+                    uz = lt[3 * c + 2] - lk[r][3 * c + 2];
+                } else {
+                    ux = fma_t(mk[r], lt[3 * c + 0], -(pj.w * lk[r][3 * c + 0]));
+                    uy = fma_t(mk[r], lt[3 * c + 1], -(pj.w * lk[r][3 * c + 1]));
+                    uz = fma_t(mk[r], lt[3 * c + 2], -(pj.w * lk[r][3 * c + 2]));
+                }
+                const T du = fma_t(dx, ux, fma_t(dy, uy, dz * uz));
+                const T t = m3r5 * du;
+                acc[r][3 * c + 0] = fma_t(t, dx, fma_t(r3, ux, acc[r][3 * c + 0]));
+                acc[r][3 * c + 1] = fma_t(t, dy, fma_t(r3, uy, acc[r][3 * c + 1]));
+                acc[r][3 * c + 2] = fma_t(t, dz, fma_t(r3, uz, acc[r][3 * c + 2]));
+            }
+        }
+    }
+}
+
 template <typename T, int ACC, int R, int TPB, int C, bool MASK>
 __global__ __launch_bounds__(TPB) void adjoint_sweep_kernel(
     const double *__restrict__ x, const double *__restrict__ m, int64_t N,
     const double *__restrict__ lam, int n_cot, int c0,
     const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
-    int persistent, double *__restrict__ part)
+    int persistent, const double *__restrict__ box_mass, double *__restrict__ part)
 {
     using V = typename V4<T>::type;
     constexpr int LW = 3 * C;
@@ -330,6 +384,8 @@ __global__ __launch_bounds__(TPB) void adjoint_sweep_kernel(
         if (it >= n_items)
             break;
         const WorkItem w = items[it];
+        const double mbox = box_mass ? box_mass[w.box] : NAN;
+        const bool eqm = !isnan(mbox);
 
         double tx[R], ty[R], tz[R];
         bool valid[R];
@@ -398,39 +454,10 @@ __global__ __launch_bounds__(TPB) void adjoint_sweep_kernel(
                 ltile[tid * LW + q] = lj[q];
             __syncthreads();
             const int nt = (int)((w.j1 - jt) < TPB ? (w.j1 - jt) : TPB);
-            for (int jj = 0; jj < nt; ++jj) {
-                const V pj = tile[jj];
-                T lt[LW];
-#pragma unroll
-                for (int q = 0; q < LW; ++q)
-                    lt[q] = ltile[jj * LW + q];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T dx = pj.x - xi[r];
-                    const T dy = pj.y - yi[r];
-                    const T dz = pj.z - zi[r];
-                    T s = fma_t(dx, dx, eps2);
-                    s = fma_t(dy, dy, s);
-                    s = fma_t(dz, dz, s);
-                    T rinv = rsqrt_t(s);
-                    if constexpr (MASK)
-                        rinv = s > (T)0 ? rinv : (T)0;
-                    const T r2 = rinv * rinv;
-                    const T r3 = r2 * rinv;
-                    const T m3r5 = (T)(-3) * (r3 * r2);
-#pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        const T ux = fma_t(mk[r], lt[3 * c + 0], -(pj.w * lk[r][3 * c + 0]));
-                        const T uy = fma_t(mk[r], lt[3 * c + 1], -(pj.w * lk[r][3 * c + 1]));
-                        const T uz = fma_t(mk[r], lt[3 * c + 2], -(pj.w * lk[r][3 * c + 2]));
-                        const T du = fma_t(dx, ux, fma_t(dy, uy, dz * uz));
-                        const T t = m3r5 * du;
-                        acc[r][3 * c + 0] = fma_t(t, dx, fma_t(r3, ux, acc[r][3 * c + 0]));
-                        acc[r][3 * c + 1] = fma_t(t, dy, fma_t(r3, uy, acc[r][3 * c + 1]));
-                        acc[r][3 * c + 2] = fma_t(t, dz, fma_t(r3, uz, acc[r][3 * c + 2]));
-                    }
-                }
-            }
+            if (eqm)
+                adjoint_tile<T, R, C, MASK, true>(tile, ltile, nt, xi, yi, zi, mk, lk, eps2, acc);
+            else
+                adjoint_tile<T, R, C, MASK, false>(tile, ltile, nt, xi, yi, zi, mk, lk, eps2, acc);
             if constexpr (ACC != kDirect) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -462,7 +489,7 @@ __global__ __launch_bounds__(TPB) void adjoint_sweep_kernel(
                         o = fold[r][3 * c + q];
                     else
                         o = (double)acc[r][3 * c + q];
-                    part[((slot * n_cot + (c0 + c)) * 3 + q) * N + i] = o;
+                    part[((slot * n_cot + (c0 + c)) * 3 + q) * N + i] = eqm ? mbox * o : o;
                 }
         }
     }
@@ -809,18 +836,18 @@ hipError_t dispatch_fwd_form(int form, const TileCfg &cfg, bool phi, bool mask, 
 template <typename T, int ACC, int R, int TPB, int C>
 hipError_t launch_adj(bool mask, const double *x, const double *m, int64_t N, const double *lam,
                       int n_cot, int c0, const WorkItem *items, int n_items, int *counter,
-                      bool persistent, double *part, hipStream_t stream)
+                      bool persistent, const double *box_mass, double *part, hipStream_t stream)
 {
     if (mask) {
         auto k = adjoint_sweep_kernel<T, ACC, R, TPB, C, true>;
         int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
         hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, lam, n_cot, c0, items,
-                           n_items, counter, persistent ? 1 : 0, part);
+                           n_items, counter, persistent ? 1 : 0, box_mass, part);
     } else {
         auto k = adjoint_sweep_kernel<T, ACC, R, TPB, C, false>;
         int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
         hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, lam, n_cot, c0, items,
-                           n_items, counter, persistent ? 1 : 0, part);
+                           n_items, counter, persistent ? 1 : 0, box_mass, part);
     }
     return hipGetLastError();
 }
@@ -828,8 +855,8 @@ hipError_t launch_adj(bool mask, const double *x, const double *m, int64_t N, co
 template <typename T, int ACC>
 hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const double *m,
                         int64_t N, int n_cot, const double *lam, const WorkItem *items,
-                        int n_items, int *counter, bool persistent, double *part,
-                        hipStream_t s)
+                        int n_items, int *counter, bool persistent, const double *box_mass,
+                        double *part, hipStream_t s)
 {
     // Cotangents in chunks of 8, then 4, then 1; the work counter is re-armed
     // before every chunk after the first.
@@ -846,19 +873,19 @@ hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const do
         if (left >= 8) {
             // eight cotangents keep 24 accumulators per target: one target per lane
             e = launch_adj<T, ACC, 1, 256, 8>(mask, x, m, N, lam, n_cot, c0, items, n_items,
-                                              counter, persistent, part, s);
+                                              counter, persistent, box_mass, part, s);
             c0 += 8;
         } else if (left >= 4) {
             e = r2 ? launch_adj<T, ACC, 2, 256, 4>(mask, x, m, N, lam, n_cot, c0, items, n_items,
-                                                    counter, persistent, part, s)
+                                                    counter, persistent, box_mass, part, s)
                    : launch_adj<T, ACC, 1, 256, 4>(mask, x, m, N, lam, n_cot, c0, items, n_items,
-                                                    counter, persistent, part, s);
+                                                    counter, persistent, box_mass, part, s);
             c0 += 4;
         } else {
             e = r2 ? launch_adj<T, ACC, 2, 256, 1>(mask, x, m, N, lam, n_cot, c0, items, n_items,
-                                                    counter, persistent, part, s)
+                                                    counter, persistent, box_mass, part, s)
                    : launch_adj<T, ACC, 1, 256, 1>(mask, x, m, N, lam, n_cot, c0, items, n_items,
-                                                    counter, persistent, part, s);
+                                                    counter, persistent, box_mass, part, s);
             c0 += 1;
         }
         if (e != hipSuccess)
@@ -924,24 +951,24 @@ hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_bo
 hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_self,
                                 const double *x, const double *m, int64_t N, int n_cot,
                                 const double *lam, const WorkItem *items, int n_items,
-                                int *counter, bool persistent, double *part,
-                                hipStream_t stream)
+                                int *counter, bool persistent, const double *box_mass,
+                                double *part, hipStream_t stream)
 {
     if (n_items <= 0)
         return hipSuccess;
     switch (precision) {
     case kFP64:
         return dispatch_adj<double, kDirect>(cfg, mask_self, x, m, N, n_cot, lam, items,
-                                             n_items, counter, persistent, part, stream);
+                                             n_items, counter, persistent, box_mass, part, stream);
     case kMixedTwoSum:
         return dispatch_adj<float, kTwoSum>(cfg, mask_self, x, m, N, n_cot, lam, items,
-                                            n_items, counter, persistent, part, stream);
+                                            n_items, counter, persistent, box_mass, part, stream);
     case kMixedF64Acc:
         return dispatch_adj<float, kFold64>(cfg, mask_self, x, m, N, n_cot, lam, items,
-                                            n_items, counter, persistent, part, stream);
+                                            n_items, counter, persistent, box_mass, part, stream);
     case kFP32:
         return dispatch_adj<float, kDirect>(cfg, mask_self, x, m, N, n_cot, lam, items,
-                                            n_items, counter, persistent, part, stream);
+                                            n_items, counter, persistent, box_mass, part, stream);
     }
     return hipErrorInvalidValue;
 }
