@@ -237,6 +237,19 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     t = time.perf_counter() - t0
     ens["per_box_loop_gpairs_s"] = (Kl + 1) * pairs_e / t / 1e9
     ens["speedup_vs_per_box_loop"] = ens["gpairs_s"] / ens["per_box_loop_gpairs_s"]
+    # the same batched step with the persistent grid (work items pulled from a
+    # device counter), and with tile shapes from the autotuner
+    colatus.set_option(colatus.OPT_PERSISTENT, 1)
+    erun(5 + Ke, 10 + Ke)
+    t = erun(10 + Ke, 10 + 2 * Ke)
+    colatus.set_option(colatus.OPT_PERSISTENT, 0)
+    ens["persistent_grid_gpairs_s"] = (Ke + 1) * pairs_e / t / 1e9
+    colatus.set_option(colatus.OPT_AUTOTUNE, 1)
+    erun(10 + 2 * Ke, 15 + 2 * Ke)
+    t = erun(15 + 2 * Ke, 15 + 3 * Ke)
+    colatus.set_option(colatus.OPT_AUTOTUNE, 0)
+    ens["autotuned_gpairs_s"] = (Ke + 1) * pairs_e / t / 1e9
+    ens["autotuned_tile"] = list(colatus.tile_config(int(sizes.max()), args.precision))
     out["ensemble_256"] = ens
     print(f"[bench] ensemble: {ens['gpairs_s']:.1f} Gpairs/s "
           f"({ens['speedup_vs_per_box_loop']:.1f}x per-box loop)", file=sys.stderr, flush=True)

@@ -207,8 +207,12 @@ const char *colatus_strerror(int code);
 #define COLATUS_OPT_TILE_R     4  /* >0: force targets per lane (1, 2, 4); 0 = auto  */
 #define COLATUS_OPT_TILE_TPB   5  /* >0: force threads per block (128, 256); 0 = auto */
 #define COLATUS_OPT_TILE_SLICES 6 /* >0: force the number of source slices; 0 = auto  */
-#define COLATUS_OPT_PERSISTENT 7  /* 1: persistent pair-sweep grid pulling work items
-                                     from a device counter (default 1)               */
+#define COLATUS_OPT_PERSISTENT 7  /* 1: persistent pair-sweep grid (about one resident
+                                     round of workgroups) pulling LPT-ordered work
+                                     items from a device counter; 0 (default): one
+                                     workgroup per work item, in the same LPT order,
+                                     left to the hardware dispatcher (measured
+                                     faster on gfx950)                               */
 #define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair loop: 0 = weight m r^-1 (r^-1)^2 and
                                      VALU accumulation; 1 = weight m r^-1 rcp(r^2);
                                      2 = weight r^-3 on the VALU, accumulation of

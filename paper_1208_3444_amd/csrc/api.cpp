@@ -31,7 +31,7 @@ struct Options {
     int64_t tile_r = 0;
     int64_t tile_tpb = 0;
     int64_t tile_slices = 0;
-    int64_t persistent = 1;
+    int64_t persistent = 0;  // one-shot grid measured faster on gfx950
     int64_t pair_form = -1;  // -1: heuristic or tuned
 };
 Options g_opt;
