@@ -469,7 +469,7 @@ hipEvent_t take_event()
 // Forward pair sweep on the workspace's buffers, with the timer if enabled.
 int run_forward_sweep(Workspace *ws, const WorkList &wl, int precision, bool phi,
                       bool mask, const double *x, const double *m, int64_t N, hipStream_t s,
-                      bool zero_counter)
+                      bool zero_counter, int64_t *step_inc = nullptr)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_opt.timer) {
@@ -485,7 +485,8 @@ int run_forward_sweep(Workspace *ws, const WorkList &wl, int precision, bool phi
                                 (int)wl.items.size(), work_counter(ws), g_opt.persistent != 0,
                                 static_cast<const double *>(ws->box_mass.ptr),
                                 static_cast<double *>(ws->part.ptr),
-                                phi ? static_cast<double *>(ws->part_phi.ptr) : nullptr, s));
+                                phi ? static_cast<double *>(ws->part_phi.ptr) : nullptr,
+                                step_inc, s));
     if (e1) {
         CHECK_HIP(hipEventRecord(e1, s));
         g_timer[0].push_back({e0, e1});
@@ -576,7 +577,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                             static_cast<const WorkItem *>(tmp.d_items.ptr), (int)tmp.items.size(),
                             work_counter(ws), g_opt.persistent != 0,
                             static_cast<const double *>(ws->box_mass.ptr),
-                            static_cast<double *>(ws->part.ptr), nullptr, s));
+                            static_cast<double *>(ws->part.ptr), nullptr, nullptr, s));
                     else
                         CHECK_HIP(launch_adjoint_sweep(
                             precision, c, false, x, m, N, 1, x,
@@ -653,9 +654,9 @@ int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, 
     hipStream_t s = P.stream;
     const bool phi = P.diag != nullptr;
     auto body = [&](hipStream_t st) -> int {
-        CHECK_HIP(launch_integrate(base, st));  // advances the step counter
+        CHECK_HIP(launch_integrate(base, st));  // re-arms the work counter
         CHECK_RC(run_forward_sweep(ws, ws->fwd, P.precision, phi, mask, P.x, P.m, P.N, st,
-                                   false));
+                                   false, step_counter(ws)));  // advances the step
         return COLATUS_OK;
     };
     const bool use_graph = g_opt.graph && !g_opt.timer && n_iter >= 8;
@@ -750,9 +751,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.G = P.G;
     A.coef = coef;
     A.step = step_counter(ws);
-    A.done = done_counter(ws);
     A.work_counter = work_counter(ws);
-    A.tick = 1;
     A.first = P.first;
     A.last = P.last;
     A.diag_part = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
@@ -760,7 +759,6 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
-    A.tick = 0;
     CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
     CHECK_HIP(launch_convert(1, p, P.v, P.N, coef, nsteps - 1, s));
     if (diag) {
@@ -1086,9 +1084,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.G = G;
     A.coef = coef;
     A.step = step_counter(ws);
-    A.done = done_counter(ws);
     A.work_counter = work_counter(ws);
-    A.tick = 1;
     A.first = 0;
     A.last = n_steps;
     A.diag_part = nullptr;
@@ -1107,13 +1103,12 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
             CHECK_HIP(hipMemcpyAsync(cx, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
             CHECK_HIP(hipMemcpyAsync(cx + n3, p, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
-        CHECK_HIP(launch_integrate(A, s));  // advances the step counter
+        CHECK_HIP(launch_integrate(A, s));
+        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
     }
     if (xN || vN) {
         CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
-        IntegrateArgs E = A;
-        E.tick = 0;
-        CHECK_HIP(launch_integrate(E, s));  // closing half kick at a_end
+        CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_end
         if (xN)
             CHECK_HIP(hipMemcpyAsync(xN, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (vN)
@@ -1139,7 +1134,8 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
             CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
             IntegrateArgs B = A;
             B.x = xn;
-            CHECK_HIP(launch_integrate(B, s));  // advances the step counter
+            CHECK_HIP(launch_integrate(B, s));
+            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
         }
         // visit x_n for n = hi .. lo+1 (and lo itself in segment 0): every grid
         // point is visited once, x_hi being the unvisited bottom of the segment above

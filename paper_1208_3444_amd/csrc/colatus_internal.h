@@ -58,11 +58,14 @@ constexpr int kDiagW = 10;
 // form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s); form 2: w = r^-3 on
 // the VALU with the accumulation on the matrix cores (forms 1, 2: FP32 only).
 // box_mass[b]: common mass of box b or NaN (see launch_box_mass), or null.
+// step_inc: if non-null, the sweep's first thread adds 1 to *step_inc (the
+// run's step counter; nothing in the sweep reads it).
 hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool with_phi,
                              bool mask_self, const double *x, const double *m,
                              int64_t N, const WorkItem *items, int n_items,
                              int *counter, bool persistent, const double *box_mass,
-                             double *part, double *part_phi, hipStream_t stream);
+                             double *part, double *part_phi, int64_t *step_inc,
+                             hipStream_t stream);
 
 // box_mass[b] = m of box b if all its masses are equal and positive, else NaN.
 hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes,
@@ -113,11 +116,9 @@ struct IntegrateArgs {
     int64_t N;
     double G;
     const StepCoef *coef;  // indexed by (n - first)
-    int64_t *step;         // device step counter n (absolute); advanced by the
-                           // last block to finish (with tick != 0)
-    int *done;             // blocks finished in this launch (zero between launches)
-    int *work_counter;     // pair-sweep work counter, re-armed with the step
-    int tick;              // advance *step and re-arm the counters at the end
+    const int64_t *step;   // device step counter n (absolute), advanced by the
+                           // next pair sweep (or a tick kernel)
+    int *work_counter;     // pair-sweep work counter, re-armed here (or null)
     int64_t first, last;
     double *diag_part;     // [rows][n_blocks][kDiagW] or null
     int precision;         // pair arithmetic of the sweep that wrote part_phi
@@ -125,8 +126,8 @@ struct IntegrateArgs {
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and
-// drift by d_n.  Reads n from *step; with tick, the last block to finish
-// sets *step = n + 1 and zeroes the work counter (graph-safe, no memset).
+// drift by d_n.  Reads n from *step and re-arms the pair-sweep work counter
+// for the sweep that follows (graph-safe, no memset).
 hipError_t launch_integrate(const IntegrateArgs &args, hipStream_t stream);
 
 // *step += 1; *counter = 0.

@@ -114,12 +114,14 @@ __global__ void convert_kernel(int mode, const double *__restrict__ src, double 
     }
 }
 
-// Deterministic tree sum of kDiagW values over a 256-thread block.
+// Deterministic tree sum of kDiagW values over the first kIntBlock threads
+// (every thread of the block calls it; the others contribute nothing).
 __device__ void block_sum_rows(double (&v)[kDiagW], double (*sh)[kIntBlock])
 {
     const int tid = threadIdx.x;
-    for (int q = 0; q < kDiagW; ++q)
-        sh[q][tid] = v[q];
+    if (tid < kIntBlock)
+        for (int q = 0; q < kDiagW; ++q)
+            sh[q][tid] = v[q];
     __syncthreads();
     for (int w = kIntBlock / 2; w > 0; w >>= 1) {
         if (tid < w) {
@@ -173,33 +175,79 @@ __device__ __forceinline__ double box_mass_of(const double *box_mass, int box)
 //   p += k2_{n-1} g                           (closing half kick, n > first)
 //   diagnostics of (x_n, p_n)                 (optional)
 //   p += k1_n g;  x += d_n p                  (opening half kick + drift, n < last)
-__global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
+// The split-source partials of one 64-particle block are summed by
+// kSliceGroups waves in parallel (wave q takes slices q, q + G, q + 2G, ...
+// in order) and combined in LDS in the fixed order q = 0, 1, ..., G-1, so the
+// result is deterministic; this keeps enough loads in flight to stream the
+// partials at cache/HBM bandwidth instead of one latency-bound thread per
+// particle.
+constexpr int kSliceGroups = 4;
+constexpr int kFinalizeThreads = kIntBlock * kSliceGroups;
+
+// Sum of n_comp strided planes (k * stride + c * N) over this thread's slice
+// group, then the fixed-order combine; valid in wave 0 afterwards.
+template <int NC>
+__device__ __forceinline__ void grouped_slice_sum(const double *__restrict__ base, int S,
+                                                  int64_t stride, int64_t N, bool valid,
+                                                  double (*sh)[kSliceGroups][kIntBlock],
+                                                  double (&out)[NC])
 {
+    const int p = threadIdx.x & (kIntBlock - 1), q = threadIdx.x / kIntBlock;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        acc[c] = 0.0;
+    if (valid) {
+#pragma unroll 4
+        for (int k = q; k < S; k += kSliceGroups) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                acc[c] += base[(int64_t)k * stride + (int64_t)c * N];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        sh[c][q][p] = acc[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double t = sh[c][0][p];
+#pragma unroll
+        for (int g = 1; g < kSliceGroups; ++g)
+            t += sh[c][g][p];
+        out[c] = t;
+    }
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateArgs A)
+{
+    __shared__ double shs[4][kSliceGroups][kIntBlock];
     __shared__ double sh[kDiagW][kIntBlock];
     const IntBlock blk = A.blocks[blockIdx.x];
-    const int64_t i = blk.i0 + threadIdx.x;
+    const int pl = threadIdx.x & (kIntBlock - 1);
+    const bool lead = threadIdx.x < kIntBlock;
+    const int64_t i = blk.i0 + pl;
     const bool valid = i < blk.i1;
     const int64_t n = *A.step;
     const int64_t row = n - A.first;
     const int64_t N = A.N;
     const int S = blk.n_slices;
 
+    double gs[3];
+    grouped_slice_sum<3>(A.part + i, S, 3 * N, N, valid, shs, gs);
+    double phs = 0.0;
+    if (A.diag_part) {
+        __syncthreads();
+        double t[1];
+        grouped_slice_sum<1>(A.part_phi + i, S, N, N, valid, shs, t);
+        phs = t[0];
+    }
+
     double v[kDiagW];
     for (int q = 0; q < kDiagW; ++q)
         v[q] = 0.0;
-    if (valid) {
-        // fixed-order sum of the slice partials; the loads are independent,
-        // unrolled so that many are in flight per thread
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-        const double *pp = A.part + i;
-        const int64_t stride = 3 * N;
-#pragma unroll 8
-        for (int k = 0; k < S; ++k) {
-            g0 += pp[(int64_t)k * stride];
-            g1 += pp[(int64_t)k * stride + N];
-            g2 += pp[(int64_t)k * stride + 2 * N];
-        }
-        const double g[3] = {A.G * g0, A.G * g1, A.G * g2};
+    if (lead && valid) {
+        const double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
         double p[3] = {A.p[i], A.p[N + i], A.p[2 * N + i]};
         double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
         if (n > A.first) {
@@ -209,10 +257,6 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
         }
         if (A.diag_part) {
             const double mi = A.m[i];
-            double phs = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < S; ++k)
-                phs += A.part_phi[(int64_t)k * N + i];
             phs -= self_potential(A.precision, mi, blk.eps, box_mass_of(A.box_mass, blk.box));
             const double phi = -A.G * phs;
             v[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
@@ -250,21 +294,8 @@ __global__ __launch_bounds__(kIntBlock) void integrate_kernel(IntegrateArgs A)
                 out[q] = v[q];
         }
     }
-    if (A.tick) {
-        // every block has read *step before it arrives here; the last to
-        // arrive advances the step and re-arms the counters for the next one
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            const int arrived = atomicAdd(A.done, 1);
-            if (arrived == A.n_blocks - 1) {
-                *A.step = n + 1;
-                *A.work_counter = 0;
-                *A.done = 0;
-                __threadfence();
-            }
-        }
-    }
+    if (A.work_counter && blockIdx.x == 0 && threadIdx.x == 0)
+        *A.work_counter = 0;
 }
 
 __global__ void tick_kernel(int64_t *step, int *counter)
@@ -329,71 +360,80 @@ __global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int row
     }
 }
 
-// acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - m / eps).
-__global__ __launch_bounds__(kIntBlock) void forces_finalize_kernel(
+// acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - self term).
+__global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     int precision, const double *__restrict__ box_mass, const IntBlock *__restrict__ blocks,
-    const double *__restrict__ part,
-    const double *__restrict__ part_phi, const double *__restrict__ m, int64_t N, double G,
-    double scale, double *__restrict__ acc, double *__restrict__ phi)
+    const double *__restrict__ part, const double *__restrict__ part_phi,
+    const double *__restrict__ m, int64_t N, double G, double scale, double *__restrict__ acc,
+    double *__restrict__ phi)
 {
+    __shared__ double shs[4][kSliceGroups][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
-    const int64_t i = blk.i0 + threadIdx.x;
-    if (i >= blk.i1)
-        return;
-    for (int c = 0; c < 3; ++c) {
-        double s = 0.0;
-        for (int k = 0; k < blk.n_slices; ++k)
-            s += part[((int64_t)k * 3 + c) * N + i];
-        acc[(int64_t)c * N + i] = scale * s;
-    }
+    const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
+    const bool valid = i < blk.i1;
+    const bool lead = threadIdx.x < kIntBlock;
+    double g[3];
+    grouped_slice_sum<3>(part + i, blk.n_slices, 3 * N, N, valid, shs, g);
+    if (lead && valid)
+        for (int c = 0; c < 3; ++c)
+            acc[(int64_t)c * N + i] = scale * g[c];
     if (phi) {
-        double s = 0.0;
-        for (int k = 0; k < blk.n_slices; ++k)
-            s += part_phi[(int64_t)k * N + i];
-        s -= self_potential(precision, m[i], blk.eps, box_mass_of(box_mass, blk.box));
-        phi[i] = -G * s;
+        __syncthreads();
+        double t[1];
+        grouped_slice_sum<1>(part_phi + i, blk.n_slices, N, N, valid, shs, t);
+        if (lead && valid)
+            phi[i] = -G * (t[0] - self_potential(precision, m[i], blk.eps,
+                                                  box_mass_of(box_mass, blk.box)));
     }
 }
 
 // out[c] = G * sum_s part[s][c]  (part [S][n_cot][3][N]).
-__global__ __launch_bounds__(kIntBlock) void vjp_finalize_kernel(
+__global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
     const IntBlock *__restrict__ blocks, const double *__restrict__ part, int64_t N, int n_cot,
     double G, double *__restrict__ out)
 {
+    __shared__ double shs[4][kSliceGroups][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
-    const int64_t i = blk.i0 + threadIdx.x;
-    if (i >= blk.i1)
-        return;
-    for (int c = 0; c < n_cot; ++c)
-        for (int q = 0; q < 3; ++q) {
-            double s = 0.0;
-            for (int k = 0; k < blk.n_slices; ++k)
-                s += part[(((int64_t)k * n_cot + c) * 3 + q) * N + i];
-            out[((int64_t)c * 3 + q) * N + i] = G * s;
-        }
+    const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
+    const bool valid = i < blk.i1;
+    const bool lead = threadIdx.x < kIntBlock;
+    for (int c = 0; c < n_cot; ++c) {
+        double w[3];
+        grouped_slice_sum<3>(part + (int64_t)c * 3 * N + i, blk.n_slices,
+                             (int64_t)n_cot * 3 * N, N, valid, shs, w);
+        if (lead && valid)
+            for (int q = 0; q < 3; ++q)
+                out[((int64_t)c * 3 + q) * N + i] = G * w[q];
+        __syncthreads();
+    }
 }
 
 // lam_x += cw * G sum_s part[s];  then (do_drift) lam_p += dnext * lam_x.
-__global__ __launch_bounds__(kIntBlock) void adjoint_update_kernel(
+__global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
     const IntBlock *__restrict__ blocks, const double *__restrict__ part, int64_t N, int n_cot,
     double G, double cw, double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift,
     double dnext)
 {
+    __shared__ double shs[4][kSliceGroups][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
-    const int64_t i = blk.i0 + threadIdx.x;
-    if (i >= blk.i1)
-        return;
-    for (int c = 0; c < n_cot; ++c)
-        for (int q = 0; q < 3; ++q) {
-            double s = 0.0;
-            for (int k = 0; k < blk.n_slices; ++k)
-                s += part[(((int64_t)k * n_cot + c) * 3 + q) * N + i];
-            const int64_t o = ((int64_t)c * 3 + q) * N + i;
-            const double lx = lam_x[o] + cw * (G * s);
-            lam_x[o] = lx;
-            if (do_drift)
-                lam_p[o] += dnext * lx;
+    const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
+    const bool valid = i < blk.i1;
+    const bool lead = threadIdx.x < kIntBlock;
+    for (int c = 0; c < n_cot; ++c) {
+        double w[3];
+        grouped_slice_sum<3>(part + (int64_t)c * 3 * N + i, blk.n_slices,
+                             (int64_t)n_cot * 3 * N, N, valid, shs, w);
+        if (lead && valid) {
+            for (int q = 0; q < 3; ++q) {
+                const int64_t o = ((int64_t)c * 3 + q) * N + i;
+                const double lx = lam_x[o] + cw * (G * w[q]);
+                lam_x[o] = lx;
+                if (do_drift)
+                    lam_p[o] += dnext * lx;
+            }
         }
+        __syncthreads();
+    }
 }
 
 __global__ void scale_kernel(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
@@ -429,7 +469,8 @@ hipError_t launch_convert(int mode, const double *src, double *dst, int64_t N,
 
 hipError_t launch_integrate(const IntegrateArgs &args, hipStream_t stream)
 {
-    hipLaunchKernelGGL(integrate_kernel, dim3(args.n_blocks), dim3(kIntBlock), 0, stream, args);
+    hipLaunchKernelGGL(integrate_kernel, dim3(args.n_blocks), dim3(kFinalizeThreads), 0, stream,
+                       args);
     return hipGetLastError();
 }
 
@@ -454,7 +495,7 @@ hipError_t launch_forces_finalize(int precision, const double *box_mass, const I
                                   const double *m, int64_t N, double G, double scale,
                                   double *acc, double *phi, hipStream_t stream)
 {
-    hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream,
+    hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
                        precision, box_mass, blocks, part, part_phi, m, N, G, scale, acc, phi);
     return hipGetLastError();
 }
@@ -465,7 +506,8 @@ hipError_t launch_vjp_finalize(int precision, const IntBlock *blocks, int n_bloc
 {
     (void)precision;
     (void)n_slices;
-    hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream, blocks,
+    hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
+                       blocks,
                        part, N, n_cot, G, out);
     return hipGetLastError();
 }
@@ -476,7 +518,7 @@ hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const dou
                                  hipStream_t stream)
 {
     (void)n_slices;
-    hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kIntBlock), 0, stream,
+    hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
                        blocks, part, N, n_cot, G, cw, lam_x, lam_p, do_drift, dnext);
     return hipGetLastError();
 }

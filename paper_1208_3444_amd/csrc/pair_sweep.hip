@@ -174,7 +174,7 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
     const double *__restrict__ x, const double *__restrict__ m, int64_t N,
     const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
     int persistent, const double *__restrict__ box_mass, double *__restrict__ part,
-    double *__restrict__ part_phi)
+    double *__restrict__ part_phi, int64_t *__restrict__ step_inc)
 {
     using V = typename V4<T>::type;
     __shared__ V tile[TPB];
@@ -182,6 +182,8 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const double *X = x, *Y = x + N, *Z = x + 2 * N;
+    if (step_inc && blockIdx.x == 0 && tid == 0)
+        *step_inc += 1;
 
     for (int iter = 0;; ++iter) {
         const int it = next_item(persistent, counter, &s_item, iter);
@@ -516,7 +518,8 @@ template <int ACC, int R, int TPB, bool PHI, bool MASK>
 __global__ __launch_bounds__(TPB) void pair_sweep_mfma_kernel(
     const double *__restrict__ x, const double *__restrict__ m, int64_t N,
     const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
-    int persistent, double *__restrict__ part, double *__restrict__ part_phi)
+    int persistent, double *__restrict__ part, double *__restrict__ part_phi,
+    int64_t *__restrict__ step_inc)
 {
     constexpr int NW = TPB / 64;
     __shared__ float4 tile[TPB];   // relative position, mass (VALU operands)
@@ -527,6 +530,8 @@ __global__ __launch_bounds__(TPB) void pair_sweep_mfma_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const double *X = x, *Y = x + N, *Z = x + 2 * N;
+    if (step_inc && blockIdx.x == 0 && tid == 0)
+        *step_inc += 1;
 
     for (int iter = 0;; ++iter) {
         const int it = next_item(persistent, counter, &s_item, iter);
@@ -726,14 +731,14 @@ int persistent_grid(K kernel, int tpb, size_t dyn_lds, int n_items)
 template <typename T, int ACC, int R, int TPB, bool PHI, bool MASK, int FORM>
 hipError_t launch_fwd(const double *x, const double *m, int64_t N, const WorkItem *items,
                       int n_items, int *counter, bool persistent, const double *box_mass,
-                      double *part, double *part_phi, hipStream_t stream)
+                      double *part, double *part_phi, int64_t *step_inc, hipStream_t stream)
 {
     auto k = pair_sweep_kernel<T, ACC, R, TPB, PHI, MASK, FORM>;
     int grid = persistent ? persistent_grid(k, TPB, 0, n_items) : n_items;
     if (grid <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, stream, x, m, N, items, n_items, counter,
-                       persistent ? 1 : 0, box_mass, part, part_phi);
+                       persistent ? 1 : 0, box_mass, part, part_phi, step_inc);
     return hipGetLastError();
 }
 
@@ -746,6 +751,7 @@ struct FwdArgs {
     bool persistent;
     const double *box_mass;
     double *part, *part_phi;
+    int64_t *step_inc;
     hipStream_t s;
 };
 
@@ -755,7 +761,7 @@ hipError_t dispatch_fwd_flags(bool phi, bool mask, const FwdArgs &a)
 #define COLATUS_FWD_F(P, M)                                                                   \
     return launch_fwd<T, ACC, R, TPB, P, M, FORM>(a.x, a.m, a.N, a.items, a.n_items, a.counter, \
                                                   a.persistent, a.box_mass, a.part, a.part_phi, \
-                                                  a.s);
+                                                  a.step_inc, a.s);
     if (phi) {
         if (mask) {
             COLATUS_FWD_F(true, true)
@@ -793,7 +799,7 @@ hipError_t launch_mfma(const FwdArgs &a)
     if (grid <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, a.s, a.x, a.m, a.N, a.items, a.n_items,
-                       a.counter, a.persistent ? 1 : 0, a.part, a.part_phi);
+                       a.counter, a.persistent ? 1 : 0, a.part, a.part_phi, a.step_inc);
     return hipGetLastError();
 }
 
@@ -906,12 +912,12 @@ hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool w
                              bool mask_self, const double *x, const double *m, int64_t N,
                              const WorkItem *items, int n_items, int *counter, bool persistent,
                              const double *box_mass, double *part, double *part_phi,
-                             hipStream_t stream)
+                             int64_t *step_inc, hipStream_t stream)
 {
     if (n_items <= 0)
         return hipSuccess;
     const FwdArgs a{x, m, N, items, n_items, counter, persistent, box_mass, part, part_phi,
-                    stream};
+                    step_inc, stream};
     switch (precision) {
     case kFP64:
         return dispatch_fwd_shape<double, kDirect, 0>(cfg, with_phi, mask_self, a);
