@@ -555,7 +555,7 @@ __global__ __launch_bounds__(TPB) void pair_sweep_mfma_kernel(
 
         float xi[R], yi[R], zi[R], ph[R], hp[R], lp[R];
         double bp[R];
-        v4f acc[R], hi[R], lo[R];
+        v4f acc[R], acc2[R], hi[R], lo[R];
         double fold[R][4];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -565,6 +565,7 @@ __global__ __launch_bounds__(TPB) void pair_sweep_mfma_kernel(
             ph[r] = hp[r] = lp[r] = 0.0f;
             bp[r] = 0.0;
             acc[r] = v4f{0.f, 0.f, 0.f, 0.f};
+            acc2[r] = v4f{0.f, 0.f, 0.f, 0.f};
             hi[r] = v4f{0.f, 0.f, 0.f, 0.f};
             lo[r] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -615,11 +616,21 @@ __global__ __launch_bounds__(TPB) void pair_sweep_mfma_kernel(
                         if constexpr (MASK)
                             rinv = s > 0.0f ? rinv : 0.0f;
                         const float w3 = rinv * (rinv * rinv);
-                        acc[r] = __builtin_amdgcn_mfma_f32_4x4x1f32(w3, bj, acc[r], 0, 0, 0);
+                        // two accumulator chains per group (even / odd sources)
+                        // so consecutive matrix instructions are independent
+                        if (u & 1)
+                            acc2[r] = __builtin_amdgcn_mfma_f32_4x4x1f32(w3, bj, acc2[r], 0, 0, 0);
+                        else
+                            acc[r] = __builtin_amdgcn_mfma_f32_4x4x1f32(w3, bj, acc[r], 0, 0, 0);
                         if constexpr (PHI)
                             ph[r] = fmaf(pj.w, rinv, ph[r]);
                     }
                 }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r] += acc2[r];
+                acc2[r] = v4f{0.f, 0.f, 0.f, 0.f};
             }
             if constexpr (ACC == kTwoSum) {
 #pragma unroll
