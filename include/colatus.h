@@ -199,8 +199,9 @@ const char *colatus_strerror(int code);
 /* ---- tuning, timing and housekeeping ----------------------------------- */
 #define COLATUS_OPT_GRAPH      1  /* 1: capture the repeated step of colatus_run in a
                                      hipGraph and replay it (default 1)              */
-#define COLATUS_OPT_TIMER      2  /* 1: bracket every pair-sweep launch with hipEvents
-                                     on its stream (default 0)                       */
+#define COLATUS_OPT_TIMER      2  /* 1: bracket every pair-sweep and integrator launch
+                                     with hipEvents on its stream (default 0; the run
+                                     then launches eagerly instead of from a graph)  */
 #define COLATUS_OPT_AUTOTUNE   3  /* 1: time candidate tile shapes on first use of an
                                      (N bucket, precision) and keep the fastest
                                      (default 0: built-in heuristic)                 */
@@ -223,9 +224,10 @@ const char *colatus_strerror(int code);
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 
-/* Pair-sweep timer: sum of hipEvent durations of the forward (kind 0) or
- * adjoint (kind 1) pair-sweep launches recorded since the last reset, and
- * their count.  Synchronises the recorded events.  reset != 0 clears.     */
+/* Kernel timer: sum of hipEvent durations (on the launching stream) of the
+ * forward pair-sweep (kind 0), adjoint pair-sweep (kind 1) or run
+ * integrator (kind 2) launches recorded since the last reset, and their
+ * count.  Synchronises the recorded events.  reset != 0 clears.           */
 int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset);
 
 /* Tile shape the library would use (or has tuned) for N particles in one

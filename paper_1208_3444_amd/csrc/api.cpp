@@ -450,7 +450,7 @@ int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, cons
 struct TimerRec {
     hipEvent_t start, stop;
 };
-std::vector<TimerRec> g_timer[2];
+std::vector<TimerRec> g_timer[3];  // forward sweep, adjoint sweep, integrator
 std::vector<hipEvent_t> g_event_pool;
 
 hipEvent_t take_event()
@@ -464,6 +464,24 @@ hipEvent_t take_event()
     if (hipEventCreate(&e) != hipSuccess)
         return nullptr;
     return e;
+}
+
+// Integrator launch, bracketed by hipEvents when the timer is enabled.
+int run_integrate(const IntegrateArgs &A, hipStream_t s)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_opt.timer) {
+        e0 = take_event();
+        e1 = take_event();
+    }
+    if (e0)
+        CHECK_HIP(hipEventRecord(e0, s));
+    CHECK_HIP(launch_integrate(A, s));
+    if (e1) {
+        CHECK_HIP(hipEventRecord(e1, s));
+        g_timer[2].push_back({e0, e1});
+    }
+    return COLATUS_OK;
 }
 
 // Forward pair sweep on the workspace's buffers, with the timer if enabled.
@@ -654,7 +672,7 @@ int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, 
     hipStream_t s = P.stream;
     const bool phi = P.diag != nullptr;
     auto body = [&](hipStream_t st) -> int {
-        CHECK_HIP(launch_integrate(base, st));  // re-arms the work counter
+        CHECK_RC(run_integrate(base, st));  // re-arms the work counter
         CHECK_RC(run_forward_sweep(ws, ws->fwd, P.precision, phi, mask, P.x, P.m, P.N, st,
                                    false, step_counter(ws)));  // advances the step
         return COLATUS_OK;
@@ -759,7 +777,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
-    CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
+    CHECK_RC(run_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
     CHECK_HIP(launch_convert(1, p, P.v, P.N, coef, nsteps - 1, s));
     if (diag) {
         CHECK_HIP(launch_diag_reduce(static_cast<const double *>(ws->diag_part.ptr), (int)rows,
@@ -865,7 +883,7 @@ int colatus_get_option(int key, int64_t *value)
 
 int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset)
 {
-    if (kind < 0 || kind > 1 || !total_ms || !launches)
+    if (kind < 0 || kind > 2 || !total_ms || !launches)
         return COLATUS_EINVAL;
     std::lock_guard<std::mutex> lock(g_mu);
     double tot = 0.0;
