@@ -305,23 +305,25 @@ int n_target_blocks(const Boxes &b, int ti)
 TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu)
 {
     TileCfg c;
+    int per_cu = 8;
     if (kind == 0) {
         if (precision == COLATUS_FP64) {
             c.R = 2;
             c.tpb = 256;
-        } else if (b.max_n >= 4096) {
-            c.R = 2;
-            c.tpb = 256;
+            per_cu = 16;
         } else {
-            c.R = 2;
-            c.tpb = 128;
+            // one target per lane and many small items measured fastest with
+            // the one-shot grid (32^3: 128 target blocks x 64 slices)
+            c.R = 1;
+            c.tpb = 256;
+            per_cu = 32;
         }
     } else {
         c.R = 1;
         c.tpb = 256;
     }
     const int tb = n_target_blocks(b, c.R * c.tpb);
-    const int want = 8 * n_cu;
+    const int want = per_cu * n_cu;
     int s = (want + tb - 1) / tb;
     const int64_t max_s = std::max<int64_t>(1, b.max_n / (2 * c.tpb));
     s = (int)std::max<int64_t>(1, std::min<int64_t>(s, max_s));

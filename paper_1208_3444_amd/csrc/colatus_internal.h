@@ -39,6 +39,18 @@ struct StepCoef {
 
 enum Precision { kFP64 = 0, kMixedTwoSum = 1, kMixedF64Acc = 2, kFP32 = 3 };
 
+// FP64 1/sqrt(s) for s > 0 finite: the hardware estimate (v_rsq_f64, about
+// 5e-8 relative on gfx950) refined by one Newton step,
+//   y1 = y0 + (y0 / 2) (1 - s y0^2),
+// which squares the error (measured maximum 4e-15 relative over 2^-60..2^20).
+// Every FP64 kernel that must reproduce another's r^-1 bit for bit uses this.
+__device__ __forceinline__ double rsqrt_refined(double s)
+{
+    const double y0 = __builtin_amdgcn_rsq(s);
+    const double e = fma(-s * y0, y0, 1.0);
+    return fma(0.5 * y0, e, y0);
+}
+
 // Shape of one pair-sweep launch.
 struct TileCfg {
     int R;        // targets per lane

@@ -156,7 +156,7 @@ __device__ __forceinline__ double self_potential(int precision, double m, double
         return 0.0;
     const double eps2 = eps * eps;
     if (precision == kFP64)
-        return m * rsqrt(eps2);
+        return m * rsqrt_refined(eps2);
     const float r = __builtin_amdgcn_rsqf((float)eps2);
     if (!isnan(mbox))
         return mbox * (double)r;

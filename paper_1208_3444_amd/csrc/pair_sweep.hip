@@ -15,8 +15,8 @@
 //     arithmetic keeps the relative accuracy of the separation itself;
 //   * per-tile FP32 partial sums are folded into FP64 or an unevaluated FP32
 //     (hi, lo) pair with TwoSum (Knuth), bounding the accumulation error;
-//   * rsqrt is the hardware v_rsq_f32 in FP32 and a Newton-refined rsqrt in
-//     FP64; no MFMA: the pair interaction is not a dense contraction.
+//   * rsqrt is the hardware v_rsq_f32 in FP32 and v_rsq_f64 refined by one
+//     Newton step in FP64; no MFMA: the pair interaction is not a dense contraction.
 //
 // The persistent variant launches about one grid of resident workgroups and
 // pulls work items from a device counter until none are left (every
@@ -35,7 +35,7 @@ template <> struct V4<float> { using type = float4; };
 template <> struct V4<double> { using type = double4; };
 
 __device__ __forceinline__ float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
-__device__ __forceinline__ double rsqrt_t(double s) { return rsqrt(s); }
+__device__ __forceinline__ double rsqrt_t(double s) { return rsqrt_refined(s); }
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
@@ -125,7 +125,7 @@ __device__ __forceinline__ int next_item(int persistent, int *counter, int *s_it
 // ---------------------------------------------------------------------------
 template <typename T> __device__ __forceinline__ T pad_coord();
 template <> __device__ __forceinline__ float pad_coord<float>() { return 1e30f; }
-template <> __device__ __forceinline__ double pad_coord<double>() { return 1e300; }
+template <> __device__ __forceinline__ double pad_coord<double>() { return 1e150; }
 
 template <typename T> __device__ __forceinline__ T rcp_t(T s);
 template <> __device__ __forceinline__ float rcp_t<float>(float s) { return __builtin_amdgcn_rcpf(s); }
@@ -234,8 +234,8 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
                 v.z = (T)(Z[j] - cz);
                 v.w = (T)m[j];
             } else {
-                // padding: so far away that s overflows to +inf, r^-1 = 0 and
-                // the pair adds exactly 0 in every form (and zero mass)
+                // padding: so far away that the pair adds nothing (FP32: s
+                // overflows to +inf and r^-1 = 0; FP64: r^-3 underflows to 0)
                 v.x = v.y = v.z = pad_coord<T>();
                 v.w = (T)0;
             }

@@ -155,7 +155,7 @@ def test_options_and_tile_config():
     assert L.colatus_set_option(8, 3) == EINVAL
     assert L.colatus_set_option(4, 3) == EINVAL
     assert L.colatus_set_option(99, 0) == EINVAL
-    assert colatus.tile_config(32768, "mixed") == (2, 256, 32, 0)
+    assert colatus.tile_config(32768, "mixed") == (1, 256, 64, 0)
     assert colatus.tile_config(32768, "fp64")[0:2] == (2, 256)
     colatus.set_option(colatus.OPT_TILE_SLICES, 3)
     colatus.set_option(colatus.OPT_PAIR_FORM, 2)

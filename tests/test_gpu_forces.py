@@ -186,7 +186,7 @@ def test_alternative_pair_forms_match_oracle(dev, form):
             got = _gpu_forces(x, m, 0.01, dev, "mixed_twosum")
             ref = oracle.forces(x, m, 0.01)
             scale = _term_scale(x, m, 0.01)
-            assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 1e-6
+            assert np.max(np.linalg.norm(got - ref, axis=0) / scale) <= 3e-6
         # softening zero masks the self pair
         x, m = inputs.random_cloud(300, 7, scale=0.5)
         got = _gpu_forces(x, m, 0.0, dev, "mixed_twosum")
