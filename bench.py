@@ -69,6 +69,8 @@ def parse():
     p.add_argument("--precision", default="mixed_twosum")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--ftle", action="store_true",
+                   help="also time the 64-tracer FTLE (192 cotangents, 200 steps)")
     p.add_argument("--cpu-sample-steps", type=int, default=24)
     p.add_argument("--calibration-copy-mib", type=int, default=0,
                    help="first run one plain elementwise pass over this many MiB (read "
@@ -244,6 +246,53 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
                     "flops_per_adjoint_pair": FLOPS_PER_PAIR_ADJ}
         print(f"[bench] {key}: {out[key]['gpairs_s']:.1f} Gpairs/s", file=sys.stderr,
               flush=True)
+
+    # the full adjoint workload: 200 steps from a = 0.2, checkpoints every 20,
+    # the tracers' summed squared final velocity (one cotangent)
+    x4, v4, m4 = (torch.from_numpy(a.copy()).to(dev) for a in (wa.x, va, wa.m))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colatus.adjoint(x4, v4, m4, wa.eps, wa.G, wa.cosmo, wa.a_begin, wa.a_end, wa.n_steps,
+                    lx, lv, checkpoint_every=wa.extra["checkpoint_every"],
+                    precision=args.precision)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    nS = wa.n_steps
+    out["adjoint_200_steps"] = {
+        "seconds": t, "forward_sweeps": 2 * nS + 1, "adjoint_sweeps": nS + 1,
+        "gpairs_s": (3 * nS + 2) * pairs / t / 1e9,
+        "tflops": (FLOPS_PER_PAIR * (2 * nS + 1) + FLOPS_PER_PAIR_ADJ * (nS + 1)) * pairs / t
+        / 1e12}
+    if args.ftle:
+        tr = [int(i) for i in wa.extra["tracers"]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam_t, lam_lna, _ = colatus.ftle(x4, v4, m4, wa.eps, wa.G, wa.cosmo, wa.a_begin,
+                                         wa.a_end, wa.n_steps, tr,
+                                         checkpoint_every=wa.extra["checkpoint_every"],
+                                         precision=args.precision)
+        t = time.perf_counter() - t0
+        out["ftle_192_cotangents"] = {"seconds": t, "tracers": len(tr),
+                                      "lambda_per_ln_a_median": float(np.median(lam_lna)),
+                                      "lambda_per_ln_a_max": float(np.max(lam_lna))}
+    print(f"[bench] adjoint 200 steps: {out['adjoint_200_steps']['seconds']:.3f} s",
+          file=sys.stderr, flush=True)
+
+    # single force evaluation at N = 64^3 in each precision
+    ws3 = inputs.precision_sweep(64)
+    x3, m3 = torch.from_numpy(ws3.x).to(dev), torch.from_numpy(ws3.m).to(dev)
+    pairs3 = float(ws3.N) ** 2
+    sweep = {}
+    for prec in ("fp32", "mixed_twosum", "mixed_f64acc", "fp64"):
+        colatus.forces(x3, m3, ws3.eps, a=0.5, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            colatus.forces(x3, m3, ws3.eps, a=0.5, precision=prec)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 3
+        sweep[prec] = {"ms": 1e3 * t, "gpairs_s": pairs3 / t / 1e9}
+    out["precision_sweep_64cubed"] = sweep
 
     # ragged ensemble: 256 boxes, N log-uniform in [512, 8192], one launch per step
     e = inputs.ragged_ensemble()

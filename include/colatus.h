@@ -214,13 +214,11 @@ const char *colatus_strerror(int code);
                                      workgroup per work item, in the same LPT order,
                                      left to the hardware dispatcher (measured
                                      faster on gfx950)                               */
-#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair loop: 0 = weight m r^-1 (r^-1)^2 and
-                                     VALU accumulation; 1 = weight m r^-1 rcp(r^2);
-                                     2 = weight r^-3 on the VALU, accumulation of
-                                     w (m x, m y, m z, m) on the matrix cores
-                                     (v_mfma_f32_4x4x1f32); -1 (default) = the
-                                     heuristic's or the autotuner's choice.  FP64
-                                     always uses 0                                   */
+#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair weight m r^-3: 0 = m r^-1 (r^-1)^2,
+                                     1 = m r^-1 rcp(r^2) (one VALU multiply fewer,
+                                     one more transcendental; measured slower);
+                                     -1 (default) = the heuristic's or the
+                                     autotuner's choice.  FP64 always uses 0         */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

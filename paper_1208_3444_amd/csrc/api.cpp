@@ -560,8 +560,8 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
             std::vector<TileCfg> cand;
             if (kind == 0) {
                 const bool fp32 = precision != COLATUS_FP64;
-                for (int form : {0, 2}) {
-                    if (form == 2 && !fp32)
+                for (int form : {0, 1}) {
+                    if (form == 1 && !fp32)
                         continue;
                     for (int r : {1, 2, 4})
                         for (int t : {128, 256})
@@ -857,7 +857,7 @@ int colatus_set_option(int key, int64_t value)
         return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: g_opt.persistent = value != 0; return COLATUS_OK;
     case COLATUS_OPT_PAIR_FORM:
-        if (value < -1 || value > 2)
+        if (value < -1 || value > 1)
             return COLATUS_EINVAL;
         g_opt.pair_form = value;
         return COLATUS_OK;

@@ -67,8 +67,7 @@ constexpr int kDiagW = 10;
 
 // Forward pair sweep: part[s][3][N] = sum over the item's sources of
 // m_j (x_j - x_k) r^-3, and part_phi[s][N] = sum m_j / r when with_phi.
-// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s); form 2: w = r^-3 on
-// the VALU with the accumulation on the matrix cores (forms 1, 2: FP32 only).
+// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s) (FP32 only).
 // box_mass[b]: common mass of box b or NaN (see launch_box_mass), or null.
 // step_inc: if non-null, the sweep's first thread adds 1 to *step_inc (the
 // run's step counter; nothing in the sweep reads it).

@@ -497,213 +497,6 @@ __global__ __launch_bounds__(TPB) void adjoint_sweep_kernel(
     }
 }
 
-// ---------------------------------------------------------------------------
-// Forward sweep, FP32 pairs with the accumulation on the matrix cores.
-//
-// The pair sum splits as  sum_j w_kj m_j (x_j - c) - (x_k - c) sum_j w_kj m_j
-// with w_kj = r^-3 and c the block centre.  The VALU computes w for the
-// lane's own target (3 subtractions, 3 FMAs, v_rsq, 2 multiplies); one
-// v_mfma_f32_4x4x1f32 per source and target group then adds w times the
-// source's (m x, m y, m z, m) to 16 independent 4x4 blocks: block b holds
-// the 4 targets of lanes 4b..4b+3, column q the component q of the source.
-// Lane l supplies A = its own w and B = component l%4 of the source, and
-// receives D[r] = block (l/4), target row r, column l%4.  At the end of the
-// item an LDS exchange gives every lane its own target's four sums and the
-// subtraction is done in FP64.  Per-tile folding (TwoSum / FP64) as in the
-// VALU sweep.
-// ---------------------------------------------------------------------------
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <int ACC, int R, int TPB, bool PHI, bool MASK>
-__global__ __launch_bounds__(TPB) void pair_sweep_mfma_kernel(
-    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
-    const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
-    int persistent, double *__restrict__ part, double *__restrict__ part_phi,
-    int64_t *__restrict__ step_inc)
-{
-    constexpr int NW = TPB / 64;
-    __shared__ float4 tile[TPB];   // relative position, mass (VALU operands)
-    __shared__ float4 btile[TPB];  // m x, m y, m z, m (matrix-core B operand)
-    __shared__ double xch[NW][64][4];
-    __shared__ double red[NW][6];
-    __shared__ int s_item;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const double *X = x, *Y = x + N, *Z = x + 2 * N;
-    if (step_inc && blockIdx.x == 0 && tid == 0)
-        *step_inc += 1;
-
-    for (int iter = 0;; ++iter) {
-        const int it = next_item(persistent, counter, &s_item, iter);
-        if (it >= n_items)
-            break;
-        const WorkItem w = items[it];
-
-        double tx[R], ty[R], tz[R];
-        bool valid[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t i = w.i0 + tid + (int64_t)r * TPB;
-            valid[r] = i < w.i1;
-            const int64_t ii = valid[r] ? i : w.i0;
-            tx[r] = X[ii];
-            ty[r] = Y[ii];
-            tz[r] = Z[ii];
-        }
-        double cx, cy, cz;
-        block_centre<TPB, R>(tx, ty, tz, valid, red, cx, cy, cz);
-
-        float xi[R], yi[R], zi[R], ph[R], hp[R], lp[R];
-        double bp[R];
-        v4f acc[R], acc2[R], hi[R], lo[R];
-        double fold[R][4];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            xi[r] = (float)(tx[r] - cx);
-            yi[r] = (float)(ty[r] - cy);
-            zi[r] = (float)(tz[r] - cz);
-            ph[r] = hp[r] = lp[r] = 0.0f;
-            bp[r] = 0.0;
-            acc[r] = v4f{0.f, 0.f, 0.f, 0.f};
-            acc2[r] = v4f{0.f, 0.f, 0.f, 0.f};
-            hi[r] = v4f{0.f, 0.f, 0.f, 0.f};
-            lo[r] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                fold[r][q] = 0.0;
-        }
-        const float eps2 = (float)w.eps2;
-        const float *bcol = reinterpret_cast<const float *>(btile) + (lane & 3);
-
-        for (int64_t jt = w.j0; jt < w.j1; jt += TPB) {
-            const int64_t j = jt + tid;
-            float4 v, bv;
-            if (j < w.j1) {
-                v.x = (float)(X[j] - cx);
-                v.y = (float)(Y[j] - cy);
-                v.z = (float)(Z[j] - cz);
-                v.w = (float)m[j];
-                bv.x = v.w * v.x;
-                bv.y = v.w * v.y;
-                bv.z = v.w * v.z;
-                bv.w = v.w;
-            } else {
-                // padding: s overflows to +inf, w = 0, and the B row is zero
-                v.x = v.y = v.z = 1e30f;
-                v.w = 0.0f;
-                bv.x = bv.y = bv.z = bv.w = 0.0f;
-            }
-            __syncthreads();
-            tile[tid] = v;
-            btile[tid] = bv;
-            __syncthreads();
-            const int nt = (int)((w.j1 - jt) < TPB ? (w.j1 - jt) : TPB);
-            const int nt4 = (nt + 3) & ~3;
-            for (int jj = 0; jj < nt4; jj += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float4 pj = tile[jj + u];
-                    const float bj = bcol[(jj + u) * 4];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const float dx = pj.x - xi[r];
-                        const float dy = pj.y - yi[r];
-                        const float dz = pj.z - zi[r];
-                        float s = fmaf(dx, dx, eps2);
-                        s = fmaf(dy, dy, s);
-                        s = fmaf(dz, dz, s);
-                        float rinv = __builtin_amdgcn_rsqf(s);
-                        if constexpr (MASK)
-                            rinv = s > 0.0f ? rinv : 0.0f;
-                        const float w3 = rinv * (rinv * rinv);
-                        // two accumulator chains per group (even / odd sources)
-                        // so consecutive matrix instructions are independent
-                        if (u & 1)
-                            acc2[r] = __builtin_amdgcn_mfma_f32_4x4x1f32(w3, bj, acc2[r], 0, 0, 0);
-                        else
-                            acc[r] = __builtin_amdgcn_mfma_f32_4x4x1f32(w3, bj, acc[r], 0, 0, 0);
-                        if constexpr (PHI)
-                            ph[r] = fmaf(pj.w, rinv, ph[r]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r] += acc2[r];
-                acc2[r] = v4f{0.f, 0.f, 0.f, 0.f};
-            }
-            if constexpr (ACC == kTwoSum) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        float h = hi[r][q], l = lo[r][q];
-                        two_sum_add(h, l, acc[r][q]);
-                        hi[r][q] = h;
-                        lo[r][q] = l;
-                    }
-                    if constexpr (PHI)
-                        two_sum_add(hp[r], lp[r], ph[r]);
-                    acc[r] = v4f{0.f, 0.f, 0.f, 0.f};
-                    ph[r] = 0.0f;
-                }
-            } else if constexpr (ACC == kFold64) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        fold[r][q] += (double)acc[r][q];
-                    if constexpr (PHI)
-                        bp[r] += (double)ph[r];
-                    acc[r] = v4f{0.f, 0.f, 0.f, 0.f};
-                    ph[r] = 0.0f;
-                }
-            }
-        }
-
-        // transpose each group's 4x4 blocks through LDS so every lane gets
-        // its own target's (P_x, P_y, P_z, W), then g = P - (x_k - c) W
-        const int64_t slot = (int64_t)w.slice;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            double d[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if constexpr (ACC == kTwoSum)
-                    d[q] = (double)hi[r][q] + (double)lo[r][q];
-                else if constexpr (ACC == kFold64)
-                    d[q] = fold[r][q];
-                else
-                    d[q] = (double)acc[r][q];
-            }
-            __syncthreads();
-            // lane l holds rows 0..3 of block l/4, column l%4
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                xch[wave][4 * (lane >> 2) + q][lane & 3] = d[q];
-            __syncthreads();
-            const double Px = xch[wave][lane][0], Py = xch[wave][lane][1];
-            const double Pz = xch[wave][lane][2], W = xch[wave][lane][3];
-            if (valid[r]) {
-                const int64_t i = w.i0 + tid + (int64_t)r * TPB;
-                part[(slot * 3 + 0) * N + i] = Px - (double)xi[r] * W;
-                part[(slot * 3 + 1) * N + i] = Py - (double)yi[r] * W;
-                part[(slot * 3 + 2) * N + i] = Pz - (double)zi[r] * W;
-                if constexpr (PHI) {
-                    double op;
-                    if constexpr (ACC == kTwoSum)
-                        op = (double)hp[r] + (double)lp[r];
-                    else if constexpr (ACC == kFold64)
-                        op = bp[r];
-                    else
-                        op = (double)ph[r];
-                    part_phi[slot * N + i] = op;
-                }
-            }
-        }
-    }
-}
-
 __global__ void zero_counter_kernel(int *counter) { *counter = 0; }
 
 // ---------------------------------------------------------------------------
@@ -802,49 +595,9 @@ hipError_t dispatch_fwd_shape(const TileCfg &cfg, bool phi, bool mask, const Fwd
     return hipErrorInvalidValue;
 }
 
-template <int ACC, int R, int TPB, bool PHI, bool MASK>
-hipError_t launch_mfma(const FwdArgs &a)
-{
-    auto k = pair_sweep_mfma_kernel<ACC, R, TPB, PHI, MASK>;
-    int grid = a.persistent ? persistent_grid(k, TPB, 0, a.n_items) : a.n_items;
-    if (grid <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(TPB), 0, a.s, a.x, a.m, a.N, a.items, a.n_items,
-                       a.counter, a.persistent ? 1 : 0, a.part, a.part_phi, a.step_inc);
-    return hipGetLastError();
-}
-
-template <int ACC, int R, int TPB>
-hipError_t dispatch_mfma_flags(bool phi, bool mask, const FwdArgs &a)
-{
-    if (phi)
-        return mask ? launch_mfma<ACC, R, TPB, true, true>(a)
-                    : launch_mfma<ACC, R, TPB, true, false>(a);
-    return mask ? launch_mfma<ACC, R, TPB, false, true>(a)
-                : launch_mfma<ACC, R, TPB, false, false>(a);
-}
-
-template <int ACC>
-hipError_t dispatch_mfma(const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
-{
-#define COLATUS_MF(RR, TT)                                                                   \
-    if (cfg.R == RR && cfg.tpb == TT)                                                        \
-        return dispatch_mfma_flags<ACC, RR, TT>(phi, mask, a);
-    COLATUS_MF(1, 256)
-    COLATUS_MF(2, 256)
-    COLATUS_MF(4, 256)
-    COLATUS_MF(1, 128)
-    COLATUS_MF(2, 128)
-    COLATUS_MF(4, 128)
-#undef COLATUS_MF
-    return hipErrorInvalidValue;
-}
-
 template <typename T, int ACC>
 hipError_t dispatch_fwd_form(int form, const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
 {
-    if (form == 2)
-        return dispatch_mfma<ACC>(cfg, phi, mask, a);
     if (form == 1)
         return dispatch_fwd_shape<T, ACC, 1>(cfg, phi, mask, a);
     return dispatch_fwd_shape<T, ACC, 0>(cfg, phi, mask, a);

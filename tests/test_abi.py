@@ -152,16 +152,16 @@ def test_options_and_tile_config():
     v = ctypes.c_int64()
     assert L.colatus_get_option(1, ctypes.byref(v)) == 0 and v.value == 1
     assert L.colatus_get_option(8, ctypes.byref(v)) == 0 and v.value == -1
-    assert L.colatus_set_option(8, 3) == EINVAL
+    assert L.colatus_set_option(8, 2) == EINVAL
     assert L.colatus_set_option(4, 3) == EINVAL
     assert L.colatus_set_option(99, 0) == EINVAL
     assert colatus.tile_config(32768, "mixed") == (1, 256, 64, 0)
     assert colatus.tile_config(32768, "fp64")[0:2] == (2, 256)
     colatus.set_option(colatus.OPT_TILE_SLICES, 3)
-    colatus.set_option(colatus.OPT_PAIR_FORM, 2)
+    colatus.set_option(colatus.OPT_PAIR_FORM, 1)
     try:
-        assert colatus.tile_config(32768, "mixed")[2:] == (3, 2)
-        assert colatus.tile_config(32768, "fp64")[3] == 2  # FP64 kernels ignore it
+        assert colatus.tile_config(32768, "mixed")[2:] == (3, 1)
+        assert colatus.tile_config(32768, "fp64")[3] == 1  # FP64 kernels ignore it
     finally:
         colatus.set_option(colatus.OPT_TILE_SLICES, 0)
         colatus.set_option(colatus.OPT_PAIR_FORM, -1)

@@ -158,10 +158,10 @@ def test_batch_boxes_do_not_interact(dev):
             assert np.max(np.abs(phi[sl] - pref) / np.abs(pref)) <= (1e-13 if prec == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("form", [1])
 def test_alternative_pair_forms_match_oracle(dev, form):
-    """Form 1 (rcp-based weight) and form 2 (matrix-core accumulation) give
-    the same sums as the default loop, to the mixed-precision tolerance."""
+    """Form 1 (rcp-based weight) gives the same sums as the default loop, to
+    the mixed-precision tolerance."""
     colatus.set_option(colatus.OPT_PAIR_FORM, form)
     try:
         w = inputs.eds_lattice(16)
@@ -218,7 +218,7 @@ def test_autotuner_picks_a_working_shape(dev):
     finally:
         colatus.set_option(colatus.OPT_AUTOTUNE, 0)
     print("tuned", cfg)
-    assert cfg[0] in (1, 2, 4) and cfg[1] in (128, 256) and cfg[2] >= 1 and cfg[3] in (0, 2)
+    assert cfg[0] in (1, 2, 4) and cfg[1] in (128, 256) and cfg[2] >= 1 and cfg[3] in (0, 1)
     ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
     e = rel_err_per_particle(got, ref)
     assert np.median(e) <= 1e-6 and e.max() <= 1e-4
