@@ -39,6 +39,16 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "pair_sweep_lcdm32_pmc.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1208_3444_amd", "csrc", "pair_sweep.hip")
 
 
+def sweep_kernel_name(N, precision):
+    from paper_1208_3444_amd import colatus
+    R, tpb, slots, form = colatus.tile_config(N, precision)
+    acc = {"mixed_twosum": "TwoSum", "mixed_f64acc": "Fold64", "fp32": "Direct"}.get(precision,
+                                                                                 "FP64")
+    if form == 2:
+        return f"pair_sweep_sym_kernel<{acc}, R={R}, {tpb // 64} wave(s)>"
+    return f"pair_sweep_kernel<{acc}, R={R}, {tpb} threads, form {form}>"
+
+
 def pmc_traffic():
     """HBM bytes per pair-sweep launch from the committed counter summary.
 
@@ -143,12 +153,12 @@ def main():
     achieved = FLOPS_PER_PAIR * pairs / (sweep_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": pmc_traffic(),
-                "kernel": "pair_sweep_kernel<float,TwoSum>", "launch_ms": sweep_ms,
+                "kernel": sweep_kernel_name(N, args.precision), "launch_ms": sweep_ms,
                 "launches": launches,
                 "flops_per_launch": FLOPS_PER_PAIR * pairs,
-                "note": "20 flops per ordered pair, N^2 pairs per launch; packed-FP32 "
-                        "instructions are disabled in this build, so the reachable VALU "
-                        "ceiling is half the listed peak"}
+                "note": "algorithmic: 20 flops per ordered pair, N^2 ordered pairs per "
+                        "launch; the symmetric loop evaluates each unordered pair once "
+                        "and applies it to both particles"}
     print(f"[bench] pair sweep {sweep_ms:.4f} ms/launch -> {achieved / 1e12:.2f} TFLOP/s",
           file=sys.stderr, flush=True)
 
@@ -163,7 +173,8 @@ def main():
                   "achieved_GBs": int_bytes / (int_launch_ms * 1e-3) / 1e9,
                   "peak_GBs": PEAK_HBM / 1e9,
                   "frac": int_bytes / (int_launch_ms * 1e-3) / PEAK_HBM,
-                  "note": "at N = 32^3 the partials (25 MB) stay in the Infinity Cache"}
+                  "note": f"{slices} partial-sum slots per particle "
+                          f"({24.0 * slices * N / 1e6:.0f} MB at this N)"}
 
     line = {
         "metric": METRIC, "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": K,

@@ -205,18 +205,28 @@ const char *colatus_strerror(int code);
 #define COLATUS_OPT_AUTOTUNE   3  /* 1: time candidate tile shapes on first use of an
                                      (N bucket, precision) and keep the fastest
                                      (default 0: built-in heuristic)                 */
-#define COLATUS_OPT_TILE_R     4  /* >0: force targets per lane (1, 2, 4); 0 = auto  */
-#define COLATUS_OPT_TILE_TPB   5  /* >0: force threads per block (128, 256); 0 = auto */
-#define COLATUS_OPT_TILE_SLICES 6 /* >0: force the number of source slices; 0 = auto  */
+#define COLATUS_OPT_TILE_R     4  /* >0: force targets per lane (forms 0, 1: 1, 2, 4;
+                                     form 2: 4, 8); 0 = auto                         */
+#define COLATUS_OPT_TILE_TPB   5  /* >0: force threads per block (forms 0, 1: 128,
+                                     256; form 2: 64, or 128 with R = 4); 0 = auto.
+                                     An unsupported combination makes the forward
+                                     calls return COLATUS_EINVAL                     */
+#define COLATUS_OPT_TILE_SLICES 6 /* >0: force the number of source slices (forms 0,
+                                     1; form 2 derives its slots from the parts);
+                                     0 = auto                                        */
 #define COLATUS_OPT_PERSISTENT 7  /* 1: persistent pair-sweep grid (about one resident
                                      round of workgroups) pulling LPT-ordered work
                                      items from a device counter; 0 (default): one
                                      workgroup per work item, in the same LPT order,
                                      left to the hardware dispatcher (measured
                                      faster on gfx950)                               */
-#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair weight m r^-3: 0 = m r^-1 (r^-1)^2,
-                                     1 = m r^-1 rcp(r^2) (one VALU multiply fewer,
-                                     one more transcendental; measured slower);
+#define COLATUS_OPT_PAIR_FORM  8  /* FP32 forward pair loop: 0 = ordered pairs, weight
+                                     m r^-1 (r^-1)^2; 1 = ordered pairs, weight
+                                     m r^-1 rcp(r^2) (one VALU multiply fewer, one
+                                     more transcendental); 2 = symmetric: each
+                                     unordered pair once, applied to both particles
+                                     (the pair force is antisymmetric, Eq. (1)),
+                                     boxes cut into parts of R x threads particles;
                                      -1 (default) = the heuristic's or the
                                      autotuner's choice.  FP64 always uses 0         */
 int colatus_set_option(int key, int64_t value);

@@ -8,13 +8,19 @@ namespace colatus {
 
 // One unit of the O(N^2) pair sweep: a block of target particles of one box
 // against a contiguous slice of that box's source particles.  The sweep
-// writes its partial sums into slot `slice` of the partial-sum buffer.
+// writes its partial sums into slot `slice` of the partial-sum buffer.  In
+// the symmetric form (form 2) a box is cut into parts; kind 0 pairs part p
+// (targets) with part q > p (sources): p's partial from q goes to slot
+// `slice` (= q), q's reaction from p to slot `rslice` (= p); kind 1 is a
+// piece of one part's targets against that whole part (slot p, no reaction).
 struct WorkItem {
     int64_t i0, i1;   // targets [i0, i1)
     int64_t j0, j1;   // sources [j0, j1)
     double eps2;      // squared softening of the box
-    int32_t slice;    // partial-sum slot
+    int32_t slice;    // partial-sum slot of the targets
     int32_t box;
+    int32_t rslice;   // partial-sum slot of the sources' reaction (form 2)
+    int32_t kind;     // form 2: 0 = pair of parts, 1 = piece of a diagonal
 };
 
 // Up to kIntBlock particles of one box, for the O(N) kernels (finalise,
@@ -54,8 +60,8 @@ __device__ __forceinline__ double rsqrt_refined(double s)
 // Shape of one pair-sweep launch.
 struct TileCfg {
     int R;        // targets per lane
-    int tpb;      // threads per block (= sources per LDS tile)
-    int slices;   // source slices per box
+    int tpb;      // threads per block (= sources per LDS tile in forms 0, 1)
+    int slices;   // source slices per box (form 2: parts of R * tpb particles)
     int form;     // FP32 pair-loop form (see launch_pair_sweep); 0 for FP64
 };
 
@@ -67,7 +73,9 @@ constexpr int kDiagW = 10;
 
 // Forward pair sweep: part[s][3][N] = sum over the item's sources of
 // m_j (x_j - x_k) r^-3, and part_phi[s][N] = sum m_j / r when with_phi.
-// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s) (FP32 only).
+// form 0: w = m r^-1 (r^-1)^2; form 1: w = m r^-1 rcp(s) (FP32 only);
+// form 2: symmetric items (FP32 only; R in {4, 8}, tpb in {64, 128}), each
+// unordered pair evaluated once and applied to both particles.
 // box_mass[b]: common mass of box b or NaN (see launch_box_mass), or null.
 // step_inc: if non-null, the sweep's first thread adds 1 to *step_inc (the
 // run's step counter; nothing in the sweep reads it).

@@ -307,6 +307,327 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric forward sweep (form 2, FP32 pairs).  The pair term of Eq. (1) is
+// antisymmetric: the pull of j on k, m_j d r^-3 with d = x_j - x_k, and the
+// pull of k on j, -m_k d r^-3, share d, s = |d|^2 + eps^2 and r^-3.  Each
+// unordered pair is therefore evaluated once and applied to both particles.
+//
+// A work item is a pair of parts (p, q), p < q, of one partition of a box.
+// The W waves of the workgroup hold part p's U = 64 R W targets in registers
+// (R per lane).  Part q's sources pass through in chunks of 64, one per lane;
+// after every step each source moves one lane on (a DPP rotation of the whole
+// wave) and carries the accumulator of its reaction with it, so after 64
+// steps every source has met every target of the wave and is back in its
+// lane with its reaction complete.  The waves' reactions are added in a fixed
+// order.  Part p's partial sum from part q goes to slot q and part q's
+// reaction from part p to slot p: each (slot, particle) is written once, and
+// the O(N) kernels add the slots in a fixed order.  The diagonal item (p, p)
+// evaluates the ordered pairs of its part with the same loop and no reaction.
+//
+// Per unordered pair with equal masses: 3 subtractions, 3 FMAs, one v_rsq,
+// 2 multiplies, 3 + 3 FMAs; per step and lane 6 rotations shared by R pairs.
+// ---------------------------------------------------------------------------
+// A value known to be equal in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// lane l receives the value lane (l - 1) mod 64 held (DPP wave_ror:1); every
+// lane of the wave must be active.
+__device__ __forceinline__ float wave_rotate(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, true));
+}
+
+// 64 steps of one source chunk against the lane's R targets.  REACT: also
+// accumulate the reaction on the travelling source (q*); EQM: the box's common
+// mass leaves the loop (weights r^-3 and r^-1 only).
+template <int R, bool REACT, bool EQM, bool PHI, bool MASK>
+__device__ __forceinline__ void sym_chunk(float sx, float sy, float sz, float sm, float &qx,
+                                          float &qy, float &qz, float &qp, const float (&xi)[R],
+                                          const float (&yi)[R], const float (&zi)[R],
+                                          const float (&mi)[R], float eps2, float (&ax)[R],
+                                          float (&ay)[R], float (&az)[R], float (&ap)[R])
+{
+#pragma unroll 2
+    for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float dx = sx - xi[r];
+            const float dy = sy - yi[r];
+            const float dz = sz - zi[r];
+            float s = fmaf(dx, dx, eps2);
+            s = fmaf(dy, dy, s);
+            s = fmaf(dz, dz, s);
+            float rinv = __builtin_amdgcn_rsqf(s);
+            if constexpr (MASK)
+                rinv = s > 0.0f ? rinv : 0.0f;
+            const float w = rinv * (rinv * rinv);
+            const float wt = EQM ? w : sm * w;
+            ax[r] = fmaf(wt, dx, ax[r]);
+            ay[r] = fmaf(wt, dy, ay[r]);
+            az[r] = fmaf(wt, dz, az[r]);
+            if constexpr (PHI)
+                ap[r] += EQM ? rinv : sm * rinv;
+            if constexpr (REACT) {
+                const float ws = EQM ? w : mi[r] * w;
+                qx = fmaf(-ws, dx, qx);
+                qy = fmaf(-ws, dy, qy);
+                qz = fmaf(-ws, dz, qz);
+                if constexpr (PHI)
+                    qp += EQM ? rinv : mi[r] * rinv;
+            }
+        }
+        sx = wave_rotate(sx);
+        sy = wave_rotate(sy);
+        sz = wave_rotate(sz);
+        if constexpr (!EQM)
+            sm = wave_rotate(sm);
+        if constexpr (REACT) {
+            qx = wave_rotate(qx);
+            qy = wave_rotate(qy);
+            qz = wave_rotate(qz);
+            if constexpr (PHI)
+                qp = wave_rotate(qp);
+        }
+    }
+}
+
+// One work item of the symmetric sweep.  REACT: a pair of parts (p < q),
+// R targets per lane, with the reaction on the sources; otherwise a piece of
+// a diagonal item: one target per lane against the whole part, no reaction
+// (every unordered pair inside the part is met twice, once from each side).
+// FOLD: the sources of a part exceed 256 and the targets' FP32 partial sums
+// are folded every 256 sources; with at most 256 every partial sum (a
+// target's from one part, a source's reaction from one part) is a single
+// FP32 sum of at most 256 terms, like the ordered loop's per-tile partials.
+template <int ACC, int R, int W, bool FOLD, bool REACT, bool PHI, bool MASK>
+__device__ __forceinline__ void sym_item(const WorkItem &w, const double *__restrict__ X,
+                                         const double *__restrict__ Y,
+                                         const double *__restrict__ Z,
+                                         const double *__restrict__ m, int64_t N,
+                                         const double *__restrict__ box_mass,
+                                         double *__restrict__ part,
+                                         double *__restrict__ part_phi, double (*red)[6],
+                                         float (*react)[W][PHI ? 4 : 3][64])
+{
+    constexpr int TPB = 64 * W;
+    constexpr int NQ = PHI ? 4 : 3;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double mbox = box_mass ? box_mass[w.box] : NAN;
+    const bool eqm = !isnan(mbox);
+
+    double tx[R], ty[R], tz[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(wave * 64 * R + r * 64 + lane);
+        valid[r] = i < w.i1;
+        const int64_t ii = valid[r] ? i : w.i0;
+        tx[r] = X[ii];
+        ty[r] = Y[ii];
+        tz[r] = Z[ii];
+    }
+    double cx, cy, cz;
+    block_centre<TPB, R>(tx, ty, tz, valid, red, cx, cy, cz);
+    cx = uniform(cx);
+    cy = uniform(cy);
+    cz = uniform(cz);
+
+    // Missing targets sit far away with zero mass: they neither pull nor are
+    // pulled (FP32 s overflows to +inf, r^-1 = 0).
+    float xi[R], yi[R], zi[R], mi[R];
+    float ax[R], ay[R], az[R], ap[R];
+    float hx[R], hy[R], hz[R], hp[R];
+    float lx[R], ly[R], lz[R], lp[R];
+    double bx[R], by[R], bz[R], bp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(wave * 64 * R + r * 64 + lane);
+        if (valid[r]) {
+            xi[r] = (float)(tx[r] - cx);
+            yi[r] = (float)(ty[r] - cy);
+            zi[r] = (float)(tz[r] - cz);
+            mi[r] = (float)m[i];
+        } else {
+            xi[r] = yi[r] = zi[r] = 1e30f;
+            mi[r] = 0.0f;
+        }
+        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+        if constexpr (FOLD) {
+            hx[r] = hy[r] = hz[r] = hp[r] = 0.0f;
+            lx[r] = ly[r] = lz[r] = lp[r] = 0.0f;
+            bx[r] = by[r] = bz[r] = bp[r] = 0.0;
+        }
+    }
+    const float eps2 = uniform((float)w.eps2);
+    const double scale = eqm ? mbox : 1.0;
+    const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
+
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t j = w.j0 + (int64_t)c * 64 + lane;
+        const bool jv = j < w.j1;
+        float sx = 1e30f, sy = 1e30f, sz = 1e30f, sm = 0.0f;
+        if (jv) {
+            sx = (float)(X[j] - cx);
+            sy = (float)(Y[j] - cy);
+            sz = (float)(Z[j] - cz);
+            sm = (float)m[j];
+        }
+        float qx = 0.0f, qy = 0.0f, qz = 0.0f, qp = 0.0f;
+        if (eqm)
+            sym_chunk<R, REACT, true, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
+                                                 eps2, ax, ay, az, ap);
+        else
+            sym_chunk<R, REACT, false, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
+                                                  eps2, ax, ay, az, ap);
+        if constexpr (FOLD) {
+            if ((c & 3) == 3 || c == n_chunks - 1) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (ACC == kTwoSum) {
+                        two_sum_add(hx[r], lx[r], ax[r]);
+                        two_sum_add(hy[r], ly[r], ay[r]);
+                        two_sum_add(hz[r], lz[r], az[r]);
+                        if constexpr (PHI)
+                            two_sum_add(hp[r], lp[r], ap[r]);
+                        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+                    } else if constexpr (ACC == kFold64) {
+                        bx[r] += (double)ax[r];
+                        by[r] += (double)ay[r];
+                        bz[r] += (double)az[r];
+                        if constexpr (PHI)
+                            bp[r] += (double)ap[r];
+                        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+                    }
+                }
+            }
+        }
+        if constexpr (REACT) {
+            // reaction on this chunk's sources: the waves' sums in a fixed order
+            double o[NQ];
+            if constexpr (W == 1) {
+                o[0] = (double)qx;
+                o[1] = (double)qy;
+                o[2] = (double)qz;
+                if constexpr (PHI)
+                    o[NQ - 1] = (double)qp;
+            } else {
+                float(*buf)[NQ][64] = react[c & 1];
+                buf[wave][0][lane] = qx;
+                buf[wave][1][lane] = qy;
+                buf[wave][2][lane] = qz;
+                if constexpr (PHI)
+                    buf[wave][NQ - 1][lane] = qp;
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if constexpr (ACC == kTwoSum) {
+                        float hi = buf[0][q][lane], lo = 0.0f;
+#pragma unroll
+                        for (int v = 1; v < W; ++v)
+                            two_sum_add(hi, lo, buf[v][q][lane]);
+                        o[q] = (double)hi + (double)lo;
+                    } else if constexpr (ACC == kFold64) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int v = 0; v < W; ++v)
+                            t += (double)buf[v][q][lane];
+                        o[q] = t;
+                    } else {
+                        float t = buf[0][q][lane];
+#pragma unroll
+                        for (int v = 1; v < W; ++v)
+                            t += buf[v][q][lane];
+                        o[q] = (double)t;
+                    }
+                }
+            }
+            if (wave == 0 && jv) {
+                const int64_t rs = (int64_t)w.rslice;
+                part[(rs * 3 + 0) * N + j] = scale * o[0];
+                part[(rs * 3 + 1) * N + j] = scale * o[1];
+                part[(rs * 3 + 2) * N + j] = scale * o[2];
+                if constexpr (PHI)
+                    part_phi[rs * N + j] = scale * o[NQ - 1];
+            }
+        }
+    }
+
+    const int64_t slot = (int64_t)w.slice;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!valid[r])
+            continue;
+        const int64_t i = w.i0 + (int64_t)(wave * 64 * R + r * 64 + lane);
+        double ox, oy, oz, op;
+        if constexpr (FOLD && ACC == kTwoSum) {
+            ox = (double)hx[r] + (double)lx[r];
+            oy = (double)hy[r] + (double)ly[r];
+            oz = (double)hz[r] + (double)lz[r];
+            op = (double)hp[r] + (double)lp[r];
+        } else if constexpr (FOLD && ACC == kFold64) {
+            ox = bx[r];
+            oy = by[r];
+            oz = bz[r];
+            op = bp[r];
+        } else {
+            ox = (double)ax[r];
+            oy = (double)ay[r];
+            oz = (double)az[r];
+            op = (double)ap[r];
+        }
+        part[(slot * 3 + 0) * N + i] = scale * ox;
+        part[(slot * 3 + 1) * N + i] = scale * oy;
+        part[(slot * 3 + 2) * N + i] = scale * oz;
+        if constexpr (PHI)
+            part_phi[slot * N + i] = scale * op;
+    }
+}
+
+// One wave per workgroup with four targets per lane is held to 80 VGPRs so
+// that six waves share each SIMD (measured 10 % faster than four at 32^3;
+// two 8-byte values of the item loop spill, outside the pair loop).
+template <int ACC, int R, int W, bool PHI, bool MASK>
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(R * W == 4 ? 6 : 1))) void pair_sweep_sym_kernel(
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
+    const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
+    int persistent, const double *__restrict__ box_mass, double *__restrict__ part,
+    double *__restrict__ part_phi, int64_t *__restrict__ step_inc)
+{
+    constexpr bool FOLD = 64 * R * W > 256;
+    __shared__ double red[W][6];
+    __shared__ float react[W > 1 ? 2 : 1][W][PHI ? 4 : 3][64];
+    __shared__ int s_item;
+    const double *X = x, *Y = x + N, *Z = x + 2 * N;
+    if (step_inc && blockIdx.x == 0 && threadIdx.x == 0)
+        *step_inc += 1;
+
+    for (int iter = 0;; ++iter) {
+        const int it = next_item(persistent, counter, &s_item, iter);
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+        if (w.kind == 0)
+            sym_item<ACC, R, W, FOLD, true, PHI, MASK>(w, X, Y, Z, m, N, box_mass, part,
+                                                       part_phi, red, react);
+        else
+            sym_item<ACC, 1, W, FOLD, false, PHI, MASK>(w, X, Y, Z, m, N, box_mass, part,
+                                                        part_phi, red, react);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint sweep: sum_j M(d)(m_k lam_j - m_j lam_k), M(d) = r^-3 I - 3 r^-5 d d^T,
 // for C cotangents sharing the geometry.  lam is [n_cot][3][N]; this launch
 // handles cotangents [c0, c0 + C).  part is [slices][n_cot][3][N].
@@ -559,6 +880,39 @@ struct FwdArgs {
     hipStream_t s;
 };
 
+template <int ACC, int R, int W, bool PHI, bool MASK>
+hipError_t launch_sym(const FwdArgs &a)
+{
+    auto k = pair_sweep_sym_kernel<ACC, R, W, PHI, MASK>;
+    int grid = a.persistent ? persistent_grid(k, 64 * W, 0, a.n_items) : a.n_items;
+    if (grid <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * W), 0, a.s, a.x, a.m, a.N, a.items, a.n_items,
+                       a.counter, a.persistent ? 1 : 0, a.box_mass, a.part, a.part_phi,
+                       a.step_inc);
+    return hipGetLastError();
+}
+
+template <int ACC, int R, int W>
+hipError_t dispatch_sym_flags(bool phi, bool mask, const FwdArgs &a)
+{
+    if (phi)
+        return mask ? launch_sym<ACC, R, W, true, true>(a) : launch_sym<ACC, R, W, true, false>(a);
+    return mask ? launch_sym<ACC, R, W, false, true>(a) : launch_sym<ACC, R, W, false, false>(a);
+}
+
+template <int ACC>
+hipError_t dispatch_sym(const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
+{
+    if (cfg.R == 4 && cfg.tpb == 64)
+        return dispatch_sym_flags<ACC, 4, 1>(phi, mask, a);
+    if (cfg.R == 8 && cfg.tpb == 64)
+        return dispatch_sym_flags<ACC, 8, 1>(phi, mask, a);
+    if (cfg.R == 4 && cfg.tpb == 128)
+        return dispatch_sym_flags<ACC, 4, 2>(phi, mask, a);
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int ACC, int R, int TPB, int FORM>
 hipError_t dispatch_fwd_flags(bool phi, bool mask, const FwdArgs &a)
 {
@@ -598,6 +952,8 @@ hipError_t dispatch_fwd_shape(const TileCfg &cfg, bool phi, bool mask, const Fwd
 template <typename T, int ACC>
 hipError_t dispatch_fwd_form(int form, const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
 {
+    if (form == 2)
+        return dispatch_sym<ACC>(cfg, phi, mask, a);
     if (form == 1)
         return dispatch_fwd_shape<T, ACC, 1>(cfg, phi, mask, a);
     return dispatch_fwd_shape<T, ACC, 0>(cfg, phi, mask, a);

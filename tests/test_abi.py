@@ -152,18 +152,31 @@ def test_options_and_tile_config():
     v = ctypes.c_int64()
     assert L.colatus_get_option(1, ctypes.byref(v)) == 0 and v.value == 1
     assert L.colatus_get_option(8, ctypes.byref(v)) == 0 and v.value == -1
-    assert L.colatus_set_option(8, 2) == EINVAL
+    assert L.colatus_set_option(8, 3) == EINVAL
     assert L.colatus_set_option(4, 3) == EINVAL
+    assert L.colatus_set_option(5, 32) == EINVAL
     assert L.colatus_set_option(99, 0) == EINVAL
-    assert colatus.tile_config(32768, "mixed") == (1, 256, 64, 0)
+    # FP32 forward sweeps: symmetric form, parts of 4 x 64 particles
+    assert colatus.tile_config(32768, "mixed") == (4, 64, 128, 2)
+    assert colatus.tile_config(1000, "fp32") == (4, 64, 4, 2)
+    # beyond 2^17 particles in a box (or FP64, or the adjoint): ordered form
+    assert colatus.tile_config(200000, "mixed")[3] == 0
     assert colatus.tile_config(32768, "fp64")[0:2] == (2, 256)
+    assert colatus.tile_config(32768, "fp64")[3] == 0
+    assert colatus.tile_config(32768, "mixed", kind=1)[3] == 0
     colatus.set_option(colatus.OPT_TILE_SLICES, 3)
     colatus.set_option(colatus.OPT_PAIR_FORM, 1)
     try:
         assert colatus.tile_config(32768, "mixed")[2:] == (3, 1)
-        assert colatus.tile_config(32768, "fp64")[3] == 1  # FP64 kernels ignore it
+        assert colatus.tile_config(32768, "fp64")[3] == 0  # FP64 always uses form 0
+        colatus.set_option(colatus.OPT_PAIR_FORM, 2)
+        # form 2 derives its slots from the part size; TILE_SLICES does not apply
+        assert colatus.tile_config(200000, "mixed") == (4, 64, 782, 2)
+        colatus.set_option(colatus.OPT_TILE_R, 8)
+        assert colatus.tile_config(4096, "mixed") == (8, 64, 8, 2)
     finally:
         colatus.set_option(colatus.OPT_TILE_SLICES, 0)
+        colatus.set_option(colatus.OPT_TILE_R, 0)
         colatus.set_option(colatus.OPT_PAIR_FORM, -1)
 
 

@@ -34,13 +34,18 @@ def test_ensemble_fp64_each_box_matches_oracle(dev):
         assert np.allclose(rows[b]["U"], dr["U"], rtol=1e-11)
 
 
-def test_ensemble_mixed_matches_single_box_runs(dev):
+@pytest.mark.parametrize("form", [2, 0])
+def test_ensemble_mixed_matches_single_box_runs(dev, form):
     """With the same tile shape, each box of the batched launch is bitwise the
-    box run on its own: boxes share no arithmetic."""
+    box run on its own: boxes share no arithmetic.  The symmetric form cuts
+    every box into parts of its own, so its default shape qualifies; the
+    ordered form's slice count depends on the largest box and is forced."""
     e, v0 = _ensemble(12, 512, 4096, 20)
-    colatus.set_option(colatus.OPT_TILE_R, 2)
-    colatus.set_option(colatus.OPT_TILE_TPB, 128)
-    colatus.set_option(colatus.OPT_TILE_SLICES, 3)
+    colatus.set_option(colatus.OPT_PAIR_FORM, form)
+    if form == 0:
+        colatus.set_option(colatus.OPT_TILE_R, 2)
+        colatus.set_option(colatus.OPT_TILE_TPB, 128)
+        colatus.set_option(colatus.OPT_TILE_SLICES, 3)
     try:
         xt, vt, mt = to_dev(e.x, dev), to_dev(v0, dev), to_dev(e.m, dev)
         rows = colatus.run(xt, vt, mt, 0.0, e.G, e.cosmo, e.a_begin, e.a_end, e.n_steps,
@@ -59,6 +64,7 @@ def test_ensemble_mixed_matches_single_box_runs(dev):
     finally:
         for k in (colatus.OPT_TILE_R, colatus.OPT_TILE_TPB, colatus.OPT_TILE_SLICES):
             colatus.set_option(k, 0)
+        colatus.set_option(colatus.OPT_PAIR_FORM, -1)
 
 
 def test_ensemble_mixed_short_run_matches_oracle(dev):

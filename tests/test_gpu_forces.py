@@ -116,6 +116,7 @@ def test_tile_shapes_agree(dev, R, tpb, slices):
     eps = 0.02
     ref = oracle.forces(x, m, eps)
     scale = _term_scale(x, m, eps)
+    colatus.set_option(colatus.OPT_PAIR_FORM, 0)
     colatus.set_option(colatus.OPT_TILE_R, R)
     colatus.set_option(colatus.OPT_TILE_TPB, tpb)
     colatus.set_option(colatus.OPT_TILE_SLICES, slices)
@@ -130,6 +131,7 @@ def test_tile_shapes_agree(dev, R, tpb, slices):
         for k in (colatus.OPT_TILE_R, colatus.OPT_TILE_TPB, colatus.OPT_TILE_SLICES):
             colatus.set_option(k, 0)
         colatus.set_option(colatus.OPT_PERSISTENT, 0)
+        colatus.set_option(colatus.OPT_PAIR_FORM, -1)
 
 
 def test_batch_boxes_do_not_interact(dev):
@@ -158,10 +160,10 @@ def test_batch_boxes_do_not_interact(dev):
             assert np.max(np.abs(phi[sl] - pref) / np.abs(pref)) <= (1e-13 if prec == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("form", [1])
+@pytest.mark.parametrize("form", [0, 1])
 def test_alternative_pair_forms_match_oracle(dev, form):
-    """Form 1 (rcp-based weight) gives the same sums as the default loop, to
-    the mixed-precision tolerance."""
+    """The ordered loops (form 0, and form 1 with an rcp-based weight) give the
+    same sums as the default loop, to the mixed-precision tolerance."""
     colatus.set_option(colatus.OPT_PAIR_FORM, form)
     try:
         w = inputs.eds_lattice(16)
@@ -218,7 +220,10 @@ def test_autotuner_picks_a_working_shape(dev):
     finally:
         colatus.set_option(colatus.OPT_AUTOTUNE, 0)
     print("tuned", cfg)
-    assert cfg[0] in (1, 2, 4) and cfg[1] in (128, 256) and cfg[2] >= 1 and cfg[3] in (0, 1)
+    if cfg[3] == 2:
+        assert cfg[:2] in ((4, 64), (8, 64), (4, 128)) and cfg[2] == -(-w.N // (cfg[0] * cfg[1]))
+    else:
+        assert cfg[0] in (1, 2, 4) and cfg[1] in (128, 256) and cfg[2] >= 1 and cfg[3] in (0, 1)
     ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
     e = rel_err_per_particle(got, ref)
     assert np.median(e) <= 1e-6 and e.max() <= 1e-4

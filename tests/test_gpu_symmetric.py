@@ -1,0 +1,170 @@
+"""GPU parity of the symmetric pair loop (pair-loop form 2) against the FP64 oracle.
+
+Form 2 evaluates each unordered pair once and applies it to both particles
+(the pair term of Eq. (1) is antisymmetric); boxes are cut into parts of
+R x threads particles and every particle receives one partial sum per part.
+Checked here for every supported shape: lattice and random clouds with
+unequal masses and ragged sizes (missing targets and sources in the last
+part), the potential, softening zero (coincident pairs masked), ragged
+batches, the persistent grid, and the 32^3 LCDM workload on sampled targets.
+Tolerances: the per-particle relative bars of the ordered loop (median 1e-6,
+max 1e-4) on the lattice and the 32^3 workload; on random clouds the
+conditioned error |a - a_ref| / sum_j |term_j| <= 5e-6.  Every partial sum
+here is one FP32 sum of at most 256 terms (a target's from one part, a
+source's reaction from one part), whose conditioned error is at most about
+(256 + 10) u = 1.6e-5 (u = 2^-24, 10 u for the pair term itself); the
+largest value observed is 3.7e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1208_3444_amd import colatus, inputs
+from conftest import rel_err_per_particle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 64), (8, 64), (4, 128)]
+
+
+def _term_scale(x, m, eps):
+    d = x[:, None, :] - x[:, :, None]
+    s = (d ** 2).sum(axis=0) + eps * eps
+    w = m[None, :] * s ** -1.5
+    np.fill_diagonal(w, 0.0)
+    return (w * np.sqrt((d ** 2).sum(axis=0))).sum(axis=1)
+
+
+def _gpu(x, m, eps, dev, prec, a=1.0, with_phi=False, batch=None):
+    out = colatus.forces(to_dev(x, dev), to_dev(m, dev), eps, a=a, precision=prec,
+                         with_phi=with_phi, batch=batch)
+    torch.cuda.synchronize()
+    if with_phi:
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+@pytest.fixture
+def form2():
+    colatus.set_option(colatus.OPT_PAIR_FORM, 2)
+    yield
+    for k in (colatus.OPT_TILE_R, colatus.OPT_TILE_TPB):
+        colatus.set_option(k, 0)
+    colatus.set_option(colatus.OPT_PERSISTENT, 0)
+    colatus.set_option(colatus.OPT_PAIR_FORM, -1)
+
+
+def _shape(R, tpb):
+    colatus.set_option(colatus.OPT_TILE_R, R)
+    colatus.set_option(colatus.OPT_TILE_TPB, tpb)
+
+
+@pytest.mark.parametrize("R,tpb", SHAPES)
+def test_lattice_with_potential(dev, form2, R, tpb):
+    _shape(R, tpb)
+    cfg = colatus.tile_config(4096, "mixed_twosum")
+    assert cfg == (R, tpb, -(-4096 // (R * tpb)), 2)
+    w = inputs.eds_lattice(16)
+    ref = oracle.forces(w.x, w.m, w.eps, a=0.1)
+    pref = oracle.potential(w.x, w.m, w.eps)
+    for prec, med, mx in (("mixed_twosum", 1e-6, 1e-4), ("mixed_f64acc", 1e-6, 1e-4),
+                          ("fp32", 1e-5, 1e-3)):
+        got, phi = _gpu(w.x, w.m, w.eps, dev, prec, a=0.1, with_phi=True)
+        e = rel_err_per_particle(got, ref)
+        ep = np.abs(phi - pref) / np.abs(pref)
+        print(f"R={R} tpb={tpb} {prec}: force median {np.median(e):.2e} max {e.max():.2e}; "
+              f"potential median {np.median(ep):.2e} max {ep.max():.2e}", flush=True)
+        assert np.median(e) <= med and e.max() <= mx
+        pm, px = (1e-6, 1e-5) if prec != "fp32" else (1e-5, 1e-4)
+        assert np.median(ep) <= pm and ep.max() <= px
+
+
+@pytest.mark.parametrize("R,tpb", SHAPES)
+@pytest.mark.parametrize("N", [1, 2, 3, 63, 64, 65, 255, 257, 511, 513, 1000, 1537])
+def test_ragged_unequal_masses(dev, form2, R, tpb, N):
+    """Parts with missing targets/sources; unequal masses take the general loop."""
+    _shape(R, tpb)
+    x, m = inputs.random_cloud(N, 100 + N, scale=0.5, mass_spread=True)
+    eps = 0.01
+    got, phi = _gpu(x, m, eps, dev, "mixed_twosum", with_phi=True)
+    if N == 1:
+        assert np.all(got == 0.0)
+        return
+    ref = oracle.forces(x, m, eps)
+    err = np.max(np.linalg.norm(got - ref, axis=0) / _term_scale(x, m, eps))
+    pref = oracle.potential(x, m, eps)
+    ep = np.max(np.abs(phi - pref) / np.abs(pref))
+    print(f"R={R} tpb={tpb} N={N}: conditioned force error {err:.2e}, potential {ep:.2e}")
+    assert err <= 5e-6 and ep <= 1e-5
+
+
+def test_equal_and_unequal_masses_agree(dev, form2):
+    """The equal-mass loop (mass factored out) and the general loop agree."""
+    x, m = inputs.random_cloud(1300, 5, scale=0.5, mass_spread=False)
+    assert np.all(m == m[0])
+    eps = 0.02
+    ref = oracle.forces(x, m, eps)
+    got_eq = _gpu(x, m, eps, dev, "mixed_twosum")
+    m2 = m.copy()
+    m2[0] *= 1.0 + 2.0 ** -40  # not equal: the general loop runs
+    got_ne = _gpu(x, m2, eps, dev, "mixed_twosum")
+    sc = _term_scale(x, m, eps)
+    assert np.max(np.linalg.norm(got_eq - ref, axis=0) / sc) <= 5e-6
+    assert np.max(np.linalg.norm(got_ne - ref, axis=0) / sc) <= 5e-6
+
+
+@pytest.mark.parametrize("R,tpb", SHAPES)
+def test_softening_zero_masks_coincident_pairs(dev, form2, R, tpb):
+    _shape(R, tpb)
+    x, m = inputs.random_cloud(700, 7, scale=0.5)
+    got = _gpu(x, m, 0.0, dev, "mixed_twosum")
+    assert np.all(np.isfinite(got))
+    err = np.max(np.linalg.norm(got - oracle.forces(x, m, 0.0), axis=0) / _term_scale(x, m, 0.0))
+    assert err <= 1e-5
+
+
+def test_batch_and_persistent_grid(dev, form2):
+    sizes = [1, 40, 513, 2, 1030, 300]
+    xs, ms, epss = [], [], []
+    for i, n in enumerate(sizes):
+        x, m = inputs.random_cloud(n, 60 + i, scale=0.5, mass_spread=bool(i % 2))
+        xs.append(x + 0.1 * i)
+        ms.append(m)
+        epss.append(0.01 * (i + 1))
+    x = np.concatenate(xs, axis=1)
+    m = np.concatenate(ms)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    runs = {}
+    for pers in (0, 1):
+        colatus.set_option(colatus.OPT_PERSISTENT, pers)
+        runs[pers] = _gpu(x, m, 0.0, dev, "mixed_twosum", a=0.5, with_phi=True,
+                          batch=(off, np.array(epss)))
+    # same items, same arithmetic: bitwise equal whatever the grid
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    got, phi = runs[0]
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        if sizes[b] == 1:
+            assert np.all(got[:, sl] == 0.0)
+            continue
+        ref = oracle.forces(xs[b], ms[b], epss[b], a=0.5)
+        scale = _term_scale(xs[b], ms[b], epss[b]) / 0.5 ** 3
+        assert np.max(np.linalg.norm(got[:, sl] - ref, axis=0) / scale) <= 5e-6
+        pref = oracle.potential(xs[b], ms[b], epss[b])
+        assert np.max(np.abs(phi[sl] - pref) / np.abs(pref)) <= 1e-5
+    # a box computed inside the batch equals the box computed alone
+    alone = _gpu(xs[4], ms[4], epss[4], dev, "mixed_twosum", a=0.5)
+    assert np.array_equal(alone, got[:, off[4]:off[5]])
+
+
+def test_lcdm_32cubed_sampled(dev, form2):
+    w = inputs.lcdm_grf(32)
+    t = np.arange(0, w.N, 37)
+    ref = oracle.forces_targets(w.x, w.m, t, w.eps, a=w.a_begin)
+    a1 = _gpu(w.x, w.m, w.eps, dev, "mixed_twosum", a=w.a_begin)
+    a2 = _gpu(w.x, w.m, w.eps, dev, "mixed_twosum", a=w.a_begin)
+    assert np.array_equal(a1, a2)
+    e = rel_err_per_particle(a1[:, t], ref)
+    print(f"form 2 32^3: median {np.median(e):.3e} max {e.max():.3e}")
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4
