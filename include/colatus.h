@@ -220,15 +220,19 @@ const char *colatus_strerror(int code);
                                      workgroup per work item, in the same LPT order,
                                      left to the hardware dispatcher (measured
                                      faster on gfx950)                               */
-#define COLATUS_OPT_PAIR_FORM  8  /* FP32 forward pair loop: 0 = ordered pairs, weight
+#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair loop: 0 = ordered pairs, weight
                                      m r^-1 (r^-1)^2; 1 = ordered pairs, weight
                                      m r^-1 rcp(r^2) (one VALU multiply fewer, one
-                                     more transcendental); 2 = symmetric: each
-                                     unordered pair once, applied to both particles
-                                     (the pair force is antisymmetric, Eq. (1)),
-                                     boxes cut into parts of R x threads particles;
-                                     -1 (default) = the heuristic's or the
-                                     autotuner's choice.  FP64 always uses 0         */
+                                     more transcendental; the adjoint treats 1 as 0);
+                                     2 = symmetric: each unordered pair once,
+                                     applied to both particles (the forward and
+                                     adjoint pair terms change sign when the two
+                                     particles swap), boxes cut into parts of
+                                     R x threads particles; -1 (default) = the
+                                     heuristic's or the autotuner's choice (2 for
+                                     the forward up to 2^17 particles per box and
+                                     for the adjoint with up to 3 cotangents, else
+                                     0).  FP64 always uses 0                         */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

@@ -339,13 +339,17 @@ TileCfg symmetric_cfg(const Boxes &b, int R, int tpb);
 // larger boxes use the ordered form, whose slot count stays near 64.
 constexpr int64_t kSymMaxN = 131072;
 
+// Cotangents up to which the adjoint uses the symmetric form (one launch per
+// cotangent); more share the geometry in the ordered form's chunks of 8.
+constexpr int kSymMaxCot = 3;
+
 // Built-in heuristic: FP32 forward sweeps use the symmetric form (each
 // unordered pair once, one wave per item, four targets per lane), measured
-// 1.36x faster than the ordered form at 32^3; FP64 and the adjoint use the
-// ordered form.
-TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu)
+// 1.36x faster than the ordered form at 32^3; so does the FP32 adjoint with
+// few cotangents.  FP64 uses the ordered form.
+TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu, int n_cot = 1)
 {
-    if (kind == 0 && precision != COLATUS_FP64 && b.max_n <= kSymMaxN)
+    if (precision != COLATUS_FP64 && b.max_n <= kSymMaxN && (kind == 0 || n_cot <= kSymMaxCot))
         return symmetric_cfg(b, 4, 64);
     return ordered_cfg(b, precision, kind, n_cu);
 }
@@ -370,14 +374,15 @@ TileCfg symmetric_cfg(const Boxes &b, int R, int tpb)
 
 TileCfg apply_overrides(TileCfg c, int kind, int precision, const Boxes &b, int n_cu)
 {
-    const bool fwd32 = kind == 0 && precision != COLATUS_FP64;
-    if (fwd32 && g_opt.pair_form >= 0 && g_opt.pair_form != c.form) {
-        if (g_opt.pair_form == 2) {
+    // the adjoint has one ordered loop: form 1 means form 0 there
+    const int want = kind == 1 && g_opt.pair_form == 1 ? 0 : (int)g_opt.pair_form;
+    if (precision != COLATUS_FP64 && want >= 0 && want != c.form) {
+        if (want == 2) {
             c = symmetric_cfg(b, 4, 64);
         } else {
             if (c.form == 2)
                 c = ordered_cfg(b, precision, kind, n_cu);
-            c.form = (int)g_opt.pair_form;
+            c.form = want;
         }
     }
     if (g_opt.tile_r > 0 && kind == 0)
@@ -395,6 +400,8 @@ bool cfg_supported(const TileCfg &c, int kind)
 {
     if (kind == 0 && c.form == 2)
         return ((c.R == 4 || c.R == 8) && c.tpb == 64) || (c.R == 4 && c.tpb == 128);
+    if (kind == 1 && c.form == 2)
+        return c.R == 4 && c.tpb == 64;
     if (kind == 0)
         return (c.R == 1 || c.R == 2 || c.R == 4) && (c.tpb == 128 || c.tpb == 256) &&
                c.slices >= 1 && (c.form == 0 || c.form == 1);
@@ -666,7 +673,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
     if (it != g_tuned.end()) {
         cfg = it->second;
     } else {
-        cfg = heuristic_cfg(b, precision, kind, n_cu);
+        cfg = heuristic_cfg(b, precision, kind, n_cu, n_cot);
         if (g_opt.autotune && x && m) {
             // time candidates on the live data; scratch outputs only
             std::vector<TileCfg> cand;
@@ -687,6 +694,8 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                             }
                 }
             } else {
+                if (precision != COLATUS_FP64 && b.max_n <= kSymMaxN && n_cot <= kSymMaxCot)
+                    cand.push_back(symmetric_cfg(b, 4, 64));
                 for (int r : {1, 2})
                     for (int per_cu : {4, 8, 16}) {
                         TileCfg c{r, 256, slices_for(b, r, 256, per_cu, n_cu), 0};

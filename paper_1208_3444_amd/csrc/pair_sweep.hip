@@ -24,6 +24,7 @@
 #include "colatus_internal.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace colatus {
 namespace {
@@ -628,6 +629,210 @@ __attribute__((amdgpu_waves_per_eu(R * W == 4 ? 6 : 1))) void pair_sweep_sym_ker
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric adjoint sweep (form 2, FP32 pairs, one cotangent per launch).
+// The adjoint pair term M(d)(m_k lam_j - m_j lam_k), M(d) = r^-3 I -
+// 3 r^-5 d d^T, changes sign when k and j swap (M(-d) = M(d)), so each
+// unordered pair is evaluated once, with the work items, slots and DPP
+// rotation of the symmetric forward sweep; the travelling source carries
+// its position, cotangent (and mass) and the accumulator of its reaction.
+// Missing sources and targets sit at 1e18 with zero mass and cotangent: s
+// stays finite in FP32 (3e36) while r^-3 underflows to 0, so d.u stays
+// finite and the pair adds exactly 0.
+// ---------------------------------------------------------------------------
+template <int R, bool REACT, bool EQM, bool MASK>
+__device__ __forceinline__ void sym_adj_chunk(float sx, float sy, float sz, float sm, float slx,
+                                              float sly, float slz, float &qx, float &qy,
+                                              float &qz, const float (&xi)[R],
+                                              const float (&yi)[R], const float (&zi)[R],
+                                              const float (&mk)[R], const float (&lkx)[R],
+                                              const float (&lky)[R], const float (&lkz)[R],
+                                              float eps2, float (&ax)[R], float (&ay)[R],
+                                              float (&az)[R])
+{
+#pragma unroll 2
+    for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float dx = sx - xi[r];
+            const float dy = sy - yi[r];
+            const float dz = sz - zi[r];
+            float s = fmaf(dx, dx, eps2);
+            s = fmaf(dy, dy, s);
+            s = fmaf(dz, dz, s);
+            float rinv = __builtin_amdgcn_rsqf(s);
+            if constexpr (MASK)
+                rinv = s > 0.0f ? rinv : 0.0f;
+            const float r2 = rinv * rinv;
+            const float r3 = r2 * rinv;
+            const float m3r5 = -3.0f * (r3 * r2);
+            float ux, uy, uz;
+            if constexpr (EQM) {
+                ux = slx - lkx[r];
+                uy = sly - lky[r];
+                uz = slz - lkz[r];
+            } else {
+                // both products rounded before the difference, so that the
+                // self pair (j = k, inside a diagonal part) gives u = 0
+                // exactly; a fused m_k lam_j - m_j lam_k would leave the
+                // product's rounding error, which r^-3 = eps^-3 amplifies
+#pragma clang fp contract(off)
+                ux = mk[r] * slx - sm * lkx[r];
+                uy = mk[r] * sly - sm * lky[r];
+                uz = mk[r] * slz - sm * lkz[r];
+            }
+            const float du = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+            const float t = m3r5 * du;
+            const float vx = fmaf(t, dx, r3 * ux);
+            const float vy = fmaf(t, dy, r3 * uy);
+            const float vz = fmaf(t, dz, r3 * uz);
+            ax[r] += vx;
+            ay[r] += vy;
+            az[r] += vz;
+            if constexpr (REACT) {
+                qx -= vx;
+                qy -= vy;
+                qz -= vz;
+            }
+        }
+        sx = wave_rotate(sx);
+        sy = wave_rotate(sy);
+        sz = wave_rotate(sz);
+        slx = wave_rotate(slx);
+        sly = wave_rotate(sly);
+        slz = wave_rotate(slz);
+        if constexpr (!EQM)
+            sm = wave_rotate(sm);
+        if constexpr (REACT) {
+            qx = wave_rotate(qx);
+            qy = wave_rotate(qy);
+            qz = wave_rotate(qz);
+        }
+    }
+}
+
+// One work item of the symmetric adjoint sweep, cotangent c of n_cot; parts
+// of at most 256 particles (one FP32 partial per slot, as in the forward).
+template <int R, bool REACT, bool MASK>
+__device__ __forceinline__ void sym_adj_item(const WorkItem &w, const double *__restrict__ X,
+                                             const double *__restrict__ Y,
+                                             const double *__restrict__ Z,
+                                             const double *__restrict__ m,
+                                             const double *__restrict__ lam, int n_cot, int c,
+                                             int64_t N, const double *__restrict__ box_mass,
+                                             double *__restrict__ part, double (*red)[6])
+{
+    const int lane = threadIdx.x & 63;
+    const double mbox = box_mass ? box_mass[w.box] : NAN;
+    const bool eqm = !isnan(mbox);
+    const double *LX = lam + ((int64_t)c * 3 + 0) * N;
+    const double *LY = lam + ((int64_t)c * 3 + 1) * N;
+    const double *LZ = lam + ((int64_t)c * 3 + 2) * N;
+
+    double tx[R], ty[R], tz[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        valid[r] = i < w.i1;
+        const int64_t ii = valid[r] ? i : w.i0;
+        tx[r] = X[ii];
+        ty[r] = Y[ii];
+        tz[r] = Z[ii];
+    }
+    double cx, cy, cz;
+    block_centre<64, R>(tx, ty, tz, valid, red, cx, cy, cz);
+    cx = uniform(cx);
+    cy = uniform(cy);
+    cz = uniform(cz);
+
+    float xi[R], yi[R], zi[R], mk[R], lkx[R], lky[R], lkz[R];
+    float ax[R], ay[R], az[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        if (valid[r]) {
+            xi[r] = (float)(tx[r] - cx);
+            yi[r] = (float)(ty[r] - cy);
+            zi[r] = (float)(tz[r] - cz);
+            mk[r] = (float)m[i];
+            lkx[r] = (float)LX[i];
+            lky[r] = (float)LY[i];
+            lkz[r] = (float)LZ[i];
+        } else {
+            xi[r] = yi[r] = zi[r] = 1e18f;
+            mk[r] = lkx[r] = lky[r] = lkz[r] = 0.0f;
+        }
+        ax[r] = ay[r] = az[r] = 0.0f;
+    }
+    const float eps2 = uniform((float)w.eps2);
+    const double scale = eqm ? mbox : 1.0;
+    const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
+
+    for (int ch = 0; ch < n_chunks; ++ch) {
+        const int64_t j = w.j0 + (int64_t)ch * 64 + lane;
+        const bool jv = j < w.j1;
+        float sx = 1e18f, sy = 1e18f, sz = 1e18f, sm = 0.0f;
+        float slx = 0.0f, sly = 0.0f, slz = 0.0f;
+        if (jv) {
+            sx = (float)(X[j] - cx);
+            sy = (float)(Y[j] - cy);
+            sz = (float)(Z[j] - cz);
+            sm = (float)m[j];
+            slx = (float)LX[j];
+            sly = (float)LY[j];
+            slz = (float)LZ[j];
+        }
+        float qx = 0.0f, qy = 0.0f, qz = 0.0f;
+        if (eqm)
+            sym_adj_chunk<R, REACT, true, MASK>(sx, sy, sz, sm, slx, sly, slz, qx, qy, qz, xi, yi,
+                                                zi, mk, lkx, lky, lkz, eps2, ax, ay, az);
+        else
+            sym_adj_chunk<R, REACT, false, MASK>(sx, sy, sz, sm, slx, sly, slz, qx, qy, qz, xi,
+                                                 yi, zi, mk, lkx, lky, lkz, eps2, ax, ay, az);
+        if constexpr (REACT) {
+            if (jv) {
+                const int64_t rs = (int64_t)w.rslice;
+                part[((rs * n_cot + c) * 3 + 0) * N + j] = scale * (double)qx;
+                part[((rs * n_cot + c) * 3 + 1) * N + j] = scale * (double)qy;
+                part[((rs * n_cot + c) * 3 + 2) * N + j] = scale * (double)qz;
+            }
+        }
+    }
+    const int64_t slot = (int64_t)w.slice;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!valid[r])
+            continue;
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        part[((slot * n_cot + c) * 3 + 0) * N + i] = scale * (double)ax[r];
+        part[((slot * n_cot + c) * 3 + 1) * N + i] = scale * (double)ay[r];
+        part[((slot * n_cot + c) * 3 + 2) * N + i] = scale * (double)az[r];
+    }
+}
+
+template <int R, bool MASK>
+__global__ __launch_bounds__(64) void adjoint_sweep_sym_kernel(
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
+    const double *__restrict__ lam, int n_cot, int c, const WorkItem *__restrict__ items,
+    int n_items, int *__restrict__ counter, int persistent, const double *__restrict__ box_mass,
+    double *__restrict__ part)
+{
+    __shared__ double red[1][6];
+    __shared__ int s_item;
+    const double *X = x, *Y = x + N, *Z = x + 2 * N;
+    for (int iter = 0;; ++iter) {
+        const int it = next_item(persistent, counter, &s_item, iter);
+        if (it >= n_items)
+            break;
+        const WorkItem w = items[it];
+        if (w.kind == 0)
+            sym_adj_item<R, true, MASK>(w, X, Y, Z, m, lam, n_cot, c, N, box_mass, part, red);
+        else
+            sym_adj_item<1, false, MASK>(w, X, Y, Z, m, lam, n_cot, c, N, box_mass, part, red);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint sweep: sum_j M(d)(m_k lam_j - m_j lam_k), M(d) = r^-3 I - 3 r^-5 d d^T,
 // for C cotangents sharing the geometry.  lam is [n_cot][3][N]; this launch
 // handles cotangents [c0, c0 + C).  part is [slices][n_cot][3][N].
@@ -672,9 +877,12 @@ __device__ __forceinline__ void adjoint_tile(const V *__restrict__ tile,
                     uy = lt[3 * c + 1] - lk[r][3 * c + 1];
                     uz = lt[3 * c + 2] - lk[r][3 * c + 2];
                 } else {
-                    ux = fma_t(mk[r], lt[3 * c + 0], -(pj.w * lk[r][3 * c + 0]));
-                    uy = fma_t(mk[r], lt[3 * c + 1], -(pj.w * lk[r][3 * c + 1]));
-                    uz = fma_t(mk[r], lt[3 * c + 2], -(pj.w * lk[r][3 * c + 2]));
+                    // rounded products, then the difference: u = 0 exactly
+                    // for the self pair (see the symmetric loop)
+#pragma clang fp contract(off)
+                    ux = mk[r] * lt[3 * c + 0] - pj.w * lk[r][3 * c + 0];
+                    uy = mk[r] * lt[3 * c + 1] - pj.w * lk[r][3 * c + 1];
+                    uz = mk[r] * lt[3 * c + 2] - pj.w * lk[r][3 * c + 2];
                 }
                 const T du = fma_t(dx, ux, fma_t(dy, uy, dz * uz));
                 const T t = m3r5 * du;
@@ -978,12 +1186,41 @@ hipError_t launch_adj(bool mask, const double *x, const double *m, int64_t N, co
     return hipGetLastError();
 }
 
+template <bool MASK>
+hipError_t launch_adj_sym(const double *x, const double *m, int64_t N, const double *lam,
+                          int n_cot, const WorkItem *items, int n_items, int *counter,
+                          bool persistent, const double *box_mass, double *part, hipStream_t s)
+{
+    auto k = adjoint_sweep_sym_kernel<4, MASK>;
+    const int grid = persistent ? persistent_grid(k, 64, 0, n_items) : n_items;
+    for (int c = 0; c < n_cot; ++c) {
+        if (c > 0 && persistent)
+            hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64), 0, s, x, m, N, lam, n_cot, c, items, n_items,
+                           counter, persistent ? 1 : 0, box_mass, part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T, int ACC>
 hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const double *m,
                         int64_t N, int n_cot, const double *lam, const WorkItem *items,
                         int n_items, int *counter, bool persistent, const double *box_mass,
                         double *part, hipStream_t s)
 {
+    if constexpr (!std::is_same<T, double>::value) {
+        if (cfg.form == 2) {
+            if (cfg.R != 4 || cfg.tpb != 64)
+                return hipErrorInvalidValue;
+            return mask ? launch_adj_sym<true>(x, m, N, lam, n_cot, items, n_items, counter,
+                                               persistent, box_mass, part, s)
+                        : launch_adj_sym<false>(x, m, N, lam, n_cot, items, n_items, counter,
+                                                persistent, box_mass, part, s);
+        }
+    }
     // Cotangents in chunks of 8, then 4, then 1; the work counter is re-armed
     // before every chunk after the first.
     int c0 = 0;

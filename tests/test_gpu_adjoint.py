@@ -139,3 +139,23 @@ def test_ftle_matches_oracle(dev):
     ltm, _, _ = colatus.ftle(*args, w.eps, w.G, w.cosmo, 0.2, 1.0, 12, tracers,
                              checkpoint_every=5, precision="mixed_twosum")
     assert np.max(np.abs(ltm - lt_r)) <= 1e-3 * max(1.0, np.abs(lt_r).max())
+
+
+@pytest.mark.parametrize("form", [0, 2])
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_force_vjp_few_particles_self_pair_adds_nothing(dev, form, N):
+    """With unequal masses the self pair's bracket m_k lam_k - m_k lam_k must be
+    exactly 0 (both products rounded before the difference); a fused form
+    leaves the rounding error of one product, which r^-3 = eps^-3 turns into
+    an error that dominates sums over few particles."""
+    x, m = inputs.random_cloud(N, 70 + N, scale=0.5)
+    lam = np.random.default_rng(N).standard_normal((1, 3, N))
+    xt, mt, lt = to_dev(x, dev), to_dev(m, dev), to_dev(lam, dev)
+    ref = oracle.force_vjp(x, m, lam[0], 0.01)
+    colatus.set_option(colatus.OPT_PAIR_FORM, form)
+    try:
+        for prec, tol in (("fp64", 1e-12), ("mixed_twosum", 1e-6), ("fp32", 1e-6)):
+            got = colatus.force_vjp(xt, mt, lt, 0.01, 1.0, precision=prec).cpu().numpy()
+            assert _rel(got[0], ref) <= tol, prec
+    finally:
+        colatus.set_option(colatus.OPT_PAIR_FORM, -1)

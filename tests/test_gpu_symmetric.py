@@ -168,3 +168,69 @@ def test_lcdm_32cubed_sampled(dev, form2):
     e = rel_err_per_particle(a1[:, t], ref)
     print(f"form 2 32^3: median {np.median(e):.3e} max {e.max():.3e}")
     assert np.median(e) <= 1e-6 and e.max() <= 1e-4
+
+
+# ---- symmetric adjoint sweep (form 2, one cotangent per launch) -------------
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("N,C,spread,eps", [(700, 1, True, 0.02), (700, 3, True, 0.02),
+                                            (1000, 2, False, 0.02), (257, 1, True, 0.0),
+                                            (65, 5, False, 0.01), (2, 1, True, 0.01)])
+def test_force_vjp_symmetric_matches_oracle(dev, form2, N, C, spread, eps):
+    """Transpose-Jacobian sweep M(d)(m_k lam_j - m_j lam_k), each unordered pair
+    once: per cotangent against the oracle's VJP (relative 2-norm <= 1e-5, the
+    ordered mixed loop's bar); ragged parts, unequal and equal masses,
+    softening zero, more cotangents than the heuristic would send here."""
+    x, m = inputs.random_cloud(N, 300 + N, scale=0.5, mass_spread=spread)
+    G = 1.3
+    lam = np.random.default_rng(C).standard_normal((C, 3, N))
+    xt, mt, lt = to_dev(x, dev), to_dev(m, dev), to_dev(lam, dev)
+    # Without softening the closest pairs' r^-5 terms dominate the sum, and
+    # the FP32 separation of such a pair (coordinates rounded relative to a
+    # part centre up to 0.5 away; the closest pair at N = 257 is 0.004 apart)
+    # carries a relative error up to u |x - c| / r = 8e-6, amplified about
+    # five times in M(d).
+    tol = 1e-5 if eps > 0 else 5e-5
+    for prec in ("mixed_twosum", "mixed_f64acc", "fp32"):
+        got = colatus.force_vjp(xt, mt, lt, eps, G, precision=prec).cpu().numpy()
+        assert np.all(np.isfinite(got))
+        for c in range(C):
+            ref = oracle.force_vjp(x, m, lam[c], eps, G=G)
+            e = _rel(got[c], ref)
+            print(f"N={N} C={C} {prec} cot {c}: {e:.2e}", flush=True)
+            assert e <= tol
+
+
+def test_force_vjp_symmetric_is_the_default_for_few_cotangents(dev):
+    assert colatus.tile_config(700, "mixed_twosum", kind=1)[3] == 2
+    x, m = inputs.random_cloud(700, 9, scale=0.5)
+    lam = np.random.default_rng(1).standard_normal((1, 3, 700))
+    xt, mt, lt = to_dev(x, dev), to_dev(m, dev), to_dev(lam, dev)
+    a = colatus.force_vjp(xt, mt, lt, 0.02, 1.0, precision="mixed_twosum").cpu().numpy()
+    colatus.set_option(colatus.OPT_PAIR_FORM, 0)
+    try:
+        b = colatus.force_vjp(xt, mt, lt, 0.02, 1.0, precision="mixed_twosum").cpu().numpy()
+    finally:
+        colatus.set_option(colatus.OPT_PAIR_FORM, -1)
+    ref = oracle.force_vjp(x, m, lam[0], 0.02)
+    assert _rel(a[0], ref) <= 1e-5 and _rel(b[0], ref) <= 1e-5
+    assert not np.array_equal(a, b)  # the two loops really differ
+
+
+def test_adjoint_run_symmetric_close_to_fp64_gradient(dev, form2):
+    w = inputs.lcdm_grf(8, seed=4, a_begin=0.2, n_steps=20)
+    v0 = w.velocities(oracle.hubble(0.2, *w.cosmo.values()))
+    tr = np.arange(0, w.N, 37)
+    xN, vN = oracle.run(w.x, v0, w.m, w.eps, w.G, w.cosmo, 0.2, 1.0, 20)
+    lv = np.zeros((3, w.N))
+    lv[:, tr] = 2 * vN[:, tr]
+    lx = np.zeros((3, w.N))
+    gx_r, gv_r, _, _ = oracle.adjoint(w.x, v0, w.m, w.eps, w.G, w.cosmo, 0.2, 1.0, 20, lx, lv)
+    args = [to_dev(a, dev) for a in (w.x, v0, w.m)]
+    gx, gv = colatus.adjoint(*args, w.eps, w.G, w.cosmo, 0.2, 1.0, 20, to_dev(lx, dev),
+                             to_dev(lv, dev), checkpoint_every=6, precision="mixed_twosum")
+    assert _rel(gx.cpu().numpy(), gx_r) <= 1e-3
+    assert _rel(gv.cpu().numpy(), gv_r) <= 1e-3
