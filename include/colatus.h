@@ -205,12 +205,14 @@ const char *colatus_strerror(int code);
 #define COLATUS_OPT_AUTOTUNE   3  /* 1: time candidate tile shapes on first use of an
                                      (N bucket, precision) and keep the fastest
                                      (default 0: built-in heuristic)                 */
-#define COLATUS_OPT_TILE_R     4  /* >0: force targets per lane (forms 0, 1: 1, 2, 4;
-                                     form 2: 4, 8); 0 = auto                         */
-#define COLATUS_OPT_TILE_TPB   5  /* >0: force threads per block (forms 0, 1: 128,
-                                     256; form 2: 64, or 128 with R = 4); 0 = auto.
-                                     An unsupported combination makes the forward
-                                     calls return COLATUS_EINVAL                     */
+#define COLATUS_OPT_TILE_R     4  /* >0: force targets per lane of the forward sweep
+                                     (forms 0, 1: 1, 2, 4; form 2: 4 or 8 with 64
+                                     threads, or 4 with 128 for FP32 pairs; 4 with
+                                     64, or 2 with 128 for FP64); 0 = auto          */
+#define COLATUS_OPT_TILE_TPB   5  /* >0: force threads per block of the forward sweep
+                                     (forms 0, 1: 128, 256; form 2: see TILE_R);
+                                     0 = auto.  An unsupported combination makes
+                                     the forward calls return COLATUS_EINVAL         */
 #define COLATUS_OPT_TILE_SLICES 6 /* >0: force the number of source slices (forms 0,
                                      1; form 2 derives its slots from the parts);
                                      0 = auto                                        */
@@ -220,7 +222,7 @@ const char *colatus_strerror(int code);
                                      workgroup per work item, in the same LPT order,
                                      left to the hardware dispatcher (measured
                                      faster on gfx950)                               */
-#define COLATUS_OPT_PAIR_FORM  8  /* FP32 pair loop: 0 = ordered pairs, weight
+#define COLATUS_OPT_PAIR_FORM  8  /* pair loop: 0 = ordered pairs, weight
                                      m r^-1 (r^-1)^2; 1 = ordered pairs, weight
                                      m r^-1 rcp(r^2) (one VALU multiply fewer, one
                                      more transcendental; the adjoint treats 1 as 0);
@@ -232,7 +234,7 @@ const char *colatus_strerror(int code);
                                      heuristic's or the autotuner's choice (2 for
                                      the forward up to 2^17 particles per box and
                                      for the adjoint with up to 3 cotangents, else
-                                     0).  FP64 always uses 0                         */
+                                     0).  FP64 pairs: 1 means 0                      */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

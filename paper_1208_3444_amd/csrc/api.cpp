@@ -343,13 +343,13 @@ constexpr int64_t kSymMaxN = 131072;
 // cotangent); more share the geometry in the ordered form's chunks of 8.
 constexpr int kSymMaxCot = 3;
 
-// Built-in heuristic: FP32 forward sweeps use the symmetric form (each
-// unordered pair once, one wave per item, four targets per lane), measured
-// 1.36x faster than the ordered form at 32^3; so does the FP32 adjoint with
-// few cotangents.  FP64 uses the ordered form.
+// Built-in heuristic: forward sweeps use the symmetric form (each unordered
+// pair once, one wave per item, four targets per lane), measured at 32^3
+// 1.36x (FP32 pairs) and 1.41x (FP64) faster than the ordered form; so does
+// the adjoint with few cotangents (1.27x and 1.84x).
 TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu, int n_cot = 1)
 {
-    if (precision != COLATUS_FP64 && b.max_n <= kSymMaxN && (kind == 0 || n_cot <= kSymMaxCot))
+    if (b.max_n <= kSymMaxN && (kind == 0 || n_cot <= kSymMaxCot))
         return symmetric_cfg(b, 4, 64);
     return ordered_cfg(b, precision, kind, n_cu);
 }
@@ -374,9 +374,11 @@ TileCfg symmetric_cfg(const Boxes &b, int R, int tpb)
 
 TileCfg apply_overrides(TileCfg c, int kind, int precision, const Boxes &b, int n_cu)
 {
-    // the adjoint has one ordered loop: form 1 means form 0 there
-    const int want = kind == 1 && g_opt.pair_form == 1 ? 0 : (int)g_opt.pair_form;
-    if (precision != COLATUS_FP64 && want >= 0 && want != c.form) {
+    // the adjoint and FP64 have one ordered loop: form 1 means form 0 there
+    int want = (int)g_opt.pair_form;
+    if (want == 1 && (kind == 1 || precision == COLATUS_FP64))
+        want = 0;
+    if (want >= 0 && want != c.form) {
         if (want == 2) {
             c = symmetric_cfg(b, 4, 64);
         } else {
@@ -396,8 +398,11 @@ TileCfg apply_overrides(TileCfg c, int kind, int precision, const Boxes &b, int 
     return c;
 }
 
-bool cfg_supported(const TileCfg &c, int kind)
+bool cfg_supported(const TileCfg &c, int kind, int precision)
 {
+    const bool fp64 = precision == COLATUS_FP64;
+    if (kind == 0 && c.form == 2 && fp64)
+        return (c.R == 4 && c.tpb == 64) || (c.R == 2 && c.tpb == 128);
     if (kind == 0 && c.form == 2)
         return ((c.R == 4 || c.R == 8) && c.tpb == 64) || (c.R == 4 && c.tpb == 128);
     if (kind == 1 && c.form == 2)
@@ -679,10 +684,15 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
             std::vector<TileCfg> cand;
             if (kind == 0) {
                 const bool fp32 = precision != COLATUS_FP64;
-                if (fp32 && b.max_n <= kSymMaxN)
-                    for (auto rt : {std::make_pair(4, 64), std::make_pair(8, 64),
-                                    std::make_pair(4, 128)})
-                        cand.push_back(symmetric_cfg(b, rt.first, rt.second));
+                if (b.max_n <= kSymMaxN) {
+                    if (fp32)
+                        for (auto rt : {std::make_pair(4, 64), std::make_pair(8, 64),
+                                        std::make_pair(4, 128)})
+                            cand.push_back(symmetric_cfg(b, rt.first, rt.second));
+                    else
+                        for (auto rt : {std::make_pair(4, 64), std::make_pair(2, 128)})
+                            cand.push_back(symmetric_cfg(b, rt.first, rt.second));
+                }
                 for (int form : {0, 1}) {
                     if (form == 1 && !fp32)
                         continue;
@@ -694,7 +704,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                             }
                 }
             } else {
-                if (precision != COLATUS_FP64 && b.max_n <= kSymMaxN && n_cot <= kSymMaxCot)
+                if (b.max_n <= kSymMaxN && n_cot <= kSymMaxCot)
                     cand.push_back(symmetric_cfg(b, 4, 64));
                 for (int r : {1, 2})
                     for (int per_cu : {4, 8, 16}) {
@@ -751,7 +761,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
         }
     }
     cfg = apply_overrides(cfg, kind, precision, b, n_cu);
-    if (!cfg_supported(cfg, kind))
+    if (!cfg_supported(cfg, kind, precision))
         return COLATUS_EINVAL;
     WorkList &wl = kind == 0 ? ws->fwd : ws->adj;
     CHECK_RC(ensure_worklist(ws, wl, b, N, cfg, s));

@@ -348,42 +348,60 @@ __device__ __forceinline__ float wave_rotate(float v)
     return __builtin_bit_cast(
         float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, true));
 }
+__device__ __forceinline__ double wave_rotate(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x13C, 0xF, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x13C, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Far-away coordinate of a missing target or source of the symmetric loops.
+// Forward: s overflows (FP32) or r^-3 underflows (FP64) and the pair adds 0.
+// Adjoint: s must stay finite so that d.u does (r^-3 underflows to 0).
+template <typename T> __device__ __forceinline__ T sym_pad();
+template <> __device__ __forceinline__ float sym_pad<float>() { return 1e30f; }
+template <> __device__ __forceinline__ double sym_pad<double>() { return 1e150; }
+template <typename T> __device__ __forceinline__ T adj_pad();
+template <> __device__ __forceinline__ float adj_pad<float>() { return 1e18f; }
+template <> __device__ __forceinline__ double adj_pad<double>() { return 1e150; }
 
 // 64 steps of one source chunk against the lane's R targets.  REACT: also
 // accumulate the reaction on the travelling source (q*); EQM: the box's common
 // mass leaves the loop (weights r^-3 and r^-1 only).
-template <int R, bool REACT, bool EQM, bool PHI, bool MASK>
-__device__ __forceinline__ void sym_chunk(float sx, float sy, float sz, float sm, float &qx,
-                                          float &qy, float &qz, float &qp, const float (&xi)[R],
-                                          const float (&yi)[R], const float (&zi)[R],
-                                          const float (&mi)[R], float eps2, float (&ax)[R],
-                                          float (&ay)[R], float (&az)[R], float (&ap)[R])
+template <typename T, int R, bool REACT, bool EQM, bool PHI, bool MASK>
+__device__ __forceinline__ void sym_chunk(T sx, T sy, T sz, T sm, T &qx,
+                                          T &qy, T &qz, T &qp, const T (&xi)[R],
+                                          const T (&yi)[R], const T (&zi)[R],
+                                          const T (&mi)[R], T eps2, T (&ax)[R],
+                                          T (&ay)[R], T (&az)[R], T (&ap)[R])
 {
 #pragma unroll 2
     for (int k = 0; k < 64; ++k) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float dx = sx - xi[r];
-            const float dy = sy - yi[r];
-            const float dz = sz - zi[r];
-            float s = fmaf(dx, dx, eps2);
-            s = fmaf(dy, dy, s);
-            s = fmaf(dz, dz, s);
-            float rinv = __builtin_amdgcn_rsqf(s);
+            const T dx = sx - xi[r];
+            const T dy = sy - yi[r];
+            const T dz = sz - zi[r];
+            T s = fma_t(dx, dx, eps2);
+            s = fma_t(dy, dy, s);
+            s = fma_t(dz, dz, s);
+            T rinv = rsqrt_t(s);
             if constexpr (MASK)
-                rinv = s > 0.0f ? rinv : 0.0f;
-            const float w = rinv * (rinv * rinv);
-            const float wt = EQM ? w : sm * w;
-            ax[r] = fmaf(wt, dx, ax[r]);
-            ay[r] = fmaf(wt, dy, ay[r]);
-            az[r] = fmaf(wt, dz, az[r]);
+                rinv = s > (T)0.0 ? rinv : (T)0.0;
+            const T w = rinv * (rinv * rinv);
+            const T wt = EQM ? w : sm * w;
+            ax[r] = fma_t(wt, dx, ax[r]);
+            ay[r] = fma_t(wt, dy, ay[r]);
+            az[r] = fma_t(wt, dz, az[r]);
             if constexpr (PHI)
                 ap[r] += EQM ? rinv : sm * rinv;
             if constexpr (REACT) {
-                const float ws = EQM ? w : mi[r] * w;
-                qx = fmaf(-ws, dx, qx);
-                qy = fmaf(-ws, dy, qy);
-                qz = fmaf(-ws, dz, qz);
+                const T ws = EQM ? w : mi[r] * w;
+                qx = fma_t(-ws, dx, qx);
+                qy = fma_t(-ws, dy, qy);
+                qz = fma_t(-ws, dz, qz);
                 if constexpr (PHI)
                     qp += EQM ? rinv : mi[r] * rinv;
             }
@@ -411,7 +429,7 @@ __device__ __forceinline__ void sym_chunk(float sx, float sy, float sz, float sm
 // are folded every 256 sources; with at most 256 every partial sum (a
 // target's from one part, a source's reaction from one part) is a single
 // FP32 sum of at most 256 terms, like the ordered loop's per-tile partials.
-template <int ACC, int R, int W, bool FOLD, bool REACT, bool PHI, bool MASK>
+template <typename T, int ACC, int R, int W, bool FOLD, bool REACT, bool PHI, bool MASK>
 __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__restrict__ X,
                                          const double *__restrict__ Y,
                                          const double *__restrict__ Z,
@@ -419,7 +437,7 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
                                          const double *__restrict__ box_mass,
                                          double *__restrict__ part,
                                          double *__restrict__ part_phi, double (*red)[6],
-                                         float (*react)[W][PHI ? 4 : 3][64])
+                                         T (*react)[W][PHI ? 4 : 3][64])
 {
     constexpr int TPB = 64 * W;
     constexpr int NQ = PHI ? 4 : 3;
@@ -446,50 +464,50 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
 
     // Missing targets sit far away with zero mass: they neither pull nor are
     // pulled (FP32 s overflows to +inf, r^-1 = 0).
-    float xi[R], yi[R], zi[R], mi[R];
-    float ax[R], ay[R], az[R], ap[R];
-    float hx[R], hy[R], hz[R], hp[R];
+    T xi[R], yi[R], zi[R], mi[R];
+    T ax[R], ay[R], az[R], ap[R];
+    float hx[R], hy[R], hz[R], hp[R];  // TwoSum (FP32 pairs only)
     float lx[R], ly[R], lz[R], lp[R];
     double bx[R], by[R], bz[R], bp[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = w.i0 + (int64_t)(wave * 64 * R + r * 64 + lane);
         if (valid[r]) {
-            xi[r] = (float)(tx[r] - cx);
-            yi[r] = (float)(ty[r] - cy);
-            zi[r] = (float)(tz[r] - cz);
-            mi[r] = (float)m[i];
+            xi[r] = (T)(tx[r] - cx);
+            yi[r] = (T)(ty[r] - cy);
+            zi[r] = (T)(tz[r] - cz);
+            mi[r] = (T)m[i];
         } else {
-            xi[r] = yi[r] = zi[r] = 1e30f;
-            mi[r] = 0.0f;
+            xi[r] = yi[r] = zi[r] = sym_pad<T>();
+            mi[r] = (T)0.0;
         }
-        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+        ax[r] = ay[r] = az[r] = ap[r] = (T)0.0;
         if constexpr (FOLD) {
-            hx[r] = hy[r] = hz[r] = hp[r] = 0.0f;
-            lx[r] = ly[r] = lz[r] = lp[r] = 0.0f;
+            hx[r] = hy[r] = hz[r] = hp[r] = (T)0.0;
+            lx[r] = ly[r] = lz[r] = lp[r] = (T)0.0;
             bx[r] = by[r] = bz[r] = bp[r] = 0.0;
         }
     }
-    const float eps2 = uniform((float)w.eps2);
+    const T eps2 = uniform((T)w.eps2);
     const double scale = eqm ? mbox : 1.0;
     const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
 
     for (int c = 0; c < n_chunks; ++c) {
         const int64_t j = w.j0 + (int64_t)c * 64 + lane;
         const bool jv = j < w.j1;
-        float sx = 1e30f, sy = 1e30f, sz = 1e30f, sm = 0.0f;
+        T sx = sym_pad<T>(), sy = sym_pad<T>(), sz = sym_pad<T>(), sm = (T)0.0;
         if (jv) {
-            sx = (float)(X[j] - cx);
-            sy = (float)(Y[j] - cy);
-            sz = (float)(Z[j] - cz);
-            sm = (float)m[j];
+            sx = (T)(X[j] - cx);
+            sy = (T)(Y[j] - cy);
+            sz = (T)(Z[j] - cz);
+            sm = (T)m[j];
         }
-        float qx = 0.0f, qy = 0.0f, qz = 0.0f, qp = 0.0f;
+        T qx = (T)0.0, qy = (T)0.0, qz = (T)0.0, qp = (T)0.0;
         if (eqm)
-            sym_chunk<R, REACT, true, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
+            sym_chunk<T, R, REACT, true, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
                                                  eps2, ax, ay, az, ap);
         else
-            sym_chunk<R, REACT, false, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
+            sym_chunk<T, R, REACT, false, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
                                                   eps2, ax, ay, az, ap);
         if constexpr (FOLD) {
             if ((c & 3) == 3 || c == n_chunks - 1) {
@@ -501,14 +519,14 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
                         two_sum_add(hz[r], lz[r], az[r]);
                         if constexpr (PHI)
                             two_sum_add(hp[r], lp[r], ap[r]);
-                        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+                        ax[r] = ay[r] = az[r] = ap[r] = (T)0.0;
                     } else if constexpr (ACC == kFold64) {
                         bx[r] += (double)ax[r];
                         by[r] += (double)ay[r];
                         bz[r] += (double)az[r];
                         if constexpr (PHI)
                             bp[r] += (double)ap[r];
-                        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+                        ax[r] = ay[r] = az[r] = ap[r] = (T)0.0;
                     }
                 }
             }
@@ -523,7 +541,7 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
                 if constexpr (PHI)
                     o[NQ - 1] = (double)qp;
             } else {
-                float(*buf)[NQ][64] = react[c & 1];
+                T(*buf)[NQ][64] = react[c & 1];
                 buf[wave][0][lane] = qx;
                 buf[wave][1][lane] = qy;
                 buf[wave][2][lane] = qz;
@@ -533,7 +551,7 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if constexpr (ACC == kTwoSum) {
-                        float hi = buf[0][q][lane], lo = 0.0f;
+                        float hi = (float)buf[0][q][lane], lo = 0.0f;
 #pragma unroll
                         for (int v = 1; v < W; ++v)
                             two_sum_add(hi, lo, buf[v][q][lane]);
@@ -545,7 +563,7 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
                             t += (double)buf[v][q][lane];
                         o[q] = t;
                     } else {
-                        float t = buf[0][q][lane];
+                        T t = buf[0][q][lane];
 #pragma unroll
                         for (int v = 1; v < W; ++v)
                             t += buf[v][q][lane];
@@ -598,9 +616,10 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
 // One wave per workgroup with four targets per lane is held to 80 VGPRs so
 // that six waves share each SIMD (measured 10 % faster than four at 32^3;
 // two 8-byte values of the item loop spill, outside the pair loop).
-template <int ACC, int R, int W, bool PHI, bool MASK>
+template <typename T, int ACC, int R, int W, bool PHI, bool MASK>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(R * W == 4 ? 6 : 1))) void pair_sweep_sym_kernel(
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R * W == 4 ? 6 : 1))) void
+pair_sweep_sym_kernel(
     const double *__restrict__ x, const double *__restrict__ m, int64_t N,
     const WorkItem *__restrict__ items, int n_items, int *__restrict__ counter,
     int persistent, const double *__restrict__ box_mass, double *__restrict__ part,
@@ -608,7 +627,7 @@ __attribute__((amdgpu_waves_per_eu(R * W == 4 ? 6 : 1))) void pair_sweep_sym_ker
 {
     constexpr bool FOLD = 64 * R * W > 256;
     __shared__ double red[W][6];
-    __shared__ float react[W > 1 ? 2 : 1][W][PHI ? 4 : 3][64];
+    __shared__ T react[W > 1 ? 2 : 1][W][PHI ? 4 : 3][64];
     __shared__ int s_item;
     const double *X = x, *Y = x + N, *Z = x + 2 * N;
     if (step_inc && blockIdx.x == 0 && threadIdx.x == 0)
@@ -620,10 +639,10 @@ __attribute__((amdgpu_waves_per_eu(R * W == 4 ? 6 : 1))) void pair_sweep_sym_ker
             break;
         const WorkItem w = items[it];
         if (w.kind == 0)
-            sym_item<ACC, R, W, FOLD, true, PHI, MASK>(w, X, Y, Z, m, N, box_mass, part,
+            sym_item<T, ACC, R, W, FOLD, true, PHI, MASK>(w, X, Y, Z, m, N, box_mass, part,
                                                        part_phi, red, react);
         else
-            sym_item<ACC, 1, W, FOLD, false, PHI, MASK>(w, X, Y, Z, m, N, box_mass, part,
+            sym_item<T, ACC, 1, W, FOLD, false, PHI, MASK>(w, X, Y, Z, m, N, box_mass, part,
                                                         part_phi, red, react);
     }
 }
@@ -639,33 +658,33 @@ __attribute__((amdgpu_waves_per_eu(R * W == 4 ? 6 : 1))) void pair_sweep_sym_ker
 // stays finite in FP32 (3e36) while r^-3 underflows to 0, so d.u stays
 // finite and the pair adds exactly 0.
 // ---------------------------------------------------------------------------
-template <int R, bool REACT, bool EQM, bool MASK>
-__device__ __forceinline__ void sym_adj_chunk(float sx, float sy, float sz, float sm, float slx,
-                                              float sly, float slz, float &qx, float &qy,
-                                              float &qz, const float (&xi)[R],
-                                              const float (&yi)[R], const float (&zi)[R],
-                                              const float (&mk)[R], const float (&lkx)[R],
-                                              const float (&lky)[R], const float (&lkz)[R],
-                                              float eps2, float (&ax)[R], float (&ay)[R],
-                                              float (&az)[R])
+template <typename T, int R, bool REACT, bool EQM, bool MASK>
+__device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx,
+                                              T sly, T slz, T &qx, T &qy,
+                                              T &qz, const T (&xi)[R],
+                                              const T (&yi)[R], const T (&zi)[R],
+                                              const T (&mk)[R], const T (&lkx)[R],
+                                              const T (&lky)[R], const T (&lkz)[R],
+                                              T eps2, T (&ax)[R], T (&ay)[R],
+                                              T (&az)[R])
 {
 #pragma unroll 2
     for (int k = 0; k < 64; ++k) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float dx = sx - xi[r];
-            const float dy = sy - yi[r];
-            const float dz = sz - zi[r];
-            float s = fmaf(dx, dx, eps2);
-            s = fmaf(dy, dy, s);
-            s = fmaf(dz, dz, s);
-            float rinv = __builtin_amdgcn_rsqf(s);
+            const T dx = sx - xi[r];
+            const T dy = sy - yi[r];
+            const T dz = sz - zi[r];
+            T s = fma_t(dx, dx, eps2);
+            s = fma_t(dy, dy, s);
+            s = fma_t(dz, dz, s);
+            T rinv = rsqrt_t(s);
             if constexpr (MASK)
-                rinv = s > 0.0f ? rinv : 0.0f;
-            const float r2 = rinv * rinv;
-            const float r3 = r2 * rinv;
-            const float m3r5 = -3.0f * (r3 * r2);
-            float ux, uy, uz;
+                rinv = s > (T)0.0 ? rinv : (T)0.0;
+            const T r2 = rinv * rinv;
+            const T r3 = r2 * rinv;
+            const T m3r5 = -(T)3.0 * (r3 * r2);
+            T ux, uy, uz;
             if constexpr (EQM) {
                 ux = slx - lkx[r];
                 uy = sly - lky[r];
@@ -680,11 +699,11 @@ __device__ __forceinline__ void sym_adj_chunk(float sx, float sy, float sz, floa
                 uy = mk[r] * sly - sm * lky[r];
                 uz = mk[r] * slz - sm * lkz[r];
             }
-            const float du = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
-            const float t = m3r5 * du;
-            const float vx = fmaf(t, dx, r3 * ux);
-            const float vy = fmaf(t, dy, r3 * uy);
-            const float vz = fmaf(t, dz, r3 * uz);
+            const T du = fma_t(dx, ux, fma_t(dy, uy, dz * uz));
+            const T t = m3r5 * du;
+            const T vx = fma_t(t, dx, r3 * ux);
+            const T vy = fma_t(t, dy, r3 * uy);
+            const T vz = fma_t(t, dz, r3 * uz);
             ax[r] += vx;
             ay[r] += vy;
             az[r] += vz;
@@ -712,7 +731,7 @@ __device__ __forceinline__ void sym_adj_chunk(float sx, float sy, float sz, floa
 
 // One work item of the symmetric adjoint sweep, cotangent c of n_cot; parts
 // of at most 256 particles (one FP32 partial per slot, as in the forward).
-template <int R, bool REACT, bool MASK>
+template <typename T, int R, bool REACT, bool MASK>
 __device__ __forceinline__ void sym_adj_item(const WorkItem &w, const double *__restrict__ X,
                                              const double *__restrict__ Y,
                                              const double *__restrict__ Z,
@@ -745,49 +764,49 @@ __device__ __forceinline__ void sym_adj_item(const WorkItem &w, const double *__
     cy = uniform(cy);
     cz = uniform(cz);
 
-    float xi[R], yi[R], zi[R], mk[R], lkx[R], lky[R], lkz[R];
-    float ax[R], ay[R], az[R];
+    T xi[R], yi[R], zi[R], mk[R], lkx[R], lky[R], lkz[R];
+    T ax[R], ay[R], az[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
         if (valid[r]) {
-            xi[r] = (float)(tx[r] - cx);
-            yi[r] = (float)(ty[r] - cy);
-            zi[r] = (float)(tz[r] - cz);
-            mk[r] = (float)m[i];
-            lkx[r] = (float)LX[i];
-            lky[r] = (float)LY[i];
-            lkz[r] = (float)LZ[i];
+            xi[r] = (T)(tx[r] - cx);
+            yi[r] = (T)(ty[r] - cy);
+            zi[r] = (T)(tz[r] - cz);
+            mk[r] = (T)m[i];
+            lkx[r] = (T)LX[i];
+            lky[r] = (T)LY[i];
+            lkz[r] = (T)LZ[i];
         } else {
-            xi[r] = yi[r] = zi[r] = 1e18f;
-            mk[r] = lkx[r] = lky[r] = lkz[r] = 0.0f;
+            xi[r] = yi[r] = zi[r] = adj_pad<T>();
+            mk[r] = lkx[r] = lky[r] = lkz[r] = (T)0.0;
         }
-        ax[r] = ay[r] = az[r] = 0.0f;
+        ax[r] = ay[r] = az[r] = (T)0.0;
     }
-    const float eps2 = uniform((float)w.eps2);
+    const T eps2 = uniform((T)w.eps2);
     const double scale = eqm ? mbox : 1.0;
     const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
 
     for (int ch = 0; ch < n_chunks; ++ch) {
         const int64_t j = w.j0 + (int64_t)ch * 64 + lane;
         const bool jv = j < w.j1;
-        float sx = 1e18f, sy = 1e18f, sz = 1e18f, sm = 0.0f;
-        float slx = 0.0f, sly = 0.0f, slz = 0.0f;
+        T sx = adj_pad<T>(), sy = adj_pad<T>(), sz = adj_pad<T>(), sm = (T)0.0;
+        T slx = (T)0.0, sly = (T)0.0, slz = (T)0.0;
         if (jv) {
-            sx = (float)(X[j] - cx);
-            sy = (float)(Y[j] - cy);
-            sz = (float)(Z[j] - cz);
-            sm = (float)m[j];
-            slx = (float)LX[j];
-            sly = (float)LY[j];
-            slz = (float)LZ[j];
+            sx = (T)(X[j] - cx);
+            sy = (T)(Y[j] - cy);
+            sz = (T)(Z[j] - cz);
+            sm = (T)m[j];
+            slx = (T)LX[j];
+            sly = (T)LY[j];
+            slz = (T)LZ[j];
         }
-        float qx = 0.0f, qy = 0.0f, qz = 0.0f;
+        T qx = (T)0.0, qy = (T)0.0, qz = (T)0.0;
         if (eqm)
-            sym_adj_chunk<R, REACT, true, MASK>(sx, sy, sz, sm, slx, sly, slz, qx, qy, qz, xi, yi,
+            sym_adj_chunk<T, R, REACT, true, MASK>(sx, sy, sz, sm, slx, sly, slz, qx, qy, qz, xi, yi,
                                                 zi, mk, lkx, lky, lkz, eps2, ax, ay, az);
         else
-            sym_adj_chunk<R, REACT, false, MASK>(sx, sy, sz, sm, slx, sly, slz, qx, qy, qz, xi,
+            sym_adj_chunk<T, R, REACT, false, MASK>(sx, sy, sz, sm, slx, sly, slz, qx, qy, qz, xi,
                                                  yi, zi, mk, lkx, lky, lkz, eps2, ax, ay, az);
         if constexpr (REACT) {
             if (jv) {
@@ -810,7 +829,7 @@ __device__ __forceinline__ void sym_adj_item(const WorkItem &w, const double *__
     }
 }
 
-template <int R, bool MASK>
+template <typename T, int R, bool MASK>
 __global__ __launch_bounds__(64) void adjoint_sweep_sym_kernel(
     const double *__restrict__ x, const double *__restrict__ m, int64_t N,
     const double *__restrict__ lam, int n_cot, int c, const WorkItem *__restrict__ items,
@@ -826,9 +845,9 @@ __global__ __launch_bounds__(64) void adjoint_sweep_sym_kernel(
             break;
         const WorkItem w = items[it];
         if (w.kind == 0)
-            sym_adj_item<R, true, MASK>(w, X, Y, Z, m, lam, n_cot, c, N, box_mass, part, red);
+            sym_adj_item<T, R, true, MASK>(w, X, Y, Z, m, lam, n_cot, c, N, box_mass, part, red);
         else
-            sym_adj_item<1, false, MASK>(w, X, Y, Z, m, lam, n_cot, c, N, box_mass, part, red);
+            sym_adj_item<T, 1, false, MASK>(w, X, Y, Z, m, lam, n_cot, c, N, box_mass, part, red);
     }
 }
 
@@ -1088,10 +1107,10 @@ struct FwdArgs {
     hipStream_t s;
 };
 
-template <int ACC, int R, int W, bool PHI, bool MASK>
+template <typename T, int ACC, int R, int W, bool PHI, bool MASK>
 hipError_t launch_sym(const FwdArgs &a)
 {
-    auto k = pair_sweep_sym_kernel<ACC, R, W, PHI, MASK>;
+    auto k = pair_sweep_sym_kernel<T, ACC, R, W, PHI, MASK>;
     int grid = a.persistent ? persistent_grid(k, 64 * W, 0, a.n_items) : a.n_items;
     if (grid <= 0)
         return hipSuccess;
@@ -1101,23 +1120,32 @@ hipError_t launch_sym(const FwdArgs &a)
     return hipGetLastError();
 }
 
-template <int ACC, int R, int W>
+template <typename T, int ACC, int R, int W>
 hipError_t dispatch_sym_flags(bool phi, bool mask, const FwdArgs &a)
 {
     if (phi)
-        return mask ? launch_sym<ACC, R, W, true, true>(a) : launch_sym<ACC, R, W, true, false>(a);
-    return mask ? launch_sym<ACC, R, W, false, true>(a) : launch_sym<ACC, R, W, false, false>(a);
+        return mask ? launch_sym<T, ACC, R, W, true, true>(a)
+                    : launch_sym<T, ACC, R, W, true, false>(a);
+    return mask ? launch_sym<T, ACC, R, W, false, true>(a)
+                : launch_sym<T, ACC, R, W, false, false>(a);
 }
 
-template <int ACC>
+template <typename T, int ACC>
 hipError_t dispatch_sym(const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
 {
-    if (cfg.R == 4 && cfg.tpb == 64)
-        return dispatch_sym_flags<ACC, 4, 1>(phi, mask, a);
-    if (cfg.R == 8 && cfg.tpb == 64)
-        return dispatch_sym_flags<ACC, 8, 1>(phi, mask, a);
-    if (cfg.R == 4 && cfg.tpb == 128)
-        return dispatch_sym_flags<ACC, 4, 2>(phi, mask, a);
+    if constexpr (sizeof(T) == 4) {
+        if (cfg.R == 4 && cfg.tpb == 64)
+            return dispatch_sym_flags<T, ACC, 4, 1>(phi, mask, a);
+        if (cfg.R == 8 && cfg.tpb == 64)
+            return dispatch_sym_flags<T, ACC, 8, 1>(phi, mask, a);
+        if (cfg.R == 4 && cfg.tpb == 128)
+            return dispatch_sym_flags<T, ACC, 4, 2>(phi, mask, a);
+    } else {
+        if (cfg.R == 4 && cfg.tpb == 64)
+            return dispatch_sym_flags<T, ACC, 4, 1>(phi, mask, a);
+        if (cfg.R == 2 && cfg.tpb == 128)
+            return dispatch_sym_flags<T, ACC, 2, 2>(phi, mask, a);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -1161,7 +1189,7 @@ template <typename T, int ACC>
 hipError_t dispatch_fwd_form(int form, const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
 {
     if (form == 2)
-        return dispatch_sym<ACC>(cfg, phi, mask, a);
+        return dispatch_sym<T, ACC>(cfg, phi, mask, a);
     if (form == 1)
         return dispatch_fwd_shape<T, ACC, 1>(cfg, phi, mask, a);
     return dispatch_fwd_shape<T, ACC, 0>(cfg, phi, mask, a);
@@ -1186,12 +1214,12 @@ hipError_t launch_adj(bool mask, const double *x, const double *m, int64_t N, co
     return hipGetLastError();
 }
 
-template <bool MASK>
+template <typename T, int R, bool MASK>
 hipError_t launch_adj_sym(const double *x, const double *m, int64_t N, const double *lam,
                           int n_cot, const WorkItem *items, int n_items, int *counter,
                           bool persistent, const double *box_mass, double *part, hipStream_t s)
 {
-    auto k = adjoint_sweep_sym_kernel<4, MASK>;
+    auto k = adjoint_sweep_sym_kernel<T, R, MASK>;
     const int grid = persistent ? persistent_grid(k, 64, 0, n_items) : n_items;
     for (int c = 0; c < n_cot; ++c) {
         if (c > 0 && persistent)
@@ -1211,15 +1239,13 @@ hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const do
                         int n_items, int *counter, bool persistent, const double *box_mass,
                         double *part, hipStream_t s)
 {
-    if constexpr (!std::is_same<T, double>::value) {
-        if (cfg.form == 2) {
-            if (cfg.R != 4 || cfg.tpb != 64)
-                return hipErrorInvalidValue;
-            return mask ? launch_adj_sym<true>(x, m, N, lam, n_cot, items, n_items, counter,
-                                               persistent, box_mass, part, s)
-                        : launch_adj_sym<false>(x, m, N, lam, n_cot, items, n_items, counter,
-                                                persistent, box_mass, part, s);
-        }
+    if (cfg.form == 2) {
+        if (cfg.R != 4 || cfg.tpb != 64)
+            return hipErrorInvalidValue;
+        return mask ? launch_adj_sym<T, 4, true>(x, m, N, lam, n_cot, items, n_items, counter,
+                                                 persistent, box_mass, part, s)
+                    : launch_adj_sym<T, 4, false>(x, m, N, lam, n_cot, items, n_items, counter,
+                                                  persistent, box_mass, part, s);
     }
     // Cotangents in chunks of 8, then 4, then 1; the work counter is re-armed
     // before every chunk after the first.
@@ -1277,6 +1303,8 @@ hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool w
                     step_inc, stream};
     switch (precision) {
     case kFP64:
+        if (form == 2)
+            return dispatch_sym<double, kDirect>(cfg, with_phi, mask_self, a);
         return dispatch_fwd_shape<double, kDirect, 0>(cfg, with_phi, mask_self, a);
     case kMixedTwoSum:
         return dispatch_fwd_form<float, kTwoSum>(form, cfg, with_phi, mask_self, a);

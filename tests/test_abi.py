@@ -156,19 +156,22 @@ def test_options_and_tile_config():
     assert L.colatus_set_option(4, 3) == EINVAL
     assert L.colatus_set_option(5, 32) == EINVAL
     assert L.colatus_set_option(99, 0) == EINVAL
-    # FP32 forward sweeps: symmetric form, parts of 4 x 64 particles
+    # forward sweeps and the few-cotangent adjoint: symmetric form, parts of
+    # 4 x 64 particles
     assert colatus.tile_config(32768, "mixed") == (4, 64, 128, 2)
     assert colatus.tile_config(1000, "fp32") == (4, 64, 4, 2)
-    # beyond 2^17 particles in a box (or FP64, or the adjoint): ordered form
+    assert colatus.tile_config(32768, "fp64") == (4, 64, 128, 2)
+    assert colatus.tile_config(32768, "mixed", kind=1) == (4, 64, 128, 2)
+    # beyond 2^17 particles in a box: ordered form
     assert colatus.tile_config(200000, "mixed")[3] == 0
-    assert colatus.tile_config(32768, "fp64")[0:2] == (2, 256)
-    assert colatus.tile_config(32768, "fp64")[3] == 0
-    assert colatus.tile_config(32768, "mixed", kind=1)[3] == 0
+    assert colatus.tile_config(200000, "fp64")[0:2] == (2, 256)
+    assert colatus.tile_config(200000, "fp64", kind=1)[3] == 0
     colatus.set_option(colatus.OPT_TILE_SLICES, 3)
     colatus.set_option(colatus.OPT_PAIR_FORM, 1)
     try:
         assert colatus.tile_config(32768, "mixed")[2:] == (3, 1)
-        assert colatus.tile_config(32768, "fp64")[3] == 0  # FP64 always uses form 0
+        assert colatus.tile_config(32768, "fp64")[3] == 0  # no form 1 for FP64 pairs
+        assert colatus.tile_config(32768, "mixed", kind=1)[3] == 0  # nor for the adjoint
         colatus.set_option(colatus.OPT_PAIR_FORM, 2)
         # form 2 derives its slots from the part size; TILE_SLICES does not apply
         assert colatus.tile_config(200000, "mixed") == (4, 64, 782, 2)

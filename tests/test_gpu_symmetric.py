@@ -234,3 +234,38 @@ def test_adjoint_run_symmetric_close_to_fp64_gradient(dev, form2):
                              to_dev(lv, dev), checkpoint_every=6, precision="mixed_twosum")
     assert _rel(gx.cpu().numpy(), gx_r) <= 1e-3
     assert _rel(gv.cpu().numpy(), gv_r) <= 1e-3
+
+
+# ---- FP64 pairs in the symmetric loops ----------------------------------------
+
+@pytest.mark.parametrize("R,tpb", [(4, 64), (2, 128)])
+def test_fp64_symmetric_forces(dev, form2, R, tpb):
+    """FP64 symmetric loop at the FP64 parity bar: lattice (median and max
+    1e-12, potential too), ragged random clouds with unequal masses (conditioned
+    1e-14), softening zero."""
+    _shape(R, tpb)
+    assert colatus.tile_config(4096, "fp64") == (R, tpb, -(-4096 // (R * tpb)), 2)
+    w = inputs.eds_lattice(16)
+    got, phi = _gpu(w.x, w.m, w.eps, dev, "fp64", a=0.1, with_phi=True)
+    e = rel_err_per_particle(got, oracle.forces(w.x, w.m, w.eps, a=0.1))
+    pref = oracle.potential(w.x, w.m, w.eps)
+    ep = np.abs(phi - pref) / np.abs(pref)
+    print(f"fp64 R={R} tpb={tpb}: force max {e.max():.2e}, potential max {ep.max():.2e}")
+    assert e.max() <= 1e-12 and ep.max() <= 1e-12
+    for N in (2, 65, 257, 1000):
+        x, m = inputs.random_cloud(N, 400 + N, scale=0.5)
+        for eps in (0.01, 0.0):
+            got = _gpu(x, m, eps, dev, "fp64")
+            ref = oracle.forces(x, m, eps)
+            err = np.max(np.linalg.norm(got - ref, axis=0) / _term_scale(x, m, eps))
+            assert err <= 1e-14, (N, eps, err)
+
+
+@pytest.mark.parametrize("N,C", [(700, 1), (65, 2), (2, 1)])
+def test_fp64_symmetric_vjp(dev, form2, N, C):
+    x, m = inputs.random_cloud(N, 500 + N, scale=0.5)
+    lam = np.random.default_rng(C).standard_normal((C, 3, N))
+    got = colatus.force_vjp(to_dev(x, dev), to_dev(m, dev), to_dev(lam, dev), 0.02, 1.3,
+                            precision="fp64").cpu().numpy()
+    for c in range(C):
+        assert _rel(got[c], oracle.force_vjp(x, m, lam[c], 0.02, G=1.3)) <= 1e-12
