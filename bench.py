@@ -163,18 +163,20 @@ def main():
           file=sys.stderr, flush=True)
 
     # the O(N) integrator (finalise the slice partials, kick, drift): HBM-
-    # bound; algorithmic bytes per particle = read S slice partials (24 B
-    # each), x and p (48 B); write x and p (48 B)
-    slices = colatus.tile_config(N, args.precision)[2]
-    int_bytes = N * (24.0 * slices + 96.0)
+    # bound; algorithmic bytes per particle = read S partial-sum slots (3
+    # components, FP32 or FP64), x and p (48 B); write x and p (48 B)
+    R_, tpb_, slices, form_ = colatus.tile_config(N, args.precision)
+    # FP32 slots (symmetric loop, FP32 pairs, parts of <= 256): 12 B per slot
+    slot_bytes = 12.0 if form_ == 2 and args.precision != "fp64" and R_ * tpb_ <= 256 else 24.0
+    int_bytes = N * (slot_bytes * slices + 96.0)
     int_launch_ms = int_ms / int_launches
     integrator = {"bound": "hbm", "launch_us": 1e3 * int_launch_ms,
                   "bytes_per_launch": int_bytes,
                   "achieved_GBs": int_bytes / (int_launch_ms * 1e-3) / 1e9,
                   "peak_GBs": PEAK_HBM / 1e9,
                   "frac": int_bytes / (int_launch_ms * 1e-3) / PEAK_HBM,
-                  "note": f"{slices} partial-sum slots per particle "
-                          f"({24.0 * slices * N / 1e6:.0f} MB at this N)"}
+                  "note": f"{slices} partial-sum slots per particle, {slot_bytes:.0f} B each "
+                          f"({slot_bytes * slices * N / 1e6:.0f} MB at this N)"}
 
     line = {
         "metric": METRIC, "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": K,

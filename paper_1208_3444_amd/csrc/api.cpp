@@ -666,6 +666,13 @@ int run_adjoint_sweep(Workspace *ws, const WorkList &wl, int precision, bool mas
 
 int prepare_box_mass(Workspace *ws, const WorkList &wl, const double *m, hipStream_t s);
 
+// The sweep writes FP32 slots without the box mass (symmetric form, FP32
+// pairs, parts of at most 256 particles: each slot is one FP32 sum).
+int slots_f32(const WorkList &wl, int precision)
+{
+    return wl.cfg.form == 2 && precision != COLATUS_FP64 && wl.cfg.R * wl.cfg.tpb <= 256 ? 1 : 0;
+}
+
 // Choose (and if asked, autotune) the tile shape, then make the work list.
 int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int precision,
                      const double *x, const double *m, int n_cot, hipStream_t s)
@@ -912,6 +919,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.diag_part = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
     A.precision = P.precision;
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
+    A.part_f32 = slots_f32(wl, P.precision);
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
     CHECK_RC(run_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
@@ -1118,7 +1126,8 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
                                      static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                      (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                      phi ? static_cast<const double *>(ws->part_phi.ptr) : nullptr,
-                                     m, N, G, G / (a * a * a), acc, phi, s));
+                                     slots_f32(wl, precision), m, N, G, G / (a * a * a), acc,
+                                     phi, s));
     return COLATUS_OK;
 }
 
@@ -1168,9 +1177,11 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
     CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n_cot * 3 * N * sizeof(double)));
     const bool mask = eps == 0.0;
     CHECK_RC(run_adjoint_sweep(ws, wl, precision, mask, x, m, N, n_cot, lam, s));
-    CHECK_HIP(launch_vjp_finalize(precision, static_cast<const IntBlock *>(wl.d_blocks.ptr),
+    CHECK_HIP(launch_vjp_finalize(static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                   (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
-                                  N, n_cot, wl.max_slices, G, out, s));
+                                  slots_f32(wl, precision),
+                                  static_cast<const double *>(ws->box_mass.ptr), N, n_cot, G, out,
+                                  s));
     return COLATUS_OK;
 }
 
@@ -1245,6 +1256,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.diag_part = nullptr;
     A.precision = precision;
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
+    A.part_f32 = slots_f32(wf, precision);
 
     // ---- forward with checkpoints --------------------------------------
     CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1305,8 +1317,9 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
             CHECK_HIP(launch_adjoint_update(static_cast<const IntBlock *>(wa.d_blocks.ptr),
                                             (int)wa.blocks.size(),
                                             static_cast<const double *>(ws->part.ptr),
-                                            wa.max_slices, N, n_cot, G, cw, lx, lp, n > 0 ? 1 : 0,
-                                            dnext, s));
+                                            slots_f32(wa, precision),
+                                            static_cast<const double *>(ws->box_mass.ptr), N,
+                                            n_cot, G, cw, lx, lp, n > 0 ? 1 : 0, dnext, s));
         }
     }
     CHECK_HIP(hipMemcpyAsync(grad_x0, lx, (size_t)n_cot * n3 * sizeof(double),

@@ -102,16 +102,21 @@ hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_sel
 // Sets *counter = 0 (graph-safe replacement for a memset node).
 hipError_t launch_zero_counter(int *counter, hipStream_t stream);
 
+// Partial-sum slots: FP64, already multiplied by the box's common mass, or
+// (part_f32 != 0: the symmetric loop with FP32 pairs and parts of at most 256)
+// FP32 without it, the buffer then read as float; readers add the slots in
+// FP64 and apply the mass.
+
 // acc = scale * sum_s part[s], phi = -G (sum_s part_phi[s] - m/eps).
 hipError_t launch_forces_finalize(int precision, const double *box_mass,
                                   const IntBlock *blocks, int n_blocks,
-                                  const double *part, const double *part_phi,
+                                  const double *part, const double *part_phi, int part_f32,
                                   const double *m, int64_t N, double G, double scale,
                                   double *acc, double *phi, hipStream_t stream);
 
 // out = G * sum_s part[s] for n_cot cotangents ([n_cot][3][N]).
-hipError_t launch_vjp_finalize(int precision, const IntBlock *blocks, int n_blocks,
-                               const double *part, int64_t N, int n_cot, int n_slices,
+hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
+                               int part_f32, const double *box_mass, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream);
 
 // Step coefficients of steps [first, last) of the global grid.
@@ -142,6 +147,7 @@ struct IntegrateArgs {
     double *diag_part;     // [rows][n_blocks][kDiagW] or null
     int precision;         // pair arithmetic of the sweep that wrote part_phi
     const double *box_mass;// per-box common mass or NaN (as given to the sweep)
+    int part_f32;          // slots are FP32 without the common mass (see above)
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and
@@ -162,9 +168,9 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 // Adjoint update after a VJP sweep at x_n (all cotangents):
 //   w = G sum_s part;  lam_x += cw * w;  then if do_drift: lam_p += dnext * lam_x.
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
-                                 int n_slices, int64_t N, int n_cot, double G, double cw,
-                                 double *lam_x, double *lam_p, int do_drift, double dnext,
-                                 hipStream_t stream);
+                                 int part_f32, const double *box_mass, int64_t N, int n_cot,
+                                 double G, double cw, double *lam_x, double *lam_p,
+                                 int do_drift, double dnext, hipStream_t stream);
 
 // lam_p = lam_v / aN^2 (mode 0) or grad_v = a0^2 lam_p (mode 1); n values.
 hipError_t launch_scale(const double *src, double *dst, int64_t n, double factor,

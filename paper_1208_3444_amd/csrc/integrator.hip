@@ -186,8 +186,8 @@ constexpr int kFinalizeThreads = kIntBlock * kSliceGroups;
 
 // Sum of n_comp strided planes (k * stride + c * N) over this thread's slice
 // group, then the fixed-order combine; valid in wave 0 afterwards.
-template <int NC>
-__device__ __forceinline__ void grouped_slice_sum(const double *__restrict__ base, int S,
+template <int NC, typename P>
+__device__ __forceinline__ void grouped_slice_sum(const P *__restrict__ base, int S,
                                                   int64_t stride, int64_t N, bool valid,
                                                   double (*sh)[kSliceGroups][kIntBlock],
                                                   double (&out)[NC])
@@ -202,7 +202,7 @@ __device__ __forceinline__ void grouped_slice_sum(const double *__restrict__ bas
         for (int k = q; k < S; k += kSliceGroups) {
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                acc[c] += base[(int64_t)k * stride + (int64_t)c * N];
+                acc[c] += (double)base[(int64_t)k * stride + (int64_t)c * N];
         }
     }
 #pragma unroll
@@ -216,6 +216,28 @@ __device__ __forceinline__ void grouped_slice_sum(const double *__restrict__ bas
         for (int g = 1; g < kSliceGroups; ++g)
             t += sh[c][g][p];
         out[c] = t;
+    }
+}
+
+// Slot sums at element offset `off`.  FP64 slots hold partial sums already
+// multiplied by the box's common mass; FP32 slots (the symmetric loop with
+// FP32 pairs, one FP32 sum per slot) hold them without it, and the mass
+// (1 when the masses differ) multiplies the FP64 total here.
+template <int NC>
+__device__ __forceinline__ void slot_sum(const double *part, int f32, int64_t off, int S,
+                                         int64_t stride, int64_t N, bool valid,
+                                         double (*sh)[kSliceGroups][kIntBlock], double mbox,
+                                         double (&out)[NC])
+{
+    if (f32) {
+        grouped_slice_sum<NC>(reinterpret_cast<const float *>(part) + off, S, stride, N, valid,
+                              sh, out);
+        const double f = isnan(mbox) ? 1.0 : mbox;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            out[c] *= f;
+    } else {
+        grouped_slice_sum<NC>(part + off, S, stride, N, valid, sh, out);
     }
 }
 
@@ -233,13 +255,14 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
     const int64_t N = A.N;
     const int S = blk.n_slices;
 
+    const double mbox = box_mass_of(A.box_mass, blk.box);
     double gs[3];
-    grouped_slice_sum<3>(A.part + i, S, 3 * N, N, valid, shs, gs);
+    slot_sum<3>(A.part, A.part_f32, i, S, 3 * N, N, valid, shs, mbox, gs);
     double phs = 0.0;
     if (A.diag_part) {
         __syncthreads();
         double t[1];
-        grouped_slice_sum<1>(A.part_phi + i, S, N, N, valid, shs, t);
+        slot_sum<1>(A.part_phi, A.part_f32, i, S, N, N, valid, shs, mbox, t);
         phs = t[0];
     }
 
@@ -257,7 +280,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
         }
         if (A.diag_part) {
             const double mi = A.m[i];
-            phs -= self_potential(A.precision, mi, blk.eps, box_mass_of(A.box_mass, blk.box));
+            phs -= self_potential(A.precision, mi, blk.eps, mbox);
             const double phi = -A.G * phs;
             v[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
             v[1] = mi * phi;
@@ -363,7 +386,7 @@ __global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int row
 // acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - self term).
 __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     int precision, const double *__restrict__ box_mass, const IntBlock *__restrict__ blocks,
-    const double *__restrict__ part, const double *__restrict__ part_phi,
+    const double *__restrict__ part, const double *__restrict__ part_phi, int part_f32,
     const double *__restrict__ m, int64_t N, double G, double scale, double *__restrict__ acc,
     double *__restrict__ phi)
 {
@@ -372,35 +395,37 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
     const bool valid = i < blk.i1;
     const bool lead = threadIdx.x < kIntBlock;
+    const double mbox = box_mass_of(box_mass, blk.box);
     double g[3];
-    grouped_slice_sum<3>(part + i, blk.n_slices, 3 * N, N, valid, shs, g);
+    slot_sum<3>(part, part_f32, i, blk.n_slices, 3 * N, N, valid, shs, mbox, g);
     if (lead && valid)
         for (int c = 0; c < 3; ++c)
             acc[(int64_t)c * N + i] = scale * g[c];
     if (phi) {
         __syncthreads();
         double t[1];
-        grouped_slice_sum<1>(part_phi + i, blk.n_slices, N, N, valid, shs, t);
+        slot_sum<1>(part_phi, part_f32, i, blk.n_slices, N, N, valid, shs, mbox, t);
         if (lead && valid)
-            phi[i] = -G * (t[0] - self_potential(precision, m[i], blk.eps,
-                                                  box_mass_of(box_mass, blk.box)));
+            phi[i] = -G * (t[0] - self_potential(precision, m[i], blk.eps, mbox));
     }
 }
 
 // out[c] = G * sum_s part[s][c]  (part [S][n_cot][3][N]).
 __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
-    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int64_t N, int n_cot,
-    double G, double *__restrict__ out)
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
+    const double *__restrict__ box_mass, int64_t N, int n_cot, double G,
+    double *__restrict__ out)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
     const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
     const bool valid = i < blk.i1;
     const bool lead = threadIdx.x < kIntBlock;
+    const double mbox = box_mass_of(box_mass, blk.box);
     for (int c = 0; c < n_cot; ++c) {
         double w[3];
-        grouped_slice_sum<3>(part + (int64_t)c * 3 * N + i, blk.n_slices,
-                             (int64_t)n_cot * 3 * N, N, valid, shs, w);
+        slot_sum<3>(part, part_f32, (int64_t)c * 3 * N + i, blk.n_slices,
+                    (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
         if (lead && valid)
             for (int q = 0; q < 3; ++q)
                 out[((int64_t)c * 3 + q) * N + i] = G * w[q];
@@ -410,19 +435,20 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
 
 // lam_x += cw * G sum_s part[s];  then (do_drift) lam_p += dnext * lam_x.
 __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
-    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int64_t N, int n_cot,
-    double G, double cw, double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift,
-    double dnext)
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
+    const double *__restrict__ box_mass, int64_t N, int n_cot, double G, double cw,
+    double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift, double dnext)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
     const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
     const bool valid = i < blk.i1;
     const bool lead = threadIdx.x < kIntBlock;
+    const double mbox = box_mass_of(box_mass, blk.box);
     for (int c = 0; c < n_cot; ++c) {
         double w[3];
-        grouped_slice_sum<3>(part + (int64_t)c * 3 * N + i, blk.n_slices,
-                             (int64_t)n_cot * 3 * N, N, valid, shs, w);
+        slot_sum<3>(part, part_f32, (int64_t)c * 3 * N + i, blk.n_slices,
+                    (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
         if (lead && valid) {
             for (int q = 0; q < 3; ++q) {
                 const int64_t o = ((int64_t)c * 3 + q) * N + i;
@@ -492,34 +518,32 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 
 hipError_t launch_forces_finalize(int precision, const double *box_mass, const IntBlock *blocks,
                                   int n_blocks, const double *part, const double *part_phi,
-                                  const double *m, int64_t N, double G, double scale,
-                                  double *acc, double *phi, hipStream_t stream)
+                                  int part_f32, const double *m, int64_t N, double G,
+                                  double scale, double *acc, double *phi, hipStream_t stream)
 {
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       precision, box_mass, blocks, part, part_phi, m, N, G, scale, acc, phi);
+                       precision, box_mass, blocks, part, part_phi, part_f32, m, N, G, scale,
+                       acc, phi);
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_finalize(int precision, const IntBlock *blocks, int n_blocks,
-                               const double *part, int64_t N, int n_cot, int n_slices, double G,
-                               double *out, hipStream_t stream)
+hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
+                               int part_f32, const double *box_mass, int64_t N, int n_cot,
+                               double G, double *out, hipStream_t stream)
 {
-    (void)precision;
-    (void)n_slices;
     hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks,
-                       part, N, n_cot, G, out);
+                       blocks, part, part_f32, box_mass, N, n_cot, G, out);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
-                                 int n_slices, int64_t N, int n_cot, double G, double cw,
-                                 double *lam_x, double *lam_p, int do_drift, double dnext,
-                                 hipStream_t stream)
+                                 int part_f32, const double *box_mass, int64_t N, int n_cot,
+                                 double G, double cw, double *lam_x, double *lam_p,
+                                 int do_drift, double dnext, hipStream_t stream)
 {
-    (void)n_slices;
     hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, N, n_cot, G, cw, lam_x, lam_p, do_drift, dnext);
+                       blocks, part, part_f32, box_mass, N, n_cot, G, cw, lam_x, lam_p, do_drift,
+                       dnext);
     return hipGetLastError();
 }
 

@@ -441,6 +441,9 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
 {
     constexpr int TPB = 64 * W;
     constexpr int NQ = PHI ? 4 : 3;
+    // FP32 pairs without folding: every slot is one FP32 sum, stored as FP32
+    // without the box mass (the readers apply it in FP64)
+    constexpr bool F32OUT = sizeof(T) == 4 && !FOLD;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double mbox = box_mass ? box_mass[w.box] : NAN;
     const bool eqm = !isnan(mbox);
@@ -573,11 +576,20 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
             }
             if (wave == 0 && jv) {
                 const int64_t rs = (int64_t)w.rslice;
-                part[(rs * 3 + 0) * N + j] = scale * o[0];
-                part[(rs * 3 + 1) * N + j] = scale * o[1];
-                part[(rs * 3 + 2) * N + j] = scale * o[2];
-                if constexpr (PHI)
-                    part_phi[rs * N + j] = scale * o[NQ - 1];
+                if constexpr (F32OUT) {
+                    float *pf = reinterpret_cast<float *>(part);
+                    pf[(rs * 3 + 0) * N + j] = qx;
+                    pf[(rs * 3 + 1) * N + j] = qy;
+                    pf[(rs * 3 + 2) * N + j] = qz;
+                    if constexpr (PHI)
+                        reinterpret_cast<float *>(part_phi)[rs * N + j] = qp;
+                } else {
+                    part[(rs * 3 + 0) * N + j] = scale * o[0];
+                    part[(rs * 3 + 1) * N + j] = scale * o[1];
+                    part[(rs * 3 + 2) * N + j] = scale * o[2];
+                    if constexpr (PHI)
+                        part_phi[rs * N + j] = scale * o[NQ - 1];
+                }
             }
         }
     }
@@ -588,6 +600,15 @@ __device__ __forceinline__ void sym_item(const WorkItem &w, const double *__rest
         if (!valid[r])
             continue;
         const int64_t i = w.i0 + (int64_t)(wave * 64 * R + r * 64 + lane);
+        if constexpr (F32OUT) {
+            float *pf = reinterpret_cast<float *>(part);
+            pf[(slot * 3 + 0) * N + i] = ax[r];
+            pf[(slot * 3 + 1) * N + i] = ay[r];
+            pf[(slot * 3 + 2) * N + i] = az[r];
+            if constexpr (PHI)
+                reinterpret_cast<float *>(part_phi)[slot * N + i] = ap[r];
+            continue;
+        }
         double ox, oy, oz, op;
         if constexpr (FOLD && ACC == kTwoSum) {
             ox = (double)hx[r] + (double)lx[r];
@@ -729,6 +750,17 @@ __device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx,
     }
 }
 
+// A slot value of the symmetric adjoint: FP32 pairs store the FP32 sum as it
+// is (the readers apply the box mass), FP64 pairs the scaled FP64 value.
+__device__ __forceinline__ void store_slot(double *part, int64_t k, float v, double)
+{
+    reinterpret_cast<float *>(part)[k] = v;
+}
+__device__ __forceinline__ void store_slot(double *part, int64_t k, double v, double scale)
+{
+    part[k] = scale * v;
+}
+
 // One work item of the symmetric adjoint sweep, cotangent c of n_cot; parts
 // of at most 256 particles (one FP32 partial per slot, as in the forward).
 template <typename T, int R, bool REACT, bool MASK>
@@ -811,9 +843,9 @@ __device__ __forceinline__ void sym_adj_item(const WorkItem &w, const double *__
         if constexpr (REACT) {
             if (jv) {
                 const int64_t rs = (int64_t)w.rslice;
-                part[((rs * n_cot + c) * 3 + 0) * N + j] = scale * (double)qx;
-                part[((rs * n_cot + c) * 3 + 1) * N + j] = scale * (double)qy;
-                part[((rs * n_cot + c) * 3 + 2) * N + j] = scale * (double)qz;
+                store_slot(part, ((rs * n_cot + c) * 3 + 0) * N + j, qx, scale);
+                store_slot(part, ((rs * n_cot + c) * 3 + 1) * N + j, qy, scale);
+                store_slot(part, ((rs * n_cot + c) * 3 + 2) * N + j, qz, scale);
             }
         }
     }
@@ -823,9 +855,9 @@ __device__ __forceinline__ void sym_adj_item(const WorkItem &w, const double *__
         if (!valid[r])
             continue;
         const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
-        part[((slot * n_cot + c) * 3 + 0) * N + i] = scale * (double)ax[r];
-        part[((slot * n_cot + c) * 3 + 1) * N + i] = scale * (double)ay[r];
-        part[((slot * n_cot + c) * 3 + 2) * N + i] = scale * (double)az[r];
+        store_slot(part, ((slot * n_cot + c) * 3 + 0) * N + i, ax[r], scale);
+        store_slot(part, ((slot * n_cot + c) * 3 + 1) * N + i, ay[r], scale);
+        store_slot(part, ((slot * n_cot + c) * 3 + 2) * N + i, az[r], scale);
     }
 }
 
