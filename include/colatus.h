@@ -232,7 +232,7 @@ const char *colatus_strerror(int code);
                                      particles swap), boxes cut into parts of
                                      R x threads particles; -1 (default) = the
                                      heuristic's or the autotuner's choice (2 for
-                                     the forward up to 2^17 particles per box and
+                                     the forward up to 2^18 particles per box and
                                      for the adjoint with up to 3 cotangents, else
                                      0).  FP64 pairs: 1 means 0                      */
 int colatus_set_option(int key, int64_t value);

@@ -335,9 +335,10 @@ TileCfg ordered_cfg(const Boxes &b, int precision, int kind, int n_cu)
 TileCfg symmetric_cfg(const Boxes &b, int R, int tpb);
 
 // Largest box for the symmetric form: its partial-sum buffer holds one slot
-// per part of 256 particles, ceil(n / 256) x n x 24 bytes (1.6 GB at 2^17);
-// larger boxes use the ordered form, whose slot count stays near 64.
-constexpr int64_t kSymMaxN = 131072;
+// per part of 256 particles, ceil(n / 256) x n x 12 bytes with FP32 pairs
+// (24 with FP64): 3.2 GB (6.4 GB) at 2^18.  Larger boxes use the ordered
+// form, whose slot count stays near 64.
+constexpr int64_t kSymMaxN = 262144;
 
 // Cotangents up to which the adjoint uses the symmetric form (one launch per
 // cotangent); more share the geometry in the ordered form's chunks of 8.

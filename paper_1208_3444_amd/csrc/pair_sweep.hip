@@ -689,7 +689,7 @@ __device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx,
                                               T eps2, T (&ax)[R], T (&ay)[R],
                                               T (&az)[R])
 {
-#pragma unroll 2
+#pragma unroll 1
     for (int k = 0; k < 64; ++k) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -702,9 +702,11 @@ __device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx,
             T rinv = rsqrt_t(s);
             if constexpr (MASK)
                 rinv = s > (T)0.0 ? rinv : (T)0.0;
+            // M(d) u = r^-3 u - 3 r^-5 (d.u) d = u' - 3 r^-2 (d.u') d with
+            // u' = r^-3 u (one multiply fewer per pair than scaling t)
             const T r2 = rinv * rinv;
             const T r3 = r2 * rinv;
-            const T m3r5 = -(T)3.0 * (r3 * r2);
+            const T m3r2 = -(T)3.0 * r2;
             T ux, uy, uz;
             if constexpr (EQM) {
                 ux = slx - lkx[r];
@@ -720,11 +722,14 @@ __device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx,
                 uy = mk[r] * sly - sm * lky[r];
                 uz = mk[r] * slz - sm * lkz[r];
             }
+            ux *= r3;
+            uy *= r3;
+            uz *= r3;
             const T du = fma_t(dx, ux, fma_t(dy, uy, dz * uz));
-            const T t = m3r5 * du;
-            const T vx = fma_t(t, dx, r3 * ux);
-            const T vy = fma_t(t, dy, r3 * uy);
-            const T vz = fma_t(t, dz, r3 * uz);
+            const T t = m3r2 * du;
+            const T vx = fma_t(t, dx, ux);
+            const T vy = fma_t(t, dy, uy);
+            const T vz = fma_t(t, dz, uz);
             ax[r] += vx;
             ay[r] += vy;
             az[r] += vz;

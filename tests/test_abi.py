@@ -162,10 +162,11 @@ def test_options_and_tile_config():
     assert colatus.tile_config(1000, "fp32") == (4, 64, 4, 2)
     assert colatus.tile_config(32768, "fp64") == (4, 64, 128, 2)
     assert colatus.tile_config(32768, "mixed", kind=1) == (4, 64, 128, 2)
-    # beyond 2^17 particles in a box: ordered form
-    assert colatus.tile_config(200000, "mixed")[3] == 0
-    assert colatus.tile_config(200000, "fp64")[0:2] == (2, 256)
-    assert colatus.tile_config(200000, "fp64", kind=1)[3] == 0
+    assert colatus.tile_config(262144, "mixed") == (4, 64, 1024, 2)
+    # beyond 2^18 particles in a box: ordered form
+    assert colatus.tile_config(300000, "mixed")[3] == 0
+    assert colatus.tile_config(300000, "fp64")[0:2] == (2, 256)
+    assert colatus.tile_config(300000, "fp64", kind=1)[3] == 0
     colatus.set_option(colatus.OPT_TILE_SLICES, 3)
     colatus.set_option(colatus.OPT_PAIR_FORM, 1)
     try:
