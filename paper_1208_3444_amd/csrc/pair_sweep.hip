@@ -1,22 +1,31 @@
 // Pair sweeps of the direct-summation (particle-particle) scheme: the O(N^2)
 // hot loop of the method (Section II: the force computation dominates the
 // cost; Appendix A: one GPU thread per target particle looping over every
-// source).  Gfx950 design, not a translation of the paper's kernel:
+// source).  Gfx950 design, not a translation of the paper's kernel.
 //
+// Symmetric loops (form 2, the default up to 2^18 particles per box): the
+// pair terms of the forward sum and of its adjoint change sign when the two
+// particles swap, so each unordered pair is evaluated once.  A box is cut
+// into parts of 256; a work item (one wave) holds part p's targets in
+// registers, four per lane, while part q's sources pass around the wave one
+// lane per step (DPP rotation) carrying their reaction accumulators.  Each
+// partial-sum slot (part p's pull on a particle) is written once; an O(N)
+// kernel adds the slots in a fixed order, so results are deterministic.
+//
+// Ordered loops (forms 0 and 1; larger boxes, many-cotangent adjoints):
 //   * a work item is (block of target particles) x (slice of sources); the
-//     slices of one target block write separate partial sums that a later
-//     O(N) kernel adds in a fixed order, so results are deterministic and a
-//     32^3 problem still spreads over thousands of wave64s;
+//     slices of one target block write separate partial sums;
 //   * each lane keeps R targets in registers; sources are staged tile by tile
 //     into LDS (one source per thread) and read back as wave-uniform
 //     broadcasts, so one LDS read feeds R pair interactions;
-//   * mixed precision stores coordinates relative to the centre of the target
-//     block's bounding box (FP64 subtract, then round to FP32), so FP32 pair
-//     arithmetic keeps the relative accuracy of the separation itself;
 //   * per-tile FP32 partial sums are folded into FP64 or an unevaluated FP32
-//     (hi, lo) pair with TwoSum (Knuth), bounding the accumulation error;
-//   * rsqrt is the hardware v_rsq_f32 in FP32 and v_rsq_f64 refined by one
-//     Newton step in FP64; no MFMA: the pair interaction is not a dense contraction.
+//     (hi, lo) pair with TwoSum (Knuth), bounding the accumulation error.
+//
+// Both: FP32 pairs use coordinates relative to the centre of the target
+// block's (part's) bounding box (FP64 subtract, then round to FP32), so the
+// FP32 pair arithmetic keeps the relative accuracy of the separation itself;
+// rsqrt is the hardware v_rsq_f32 in FP32 and v_rsq_f64 refined by one Newton
+// step in FP64; no MFMA: the pair interaction is not a dense contraction.
 //
 // The persistent variant launches about one grid of resident workgroups and
 // pulls work items from a device counter until none are left (every
@@ -371,11 +380,10 @@ template <> __device__ __forceinline__ double adj_pad<double>() { return 1e150; 
 // accumulate the reaction on the travelling source (q*); EQM: the box's common
 // mass leaves the loop (weights r^-3 and r^-1 only).
 template <typename T, int R, bool REACT, bool EQM, bool PHI, bool MASK>
-__device__ __forceinline__ void sym_chunk(T sx, T sy, T sz, T sm, T &qx,
-                                          T &qy, T &qz, T &qp, const T (&xi)[R],
-                                          const T (&yi)[R], const T (&zi)[R],
-                                          const T (&mi)[R], T eps2, T (&ax)[R],
-                                          T (&ay)[R], T (&az)[R], T (&ap)[R])
+__device__ __forceinline__ void sym_chunk(T sx, T sy, T sz, T sm, T &qx, T &qy, T &qz, T &qp,
+                                          const T (&xi)[R], const T (&yi)[R], const T (&zi)[R],
+                                          const T (&mi)[R], T eps2, T (&ax)[R], T (&ay)[R],
+                                          T (&az)[R], T (&ap)[R])
 {
 #pragma unroll 2
     for (int k = 0; k < 64; ++k) {
@@ -680,14 +688,12 @@ pair_sweep_sym_kernel(
 // finite and the pair adds exactly 0.
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool REACT, bool EQM, bool MASK>
-__device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx,
-                                              T sly, T slz, T &qx, T &qy,
-                                              T &qz, const T (&xi)[R],
+__device__ __forceinline__ void sym_adj_chunk(T sx, T sy, T sz, T sm, T slx, T sly, T slz,
+                                              T &qx, T &qy, T &qz, const T (&xi)[R],
                                               const T (&yi)[R], const T (&zi)[R],
                                               const T (&mk)[R], const T (&lkx)[R],
-                                              const T (&lky)[R], const T (&lkz)[R],
-                                              T eps2, T (&ax)[R], T (&ay)[R],
-                                              T (&az)[R])
+                                              const T (&lky)[R], const T (&lkz)[R], T eps2,
+                                              T (&ax)[R], T (&ay)[R], T (&az)[R])
 {
 #pragma unroll 1
     for (int k = 0; k < 64; ++k) {
