@@ -9,8 +9,11 @@ arithmetic, and the citation of the paper passage each function follows,
 lives there:
 
 * ``forces``           -- Eq. (1) pair sum, a^-3 G sum m_j (x_j - x_k) r^-3
+                          (+ the Eq. (10) attractor when given)
 * ``potential``        -- softened potential whose gradient is that sum
 * ``force_vjp``        -- transpose Jacobian of the comoving pair sum
+* ``attractor_field``, ``attractor_vjp`` -- the Eq. (10) deformation term
+  alone: a fixed point of strength S = C psi at x_psi
 * ``hubble``           -- Eq. (2)
 * ``time_integral``    -- the cosmic-time, kick and drift integrals of Eq. (9)
 * ``step_coefficients``-- the kick/drift/kick coefficients of one step
@@ -60,12 +63,16 @@ def _load():
     lib.oracle_potential.argtypes = [_p, _p, _i64, _d, _d, _p]
     lib.oracle_force_vjp.restype = None
     lib.oracle_force_vjp.argtypes = [_p, _p, _i64, _d, _d, _p, _p]
+    lib.oracle_attractor_add.restype = None
+    lib.oracle_attractor_add.argtypes = [_p, _i64, _d, _d, _p, _p, _p]
+    lib.oracle_attractor_vjp.restype = None
+    lib.oracle_attractor_vjp.argtypes = [_p, _i64, _d, _d, _p, _p, _p]
     lib.oracle_run.restype = ctypes.c_int
     lib.oracle_run.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i64, _i64, _p]
+        [_d, _d, _i64, _i64, _i64, _p, _d, _p]
     lib.oracle_adjoint.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i32, _p, _p, _p, _p, _p, _p]
+        [_d, _d, _i64, _i32, _p, _p, _p, _p, _p, _p, _d, _p, _p]
     _lib = lib
     return lib
 
@@ -102,13 +109,45 @@ def step_coefficients(cosmo, a_begin, a_end, n_steps, n):
     return tuple(out)
 
 
-def forces(x, m, eps, G=1.0, a=1.0):
+def _att(attractor):
+    """(S, xpsi array or None) from None or (S, (x, y, z))."""
+    if attractor is None:
+        return 0.0, None
+    S, xp = attractor
+    return float(S), np.ascontiguousarray(xp, dtype=np.float64).reshape(3)
+
+
+def attractor_field(x, eps, attractor):
+    """(f, phi_ext): the Eq. (10) term added to the comoving sum g and its
+    potential, for attractor = (S, (x, y, z))."""
+    x = _c(x)
+    N = x.shape[1]
+    S, xp = _att(attractor)
+    f = np.zeros((3, N))
+    phi = np.zeros(N)
+    _load().oracle_attractor_add(_ptr(x), N, eps, S, _ptr(xp), _ptr(f), _ptr(phi))
+    return f, phi
+
+
+def attractor_vjp(x, lam, eps, attractor):
+    x = _c(x)
+    lam = _c(lam)
+    N = x.shape[1]
+    S, xp = _att(attractor)
+    out = np.empty((3, N))
+    _load().oracle_attractor_vjp(_ptr(x), N, eps, S, _ptr(xp), _ptr(lam), _ptr(out))
+    return out
+
+
+def forces(x, m, eps, G=1.0, a=1.0, attractor=None):
     x = _c(x)
     m = _c(m)
     N = m.shape[0]
     assert x.shape == (3, N)
     acc = np.empty((3, N))
     _load().oracle_forces(_ptr(x), _ptr(m), N, eps, G, a, _ptr(acc))
+    if attractor is not None:
+        acc += attractor_field(x, eps, attractor)[0] / a ** 3
     return acc
 
 
@@ -123,31 +162,35 @@ def forces_targets(x, m, targets, eps, G=1.0, a=1.0):
     return acc
 
 
-def potential(x, m, eps, G=1.0):
+def potential(x, m, eps, G=1.0, attractor=None):
     x = _c(x)
     m = _c(m)
     N = m.shape[0]
     phi = np.empty(N)
     _load().oracle_potential(_ptr(x), _ptr(m), N, eps, G, _ptr(phi))
+    if attractor is not None:
+        phi += attractor_field(x, eps, attractor)[1]
     return phi
 
 
-def force_vjp(x, m, lam, eps, G=1.0):
+def force_vjp(x, m, lam, eps, G=1.0, attractor=None):
     x = _c(x)
     m = _c(m)
     lam = _c(lam)
     N = m.shape[0]
     out = np.empty((3, N))
     _load().oracle_force_vjp(_ptr(x), _ptr(m), N, eps, G, _ptr(lam), _ptr(out))
+    if attractor is not None:
+        out += attractor_vjp(x, lam, eps, attractor)
     return out
 
 
 def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
-        last_step=None, diag=False):
+        last_step=None, diag=False, attractor=None):
     """Kick-drift-kick run over steps first_step..last_step-1 of the grid.
 
     Returns (x, v) at a_{last_step}, and the diagnostics rows (dict of arrays)
-    if diag is true.
+    if diag is true.  attractor: None or (S, (x, y, z)), the Eq. (10) term.
     """
     if last_step is None:
         last_step = n_steps
@@ -155,11 +198,12 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
     v = _c(v).copy()
     m = _c(m)
     N = m.shape[0]
+    S, xp = _att(attractor)
     rows = np.zeros((last_step - first_step + 1, len(DIAG_FIELDS))) if diag else None
     rc = _load().oracle_run(
         _ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
         cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
-        first_step, last_step, _ptr(rows))
+        first_step, last_step, _ptr(rows), S, _ptr(xp))
     if rc != 0:
         raise ValueError("oracle_run: invalid arguments")
     if diag:
@@ -167,11 +211,13 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
     return x, v
 
 
-def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN):
+def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
+            attractor=None):
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x0, v0).
 
     lam_xN, lam_vN: (C, 3, N) or (3, N).  Returns (grad_x0, grad_v0, xN, vN)
-    with the gradients shaped like the cotangents.
+    with the gradients shaped like the cotangents; with an attractor
+    (S, (x, y, z)) also grad_att, (C, 4) (or (4,)): d/dS, d/dx_psi.
     """
     x0 = _c(x0)
     v0 = _c(v0)
@@ -187,14 +233,20 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN):
     gv = np.empty_like(lv)
     xN = np.empty((3, N))
     vN = np.empty((3, N))
+    S, xp = _att(attractor)
+    ga = np.zeros((C, 4)) if attractor is not None else None
     rc = _load().oracle_adjoint(
         _ptr(x0), _ptr(v0), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
         cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
-        C, _ptr(lx), _ptr(lv), _ptr(gx), _ptr(gv), _ptr(xN), _ptr(vN))
+        C, _ptr(lx), _ptr(lv), _ptr(gx), _ptr(gv), _ptr(xN), _ptr(vN), S, _ptr(xp),
+        _ptr(ga))
     if rc != 0:
         raise ValueError("oracle_adjoint: invalid arguments")
     if squeeze:
         gx, gv = gx[0], gv[0]
+        ga = ga[0] if ga is not None else None
+    if attractor is not None:
+        return gx, gv, xN, vN, ga
     return gx, gv, xN, vN
 
 

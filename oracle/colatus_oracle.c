@@ -31,6 +31,9 @@
  *  - Softening is Plummer, in comoving units, as written in Eq. (1).
  *  - Static limit: H0 == 0 keeps a fixed at a_begin; then the "a_end"
  *    argument of the run is the total elapsed time and dt = a_end/n_steps.
+ *  - Eq. (10)'s deformation term is a fixed attractor of strength S = C psi
+ *    at x_psi, softened with the same eps and added to g with the attractive
+ *    sign of Eq. (1) (see oracle_attractor_add).
  *
  * Parity pins for every function live in the tests (closed forms,
  * invariants, brute force, finite differences).
@@ -289,6 +292,110 @@ void oracle_force_vjp(const double *x, const double *m, int64_t N, double eps,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Deformation attractor of Eq. (10).                                       */
+/* ------------------------------------------------------------------------ */
+/* Eq. (10) adds to the gradient of Eq. (1) the term
+ *   -C psi (x_k - x_psi) / (|x_k - x_psi|^2 + eps^2)^{3/2},
+ * the pull of a fixed point at x_psi (the paper notes it acts like a mass
+ * particle at a fixed position).  C and psi enter only as their product, the
+ * strength S = C psi (units of G m).  With the attractive reading of Eq. (1)
+ * the comoving field added to g is
+ *   f_k = S (x_psi - x_k) / (|x_psi - x_k|^2 + eps^2)^{3/2},
+ * its potential phi_k = -S / sqrt(|x_psi - x_k|^2 + eps^2) (an external
+ * field: the energy is sum m phi, not half of it), and its derivative
+ * df_k/dx_k = -S M(d), d = x_psi - x_k.  att_x == NULL: no attractor.
+ * Adds f into g and (phi != NULL) phi_ext into phi.                       */
+void oracle_attractor_add(const double *x, int64_t N, double eps, double S,
+                          const double *att_x, double *g, double *phi)
+{
+    if (!att_x)
+        return;
+    const double eps2 = eps * eps;
+    for (int64_t k = 0; k < N; ++k) {
+        double dx = att_x[0] - x[k];
+        double dy = att_x[1] - x[N + k];
+        double dz = att_x[2] - x[2 * N + k];
+        double s = dx * dx + dy * dy + dz * dz + eps2;
+        double r = sqrt(s);
+        double r3 = 1.0 / (s * r);
+        if (g) {
+            g[k] += S * dx * r3;
+            g[N + k] += S * dy * r3;
+            g[2 * N + k] += S * dz * r3;
+        }
+        if (phi)
+            phi[k] += -S / r;
+    }
+}
+
+/* M(d) lam with M(d) = s^{-3/2} I - 3 s^{-5/2} d d^T, s = |d|^2 + eps^2,
+ * d = x_psi - x_k; also returns lam . d s^{-3/2} (= lam . f_k / S).        */
+static void attractor_m(const double *x, int64_t N, int64_t k, double eps2,
+                        const double *att_x, const double *lam, double out[3],
+                        double *lam_f)
+{
+    double dx = att_x[0] - x[k];
+    double dy = att_x[1] - x[N + k];
+    double dz = att_x[2] - x[2 * N + k];
+    double s = dx * dx + dy * dy + dz * dz + eps2;
+    double rinv = 1.0 / sqrt(s);
+    double r3 = rinv * rinv * rinv;
+    double r5 = r3 * rinv * rinv;
+    double lx = lam[k], ly = lam[N + k], lz = lam[2 * N + k];
+    double dl = dx * lx + dy * ly + dz * lz;
+    out[0] = r3 * lx - 3.0 * r5 * dl * dx;
+    out[1] = r3 * ly - 3.0 * r5 * dl * dy;
+    out[2] = r3 * lz - 3.0 * r5 * dl * dz;
+    *lam_f = dl * r3;
+}
+
+/* out += (d f / d x)^T lam = -S M(d_k) lam_k for every particle.          */
+static void attractor_vjp_add(const double *x, int64_t N, double eps, double S,
+                              const double *att_x, const double *lam, double *out)
+{
+    if (!att_x)
+        return;
+    for (int64_t k = 0; k < N; ++k) {
+        double mv[3], lf;
+        attractor_m(x, N, k, eps * eps, att_x, lam, mv, &lf);
+        out[k] += -S * mv[0];
+        out[N + k] += -S * mv[1];
+        out[2 * N + k] += -S * mv[2];
+    }
+}
+
+/* Parameter derivatives of lam . f:  grad[0] += c sum_k lam_k . f_k / S
+ * (f is linear in S) and grad[1..3] += c sum_k S M(d_k) lam_k (df_k/dx_psi
+ * = S M(d_k)), c being the kick factor that multiplied f.                 */
+static void attractor_grad_add(const double *x, int64_t N, double eps, double S,
+                               const double *att_x, const double *lam, double c,
+                               double *grad)
+{
+    if (!att_x || !grad)
+        return;
+    ksum g[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int64_t k = 0; k < N; ++k) {
+        double mv[3], lf;
+        attractor_m(x, N, k, eps * eps, att_x, lam, mv, &lf);
+        ksum_add(&g[0], lf);
+        ksum_add(&g[1], S * mv[0]);
+        ksum_add(&g[2], S * mv[1]);
+        ksum_add(&g[3], S * mv[2]);
+    }
+    for (int q = 0; q < 4; ++q)
+        grad[q] += c * ksum_value(&g[q]);
+}
+
+/* out = (d f / d x)^T lam alone.                                          */
+void oracle_attractor_vjp(const double *x, int64_t N, double eps, double S,
+                          const double *att_x, const double *lam, double *out)
+{
+    for (int64_t i = 0; i < 3 * N; ++i)
+        out[i] = 0.0;
+    attractor_vjp_add(x, N, eps, S, att_x, lam, out);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time grid and step coefficients.                                         */
 /* ------------------------------------------------------------------------ */
 
@@ -357,18 +464,22 @@ void oracle_step_coefficients(double H0, double OmR, double OmM, double OmK,
 #define DIAG_W 11
 
 static void energies(const double *x, const double *p, const double *m,
-                     int64_t N, double eps, double G, double a, double *K,
-                     double *U, double *P, double *L)
+                     int64_t N, double eps, double G, double a, double S,
+                     const double *att_x, double *K, double *U, double *P,
+                     double *L)
 {
     double *phi = (double *)malloc(sizeof(double) * (size_t)N);
+    double *phe = (double *)calloc((size_t)N, sizeof(double));
     oracle_potential(x, m, N, eps, G, phi);
-    ksum kk = {0, 0}, uu = {0, 0};
+    oracle_attractor_add(x, N, eps, S, att_x, NULL, phe);
+    ksum kk = {0, 0}, uu = {0, 0}, ue = {0, 0};
     ksum pp[3] = {{0, 0}, {0, 0}, {0, 0}}, ll[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int64_t k = 0; k < N; ++k) {
         double X = x[k], Y = x[N + k], Z = x[2 * N + k];
         double px = p[k], py = p[N + k], pz = p[2 * N + k];
         ksum_add(&kk, 0.5 * m[k] * (px * px + py * py + pz * pz));
         ksum_add(&uu, m[k] * phi[k]);
+        ksum_add(&ue, m[k] * phe[k]);
         ksum_add(&pp[0], m[k] * px);
         ksum_add(&pp[1], m[k] * py);
         ksum_add(&pp[2], m[k] * pz);
@@ -377,12 +488,13 @@ static void energies(const double *x, const double *p, const double *m,
         ksum_add(&ll[2], m[k] * (X * py - Y * px));
     }
     *K = ksum_value(&kk) / (a * a);
-    *U = 0.5 * ksum_value(&uu) / a;
+    *U = (0.5 * ksum_value(&uu) + ksum_value(&ue)) / a;
     for (int i = 0; i < 3; ++i) {
         P[i] = ksum_value(&pp[i]);
         L[i] = ksum_value(&ll[i]);
     }
     free(phi);
+    free(phe);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -394,7 +506,8 @@ static void energies(const double *x, const double *p, const double *m,
 int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
                double G, double H0, double OmR, double OmM, double OmK,
                double OmL, double a_begin, double a_end, int64_t n_steps,
-               int64_t first_step, int64_t last_step, double *diag)
+               int64_t first_step, int64_t last_step, double *diag, double att_S,
+               const double *att_x)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
@@ -407,11 +520,12 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
     for (size_t i = 0; i < n3; ++i)
         p[i] = a * a * v[i];
     oracle_forces(x, m, N, eps, G, 1.0, g);
+    oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
 
     double t = 0.0, E0 = 0.0, li_int = 0.0, prev_src = 0.0;
     if (diag) {
         double K, U, P[3], L[3];
-        energies(x, p, m, N, eps, G, a, &K, &U, P, L);
+        energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
         E0 = K + U;
         prev_src = 2.0 * K + U;
         double *row = diag;
@@ -425,6 +539,7 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
         for (size_t i = 0; i < n3; ++i)
             x[i] += s.d * p[i];
         oracle_forces(x, m, N, eps, G, 1.0, g);
+        oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
         for (size_t i = 0; i < n3; ++i)
             p[i] += s.k2 * g[i];
         double a_prev = a;
@@ -432,7 +547,7 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
         t += s.dt;
         if (diag) {
             double K, U, P[3], L[3];
-            energies(x, p, m, N, eps, G, a, &K, &U, P, L);
+            energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
             double src = 2.0 * K + U;
             double dlna = (c.H0 == 0.0) ? 0.0 : log(a) - log(a_prev);
             li_int += 0.5 * (prev_src + src) * dlna;
@@ -466,7 +581,8 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
                    double OmM, double OmK, double OmL, double a_begin,
                    double a_end, int64_t n_steps, int32_t n_cot,
                    const double *lam_xN, const double *lam_vN, double *grad_x0,
-                   double *grad_v0, double *xN, double *vN)
+                   double *grad_v0, double *xN, double *vN, double att_S,
+                   const double *att_x, double *grad_att)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || n_cot < 1)
@@ -483,6 +599,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
     for (size_t i = 0; i < n3; ++i)
         p[i] = a0 * a0 * v0[i];
     oracle_forces(xs, m, N, eps, G, 1.0, g);
+    oracle_attractor_add(xs, N, eps, att_S, att_x, g, NULL);
     for (int64_t n = 0; n < n_steps; ++n) {
         coef[n] = step_coefficients(&c, a_begin, a_end, n_steps, n);
         double *xn = xs + (size_t)n * n3, *xn1 = xs + (size_t)(n + 1) * n3;
@@ -491,6 +608,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
         for (size_t i = 0; i < n3; ++i)
             xn1[i] = xn[i] + coef[n].d * p[i];
         oracle_forces(xn1, m, N, eps, G, 1.0, g);
+        oracle_attractor_add(xn1, N, eps, att_S, att_x, g, NULL);
         for (size_t i = 0; i < n3; ++i)
             p[i] += coef[n].k2 * g[i];
     }
@@ -506,6 +624,10 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
     for (int32_t ci = 0; ci < n_cot; ++ci) {
         const double *lxN = lam_xN + (size_t)ci * n3;
         const double *lvN = lam_vN + (size_t)ci * n3;
+        double *ga = grad_att ? grad_att + 4 * (size_t)ci : NULL;
+        if (ga)
+            for (int q = 0; q < 4; ++q)
+                ga[q] = 0.0;
         for (size_t i = 0; i < n3; ++i) {
             lx[i] = lxN[i];
             lp[i] = lvN[i] / (aN * aN);
@@ -513,11 +635,15 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
         for (int64_t n = n_steps - 1; n >= 0; --n) {
             double *xn = xs + (size_t)n * n3, *xn1 = xs + (size_t)(n + 1) * n3;
             oracle_force_vjp(xn1, m, N, eps, G, lp, w);
+            attractor_vjp_add(xn1, N, eps, att_S, att_x, lp, w);
+            attractor_grad_add(xn1, N, eps, att_S, att_x, lp, coef[n].k2, ga);
             for (size_t i = 0; i < n3; ++i)
                 lx[i] += coef[n].k2 * w[i];
             for (size_t i = 0; i < n3; ++i)
                 lp[i] += coef[n].d * lx[i];
             oracle_force_vjp(xn, m, N, eps, G, lp, w);
+            attractor_vjp_add(xn, N, eps, att_S, att_x, lp, w);
+            attractor_grad_add(xn, N, eps, att_S, att_x, lp, coef[n].k1, ga);
             for (size_t i = 0; i < n3; ++i)
                 lx[i] += coef[n].k1 * w[i];
         }
