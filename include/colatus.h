@@ -13,7 +13,9 @@
  *     operators of Eq. (9), with a(t) from the Friedmann equation, Eq. (2);
  *   - the discrete adjoint (vector-Jacobian product) of that step, used for
  *     trajectory sensitivities and finite-time Lyapunov exponents of the
- *     chaotic-advection study the paper motivates (Sections I and IV).
+ *     chaotic-advection study the paper motivates (Sections I and IV);
+ *   - optionally the deformation term of Eq. (10), a fixed attractor, in
+ *     the forces, the run and the adjoint (with its parameter gradients).
  *
  * Conventions shared by every entry point
  *   - Arrays named x, v, acc, lam_*, grad_* are structure-of-arrays float64
@@ -92,6 +94,23 @@ typedef struct {
     const double *eps;          /* host, n_boxes     */
 } colatus_batch;
 
+/* ---- deformation attractor (Eq. (10)) --------------------------------- */
+/* The deformation term of Eq. (10): a fixed point at comoving x_psi that
+ * pulls every particle like a mass S/G would, S = C psi (C and psi enter
+ * only as their product).  It adds to the comoving sum g of particle k
+ *     S (x_psi - x_k) / (|x_psi - x_k|^2 + eps^2)^{3/2}
+ * (attractive, as the pair term of Eq. (1) is read; eps is the particle's
+ * box softening), and -S / sqrt(|x_psi - x_k|^2 + eps^2) to its potential;
+ * the diagnostics count this external energy once (not halved).  x_psi is
+ * the same comoving point in every box of a batch.  HOST pointer, read
+ * during the call only; NULL means Eq. (1) alone.  strength and x must be
+ * finite (strength 0 adds nothing but still yields d/dS in colatus_adjoint).
+ * A particle exactly at x_psi with eps == 0 gives Inf/NaN.                 */
+typedef struct {
+    double strength; /* S = C psi */
+    double x[3];     /* x_psi, comoving */
+} colatus_attractor;
+
 /* ---- diagnostics row --------------------------------------------------- */
 /* One row per integer grid point a_n visited by a run (first row: the start
  * state).  With p = a^2 v:
@@ -121,10 +140,13 @@ typedef struct {
  *        no a factor); its negative gradient is the comoving pair sum.
  *   precision: COLATUS_FP64 / _MIXED_TWOSUM / _MIXED_F64ACC / _FP32.
  *   eps >= 0 (eps == 0 with two coincident particles gives Inf/NaN), G finite,
- *   a > 0.  batch: see colatus_batch, or NULL.                            */
+ *   a > 0.  batch: see colatus_batch, or NULL.
+ *   attractor: see colatus_attractor, or NULL; its field (times a^-3) and
+ *   potential are added to acc and phi, in FP64 for every precision.       */
 int colatus_forces(const double *x, const double *m, int64_t N, double eps,
                    double G, double a, int precision, double *acc, double *phi,
-                   const colatus_batch *batch, void *stream);
+                   const colatus_batch *batch, const colatus_attractor *attractor,
+                   void *stream);
 
 /* One kick-drift-kick step (Eq. (9) operators, Section II) from a to a_next,
  * in place on x and v (comoving position and dx/dt):
@@ -134,11 +156,13 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps,
  * D(a1,a2) = int_{a1}^{a2} da/(a^3 H), H from Eq. (2).
  * Static limit H0 == 0: a stays fixed and a_next is read as the time step
  * dt (K = dt/(2a) each, D = dt/a^2).  Costs two force evaluations; use
- * colatus_run for many steps (one evaluation per step).                    */
+ * colatus_run for many steps (one evaluation per step).  With an attractor
+ * (or NULL) g includes the Eq. (10) term.                                   */
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
                  double G, double H0, double Om_R, double Om_M, double Om_K,
                  double Om_L, double a, double a_next, int precision,
-                 const colatus_batch *batch, void *stream);
+                 const colatus_batch *batch, const colatus_attractor *attractor,
+                 void *stream);
 
 /* Steps first_step .. last_step-1 of the global grid a_n = a_begin
  * exp(n ln(a_end/a_begin)/n_steps), a_{n_steps} = a_end, in place on x, v.
@@ -152,12 +176,14 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
  *         holds n_boxes consecutive blocks of rows (box-major).
  * Requires n_steps >= 1, 0 <= first_step < last_step <= n_steps, a_begin > 0,
  * a_end > 0 (or > 0 elapsed time in the static limit), H^2 > 0 on the range
- * (else COLATUS_EFRIEDMANN).                                              */
+ * (else COLATUS_EFRIEDMANN).  attractor (or NULL): the Eq. (10) term joins g
+ * at every kick and its energy joins U.                                    */
 int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
                 double G, double H0, double Om_R, double Om_M, double Om_K,
                 double Om_L, double a_begin, double a_end, int64_t n_steps,
                 int64_t first_step, int64_t last_step, int precision,
-                colatus_diag *diag, const colatus_batch *batch, void *stream);
+                colatus_diag *diag, const colatus_batch *batch,
+                const colatus_attractor *attractor, void *stream);
 
 /* Reverse-mode derivative of the full run [0, n_steps) of colatus_run
  * (discretise-then-differentiate: the exact gradient of the computed map).
@@ -172,21 +198,30 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
  *   M(d) = r^-3 I - 3 r^-5 d d^T,  d = x_j - x_k,
  * is evaluated by its own O(N^2) pair sweep in the given precision, once
  * per step for all cotangents together.  1 <= n_cot <= 4096; batch must be
- * NULL (single box).                                                        */
+ * NULL (single box).
+ * With an attractor (Eq. (10), or NULL) the run is the attractor's run; its
+ * transpose Jacobian -S M(d) (d = x_psi - x_k) joins the pair sum's, and
+ * grad_attractor ([n_cot][4] device, or NULL; requires an attractor)
+ * receives d<lam, state_N>/dS and d<lam, state_N>/dx_psi per cotangent,
+ * accumulated in a fixed order (deterministic).                            */
 int colatus_adjoint(const double *x0, const double *v0, const double *m,
                     int64_t N, double eps, double G, double H0, double Om_R,
                     double Om_M, double Om_K, double Om_L, double a_begin,
                     double a_end, int64_t n_steps, int64_t checkpoint_every,
                     int32_t n_cot, const double *lam_xN, const double *lam_vN,
                     double *grad_x0, double *grad_v0, double *xN, double *vN,
-                    int precision, const colatus_batch *batch, void *stream);
+                    double *grad_attractor, int precision,
+                    const colatus_batch *batch, const colatus_attractor *attractor,
+                    void *stream);
 
-/* Transpose-Jacobian product of the comoving pair sum g (Eq. (1) without
- * a^-3) alone: out[c] = J(x)^T lam[c] for n_cot cotangents, arrays
- * [n_cot][3][N] device.  The building block of colatus_adjoint.           */
+/* Transpose-Jacobian product of the comoving sum g (Eq. (1) without a^-3,
+ * plus the Eq. (10) attractor's field when attractor is non-NULL):
+ * out[c] = J(x)^T lam[c] for n_cot cotangents, arrays [n_cot][3][N]
+ * device.  The building block of colatus_adjoint.                         */
 int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps,
                       double G, int32_t n_cot, const double *lam, double *out,
-                      int precision, void *stream);
+                      int precision, const colatus_attractor *attractor,
+                      void *stream);
 
 /* Hubble rate of Eq. (2) at scale factor a, on the host.  Returns
  * COLATUS_EFRIEDMANN if H^2 < 0 there.                                    */

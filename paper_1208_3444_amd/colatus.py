@@ -40,13 +40,14 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "EFRIEDMANN", -3: "ENODEV", -4: "ENOMEM", -
 _d, _i64, _i32, _i, _p = (ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
                           ctypes.c_void_p)
 SIGNATURES = {
-    "colatus_forces": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p]),
-    "colatus_step": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i, _p, _p]),
+    "colatus_forces": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p, _p]),
+    "colatus_step": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i, _p, _p,
+                          _p]),
     "colatus_run": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                         _i64, _i, _p, _p, _p]),
+                         _i64, _i, _p, _p, _p, _p]),
     "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                             _i32, _p, _p, _p, _p, _p, _p, _i, _p, _p]),
-    "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p]),
+                             _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p]),
+    "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p]),
     "colatus_hubble": (_i, [_d, _d, _d, _d, _d, _d, ctypes.POINTER(_d)]),
     "colatus_strerror": (ctypes.c_char_p, [_i]),
     "colatus_set_option": (_i, [_i, _i64]),
@@ -68,6 +69,22 @@ class ColatusError(RuntimeError):
 class _Batch(ctypes.Structure):
     _fields_ = [("n_boxes", ctypes.c_int32), ("box_offsets", ctypes.c_void_p),
                 ("eps", ctypes.c_void_p)]
+
+
+class _Attractor(ctypes.Structure):
+    _fields_ = [("strength", _d), ("x", _d * 3)]
+
+
+def _attractor(att):
+    """att = (S, (x, y, z)) -> pointer to a colatus_attractor, or None."""
+    if att is None:
+        return None, None
+    S, xp = att
+    xp = [float(v) for v in xp]
+    if len(xp) != 3:
+        raise ValueError("attractor position must have 3 components")
+    a = _Attractor(float(S), (_d * 3)(*xp))
+    return ctypes.byref(a), a
 
 
 class Diag(ctypes.Structure):
@@ -140,21 +157,24 @@ def _batch(batch):
     return b, (off, eps)
 
 
-def forces(x, m, eps, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False, batch=None):
+def forces(x, m, eps, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False, batch=None,
+           attractor=None):
     """a^-3 G sum_{j != k} m_j (x_j - x_k) / (|x_j - x_k|^2 + eps^2)^{3/2}  (Eq. (1)).
 
     Returns acc (3, N), and phi (N,) (-G sum m_j / r) if with_phi.
+    attractor: None or (S, (x, y, z)), the Eq. (10) deformation term.
     """
     N = m.shape[0]
     px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
     acc = torch.empty_like(x)
     phi = torch.empty_like(m) if with_phi else None
     b, keep = _batch(batch)
+    pa, keep_a = _attractor(attractor)
     rc = lib().colatus_forces(px, pm, N, float(eps) if batch is None else 0.0, float(G),
                               float(a), _prec(precision), ctypes.c_void_p(acc.data_ptr()),
                               ctypes.c_void_p(phi.data_ptr()) if with_phi else None,
-                              ctypes.byref(b) if b is not None else None, _stream(x))
-    del keep
+                              ctypes.byref(b) if b is not None else None, pa, _stream(x))
+    del keep, keep_a
     _check("colatus_forces", rc)
     return (acc, phi) if with_phi else acc
 
@@ -164,15 +184,17 @@ def _cosmo(c):
             float(c["Om_L"]))
 
 
-def step(x, v, m, eps, G, cosmo, a, a_next, precision="mixed_twosum", batch=None):
+def step(x, v, m, eps, G, cosmo, a, a_next, precision="mixed_twosum", batch=None,
+         attractor=None):
     """One kick-drift-kick step from a to a_next, in place on x and v."""
     N = m.shape[0]
     px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
     b, keep = _batch(batch)
+    pa, keep_a = _attractor(attractor)
     rc = lib().colatus_step(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
                             *_cosmo(cosmo), float(a), float(a_next), _prec(precision),
-                            ctypes.byref(b) if b is not None else None, _stream(x))
-    del keep
+                            ctypes.byref(b) if b is not None else None, pa, _stream(x))
+    del keep, keep_a
     _check("colatus_step", rc)
 
 
@@ -191,25 +213,27 @@ def _diag_dict(rows):
 
 
 def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step=None,
-        precision="mixed_twosum", diag=False, batch=None):
+        precision="mixed_twosum", diag=False, batch=None, attractor=None):
     """Kick-drift-kick steps [first_step, last_step) of the global ln-a grid, in place.
 
     Returns the diagnostics (dict of numpy arrays, one entry per grid point;
     with a batch, a list of such dicts, one per box) if diag, else None.
+    attractor: None or (S, (x, y, z)), the Eq. (10) deformation term.
     """
     if last_step is None:
         last_step = n_steps
     N = m.shape[0]
     px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
     b, keep = _batch(batch)
+    pa, keep_a = _attractor(attractor)
     n_boxes = 1 if batch is None else len(keep[1])
     rows = (Diag * (n_boxes * (last_step - first_step + 1)))() if diag else None
     rc = lib().colatus_run(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
                            *_cosmo(cosmo), float(a_begin), float(a_end), int(n_steps),
                            int(first_step), int(last_step), _prec(precision),
                            ctypes.cast(rows, ctypes.c_void_p) if diag else None,
-                           ctypes.byref(b) if b is not None else None, _stream(x))
-    del keep
+                           ctypes.byref(b) if b is not None else None, pa, _stream(x))
+    del keep, keep_a
     _check("colatus_run", rc)
     if not diag:
         return None
@@ -218,25 +242,32 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step
     return per_box[0] if batch is None else per_box
 
 
-def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum"):
-    """J(x)^T lam for the comoving pair sum; lam (3, N) or (C, 3, N)."""
+def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum", attractor=None):
+    """J(x)^T lam for the comoving sum (pair sum, plus the Eq. (10) attractor
+    if given); lam (3, N) or (C, 3, N)."""
     N = m.shape[0]
     px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
     C = 1 if lam.dim() == 2 else lam.shape[0]
     pl = _dev(lam, "lam", (3, N) if lam.dim() == 2 else (C, 3, N))
     out = torch.empty_like(lam)
+    pa, keep_a = _attractor(attractor)
     rc = lib().colatus_force_vjp(px, pm, N, float(eps), float(G), C, pl,
-                                 ctypes.c_void_p(out.data_ptr()), _prec(precision), _stream(x))
+                                 ctypes.c_void_p(out.data_ptr()), _prec(precision), pa,
+                                 _stream(x))
+    del keep_a
     _check("colatus_force_vjp", rc)
     return out
 
 
 def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
-            checkpoint_every=20, precision="mixed_twosum", return_state=False):
+            checkpoint_every=20, precision="mixed_twosum", return_state=False,
+            attractor=None):
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x_0, v_0).
 
     lam_xN, lam_vN: (3, N) or (C, 3, N).  Returns (grad_x0, grad_v0) shaped
-    like the cotangents, plus (x_N, v_N) if return_state.
+    like the cotangents, plus (x_N, v_N) if return_state.  With an attractor
+    (S, (x, y, z)) (Eq. (10)) the run includes it and the gradient with
+    respect to (S, x_psi) is appended: (4,) or (C, 4).
     """
     N = m.shape[0]
     px, pv, pm = _dev(x0, "x0", (3, N)), _dev(v0, "v0", (3, N)), _dev(m, "m", (N,))
@@ -246,26 +277,35 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
     gx, gv = torch.empty_like(lam_xN), torch.empty_like(lam_vN)
     xN = torch.empty_like(x0) if return_state else None
     vN = torch.empty_like(v0) if return_state else None
+    pa, keep_a = _attractor(attractor)
+    ga = None
+    if attractor is not None:
+        ga = torch.empty((4,) if lam_xN.dim() == 2 else (C, 4), dtype=torch.float64,
+                         device=x0.device)
     rc = lib().colatus_adjoint(
         px, pv, pm, N, float(eps), float(G), *_cosmo(cosmo), float(a_begin), float(a_end),
         int(n_steps), int(checkpoint_every), C, plx, plv, ctypes.c_void_p(gx.data_ptr()),
         ctypes.c_void_p(gv.data_ptr()),
         ctypes.c_void_p(xN.data_ptr()) if return_state else None,
         ctypes.c_void_p(vN.data_ptr()) if return_state else None,
-        _prec(precision), None, _stream(x0))
+        ctypes.c_void_p(ga.data_ptr()) if ga is not None else None,
+        _prec(precision), None, pa, _stream(x0))
+    del keep_a
     _check("colatus_adjoint", rc)
-    if return_state:
-        return gx, gv, xN, vN
-    return gx, gv
+    out = (gx, gv) + ((xN, vN) if return_state else ())
+    if ga is not None:
+        out = out + (ga,)
+    return out
 
 
 class ColatusRun(torch.autograd.Function):
     """(x_0, v_0) -> (x_N, v_N) of a full run, differentiable by the discrete adjoint.
 
     ``ColatusRun.apply(x0, v0, m, params)`` with params a dict holding eps, G,
-    cosmo, a_begin, a_end, n_steps and optionally checkpoint_every and
-    precision.  The backward pass calls colatus_adjoint, which re-runs the
-    forward with checkpoints and returns gradients for x0 and v0.
+    cosmo, a_begin, a_end, n_steps and optionally checkpoint_every, precision
+    and attractor (S, (x, y, z)).  The backward pass calls colatus_adjoint,
+    which re-runs the forward with checkpoints and returns gradients for x0
+    and v0.
     """
 
     @staticmethod
@@ -273,7 +313,8 @@ class ColatusRun(torch.autograd.Function):
         x = x0.detach().clone()
         v = v0.detach().clone()
         run(x, v, m, params["eps"], params["G"], params["cosmo"], params["a_begin"],
-            params["a_end"], params["n_steps"], precision=params.get("precision", "mixed_twosum"))
+            params["a_end"], params["n_steps"], precision=params.get("precision", "mixed_twosum"),
+            attractor=params.get("attractor"))
         ctx.save_for_backward(x0.detach(), v0.detach(), m)
         ctx.params = params
         return x, v
@@ -284,14 +325,15 @@ class ColatusRun(torch.autograd.Function):
         P = ctx.params
         gx = torch.zeros_like(x0) if gx is None else gx.contiguous()
         gv = torch.zeros_like(v0) if gv is None else gv.contiguous()
-        dx, dv = adjoint(x0, v0, m, P["eps"], P["G"], P["cosmo"], P["a_begin"], P["a_end"],
-                         P["n_steps"], gx, gv, checkpoint_every=P.get("checkpoint_every", 20),
-                         precision=P.get("precision", "mixed_twosum"))
-        return dx, dv, None, None
+        res = adjoint(x0, v0, m, P["eps"], P["G"], P["cosmo"], P["a_begin"], P["a_end"],
+                      P["n_steps"], gx, gv, checkpoint_every=P.get("checkpoint_every", 20),
+                      precision=P.get("precision", "mixed_twosum"),
+                      attractor=P.get("attractor"))
+        return res[0], res[1], None, None
 
 
 def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_every=20,
-         precision="mixed_twosum"):
+         precision="mixed_twosum", attractor=None):
     """Finite-time Lyapunov exponents of tracer particles.
 
     The 3x3 block d x_t(a_end) / d x_t(a_begin) of each tracer is read off
@@ -309,8 +351,8 @@ def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_
         for i in range(3):
             lam_x[3 * ti + i, i, int(t)] = 1.0
     lam_v = torch.zeros_like(lam_x)
-    gx, _ = adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_x, lam_v,
-                    checkpoint_every=checkpoint_every, precision=precision)
+    gx = adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_x, lam_v,
+                 checkpoint_every=checkpoint_every, precision=precision, attractor=attractor)[0]
     g = gx.cpu().numpy()
     phi = np.empty((T, 3, 3))
     for ti, t in enumerate(tracers):

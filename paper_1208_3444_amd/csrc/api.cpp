@@ -154,7 +154,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
-        box_mass;
+        box_mass, att_acc;
     WorkList fwd, adj;
 };
 
@@ -200,6 +200,18 @@ int ensure(Buffer &b, size_t bytes)
     const size_t rounded = (bytes + 4095) & ~(size_t)4095;
     CHECK_HIP(hipMalloc(&b.ptr, rounded));
     b.cap = rounded;
+    return COLATUS_OK;
+}
+
+// Host checks of the Eq. (10) attractor argument (NULL: none).
+int resolve_attractor(const colatus_attractor *a, Attractor &out)
+{
+    out = Attractor{0, 0.0, 0.0, 0.0, 0.0};
+    if (!a)
+        return COLATUS_OK;
+    if (!is_fin(a->strength) || !is_fin(a->x[0]) || !is_fin(a->x[1]) || !is_fin(a->x[2]))
+        return COLATUS_EINVAL;
+    out = Attractor{1, a->strength, a->x[0], a->x[1], a->x[2]};
     return COLATUS_OK;
 }
 
@@ -808,6 +820,7 @@ struct RunParams {
     int precision;
     colatus_diag *diag;
     hipStream_t stream;
+    Attractor att;
 };
 
 int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, bool mask,
@@ -921,6 +934,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.precision = P.precision;
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
     A.part_f32 = slots_f32(wl, P.precision);
+    A.att = P.att;
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
     CHECK_RC(run_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
@@ -948,7 +962,7 @@ int run_impl(const RunParams &P, const Boxes &b)
 // ===========================================================================
 extern "C" {
 
-int colatus_version(void) { return 10000; }
+int colatus_version(void) { return 10100; }
 
 const char *colatus_strerror(int code)
 {
@@ -1089,7 +1103,7 @@ int colatus_release(void)
                            &ws->diag_out, &ws->counters, &ws->lam_x, &ws->lam_p, &ws->ckpt,
                            &ws->seg, &ws->fwd.d_items, &ws->fwd.d_blocks, &ws->fwd.d_box_first,
                            &ws->adj.d_items, &ws->adj.d_blocks, &ws->adj.d_box_first,
-                           &ws->fwd.d_off, &ws->adj.d_off, &ws->box_mass})
+                           &ws->fwd.d_off, &ws->adj.d_off, &ws->box_mass, &ws->att_acc})
             if (bb->ptr)
                 hipFree(bb->ptr);
         if (ws->cap_stream)
@@ -1102,13 +1116,15 @@ int colatus_release(void)
 
 int colatus_forces(const double *x, const double *m, int64_t N, double eps, double G, double a,
                    int precision, double *acc, double *phi, const colatus_batch *batch,
-                   void *stream)
+                   const colatus_attractor *attractor, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || !is_fin(a) || a <= 0.0)
         return COLATUS_EINVAL;
     CHECK_RC(check_ptrs({x, m, acc}));
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, batch, b));
+    Attractor att;
+    CHECK_RC(resolve_attractor(attractor, att));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
     std::lock_guard<std::mutex> lock(g_mu);
@@ -1127,15 +1143,16 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
                                      static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                      (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                      phi ? static_cast<const double *>(ws->part_phi.ptr) : nullptr,
-                                     slots_f32(wl, precision), m, N, G, G / (a * a * a), acc,
-                                     phi, s));
+                                     slots_f32(wl, precision), x, m, N, G, G / (a * a * a), att,
+                                     1.0 / (a * a * a), acc, phi, s));
     return COLATUS_OK;
 }
 
 int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, double G,
                 double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a_begin,
                 double a_end, int64_t n_steps, int64_t first_step, int64_t last_step,
-                int precision, colatus_diag *diag, const colatus_batch *batch, void *stream)
+                int precision, colatus_diag *diag, const colatus_batch *batch,
+                const colatus_attractor *attractor, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
         return COLATUS_EINVAL;
@@ -1145,22 +1162,25 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, batch, b));
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    Attractor att;
+    CHECK_RC(resolve_attractor(attractor, att));
     RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
-                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream)};
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att};
     return run_impl(P, b);
 }
 
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, double G,
                  double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a,
-                 double a_next, int precision, const colatus_batch *batch, void *stream)
+                 double a_next, int precision, const colatus_batch *batch,
+                 const colatus_attractor *attractor, void *stream)
 {
     return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
-                       precision, nullptr, batch, stream);
+                       precision, nullptr, batch, attractor, stream);
 }
 
 int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, double G,
                       int32_t n_cot, const double *lam, double *out, int precision,
-                      void *stream)
+                      const colatus_attractor *attractor, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_cot < 1 ||
         n_cot > kMaxCot)
@@ -1168,6 +1188,8 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
     CHECK_RC(check_ptrs({x, m, lam, out}));
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, nullptr, b));
+    Attractor att;
+    CHECK_RC(resolve_attractor(attractor, att));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
     std::lock_guard<std::mutex> lock(g_mu);
@@ -1181,8 +1203,8 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
     CHECK_HIP(launch_vjp_finalize(static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                   (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                   slots_f32(wl, precision),
-                                  static_cast<const double *>(ws->box_mass.ptr), N, n_cot, G, out,
-                                  s));
+                                  static_cast<const double *>(ws->box_mass.ptr), x, lam, att, N,
+                                  n_cot, G, out, s));
     return COLATUS_OK;
 }
 
@@ -1190,15 +1212,20 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                     double G, double H0, double Om_R, double Om_M, double Om_K, double Om_L,
                     double a_begin, double a_end, int64_t n_steps, int64_t checkpoint_every,
                     int32_t n_cot, const double *lam_xN, const double *lam_vN, double *grad_x0,
-                    double *grad_v0, double *xN, double *vN, int precision,
-                    const colatus_batch *batch, void *stream)
+                    double *grad_v0, double *xN, double *vN, double *grad_attractor,
+                    int precision, const colatus_batch *batch,
+                    const colatus_attractor *attractor, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
         checkpoint_every < 1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
         return COLATUS_EINVAL;
+    if (grad_attractor && !attractor)
+        return COLATUS_EINVAL;
     CHECK_RC(check_ptrs({x0, v0, m, lam_xN, lam_vN, grad_x0, grad_v0}));
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, nullptr, b));
+    Attractor att;
+    CHECK_RC(resolve_attractor(attractor, att));
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
@@ -1258,6 +1285,16 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.precision = precision;
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
     A.part_f32 = slots_f32(wf, precision);
+    A.att = att;
+    // per-block accumulators of the attractor's parameter derivatives
+    double *acc_att = nullptr;
+    const int n_ablk = (int)wa.blocks.size();
+    if (grad_attractor) {
+        const size_t n_acc = (size_t)n_ablk * (size_t)n_cot * 4;
+        CHECK_RC(ensure(ws->att_acc, n_acc * sizeof(double)));
+        acc_att = static_cast<double *>(ws->att_acc.ptr);
+        CHECK_HIP(launch_fill(acc_att, (int64_t)n_acc, 0.0, s));
+    }
 
     // ---- forward with checkpoints --------------------------------------
     CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1316,16 +1353,18 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                               (n > 0 ? hc[(size_t)n - 1].k2 : 0.0);
             const double dnext = n > 0 ? hc[(size_t)n - 1].d : 0.0;
             CHECK_HIP(launch_adjoint_update(static_cast<const IntBlock *>(wa.d_blocks.ptr),
-                                            (int)wa.blocks.size(),
-                                            static_cast<const double *>(ws->part.ptr),
+                                            n_ablk, static_cast<const double *>(ws->part.ptr),
                                             slots_f32(wa, precision),
-                                            static_cast<const double *>(ws->box_mass.ptr), N,
-                                            n_cot, G, cw, lx, lp, n > 0 ? 1 : 0, dnext, s));
+                                            static_cast<const double *>(ws->box_mass.ptr), xs,
+                                            att, acc_att, N, n_cot, G, cw, lx, lp,
+                                            n > 0 ? 1 : 0, dnext, s));
         }
     }
     CHECK_HIP(hipMemcpyAsync(grad_x0, lx, (size_t)n_cot * n3 * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     CHECK_HIP(launch_scale(lp, grad_v0, (int64_t)n_cot * (int64_t)n3, a0 * a0, s));
+    if (grad_attractor)
+        CHECK_HIP(launch_att_grad_reduce(acc_att, n_ablk, n_cot, grad_attractor, s));
     return COLATUS_OK;
 }
 

@@ -57,6 +57,16 @@ __device__ __forceinline__ double rsqrt_refined(double s)
     return fma(0.5 * y0, e, y0);
 }
 
+// Deformation attractor of Eq. (10): a fixed point of strength S = C psi at
+// comoving (x, y, z) adding S d (|d|^2 + eps^2)^{-3/2}, d = x_psi - x_k, to
+// the comoving sum g of every particle (eps: its box's softening), with the
+// potential -S / sqrt(|d|^2 + eps^2) counted once in the energy.  on == 0:
+// no attractor (Eq. (1) alone).
+struct Attractor {
+    int on;
+    double S, x, y, z;
+};
+
 // Shape of one pair-sweep launch.
 struct TileCfg {
     int R;        // targets per lane
@@ -107,16 +117,20 @@ hipError_t launch_zero_counter(int *counter, hipStream_t stream);
 // FP32 without it, the buffer then read as float; readers add the slots in
 // FP64 and apply the mass.
 
-// acc = scale * sum_s part[s], phi = -G (sum_s part_phi[s] - m/eps).
+// acc = scale * sum_s part[s] + inv_a3 f_att(x), phi = -G (sum_s part_phi[s] -
+// m/eps) + phi_att(x).
 hipError_t launch_forces_finalize(int precision, const double *box_mass,
                                   const IntBlock *blocks, int n_blocks,
                                   const double *part, const double *part_phi, int part_f32,
-                                  const double *m, int64_t N, double G, double scale,
+                                  const double *x, const double *m, int64_t N, double G,
+                                  double scale, const Attractor &att, double inv_a3,
                                   double *acc, double *phi, hipStream_t stream);
 
-// out = G * sum_s part[s] for n_cot cotangents ([n_cot][3][N]).
+// out = G * sum_s part[s] - S M(d) lam (attractor) for n_cot cotangents
+// ([n_cot][3][N]).
 hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
-                               int part_f32, const double *box_mass, int64_t N, int n_cot,
+                               int part_f32, const double *box_mass, const double *x,
+                               const double *lam, const Attractor &att, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream);
 
 // Step coefficients of steps [first, last) of the global grid.
@@ -148,6 +162,7 @@ struct IntegrateArgs {
     int precision;         // pair arithmetic of the sweep that wrote part_phi
     const double *box_mass;// per-box common mass or NaN (as given to the sweep)
     int part_f32;          // slots are FP32 without the common mass (see above)
+    Attractor att;         // Eq. (10) term added to g (att.on == 0: none)
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and
@@ -166,11 +181,23 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
                               hipStream_t stream);
 
 // Adjoint update after a VJP sweep at x_n (all cotangents):
-//   w = G sum_s part;  lam_x += cw * w;  then if do_drift: lam_p += dnext * lam_x.
+//   w = G sum_s part - S M(d) lam_p;  lam_x += cw * w;
+//   then if do_drift: lam_p += dnext * lam_x.
+// With the attractor on and att_acc non-null, block b also adds
+// cw * (sum_k lam_p . f_k / S, sum_k S M(d_k) lam_p) over its particles to
+// att_acc[b][c][0..4) (its own row only: deterministic, no atomics).
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
-                                 int part_f32, const double *box_mass, int64_t N, int n_cot,
+                                 int part_f32, const double *box_mass, const double *x,
+                                 const Attractor &att, double *att_acc, int64_t N, int n_cot,
                                  double G, double cw, double *lam_x, double *lam_p,
                                  int do_drift, double dnext, hipStream_t stream);
+
+// out[c][q] = sum over blocks b (in order) of att_acc[b][c][q], q < 4.
+hipError_t launch_att_grad_reduce(const double *att_acc, int n_blocks, int n_cot, double *out,
+                                  hipStream_t stream);
+
+// p[0..n) = value (a fill kernel; graph-safe).
+hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t stream);
 
 // lam_p = lam_v / aN^2 (mode 0) or grad_v = a0^2 lam_p (mode 1); n values.
 hipError_t launch_scale(const double *src, double *dst, int64_t n, double factor,

@@ -168,6 +168,41 @@ __device__ __forceinline__ double box_mass_of(const double *box_mass, int box)
     return box_mass ? box_mass[box] : NAN;
 }
 
+// Eq. (10) attractor at particle position (px, py, pz), softening eps: adds
+// its field S d r^-3 (d = x_psi - x, r^2 = |d|^2 + eps^2) to f and returns
+// its potential -S / r.  FP64 with IEEE square root and division.
+__device__ __forceinline__ double attractor_pull(const Attractor &A, double px, double py,
+                                                 double pz, double eps, double (&f)[3])
+{
+    const double dx = A.x - px, dy = A.y - py, dz = A.z - pz;
+    const double s = dx * dx + dy * dy + dz * dz + eps * eps;
+    const double r = sqrt(s);
+    const double r3 = 1.0 / (s * r);
+    f[0] += A.S * dx * r3;
+    f[1] += A.S * dy * r3;
+    f[2] += A.S * dz * r3;
+    return -A.S / r;
+}
+
+// M(d) l with M(d) = r^-3 I - 3 r^-5 d d^T (the attractor's field derivative
+// is -S M(d) with respect to the particle, +S M(d) with respect to x_psi);
+// also returns l . d r^-3 (= l . f / S).
+__device__ __forceinline__ double attractor_m(const Attractor &A, double px, double py,
+                                              double pz, double eps, const double (&l)[3],
+                                              double (&mv)[3])
+{
+    const double dx = A.x - px, dy = A.y - py, dz = A.z - pz;
+    const double s = dx * dx + dy * dy + dz * dz + eps * eps;
+    const double rinv = 1.0 / sqrt(s);
+    const double r3 = rinv * rinv * rinv;
+    const double r5 = r3 * rinv * rinv;
+    const double dl = dx * l[0] + dy * l[1] + dz * l[2];
+    mv[0] = r3 * l[0] - 3.0 * r5 * dl * dx;
+    mv[1] = r3 * l[1] - 3.0 * r5 * dl * dy;
+    mv[2] = r3 * l[2] - 3.0 * r5 * dl * dz;
+    return dl * r3;
+}
+
 // Kick-drift-kick in canonical momentum p = a^2 v (Eq. (9) with the kick
 // factor int dt/a acting on g = G sum m_j (x_j - x_k) r^-3 and the drift
 // factor int dt/a^2 acting on p).  One launch per grid point n:
@@ -270,9 +305,12 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
     for (int q = 0; q < kDiagW; ++q)
         v[q] = 0.0;
     if (lead && valid) {
-        const double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
+        double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
         double p[3] = {A.p[i], A.p[N + i], A.p[2 * N + i]};
         double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
+        double phe = 0.0;  // attractor potential (external: counted once)
+        if (A.att.on)
+            phe = attractor_pull(A.att, xx[0], xx[1], xx[2], blk.eps, g);
         if (n > A.first) {
             const double k2 = A.coef[row - 1].k2;
             for (int c = 0; c < 3; ++c)
@@ -281,7 +319,9 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
         if (A.diag_part) {
             const double mi = A.m[i];
             phs -= self_potential(A.precision, mi, blk.eps, mbox);
-            const double phi = -A.G * phs;
+            // U = (1/2a) sum m (phi_pair + 2 phi_att): the pair potential is
+            // shared by two particles, the attractor's belongs to one
+            const double phi = -A.G * phs + 2.0 * phe;
             v[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
             v[1] = mi * phi;
             v[2] = mi * p[0];
@@ -387,7 +427,8 @@ __global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int row
 __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     int precision, const double *__restrict__ box_mass, const IntBlock *__restrict__ blocks,
     const double *__restrict__ part, const double *__restrict__ part_phi, int part_f32,
-    const double *__restrict__ m, int64_t N, double G, double scale, double *__restrict__ acc,
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N, double G,
+    double scale, Attractor att, double inv_a3, double *__restrict__ acc,
     double *__restrict__ phi)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
@@ -398,22 +439,26 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     const double mbox = box_mass_of(box_mass, blk.box);
     double g[3];
     slot_sum<3>(part, part_f32, i, blk.n_slices, 3 * N, N, valid, shs, mbox, g);
+    double f[3] = {0.0, 0.0, 0.0}, phe = 0.0;
+    if (att.on && lead && valid)
+        phe = attractor_pull(att, x[i], x[N + i], x[2 * N + i], blk.eps, f);
     if (lead && valid)
         for (int c = 0; c < 3; ++c)
-            acc[(int64_t)c * N + i] = scale * g[c];
+            acc[(int64_t)c * N + i] = scale * g[c] + inv_a3 * f[c];
     if (phi) {
         __syncthreads();
         double t[1];
         slot_sum<1>(part_phi, part_f32, i, blk.n_slices, N, N, valid, shs, mbox, t);
         if (lead && valid)
-            phi[i] = -G * (t[0] - self_potential(precision, m[i], blk.eps, mbox));
+            phi[i] = -G * (t[0] - self_potential(precision, m[i], blk.eps, mbox)) + phe;
     }
 }
 
 // out[c] = G * sum_s part[s][c]  (part [S][n_cot][3][N]).
 __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
     const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
-    const double *__restrict__ box_mass, int64_t N, int n_cot, double G,
+    const double *__restrict__ box_mass, const double *__restrict__ x,
+    const double *__restrict__ lam, Attractor att, int64_t N, int n_cot, double G,
     double *__restrict__ out)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
@@ -426,9 +471,20 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
         double w[3];
         slot_sum<3>(part, part_f32, (int64_t)c * 3 * N + i, blk.n_slices,
                     (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
-        if (lead && valid)
+        if (lead && valid) {
+            double o[3] = {G * w[0], G * w[1], G * w[2]};
+            if (att.on) {
+                const double l[3] = {lam[((int64_t)c * 3 + 0) * N + i],
+                                     lam[((int64_t)c * 3 + 1) * N + i],
+                                     lam[((int64_t)c * 3 + 2) * N + i]};
+                double mv[3];
+                (void)attractor_m(att, x[i], x[N + i], x[2 * N + i], blk.eps, l, mv);
+                for (int q = 0; q < 3; ++q)
+                    o[q] -= att.S * mv[q];
+            }
             for (int q = 0; q < 3; ++q)
-                out[((int64_t)c * 3 + q) * N + i] = G * w[q];
+                out[((int64_t)c * 3 + q) * N + i] = o[q];
+        }
         __syncthreads();
     }
 }
@@ -436,12 +492,15 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
 // lam_x += cw * G sum_s part[s];  then (do_drift) lam_p += dnext * lam_x.
 __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
     const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
-    const double *__restrict__ box_mass, int64_t N, int n_cot, double G, double cw,
+    const double *__restrict__ box_mass, const double *__restrict__ x, Attractor att,
+    double *__restrict__ att_acc, int64_t N, int n_cot, double G, double cw,
     double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift, double dnext)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
+    __shared__ double sg[4][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
-    const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
+    const int pl = threadIdx.x & (kIntBlock - 1);
+    const int64_t i = blk.i0 + pl;
     const bool valid = i < blk.i1;
     const bool lead = threadIdx.x < kIntBlock;
     const double mbox = box_mass_of(box_mass, blk.box);
@@ -449,17 +508,64 @@ __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
         double w[3];
         slot_sum<3>(part, part_f32, (int64_t)c * 3 * N + i, blk.n_slices,
                     (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
+        double gp[4] = {0.0, 0.0, 0.0, 0.0};
         if (lead && valid) {
+            double o[3] = {G * w[0], G * w[1], G * w[2]};
+            if (att.on) {
+                // lam_p as the sweep saw it (before this update's drift)
+                const double l[3] = {lam_p[((int64_t)c * 3 + 0) * N + i],
+                                     lam_p[((int64_t)c * 3 + 1) * N + i],
+                                     lam_p[((int64_t)c * 3 + 2) * N + i]};
+                double mv[3];
+                gp[0] = attractor_m(att, x[i], x[N + i], x[2 * N + i], blk.eps, l, mv);
+                for (int q = 0; q < 3; ++q) {
+                    o[q] -= att.S * mv[q];
+                    gp[1 + q] = att.S * mv[q];
+                }
+            }
             for (int q = 0; q < 3; ++q) {
-                const int64_t o = ((int64_t)c * 3 + q) * N + i;
-                const double lx = lam_x[o] + cw * (G * w[q]);
-                lam_x[o] = lx;
+                const int64_t k = ((int64_t)c * 3 + q) * N + i;
+                const double lx = lam_x[k] + cw * o[q];
+                lam_x[k] = lx;
                 if (do_drift)
-                    lam_p[o] += dnext * lx;
+                    lam_p[k] += dnext * lx;
+            }
+        }
+        if (att.on && att_acc) {
+            // this block's parameter derivatives, summed in particle order
+            if (lead)
+                for (int q = 0; q < 4; ++q)
+                    sg[q][pl] = gp[q];
+            __syncthreads();
+            if (threadIdx.x < 4) {
+                double t = 0.0;
+                for (int k = 0; k < kIntBlock; ++k)
+                    t += sg[threadIdx.x][k];
+                att_acc[((int64_t)blockIdx.x * n_cot + c) * 4 + threadIdx.x] += cw * t;
             }
         }
         __syncthreads();
     }
+}
+
+// out[c][q] = sum_b att_acc[b][c][q] over blocks in order.
+__global__ void att_grad_reduce_kernel(const double *__restrict__ att_acc, int n_blocks,
+                                       int n_cot, double *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)n_cot * 4)
+        return;
+    double t = 0.0;
+    for (int b = 0; b < n_blocks; ++b)
+        t += att_acc[(int64_t)b * n_cot * 4 + k];
+    out[k] = t;
+}
+
+__global__ void fill_kernel(double *__restrict__ p, int64_t n, double value)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n)
+        p[k] = value;
 }
 
 __global__ void scale_kernel(const double *__restrict__ src, double *__restrict__ dst, int64_t n,
@@ -518,32 +624,52 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 
 hipError_t launch_forces_finalize(int precision, const double *box_mass, const IntBlock *blocks,
                                   int n_blocks, const double *part, const double *part_phi,
-                                  int part_f32, const double *m, int64_t N, double G,
-                                  double scale, double *acc, double *phi, hipStream_t stream)
+                                  int part_f32, const double *x, const double *m, int64_t N,
+                                  double G, double scale, const Attractor &att, double inv_a3,
+                                  double *acc, double *phi, hipStream_t stream)
 {
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       precision, box_mass, blocks, part, part_phi, part_f32, m, N, G, scale,
-                       acc, phi);
+                       precision, box_mass, blocks, part, part_phi, part_f32, x, m, N, G, scale,
+                       att, inv_a3, acc, phi);
     return hipGetLastError();
 }
 
 hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
-                               int part_f32, const double *box_mass, int64_t N, int n_cot,
+                               int part_f32, const double *box_mass, const double *x,
+                               const double *lam, const Attractor &att, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, part_f32, box_mass, N, n_cot, G, out);
+                       blocks, part, part_f32, box_mass, x, lam, att, N, n_cot, G, out);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
-                                 int part_f32, const double *box_mass, int64_t N, int n_cot,
+                                 int part_f32, const double *box_mass, const double *x,
+                                 const Attractor &att, double *att_acc, int64_t N, int n_cot,
                                  double G, double cw, double *lam_x, double *lam_p,
                                  int do_drift, double dnext, hipStream_t stream)
 {
     hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, part_f32, box_mass, N, n_cot, G, cw, lam_x, lam_p, do_drift,
-                       dnext);
+                       blocks, part, part_f32, box_mass, x, att, att_acc, N, n_cot, G, cw, lam_x,
+                       lam_p, do_drift, dnext);
+    return hipGetLastError();
+}
+
+hipError_t launch_att_grad_reduce(const double *att_acc, int n_blocks, int n_cot, double *out,
+                                  hipStream_t stream)
+{
+    const int64_t n = (int64_t)n_cot * 4;
+    hipLaunchKernelGGL(att_grad_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream,
+                       att_acc, n_blocks, n_cot, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t stream)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p, n, value);
     return hipGetLastError();
 }
 

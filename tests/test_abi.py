@@ -24,6 +24,17 @@ def _declared():
     return sorted(set(re.findall(r"\b(colatus_[a-z0-9_]+)\s*\(", text)))
 
 
+def _declared_arity():
+    """Number of parameters of every prototype in the header."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(colatus_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", text):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
 def _has_gpu():
     try:
         import torch
@@ -39,6 +50,10 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(colatus.SIGNATURES), "binding signatures out of sync with header"
+    arity = _declared_arity()
+    assert set(arity) == set(names)
+    for n, (_, args) in colatus.SIGNATURES.items():
+        assert len(args) == arity[n], (n, len(args), arity[n])
 
 
 def test_strerror_and_version():
@@ -46,7 +61,7 @@ def test_strerror_and_version():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.colatus_strerror(code)
     assert L.colatus_strerror(-99) == b"unknown error code"
-    assert L.colatus_version() == 10000
+    assert L.colatus_version() == 10100
 
 
 def test_forces_rejects_bad_arguments():
@@ -57,7 +72,7 @@ def test_forces_rejects_bad_arguments():
     def call(**kw):
         a = dict(ok, **kw)
         return f(a["x"], a["m"], a["N"], a["eps"], a["G"], a["a"], a["prec"], a["acc"],
-                 a["phi"], None, None)
+                 a["phi"], None, a.get("att"), None)
 
     assert call(N=0) == EINVAL
     assert call(N=(1 << 28) + 1) == EINVAL
@@ -69,6 +84,10 @@ def test_forces_rejects_bad_arguments():
     assert call(prec=4) == EINVAL
     assert call(x=None) == EINVAL
     assert call(acc=None) == EINVAL
+    # the Eq. (10) attractor must be finite
+    for bad in ((float("nan"), (0.0, 0.0, 0.0)), (1.0, (0.0, float("inf"), 0.0))):
+        pa, keep = colatus._attractor(bad)
+        assert call(att=pa) == EINVAL
 
 
 def test_batch_descriptor_checks():
@@ -77,17 +96,18 @@ def test_batch_descriptor_checks():
     off = np.array([0, 10, 10, 30], dtype=np.int64)  # empty box
     eps = np.array([0.1, 0.1, 0.1])
     b = colatus._Batch(3, off.ctypes.data, eps.ctypes.data)
-    rc = L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b), None)
+    rc = L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b), None,
+                          None)
     assert rc == EINVAL
     off2 = np.array([0, 10, 25], dtype=np.int64)  # does not end at N
     b2 = colatus._Batch(2, off2.ctypes.data, eps.ctypes.data)
     assert L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b2),
-                            None) == EINVAL
+                            None, None) == EINVAL
     eps3 = np.array([0.1, -0.1])
     off3 = np.array([0, 10, 30], dtype=np.int64)
     b3 = colatus._Batch(2, off3.ctypes.data, eps3.ctypes.data)
     assert L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b3),
-                            None) == EINVAL
+                            None, None) == EINVAL
 
 
 def _run(**kw):
@@ -97,7 +117,7 @@ def _run(**kw):
     a.update(kw)
     return L.colatus_run(a["x"], a["v"], a["m"], a["N"], a["eps"], a["G"], *a["cos"],
                          a["a0"], a["a1"], a["n"], a["first"], a["last"], a["prec"], None, None,
-                         None)
+                         a.get("att"), None)
 
 
 def test_run_rejects_bad_arguments():
@@ -112,6 +132,8 @@ def test_run_rejects_bad_arguments():
     assert _run(cos=(1.0, 0, float("nan"), 0, 0)) == EINVAL
     assert _run(v=None) == EINVAL
     assert _run(prec=7) == EINVAL
+    pa, keep = colatus._attractor((0.5, (0.0, float("nan"), 0.0)))
+    assert _run(att=pa) == EINVAL
 
 
 def test_run_rejects_unphysical_friedmann_range():
@@ -126,16 +148,20 @@ def test_adjoint_rejects_bad_arguments():
     L = colatus.lib()
 
     def call(**kw):
-        a = dict(N=8, K=5, C=1, batch=None, prec=1)
+        a = dict(N=8, K=5, C=1, batch=None, prec=1, ga=None, att=None)
         a.update(kw)
         return L.colatus_adjoint(FAKE, FAKE, FAKE, a["N"], 0.01, 1.0, *LCDM, 0.2, 1.0, 10,
-                                 a["K"], a["C"], FAKE, FAKE, FAKE, FAKE, None, None, a["prec"],
-                                 a["batch"], None)
+                                 a["K"], a["C"], FAKE, FAKE, FAKE, FAKE, None, None, a["ga"],
+                                 a["prec"], a["batch"], a["att"], None)
 
     assert call(K=0) == EINVAL
     assert call(C=0) == EINVAL
     assert call(C=5000) == EINVAL
     assert call(batch=FAKE) == EINVAL
+    # attractor gradients need an attractor
+    assert call(ga=FAKE) == EINVAL
+    pa, keep = colatus._attractor((float("inf"), (0.0, 0.0, 0.0)))
+    assert call(att=pa) == EINVAL
 
 
 def test_hubble_host():
@@ -188,4 +214,5 @@ def test_options_and_tile_config():
 def test_valid_call_without_device_is_enodev():
     assert _run() == ENODEV
     L = colatus.lib()
-    assert L.colatus_forces(FAKE, FAKE, 16, 0.01, 1.0, 1.0, 0, FAKE, None, None, None) == ENODEV
+    assert L.colatus_forces(FAKE, FAKE, 16, 0.01, 1.0, 1.0, 0, FAKE, None, None, None,
+                            None) == ENODEV
