@@ -229,6 +229,21 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     out["mixed_fwd_diag"] = {"gpairs_s": (Kg + 1) * pairs / t / 1e9,
                              "ms_per_step": 1e3 * t / Kg}
 
+    # the same run with the Eq. (10) deformation attractor at the box centre
+    # (strength 0.05, a tenth of the box mass in units of G m): O(N) work
+    x, v, m = state()
+    att = (0.05, (0.5, 0.5, 0.5))
+    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=0,
+                last_step=5, precision=args.precision, attractor=att)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=5,
+                last_step=5 + Kg, precision=args.precision, attractor=att)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["mixed_fwd_attractor"] = {"gpairs_s": (Kg + 1) * pairs / t / 1e9,
+                                  "ms_per_step": 1e3 * t / Kg, "attractor": [0.05, 0.5, 0.5, 0.5]}
+
     # forward + adjoint (adjoint workload recipe, 200 steps from a = 0.2,
     # checkpoints every 20), one cotangent: the tracers' |v|^2 loss
     wa = inputs.adjoint_run(32)
