@@ -18,6 +18,8 @@ lives there:
 * ``time_integral``    -- the cosmic-time, kick and drift integrals of Eq. (9)
 * ``step_coefficients``-- the kick/drift/kick coefficients of one step
 * ``run``              -- kick-drift-kick run built from Eq. (9), diagnostics
+* ``run_he``           -- the paper's difference equations, Eqs. (3)-(5)
+* ``he_coefficients``  -- (tau, a, H) of one step of ``run_he``
 * ``adjoint``          -- discrete reverse mode of ``run``
 * ``ftle``             -- finite-time Lyapunov exponent of tracer particles
 
@@ -70,6 +72,11 @@ def _load():
     lib.oracle_run.restype = ctypes.c_int
     lib.oracle_run.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
         [_d, _d, _i64, _i64, _i64, _p, _d, _p]
+    lib.oracle_run_he.restype = ctypes.c_int
+    lib.oracle_run_he.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
+        [_d, _d, _i64, _i64, _i64, _p, _d, _p]
+    lib.oracle_he_coefficients.restype = None
+    lib.oracle_he_coefficients.argtypes = [_d] * 7 + [_i64, _i64, _p]
     lib.oracle_adjoint.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
         [_d, _d, _i64, _i32, _p, _p, _p, _p, _p, _p, _d, _p, _p]
@@ -209,6 +216,38 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
     if diag:
         return x, v, {f: rows[:, i].copy() for i, f in enumerate(DIAG_FIELDS)}
     return x, v
+
+
+def run_he(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
+           last_step=None, diag=False, attractor=None):
+    """Steps of the paper's difference equations (Eqs. (3)-(5)) on the same
+    grid as ``run``; returns (x, v) and the diagnostics rows if diag."""
+    if last_step is None:
+        last_step = n_steps
+    x = _c(x).copy()
+    v = _c(v).copy()
+    m = _c(m)
+    N = m.shape[0]
+    S, xp = _att(attractor)
+    rows = np.zeros((last_step - first_step + 1, len(DIAG_FIELDS))) if diag else None
+    rc = _load().oracle_run_he(
+        _ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
+        cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
+        first_step, last_step, _ptr(rows), S, _ptr(xp))
+    if rc != 0:
+        raise ValueError("oracle_run_he: invalid arguments")
+    if diag:
+        return x, v, {f: rows[:, i].copy() for i, f in enumerate(DIAG_FIELDS)}
+    return x, v
+
+
+def he_coefficients(cosmo, a_begin, a_end, n_steps, n):
+    """(tau, a_half, H_half) of step n of ``run_he``."""
+    out = np.zeros(3)
+    _load().oracle_he_coefficients(
+        cosmo["H0"], cosmo["Om_R"], cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"],
+        a_begin, a_end, n_steps, n, _ptr(out))
+    return tuple(out)
 
 
 def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,

@@ -566,6 +566,130 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's difference equations, Eqs. (3)-(5) (Hockney-Eastwood):       */
+/*   x^{n+1/2} = x^n + tau v^n / 2                                          */
+/*   v^{n+1}   = v^n (1 - H tau)/(1 + H tau)                                */
+/*               + g(x^{n+1/2}) tau / (a^3 (1 + H tau))                     */
+/*   x^{n+1}   = x^{n+1/2} + tau v^{n+1} / 2                                */
+/* with v = dx/dt the comoving velocity, g the comoving force sum (the      */
+/* gradient term of Eq. (4) read with the attractive sign, as Eq. (1)),     */
+/* tau the cosmic time of the step and H, a taken at the step's half time   */
+/* t^{n+1/2} = t^n + tau/2.  The steps use the same grid a_n as the run.    */
+/* ------------------------------------------------------------------------ */
+
+/* (tau, a_h, H_h) of step n: tau = t(a_{n+1}) - t(a_n); a_h solves
+ * t(a_h) - t(a_n) = tau / 2 (bisection on the monotone time integral);
+ * H_h = H(a_h).  Static limit: tau = dt, a_h = a, H_h = 0.                 */
+typedef struct { double tau, ah, Hh; } he_coef;
+
+static he_coef he_coefficients(const cosmo *c, double a_begin, double a_end,
+                               int64_t n_steps, int64_t n)
+{
+    he_coef h;
+    if (c->H0 == 0.0) {
+        h.tau = a_end / (double)n_steps;
+        h.ah = a_begin;
+        h.Hh = 0.0;
+        return h;
+    }
+    double a0 = grid_a(c, a_begin, a_end, n_steps, (double)n);
+    double a1 = grid_a(c, a_begin, a_end, n_steps, (double)(n + 1));
+    h.tau = time_integral(c, 1, a0, a1);
+    double half = 0.5 * h.tau;
+    double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+    for (int it = 0; it < 200 && hi > lo; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi)
+            break;
+        double t = time_integral(c, 1, a0, mid);
+        /* t grows with mid for a0 < a1 (expanding) and shrinks otherwise */
+        int below = (a0 < a1) ? (t < half) : (t > half);
+        if (below)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    h.ah = 0.5 * (lo + hi);
+    h.Hh = oracle_hubble(h.ah, c->H0, c->OmR, c->OmM, c->OmK, c->OmL);
+    return h;
+}
+
+void oracle_he_coefficients(double H0, double OmR, double OmM, double OmK, double OmL,
+                            double a_begin, double a_end, int64_t n_steps, int64_t n,
+                            double *out)
+{
+    cosmo c = {H0, OmR, OmM, OmK, OmL};
+    he_coef h = he_coefficients(&c, a_begin, a_end, n_steps, n);
+    out[0] = h.tau;
+    out[1] = h.ah;
+    out[2] = h.Hh;
+}
+
+/* Steps first_step..last_step-1 of Eqs. (3)-(5) in place on x, v; diag as in
+ * oracle_run (the state at the integer points, K = 1/2 sum m a^2 |v|^2).   */
+int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
+                  double G, double H0, double OmR, double OmM, double OmK,
+                  double OmL, double a_begin, double a_end, int64_t n_steps,
+                  int64_t first_step, int64_t last_step, double *diag, double att_S,
+                  const double *att_x)
+{
+    cosmo c = {H0, OmR, OmM, OmK, OmL};
+    if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
+        last_step > n_steps)
+        return -1;
+    size_t n3 = 3 * (size_t)N;
+    double *g = (double *)malloc(sizeof(double) * n3);
+    double *p = (double *)malloc(sizeof(double) * n3);
+    double a = grid_a(&c, a_begin, a_end, n_steps, (double)first_step);
+    double t = 0.0, E0 = 0.0, li_int = 0.0, prev_src = 0.0;
+    if (diag) {
+        double K, U, P[3], L[3];
+        for (size_t i = 0; i < n3; ++i)
+            p[i] = a * a * v[i];
+        energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
+        E0 = K + U;
+        prev_src = 2.0 * K + U;
+        double *row = diag;
+        row[0] = a; row[1] = 0.0; row[2] = K; row[3] = U; row[4] = 0.0;
+        for (int i = 0; i < 3; ++i) { row[5 + i] = P[i]; row[8 + i] = L[i]; }
+    }
+    for (int64_t n = first_step; n < last_step; ++n) {
+        he_coef h = he_coefficients(&c, a_begin, a_end, n_steps, n);
+        double tau = h.tau, Ht = h.Hh * h.tau;
+        for (size_t i = 0; i < n3; ++i)
+            x[i] += 0.5 * tau * v[i];
+        oracle_forces(x, m, N, eps, G, 1.0, g);
+        oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
+        double drag = (1.0 - Ht) / (1.0 + Ht);
+        double kick = tau / (h.ah * h.ah * h.ah * (1.0 + Ht));
+        for (size_t i = 0; i < n3; ++i)
+            v[i] = v[i] * drag + g[i] * kick;
+        for (size_t i = 0; i < n3; ++i)
+            x[i] += 0.5 * tau * v[i];
+        double a_prev = a;
+        a = grid_a(&c, a_begin, a_end, n_steps, (double)(n + 1));
+        t += tau;
+        if (diag) {
+            double K, U, P[3], L[3];
+            for (size_t i = 0; i < n3; ++i)
+                p[i] = a * a * v[i];
+            energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
+            double src = 2.0 * K + U;
+            double dlna = (c.H0 == 0.0) ? 0.0 : log(a) - log(a_prev);
+            li_int += 0.5 * (prev_src + src) * dlna;
+            prev_src = src;
+            double *row = diag + (size_t)(n + 1 - first_step) * DIAG_W;
+            row[0] = a; row[1] = t; row[2] = K; row[3] = U;
+            row[4] = K + U - E0 + li_int;
+            for (int i = 0; i < 3; ++i) { row[5 + i] = P[i]; row[8 + i] = L[i]; }
+        }
+    }
+    free(g);
+    free(p);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Discrete adjoint (reverse mode of the run map, every state stored).      */
 /* Forward step n:  p' = p_n + k1 g(x_n);  x_{n+1} = x_n + d p';            */
 /*                  p_{n+1} = p' + k2 g(x_{n+1}).                           */
