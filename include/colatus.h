@@ -185,6 +185,25 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
                 colatus_diag *diag, const colatus_batch *batch,
                 const colatus_attractor *attractor, void *stream);
 
+/* The paper's own difference equations, Eqs. (3)-(5) (after Hockney and
+ * Eastwood), on the grid of colatus_run, in place on x and v:
+ *   x^{n+1/2} = x^n + tau v^n / 2
+ *   v^{n+1}   = v^n (1 - H tau)/(1 + H tau) + g(x^{n+1/2}) tau / (a^3 (1 + H tau))
+ *   x^{n+1}   = x^{n+1/2} + tau v^{n+1} / 2
+ * with g the comoving sum of Eq. (1) (attractive sign; plus the attractor if
+ * given), tau the cosmic time of the step and H, a at its half time
+ * t^n + tau/2.  The paper notes this scheme is not symplectic; it is offered
+ * beside the kick-drift-kick step for that comparison (diagnostics rows as in
+ * colatus_run; each row costs one more pair sweep with the potential, at the
+ * integer-point positions).  One pair sweep per step, launched without
+ * graph capture.  Arguments, limits and errors as colatus_run.            */
+int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
+                   double G, double H0, double Om_R, double Om_M, double Om_K,
+                   double Om_L, double a_begin, double a_end, int64_t n_steps,
+                   int64_t first_step, int64_t last_step, int precision,
+                   colatus_diag *diag, const colatus_batch *batch,
+                   const colatus_attractor *attractor, void *stream);
+
 /* Reverse-mode derivative of the full run [0, n_steps) of colatus_run
  * (discretise-then-differentiate: the exact gradient of the computed map).
  * For each of n_cot cotangent pairs (lam_xN[c], lam_vN[c]), each [3][N],

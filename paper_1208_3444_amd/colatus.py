@@ -45,6 +45,8 @@ SIGNATURES = {
                           _p]),
     "colatus_run": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                          _i64, _i, _p, _p, _p, _p]),
+    "colatus_run_he": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
+                            _i64, _i, _p, _p, _p, _p]),
     "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                              _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p]),
     "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p]),
@@ -213,12 +215,14 @@ def _diag_dict(rows):
 
 
 def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step=None,
-        precision="mixed_twosum", diag=False, batch=None, attractor=None):
+        precision="mixed_twosum", diag=False, batch=None, attractor=None, scheme="kdk"):
     """Kick-drift-kick steps [first_step, last_step) of the global ln-a grid, in place.
 
     Returns the diagnostics (dict of numpy arrays, one entry per grid point;
     with a batch, a list of such dicts, one per box) if diag, else None.
     attractor: None or (S, (x, y, z)), the Eq. (10) deformation term.
+    scheme: 'kdk' (the Eq. (9) operators, colatus_run) or 'he' (the paper's
+    difference equations, Eqs. (3)-(5), colatus_run_he).
     """
     if last_step is None:
         last_step = n_steps
@@ -228,13 +232,16 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step
     pa, keep_a = _attractor(attractor)
     n_boxes = 1 if batch is None else len(keep[1])
     rows = (Diag * (n_boxes * (last_step - first_step + 1)))() if diag else None
-    rc = lib().colatus_run(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
-                           *_cosmo(cosmo), float(a_begin), float(a_end), int(n_steps),
-                           int(first_step), int(last_step), _prec(precision),
-                           ctypes.cast(rows, ctypes.c_void_p) if diag else None,
-                           ctypes.byref(b) if b is not None else None, pa, _stream(x))
+    if scheme not in ("kdk", "he"):
+        raise ValueError("scheme must be 'kdk' (Eq. (9) operators) or 'he' (Eqs. (3)-(5))")
+    fn = lib().colatus_run if scheme == "kdk" else lib().colatus_run_he
+    rc = fn(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
+            *_cosmo(cosmo), float(a_begin), float(a_end), int(n_steps),
+            int(first_step), int(last_step), _prec(precision),
+            ctypes.cast(rows, ctypes.c_void_p) if diag else None,
+            ctypes.byref(b) if b is not None else None, pa, _stream(x))
     del keep, keep_a
-    _check("colatus_run", rc)
+    _check("colatus_run" if scheme == "kdk" else "colatus_run_he", rc)
     if not diag:
         return None
     nr = last_step - first_step + 1

@@ -154,7 +154,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
-        box_mass, att_acc;
+        box_mass, att_acc, he_x;
     WorkList fwd, adj;
 };
 
@@ -1103,7 +1103,8 @@ int colatus_release(void)
                            &ws->diag_out, &ws->counters, &ws->lam_x, &ws->lam_p, &ws->ckpt,
                            &ws->seg, &ws->fwd.d_items, &ws->fwd.d_blocks, &ws->fwd.d_box_first,
                            &ws->adj.d_items, &ws->adj.d_blocks, &ws->adj.d_box_first,
-                           &ws->fwd.d_off, &ws->adj.d_off, &ws->box_mass, &ws->att_acc})
+                           &ws->fwd.d_off, &ws->adj.d_off, &ws->box_mass, &ws->att_acc,
+                           &ws->he_x})
             if (bb->ptr)
                 hipFree(bb->ptr);
         if (ws->cap_stream)
@@ -1146,6 +1147,117 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
                                      slots_f32(wl, precision), x, m, N, G, G / (a * a * a), att,
                                      1.0 / (a * a * a), acc, phi, s));
     return COLATUS_OK;
+}
+
+// The paper's difference equations, Eqs. (3)-(5): per step one sweep at the
+// half-step positions and one O(N) update (kick with drag, the two half
+// drifts fused across steps); with diagnostics, a potential sweep at the
+// integer-point positions as well.  Launched eagerly.
+int run_he_impl(const RunParams &P, const Boxes &b)
+{
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(P.stream, ws));
+    hipStream_t s = P.stream;
+    CHECK_RC(prepare_worklist(ws, 0, b, P.N, P.precision, P.x, P.m, 1, s));
+    const WorkList &wl = ws->fwd;
+    CHECK_RC(prepare_box_mass(ws, wl, P.m, s));
+    const int64_t nsteps = P.last - P.first;
+    const int64_t rows = nsteps + 1;
+    const int n_boxes = (int)b.eps.size();
+    const size_t n3 = 3 * (size_t)P.N;
+    CHECK_RC(ensure(ws->coef, (size_t)nsteps * sizeof(StepCoef)));
+    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n3 * sizeof(double)));
+    const bool diag = P.diag != nullptr;
+    if (diag) {
+        CHECK_RC(ensure(ws->he_x, n3 * sizeof(double)));
+        CHECK_RC(ensure(ws->part_phi, (size_t)wl.max_slices * P.N * sizeof(double)));
+        CHECK_RC(ensure(ws->diag_part, (size_t)rows * wl.blocks.size() * kDiagW * sizeof(double)));
+        CHECK_RC(ensure(ws->diag_out, (size_t)n_boxes * rows * sizeof(colatus_diag)));
+    }
+    bool mask = false;
+    for (double e : b.eps)
+        mask = mask || e == 0.0;
+
+    StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
+    double *vw = static_cast<double *>(ws->p.ptr);  // the velocity, updated in place
+    double *xi = diag ? static_cast<double *>(ws->he_x.ptr) : nullptr;
+    const IntBlock *blocks = static_cast<const IntBlock *>(wl.d_blocks.ptr);
+    const int n_blocks = (int)wl.blocks.size();
+    const int f32 = slots_f32(wl, P.precision);
+    const double *bm = static_cast<const double *>(ws->box_mass.ptr);
+    double *dpart = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
+    const double *pphi = static_cast<const double *>(ws->part_phi.ptr);
+    CHECK_HIP(launch_coefficients(P.H0, P.OmR, P.OmM, P.OmK, P.OmL, P.a_begin, P.a_end,
+                                  P.n_steps, P.first, P.last, coef, s));
+    CHECK_HIP(hipMemcpyAsync(vw, P.v, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (diag) {
+        CHECK_RC(run_forward_sweep(ws, wl, P.precision, true, mask, P.x, P.m, P.N, s, true));
+        CHECK_HIP(launch_state_diag(P.x, vw, P.m, pphi, f32, blocks, n_blocks, P.N, P.G, coef,
+                                    0, P.precision, bm, P.att, dpart, s));
+    }
+    CHECK_HIP(launch_he_drift(P.x, vw, P.N, coef, 0, 0.5, s));
+    HEArgs H;
+    H.x = P.x;
+    H.v = vw;
+    H.xi = xi;
+    H.part = static_cast<const double *>(ws->part.ptr);
+    H.part_f32 = f32;
+    H.blocks = blocks;
+    H.n_blocks = n_blocks;
+    H.N = P.N;
+    H.G = P.G;
+    H.coef = coef;
+    H.box_mass = bm;
+    H.att = P.att;
+    for (int64_t r = 0; r < nsteps; ++r) {
+        CHECK_RC(run_forward_sweep(ws, wl, P.precision, false, mask, P.x, P.m, P.N, s, true));
+        H.row = r;
+        H.last = r + 1 == nsteps ? 1 : 0;
+        CHECK_HIP(launch_he_step(H, s));
+        if (diag) {
+            CHECK_RC(run_forward_sweep(ws, wl, P.precision, true, mask, xi, P.m, P.N, s, true));
+            CHECK_HIP(launch_state_diag(xi, vw, P.m, pphi, f32, blocks, n_blocks, P.N, P.G, coef,
+                                        r + 1, P.precision, bm, P.att, dpart, s));
+        }
+    }
+    CHECK_HIP(hipMemcpyAsync(P.v, vw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (diag) {
+        CHECK_HIP(launch_diag_reduce(dpart, (int)rows, blocks, n_blocks, n_boxes,
+                                     static_cast<const int32_t *>(wl.d_box_first.ptr), coef,
+                                     P.H0, static_cast<double *>(ws->diag_out.ptr), s));
+        CHECK_HIP(hipMemcpyAsync(P.diag, ws->diag_out.ptr,
+                                 (size_t)n_boxes * rows * sizeof(colatus_diag),
+                                 hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        for (int64_t q = 0; q < (int64_t)n_boxes * rows; ++q)
+            if (P.diag[q].flags & 1u)
+                return COLATUS_ENONFINITE;
+    }
+    return COLATUS_OK;
+}
+
+int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps, double G,
+                   double H0, double Om_R, double Om_M, double Om_K, double Om_L,
+                   double a_begin, double a_end, int64_t n_steps, int64_t first_step,
+                   int64_t last_step, int precision, colatus_diag *diag,
+                   const colatus_batch *batch, const colatus_attractor *attractor,
+                   void *stream)
+{
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
+        return COLATUS_EINVAL;
+    if (n_steps < 1 || first_step < 0 || last_step <= first_step || last_step > n_steps)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, v, m}));
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, batch, b));
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    Attractor att;
+    CHECK_RC(resolve_attractor(attractor, att));
+    RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att};
+    return run_he_impl(P, b);
 }
 
 int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, double G,

@@ -33,14 +33,17 @@ struct IntBlock {
     int32_t n_slices; // partial-sum slots written for this box
 };
 
-// Coefficients of step n of a run (Eq. (9) integrals).
+// Coefficients of step n of a run (Eq. (9) integrals), and of the paper's
+// difference equations, Eqs. (3)-(5), on the same grid.
 struct StepCoef {
     double k1;   // int_{a_n}^{a_n+1/2} dt / a
     double d;    // int_{a_n}^{a_n+1} dt / a^2
     double k2;   // int_{a_n+1/2}^{a_n+1} dt / a
-    double dt;   // cosmic time of the step
+    double dt;   // cosmic time of the step (tau of Eqs. (3)-(5))
     double a0;   // a_n
     double a1;   // a_{n+1}
+    double ah;   // a at the half time t_n + dt/2 (Eqs. (3)-(5))
+    double Hh;   // H(ah)
 };
 
 enum Precision { kFP64 = 0, kMixedTwoSum = 1, kMixedF64Acc = 2, kFP32 = 3 };
@@ -172,6 +175,41 @@ hipError_t launch_integrate(const IntegrateArgs &args, hipStream_t stream);
 
 // *step += 1; *counter = 0.
 hipError_t launch_tick(int64_t *step, int *counter, hipStream_t stream);
+
+// ---- the paper's difference equations, Eqs. (3)-(5) ------------------------
+// x += f * coef[idx].dt * v over all particles (the opening half drift).
+hipError_t launch_he_drift(double *x, const double *v, int64_t N, const StepCoef *coef,
+                           int64_t idx, double f, hipStream_t stream);
+
+struct HEArgs {
+    double *x;             // [3][N]: x^{n+1/2} in; x^{n+3/2} (or x^{n+1} at the end) out
+    double *v;             // [3][N]: v^n in, v^{n+1} out
+    double *xi;            // [3][N] or null: receives x^{n+1}
+    const double *part;    // slots of the sweep at x^{n+1/2}
+    int part_f32;
+    const IntBlock *blocks;
+    int n_blocks;
+    int64_t N;
+    double G;
+    const StepCoef *coef;  // indexed by row
+    int64_t row;           // n - first
+    int last;              // n + 1 == last step of the call
+    const double *box_mass;
+    Attractor att;
+};
+// v = v (1 - H tau)/(1 + H tau) + g(x^{n+1/2}) tau / (a^3 (1 + H tau)) with H, a
+// at the half time; x^{n+1} = x^{n+1/2} + tau v / 2; then the next step's
+// opening half drift unless last.
+hipError_t launch_he_step(const HEArgs &args, hipStream_t stream);
+
+// Diagnostics row `row` of the state (x, v) at scale factor a_of(row):
+// row 0 -> coef[0].a0, row r > 0 -> coef[r - 1].a1; p = a^2 v; the potential
+// from the PHI slots of a sweep at x (plus the attractor).
+hipError_t launch_state_diag(const double *x, const double *v, const double *m,
+                             const double *part_phi, int part_f32, const IntBlock *blocks,
+                             int n_blocks, int64_t N, double G, const StepCoef *coef,
+                             int64_t row, int precision, const double *box_mass,
+                             const Attractor &att, double *diag_part, hipStream_t stream);
 
 // Reduce per-block diagnostics rows per box and accumulate LI / t.
 // out: [n_boxes][rows] rows of colatus_diag layout (as doubles, 14 each).

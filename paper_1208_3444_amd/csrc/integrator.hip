@@ -80,6 +80,8 @@ __global__ void coefficients_kernel(Cosmo c, double a_begin, double a_end, int64
         s.dt = dt;
         s.a0 = a;
         s.a1 = a;
+        s.ah = a;
+        s.Hh = 0.0;
     } else {
         const double delta = log(a_end / a_begin) / (double)n_steps;
         const double a0 = a_begin * exp((double)n * delta);
@@ -95,6 +97,19 @@ __global__ void coefficients_kernel(Cosmo c, double a_begin, double a_end, int64
         s.dt = lo[0] + hi[0];
         s.a0 = a0;
         s.a1 = a1;
+        // half time of Eqs. (3)-(5): solve int_{s0}^{u} ds / H = dt / 2 for
+        // u = ln a by Newton's method (derivative 1/H), from the ln-a midpoint
+        double u = sh;
+        for (int it = 0; it < 8; ++it) {
+            double t[3];
+            time_integrals(c, s0, u, t);
+            const double du = (t[0] - 0.5 * s.dt) * hubble(c, exp(u));
+            u -= du;
+            if (fabs(du) <= 1e-15 * fabs(u) + 1e-300)
+                break;
+        }
+        s.ah = exp(u);
+        s.Hh = hubble(c, s.ah);
     }
     coef[n - first] = s;
 }
@@ -548,6 +563,99 @@ __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// The paper's difference equations, Eqs. (3)-(5), in the comoving velocity v:
+// one sweep per step at the half-step positions, this O(N) update after it.
+// ---------------------------------------------------------------------------
+__global__ void he_drift_kernel(double *__restrict__ x, const double *__restrict__ v,
+                                int64_t n3, const StepCoef *__restrict__ coef, int64_t idx,
+                                double f)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3)
+        x[i] += f * coef[idx].dt * v[i];
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void he_step_kernel(HEArgs A)
+{
+    __shared__ double shs[4][kSliceGroups][kIntBlock];
+    const IntBlock blk = A.blocks[blockIdx.x];
+    const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
+    const bool valid = i < blk.i1;
+    const bool lead = threadIdx.x < kIntBlock;
+    const int64_t N = A.N;
+    const double mbox = box_mass_of(A.box_mass, blk.box);
+    double gs[3];
+    slot_sum<3>(A.part, A.part_f32, i, blk.n_slices, 3 * N, N, valid, shs, mbox, gs);
+    if (!(lead && valid))
+        return;
+    const StepCoef cf = A.coef[A.row];
+    double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
+    double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
+    double vv[3] = {A.v[i], A.v[N + i], A.v[2 * N + i]};
+    if (A.att.on)
+        (void)attractor_pull(A.att, xx[0], xx[1], xx[2], blk.eps, g);
+    const double tau = cf.dt, Ht = cf.Hh * tau;
+    const double drag = (1.0 - Ht) / (1.0 + Ht);
+    const double kick = tau / (cf.ah * cf.ah * cf.ah * (1.0 + Ht));
+    const double tnext = A.last ? 0.0 : A.coef[A.row + 1].dt;
+    for (int c = 0; c < 3; ++c) {
+        vv[c] = vv[c] * drag + g[c] * kick;
+        const double xi = xx[c] + 0.5 * tau * vv[c];
+        if (A.xi)
+            A.xi[(int64_t)c * N + i] = xi;
+        A.x[(int64_t)c * N + i] = A.last ? xi : xi + 0.5 * tnext * vv[c];
+        A.v[(int64_t)c * N + i] = vv[c];
+    }
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void state_diag_kernel(
+    const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ m,
+    const double *__restrict__ part_phi, int part_f32, const IntBlock *__restrict__ blocks,
+    int n_blocks, int64_t N, double G, const StepCoef *__restrict__ coef, int64_t row,
+    int precision, const double *__restrict__ box_mass, Attractor att,
+    double *__restrict__ diag_part)
+{
+    __shared__ double shs[4][kSliceGroups][kIntBlock];
+    __shared__ double sh[kDiagW][kIntBlock];
+    const IntBlock blk = blocks[blockIdx.x];
+    const int64_t i = blk.i0 + (threadIdx.x & (kIntBlock - 1));
+    const bool valid = i < blk.i1;
+    const bool lead = threadIdx.x < kIntBlock;
+    const double mbox = box_mass_of(box_mass, blk.box);
+    double t[1];
+    slot_sum<1>(part_phi, part_f32, i, blk.n_slices, N, N, valid, shs, mbox, t);
+    double w[kDiagW];
+    for (int q = 0; q < kDiagW; ++q)
+        w[q] = 0.0;
+    if (lead && valid) {
+        const double a = row == 0 ? coef[0].a0 : coef[row - 1].a1;
+        const double mi = m[i];
+        const double xx[3] = {x[i], x[N + i], x[2 * N + i]};
+        const double p[3] = {a * a * v[i], a * a * v[N + i], a * a * v[2 * N + i]};
+        double f[3] = {0.0, 0.0, 0.0};
+        const double phe = att.on ? attractor_pull(att, xx[0], xx[1], xx[2], blk.eps, f) : 0.0;
+        const double phi = -G * (t[0] - self_potential(precision, mi, blk.eps, mbox)) + 2.0 * phe;
+        w[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        w[1] = mi * phi;
+        w[2] = mi * p[0];
+        w[3] = mi * p[1];
+        w[4] = mi * p[2];
+        w[5] = mi * (xx[1] * p[2] - xx[2] * p[1]);
+        w[6] = mi * (xx[2] * p[0] - xx[0] * p[2]);
+        w[7] = mi * (xx[0] * p[1] - xx[1] * p[0]);
+        w[9] = (finite3(xx[0], xx[1], xx[2]) && finite3(p[0], p[1], p[2]) && isfinite(phi))
+                   ? 0.0
+                   : 1.0;
+    }
+    block_sum_rows(w, sh);
+    if (threadIdx.x == 0) {
+        double *out = diag_part + (row * n_blocks + blockIdx.x) * kDiagW;
+        for (int q = 0; q < kDiagW; ++q)
+            out[q] = w[q];
+    }
+}
+
 // out[c][q] = sum_b att_acc[b][c][q] over blocks in order.
 __global__ void att_grad_reduce_kernel(const double *__restrict__ att_acc, int n_blocks,
                                        int n_cot, double *__restrict__ out)
@@ -670,6 +778,33 @@ hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t stream)
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_he_drift(double *x, const double *v, int64_t N, const StepCoef *coef,
+                           int64_t idx, double f, hipStream_t stream)
+{
+    hipLaunchKernelGGL(he_drift_kernel, dim3(blocks_for(3 * N, 256)), dim3(256), 0, stream, x, v,
+                       3 * N, coef, idx, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_he_step(const HEArgs &args, hipStream_t stream)
+{
+    hipLaunchKernelGGL(he_step_kernel, dim3(args.n_blocks), dim3(kFinalizeThreads), 0, stream,
+                       args);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_diag(const double *x, const double *v, const double *m,
+                             const double *part_phi, int part_f32, const IntBlock *blocks,
+                             int n_blocks, int64_t N, double G, const StepCoef *coef,
+                             int64_t row, int precision, const double *box_mass,
+                             const Attractor &att, double *diag_part, hipStream_t stream)
+{
+    hipLaunchKernelGGL(state_diag_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream, x,
+                       v, m, part_phi, part_f32, blocks, n_blocks, N, G, coef, row, precision,
+                       box_mass, att, diag_part);
     return hipGetLastError();
 }
 
