@@ -244,6 +244,35 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     out["mixed_fwd_attractor"] = {"gpairs_s": (Kg + 1) * pairs / t / 1e9,
                                   "ms_per_step": 1e3 * t / Kg, "attractor": [0.05, 0.5, 0.5, 0.5]}
 
+    # the paper's difference equations, Eqs. (3)-(5): throughput over the
+    # timed steps, and the Layzer-Irvine residual of the whole 1000-step run
+    # against the kick-drift-kick scheme's (the paper calls the former not
+    # symplectic)
+    x, v, m = state()
+    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=0,
+                last_step=5, precision=args.precision, scheme="he")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=5,
+                last_step=5 + Kg, precision=args.precision, scheme="he")
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    li = {}
+    for scheme in ("kdk", "he"):
+        x, v, m = state()
+        d = colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
+                        precision=args.precision, diag=True, scheme=scheme)
+        u = np.abs(d["U"]).max()
+        li[scheme] = {"LI_end_over_maxU": float(abs(d["LI"][-1]) / u),
+                      "LI_max_over_maxU": float(np.abs(d["LI"]).max() / u)}
+    # one sweep per step (the force at the half step; none at the grid points)
+    out["he_difference_equations"] = {"gpairs_s": Kg * pairs / t / 1e9,
+                                      "ms_per_step": 1e3 * t / Kg,
+                                      "layzer_irvine_1000_steps": li}
+    print(f"[bench] Eqs. (3)-(5): {out['he_difference_equations']['gpairs_s']:.1f} Gpairs/s; "
+          f"LI/U kdk {li['kdk']['LI_max_over_maxU']:.2e} he {li['he']['LI_max_over_maxU']:.2e}",
+          file=sys.stderr, flush=True)
+
     # forward + adjoint (adjoint workload recipe, 200 steps from a = 0.2,
     # checkpoints every 20), one cotangent: the tracers' |v|^2 loss
     wa = inputs.adjoint_run(32)
