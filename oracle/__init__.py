@@ -71,10 +71,12 @@ def _load():
     lib.oracle_attractor_vjp.argtypes = [_p, _i64, _d, _d, _p, _p, _p]
     lib.oracle_run.restype = ctypes.c_int
     lib.oracle_run.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i64, _i64, _p, _d, _p]
+        [_d, _d, _i64, _i64, _i64, _p, _d, _p, _p, _i64, _p]
     lib.oracle_run_he.restype = ctypes.c_int
     lib.oracle_run_he.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i64, _i64, _p, _d, _p]
+        [_d, _d, _i64, _i64, _i64, _p, _d, _p, _p, _i64, _p]
+    lib.oracle_velocity_spectrum.restype = None
+    lib.oracle_velocity_spectrum.argtypes = [_p, _i64, _i64, ctypes.c_int, _p]
     lib.oracle_he_coefficients.restype = None
     lib.oracle_he_coefficients.argtypes = [_d] * 7 + [_i64, _i64, _p]
     lib.oracle_adjoint.restype = ctypes.c_int
@@ -192,13 +194,8 @@ def force_vjp(x, m, lam, eps, G=1.0, attractor=None):
     return out
 
 
-def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
-        last_step=None, diag=False, attractor=None):
-    """Kick-drift-kick run over steps first_step..last_step-1 of the grid.
-
-    Returns (x, v) at a_{last_step}, and the diagnostics rows (dict of arrays)
-    if diag is true.  attractor: None or (S, (x, y, z)), the Eq. (10) term.
-    """
+def _run(fn, name, x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step, last_step,
+         diag, attractor, tracers):
     if last_step is None:
         last_step = n_steps
     x = _c(x).copy()
@@ -206,39 +203,60 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
     m = _c(m)
     N = m.shape[0]
     S, xp = _att(attractor)
-    rows = np.zeros((last_step - first_step + 1, len(DIAG_FIELDS))) if diag else None
-    rc = _load().oracle_run(
-        _ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
-        cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
-        first_step, last_step, _ptr(rows), S, _ptr(xp))
+    nr = last_step - first_step + 1
+    rows = np.zeros((nr, len(DIAG_FIELDS))) if diag else None
+    trk = track = None
+    if tracers is not None:
+        trk = np.ascontiguousarray(tracers, dtype=np.int64)
+        if trk.ndim != 1 or trk.size == 0 or trk.min() < 0 or trk.max() >= N:
+            raise ValueError(f"{name}: tracers must be indices in [0, N)")
+        track = np.zeros((nr, 2, 3, trk.size))
+    rc = fn(_ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
+            cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
+            first_step, last_step, _ptr(rows), S, _ptr(xp),
+            trk.ctypes.data_as(_p) if trk is not None else None,
+            0 if trk is None else trk.size, _ptr(track))
     if rc != 0:
-        raise ValueError("oracle_run: invalid arguments")
+        raise ValueError(f"{name}: invalid arguments")
+    out = [x, v]
     if diag:
-        return x, v, {f: rows[:, i].copy() for i, f in enumerate(DIAG_FIELDS)}
-    return x, v
+        out.append({f: rows[:, i].copy() for i, f in enumerate(DIAG_FIELDS)})
+    if tracers is not None:
+        out.append(track)
+    return tuple(out)
+
+
+def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
+        last_step=None, diag=False, attractor=None, tracers=None):
+    """Kick-drift-kick run over steps first_step..last_step-1 of the grid.
+
+    Returns (x, v) at a_{last_step}, then the diagnostics rows (dict of
+    arrays) if diag is true, then the tracer track (rows, 2, 3, T) -- x and
+    v = dx/dt of particles ``tracers`` at every grid point -- if tracers is
+    given.  attractor: None or (S, (x, y, z)), the Eq. (10) term.
+    """
+    return _run(_load().oracle_run, "oracle_run", x, v, m, eps, G, cosmo, a_begin, a_end,
+                n_steps, first_step, last_step, diag, attractor, tracers)
 
 
 def run_he(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
-           last_step=None, diag=False, attractor=None):
+           last_step=None, diag=False, attractor=None, tracers=None):
     """Steps of the paper's difference equations (Eqs. (3)-(5)) on the same
-    grid as ``run``; returns (x, v) and the diagnostics rows if diag."""
-    if last_step is None:
-        last_step = n_steps
-    x = _c(x).copy()
-    v = _c(v).copy()
-    m = _c(m)
-    N = m.shape[0]
-    S, xp = _att(attractor)
-    rows = np.zeros((last_step - first_step + 1, len(DIAG_FIELDS))) if diag else None
-    rc = _load().oracle_run_he(
-        _ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
-        cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
-        first_step, last_step, _ptr(rows), S, _ptr(xp))
-    if rc != 0:
-        raise ValueError("oracle_run_he: invalid arguments")
-    if diag:
-        return x, v, {f: rows[:, i].copy() for i, f in enumerate(DIAG_FIELDS)}
-    return x, v
+    grid as ``run``; returns as ``run``."""
+    return _run(_load().oracle_run_he, "oracle_run_he", x, v, m, eps, G, cosmo, a_begin,
+                a_end, n_steps, first_step, last_step, diag, attractor, tracers)
+
+
+def velocity_spectrum(track, remove_mean=False):
+    """Periodogram of each tracer's velocity over the rows of a track
+    (rows, 2, 3, T): E[t, k] = (1/M) sum_c |sum_n w_c[n] e^{-2 pi i k n/M}|^2,
+    k = 0..M/2, w = v (less its mean if remove_mean).  Returns (T, M//2 + 1)."""
+    track = _c(track)
+    M, two, three, T = track.shape
+    assert two == 2 and three == 3
+    out = np.zeros((T, M // 2 + 1))
+    _load().oracle_velocity_spectrum(_ptr(track), M, T, 1 if remove_mean else 0, _ptr(out))
+    return out
 
 
 def he_coefficients(cosmo, a_begin, a_end, n_steps, n):

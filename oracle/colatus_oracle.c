@@ -498,16 +498,38 @@ static void energies(const double *x, const double *p, const double *m,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tracer tracks: the state of chosen particles at every grid point a run   */
+/* visits, so that a single particle's velocity can be followed step by     */
+/* step (the purpose the introduction gives the method).  Row r of a track  */
+/* holds [2][3][T] doubles: x_c of particle trk[t] at [0][c][t], its         */
+/* comoving velocity v_c = dx/dt at [1][c][t].  The velocity is given as   */
+/* v itself (scale 1) or as p = a^2 v (scale 1/a^2).                       */
+/* ------------------------------------------------------------------------ */
+static void record_track(const double *x, const double *vel, double a, int use_p,
+                         int64_t N, const int64_t *trk, int64_t T, double *row)
+{
+    for (int64_t t = 0; t < T; ++t) {
+        int64_t k = trk[t];
+        for (int c = 0; c < 3; ++c) {
+            row[(size_t)c * T + t] = x[(size_t)c * N + k];
+            double w = vel[(size_t)c * N + k];
+            row[(size_t)(3 + c) * T + t] = use_p ? w / (a * a) : w;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Run: kick-drift-kick steps first_step..last_step-1 of the global grid.   */
 /*   p = a_n^2 v;  p += k1 g(x_n);  x += d p;  p += k2 g(x_{n+1}).          */
 /* On return x, v hold the state at a_{last_step} (v = p/a^2).              */
-/* diag (optional) receives last-first+1 rows of DIAG_W doubles.            */
+/* diag (optional) receives last-first+1 rows of DIAG_W doubles; track      */
+/* (optional, with trk[n_trk]) the same rows of tracer states.              */
 /* ------------------------------------------------------------------------ */
 int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
                double G, double H0, double OmR, double OmM, double OmK,
                double OmL, double a_begin, double a_end, int64_t n_steps,
                int64_t first_step, int64_t last_step, double *diag, double att_S,
-               const double *att_x)
+               const double *att_x, const int64_t *trk, int64_t n_trk, double *track)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
@@ -521,6 +543,9 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
         p[i] = a * a * v[i];
     oracle_forces(x, m, N, eps, G, 1.0, g);
     oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
+    const size_t trow = 6 * (size_t)n_trk;
+    if (track)
+        record_track(x, v, a, 0, N, trk, n_trk, track);
 
     double t = 0.0, E0 = 0.0, li_int = 0.0, prev_src = 0.0;
     if (diag) {
@@ -545,6 +570,8 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
         double a_prev = a;
         a = grid_a(&c, a_begin, a_end, n_steps, (double)(n + 1));
         t += s.dt;
+        if (track)
+            record_track(x, p, a, 1, N, trk, n_trk, track + (size_t)(n + 1 - first_step) * trow);
         if (diag) {
             double K, U, P[3], L[3];
             energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
@@ -631,7 +658,7 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                   double G, double H0, double OmR, double OmM, double OmK,
                   double OmL, double a_begin, double a_end, int64_t n_steps,
                   int64_t first_step, int64_t last_step, double *diag, double att_S,
-                  const double *att_x)
+                  const double *att_x, const int64_t *trk, int64_t n_trk, double *track)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
@@ -642,6 +669,9 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
     double *p = (double *)malloc(sizeof(double) * n3);
     double a = grid_a(&c, a_begin, a_end, n_steps, (double)first_step);
     double t = 0.0, E0 = 0.0, li_int = 0.0, prev_src = 0.0;
+    const size_t trow = 6 * (size_t)n_trk;
+    if (track)
+        record_track(x, v, a, 0, N, trk, n_trk, track);
     if (diag) {
         double K, U, P[3], L[3];
         for (size_t i = 0; i < n3; ++i)
@@ -669,6 +699,8 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
         double a_prev = a;
         a = grid_a(&c, a_begin, a_end, n_steps, (double)(n + 1));
         t += tau;
+        if (track)
+            record_track(x, v, a, 0, N, trk, n_trk, track + (size_t)(n + 1 - first_step) * trow);
         if (diag) {
             double K, U, P[3], L[3];
             for (size_t i = 0; i < n3; ++i)
@@ -687,6 +719,52 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
     free(g);
     free(p);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Velocity power spectrum of a tracer's track: the periodogram of its      */
+/* velocity series over the M rows (the "energy power spectrum" of a single */
+/* particle's velocity that the introduction names as the method's goal):   */
+/*   E(k) = (1/M) sum_c | sum_{n<M} w_c[n] exp(-2 pi i k n / M) |^2,        */
+/*   k = 0 .. M/2,  w_c[n] = v_c at row n, less its mean over the rows if   */
+/*   remove_mean.  The rows are the run's grid points, uniform in ln a, so  */
+/*   k counts cycles per M steps of that grid.  The phase k n is reduced    */
+/*   modulo M exactly before the angle is formed.                           */
+/* out[t][k], (M/2 + 1) values per tracer.                                  */
+/* ------------------------------------------------------------------------ */
+void oracle_velocity_spectrum(const double *track, int64_t M, int64_t T, int remove_mean,
+                              double *out)
+{
+    const int64_t K = M / 2 + 1;
+    const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < T; ++t) {
+        double *w = (double *)malloc(sizeof(double) * (size_t)M);
+        for (int64_t k = 0; k < K; ++k)
+            out[t * K + k] = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            ksum mean = {0, 0};
+            for (int64_t n = 0; n < M; ++n) {
+                w[n] = track[(size_t)n * 6 * T + (size_t)(3 + c) * T + t];
+                ksum_add(&mean, w[n]);
+            }
+            double mu = remove_mean ? ksum_value(&mean) / (double)M : 0.0;
+            for (int64_t n = 0; n < M; ++n)
+                w[n] -= mu;
+            for (int64_t k = 0; k < K; ++k) {
+                ksum re = {0, 0}, im = {0, 0};
+                for (int64_t n = 0; n < M; ++n) {
+                    int64_t j = (k * n) % M;
+                    double ang = two_pi * (double)j / (double)M;
+                    ksum_add(&re, w[n] * cos(ang));
+                    ksum_add(&im, -w[n] * sin(ang));
+                }
+                double r = ksum_value(&re), i = ksum_value(&im);
+                out[t * K + k] += (r * r + i * i) / (double)M;
+            }
+        }
+        free(w);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
