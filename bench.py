@@ -273,6 +273,34 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
           f"LI/U kdk {li['kdk']['LI_max_over_maxU']:.2e} he {li['he']['LI_max_over_maxU']:.2e}",
           file=sys.stderr, flush=True)
 
+    # tracer tracks of 64 particles at every grid point over the timed steps,
+    # then the velocity power spectrum of their whole 1000-step tracks
+    tr = np.random.default_rng(55).choice(N, 64, replace=False)
+    x, v, m = state()
+    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=0,
+                last_step=5, precision=args.precision, tracers=tr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=5,
+                last_step=5 + Kg, precision=args.precision, tracers=tr)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    x, v, m = state()
+    _, track = colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
+                           precision=args.precision, tracers=tr)
+    colatus.velocity_spectrum(track, remove_mean=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(10):
+        colatus.velocity_spectrum(track, remove_mean=True)
+    torch.cuda.synchronize()
+    out["tracks_64"] = {"gpairs_s": (Kg + 1) * pairs / t / 1e9, "ms_per_step": 1e3 * t / Kg,
+                        "track_rows": int(track.shape[0]),
+                        "spectrum_ms": 1e3 * (time.perf_counter() - t1) / 10}
+    print(f"[bench] 64 tracers: {out['tracks_64']['gpairs_s']:.1f} Gpairs/s; spectrum of "
+          f"{track.shape[0]} rows {out['tracks_64']['spectrum_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+
     # forward + adjoint (adjoint workload recipe, 200 steps from a = 0.2,
     # checkpoints every 20), one cotangent: the tracers' |v|^2 loss
     wa = inputs.adjoint_run(32)

@@ -111,6 +111,25 @@ typedef struct {
     double x[3];     /* x_psi, comoving */
 } colatus_attractor;
 
+/* ---- tracer tracks ----------------------------------------------------- */
+/* The state of chosen particles at every grid point a run visits, so that
+ * a single particle's velocity can be followed step by step (Section I and
+ * Section IV give this as the method's purpose).
+ *   index: HOST array of n_tracers distinct particle indices in [0, N)
+ *          (global indices when a batch is given), read during the call.
+ *   out:   DEVICE array [rows][2][3][n_tracers], rows = last_step -
+ *          first_step + 1, written by the call: out[r][0][c][t] = x_c and
+ *          out[r][1][c][t] = v_c (= dx/dt, comoving) of particle index[t] at
+ *          grid point first_step + r; row 0 is the start state as given.
+ * 1 <= n_tracers <= 65536, else COLATUS_EINVAL (as for a repeated or
+ * out-of-range index, or a NULL pointer).  Recording adds no launch per
+ * step (the step kernels write the rows).                                 */
+typedef struct {
+    int32_t n_tracers;
+    const int64_t *index; /* host, n_tracers */
+    double *out;          /* device, [rows][2][3][n_tracers] */
+} colatus_tracks;
+
 /* ---- diagnostics row --------------------------------------------------- */
 /* One row per integer grid point a_n visited by a run (first row: the start
  * state).  With p = a^2 v:
@@ -177,13 +196,15 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
  * Requires n_steps >= 1, 0 <= first_step < last_step <= n_steps, a_begin > 0,
  * a_end > 0 (or > 0 elapsed time in the static limit), H^2 > 0 on the range
  * (else COLATUS_EFRIEDMANN).  attractor (or NULL): the Eq. (10) term joins g
- * at every kick and its energy joins U.                                    */
+ * at every kick and its energy joins U.  tracks (or NULL): see
+ * colatus_tracks; rows r >= 1 hold v = p / a^2 as the final v does.        */
 int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
                 double G, double H0, double Om_R, double Om_M, double Om_K,
                 double Om_L, double a_begin, double a_end, int64_t n_steps,
                 int64_t first_step, int64_t last_step, int precision,
                 colatus_diag *diag, const colatus_batch *batch,
-                const colatus_attractor *attractor, void *stream);
+                const colatus_attractor *attractor, const colatus_tracks *tracks,
+                void *stream);
 
 /* The paper's own difference equations, Eqs. (3)-(5) (after Hockney and
  * Eastwood), on the grid of colatus_run, in place on x and v:
@@ -196,13 +217,32 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
  * beside the kick-drift-kick step for that comparison (diagnostics rows as in
  * colatus_run; each row costs one more pair sweep with the potential, at the
  * integer-point positions).  One pair sweep per step, launched without
- * graph capture.  Arguments, limits and errors as colatus_run.            */
+ * graph capture.  Arguments, limits and errors as colatus_run (tracks: the
+ * state at the integer points, x^n and v^n).                              */
 int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                    double G, double H0, double Om_R, double Om_M, double Om_K,
                    double Om_L, double a_begin, double a_end, int64_t n_steps,
                    int64_t first_step, int64_t last_step, int precision,
                    colatus_diag *diag, const colatus_batch *batch,
-                   const colatus_attractor *attractor, void *stream);
+                   const colatus_attractor *attractor, const colatus_tracks *tracks,
+                   void *stream);
+
+/* Velocity power spectrum of each tracer of a track (the power spectrum of
+ * a single particle's velocity series that Section I names as the method's
+ * goal): the periodogram over the track's rows,
+ *   out[t][k] = (1/rows) sum_c | sum_{n < rows} w_c[n] exp(-2 pi i k n / rows) |^2,
+ *   k = 0 .. rows/2,  w_c[n] = v_c of tracer t at row n, less its mean over
+ *   the rows if remove_mean != 0.
+ * The rows are grid points uniform in ln a, so k counts cycles per `rows`
+ * grid steps.  Parseval: out[t][0] + 2 sum_{0<k<rows/2} out[t][k]
+ * (+ out[t][rows/2] for even rows) = sum_n |w[n]|^2.
+ *   track: DEVICE [rows][2][3][n_tracers] (as colatus_tracks.out).
+ *   out:   DEVICE [n_tracers][rows/2 + 1], written.
+ * FP64 throughout; the phase k n is reduced modulo rows exactly before the
+ * twiddle factor is formed.  A direct transform: cost ~ rows^2 n_tracers.
+ * 1 <= rows <= 131072 and 1 <= n_tracers <= 65536, else COLATUS_EINVAL.   */
+int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_tracers,
+                              int remove_mean, double *out, void *stream);
 
 /* Reverse-mode derivative of the full run [0, n_steps) of colatus_run
  * (discretise-then-differentiate: the exact gradient of the computed map).

@@ -44,9 +44,10 @@ SIGNATURES = {
     "colatus_step": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i, _p, _p,
                           _p]),
     "colatus_run": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                         _i64, _i, _p, _p, _p, _p]),
+                         _i64, _i, _p, _p, _p, _p, _p]),
     "colatus_run_he": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                            _i64, _i, _p, _p, _p, _p]),
+                            _i64, _i, _p, _p, _p, _p, _p]),
+    "colatus_velocity_spectrum": (_i, [_p, _i64, _i32, _i, _p, _p]),
     "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                              _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p]),
     "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p]),
@@ -87,6 +88,24 @@ def _attractor(att):
         raise ValueError("attractor position must have 3 components")
     a = _Attractor(float(S), (_d * 3)(*xp))
     return ctypes.byref(a), a
+
+
+class _Tracks(ctypes.Structure):
+    _fields_ = [("n_tracers", ctypes.c_int32), ("index", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+def _tracks(tracers, rows, like):
+    """tracers (sequence of particle indices) -> (pointer to a colatus_tracks,
+    objects to keep alive, the device track tensor (rows, 2, 3, T))."""
+    if tracers is None:
+        return None, None, None
+    import numpy as np
+    idx = np.ascontiguousarray(np.asarray(tracers, dtype=np.int64).reshape(-1))
+    track = torch.empty((rows, 2, 3, idx.size), dtype=torch.float64, device=like.device)
+    t = _Tracks(int(idx.size), idx.ctypes.data_as(ctypes.c_void_p),
+                ctypes.c_void_p(track.data_ptr()))
+    return ctypes.byref(t), (t, idx), track
 
 
 class Diag(ctypes.Structure):
@@ -215,7 +234,8 @@ def _diag_dict(rows):
 
 
 def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step=None,
-        precision="mixed_twosum", diag=False, batch=None, attractor=None, scheme="kdk"):
+        precision="mixed_twosum", diag=False, batch=None, attractor=None, scheme="kdk",
+        tracers=None):
     """Kick-drift-kick steps [first_step, last_step) of the global ln-a grid, in place.
 
     Returns the diagnostics (dict of numpy arrays, one entry per grid point;
@@ -223,6 +243,9 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step
     attractor: None or (S, (x, y, z)), the Eq. (10) deformation term.
     scheme: 'kdk' (the Eq. (9) operators, colatus_run) or 'he' (the paper's
     difference equations, Eqs. (3)-(5), colatus_run_he).
+    tracers: None or particle indices; then the return value is the pair
+    (diagnostics or None, track), track a device tensor (rows, 2, 3, T) of
+    x and v = dx/dt of each tracer at every grid point of the call.
     """
     if last_step is None:
         last_step = n_steps
@@ -231,22 +254,40 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step
     b, keep = _batch(batch)
     pa, keep_a = _attractor(attractor)
     n_boxes = 1 if batch is None else len(keep[1])
-    rows = (Diag * (n_boxes * (last_step - first_step + 1)))() if diag else None
+    nr = last_step - first_step + 1
+    rows = (Diag * (n_boxes * nr))() if diag else None
     if scheme not in ("kdk", "he"):
         raise ValueError("scheme must be 'kdk' (Eq. (9) operators) or 'he' (Eqs. (3)-(5))")
+    pt, keep_t, track = _tracks(tracers, nr, x)
     fn = lib().colatus_run if scheme == "kdk" else lib().colatus_run_he
     rc = fn(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
             *_cosmo(cosmo), float(a_begin), float(a_end), int(n_steps),
             int(first_step), int(last_step), _prec(precision),
             ctypes.cast(rows, ctypes.c_void_p) if diag else None,
-            ctypes.byref(b) if b is not None else None, pa, _stream(x))
-    del keep, keep_a
+            ctypes.byref(b) if b is not None else None, pa, pt, _stream(x))
+    del keep, keep_a, keep_t
     _check("colatus_run" if scheme == "kdk" else "colatus_run_he", rc)
-    if not diag:
-        return None
-    nr = last_step - first_step + 1
-    per_box = [_diag_dict(rows[k * nr:(k + 1) * nr]) for k in range(n_boxes)]
-    return per_box[0] if batch is None else per_box
+    d = None
+    if diag:
+        per_box = [_diag_dict(rows[k * nr:(k + 1) * nr]) for k in range(n_boxes)]
+        d = per_box[0] if batch is None else per_box
+    return d if tracers is None else (d, track)
+
+
+def velocity_spectrum(track, remove_mean=False):
+    """Periodogram of each tracer's velocity over the rows of a track
+    (rows, 2, 3, T) on the device: out[t, k] = (1/rows) sum_c |sum_n
+    w_c[n] exp(-2 pi i k n / rows)|^2, k = 0..rows//2, w = v (less its mean
+    over the rows if remove_mean).  Returns a (T, rows//2 + 1) tensor."""
+    if track.dim() != 4 or track.shape[1] != 2 or track.shape[2] != 3:
+        raise ValueError("track must be (rows, 2, 3, T)")
+    M, T = track.shape[0], track.shape[3]
+    pt = _dev(track, "track", tuple(track.shape))
+    out = torch.empty((T, M // 2 + 1), dtype=torch.float64, device=track.device)
+    rc = lib().colatus_velocity_spectrum(pt, M, T, 1 if remove_mean else 0,
+                                         ctypes.c_void_p(out.data_ptr()), _stream(track))
+    _check("colatus_velocity_spectrum", rc)
+    return out
 
 
 def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum", attractor=None):

@@ -154,7 +154,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
-        box_mass, att_acc, he_x;
+        box_mass, att_acc, he_x, track_idx, track_slot, twiddle;
     WorkList fwd, adj;
 };
 
@@ -212,6 +212,36 @@ int resolve_attractor(const colatus_attractor *a, Attractor &out)
     if (!is_fin(a->strength) || !is_fin(a->x[0]) || !is_fin(a->x[1]) || !is_fin(a->x[2]))
         return COLATUS_EINVAL;
     out = Attractor{1, a->strength, a->x[0], a->x[1], a->x[2]};
+    return COLATUS_OK;
+}
+
+// Tracer tracks: validated host index list and the caller's device output.
+constexpr int32_t kMaxTracers = 65536;
+constexpr int64_t kMaxSpectrumRows = (int64_t)1 << 17;
+
+struct Tracks {
+    int32_t n = 0;
+    const int64_t *index = nullptr;
+    double *out = nullptr;
+};
+
+int resolve_tracks(const colatus_tracks *t, int64_t N, Tracks &out)
+{
+    out = Tracks{};
+    if (!t)
+        return COLATUS_OK;
+    if (t->n_tracers < 1 || t->n_tracers > kMaxTracers || !t->index || !t->out)
+        return COLATUS_EINVAL;
+    std::vector<int64_t> idx(t->index, t->index + t->n_tracers);
+    std::sort(idx.begin(), idx.end());
+    if (idx.front() < 0 || idx.back() >= N)
+        return COLATUS_EINVAL;
+    for (size_t k = 1; k < idx.size(); ++k)
+        if (idx[k] == idx[k - 1])
+            return COLATUS_EINVAL;
+    out.n = t->n_tracers;
+    out.index = t->index;
+    out.out = t->out;
     return COLATUS_OK;
 }
 
@@ -821,7 +851,27 @@ struct RunParams {
     colatus_diag *diag;
     hipStream_t stream;
     Attractor att;
+    Tracks trk;
 };
+
+// Upload the tracer list, build the particle -> tracer map and write the
+// start-state row of the track (x and v as given).
+int prepare_tracks(Workspace *ws, const RunParams &P)
+{
+    if (P.trk.n == 0)
+        return COLATUS_OK;
+    hipStream_t s = P.stream;
+    CHECK_RC(ensure(ws->track_idx, (size_t)P.trk.n * sizeof(int64_t)));
+    CHECK_RC(ensure(ws->track_slot, (size_t)P.N * sizeof(int32_t)));
+    const int64_t *didx = static_cast<const int64_t *>(ws->track_idx.ptr);
+    CHECK_HIP(hipMemcpyAsync(ws->track_idx.ptr, P.trk.index, (size_t)P.trk.n * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
+    CHECK_HIP(hipStreamSynchronize(s));  // the host list is the caller's
+    CHECK_HIP(launch_track_slots(static_cast<int32_t *>(ws->track_slot.ptr), P.N, didx, P.trk.n,
+                                 s));
+    CHECK_HIP(launch_track_gather(P.x, P.v, P.N, didx, P.trk.n, P.trk.out, s));
+    return COLATUS_OK;
+}
 
 int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, bool mask,
                   int64_t n_iter)
@@ -935,6 +985,10 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
     A.part_f32 = slots_f32(wl, P.precision);
     A.att = P.att;
+    CHECK_RC(prepare_tracks(ws, P));
+    A.track_slot = P.trk.n ? static_cast<const int32_t *>(ws->track_slot.ptr) : nullptr;
+    A.track = P.trk.out;
+    A.n_tracers = P.trk.n;
 
     CHECK_RC(enqueue_steps(ws, P, A, mask, nsteps));
     CHECK_RC(run_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
@@ -962,7 +1016,7 @@ int run_impl(const RunParams &P, const Boxes &b)
 // ===========================================================================
 extern "C" {
 
-int colatus_version(void) { return 10100; }
+int colatus_version(void) { return 10200; }
 
 const char *colatus_strerror(int code)
 {
@@ -1192,6 +1246,7 @@ int run_he_impl(const RunParams &P, const Boxes &b)
     CHECK_HIP(launch_coefficients(P.H0, P.OmR, P.OmM, P.OmK, P.OmL, P.a_begin, P.a_end,
                                   P.n_steps, P.first, P.last, coef, s));
     CHECK_HIP(hipMemcpyAsync(vw, P.v, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CHECK_RC(prepare_tracks(ws, P));
     if (diag) {
         CHECK_RC(run_forward_sweep(ws, wl, P.precision, true, mask, P.x, P.m, P.N, s, true));
         CHECK_HIP(launch_state_diag(P.x, vw, P.m, pphi, f32, blocks, n_blocks, P.N, P.G, coef,
@@ -1211,6 +1266,9 @@ int run_he_impl(const RunParams &P, const Boxes &b)
     H.coef = coef;
     H.box_mass = bm;
     H.att = P.att;
+    H.track_slot = P.trk.n ? static_cast<const int32_t *>(ws->track_slot.ptr) : nullptr;
+    H.track = P.trk.out;
+    H.n_tracers = P.trk.n;
     for (int64_t r = 0; r < nsteps; ++r) {
         CHECK_RC(run_forward_sweep(ws, wl, P.precision, false, mask, P.x, P.m, P.N, s, true));
         H.row = r;
@@ -1243,7 +1301,7 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                    double a_begin, double a_end, int64_t n_steps, int64_t first_step,
                    int64_t last_step, int precision, colatus_diag *diag,
                    const colatus_batch *batch, const colatus_attractor *attractor,
-                   void *stream)
+                   const colatus_tracks *tracks, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
         return COLATUS_EINVAL;
@@ -1255,8 +1313,11 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
     Attractor att;
     CHECK_RC(resolve_attractor(attractor, att));
+    Tracks trk;
+    CHECK_RC(resolve_tracks(tracks, N, trk));
     RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
-                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att};
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att,
+                trk};
     return run_he_impl(P, b);
 }
 
@@ -1264,7 +1325,8 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
                 double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a_begin,
                 double a_end, int64_t n_steps, int64_t first_step, int64_t last_step,
                 int precision, colatus_diag *diag, const colatus_batch *batch,
-                const colatus_attractor *attractor, void *stream)
+                const colatus_attractor *attractor, const colatus_tracks *tracks,
+                void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
         return COLATUS_EINVAL;
@@ -1276,8 +1338,11 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
     Attractor att;
     CHECK_RC(resolve_attractor(attractor, att));
+    Tracks trk;
+    CHECK_RC(resolve_tracks(tracks, N, trk));
     RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
-                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att};
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att,
+                trk};
     return run_impl(P, b);
 }
 
@@ -1287,7 +1352,23 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, d
                  const colatus_attractor *attractor, void *stream)
 {
     return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
-                       precision, nullptr, batch, attractor, stream);
+                       precision, nullptr, batch, attractor, nullptr, stream);
+}
+
+int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_tracers,
+                              int remove_mean, double *out, void *stream)
+{
+    if (rows < 1 || rows > kMaxSpectrumRows || n_tracers < 1 || n_tracers > kMaxTracers)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({track, out}));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(ensure(ws->twiddle, (size_t)rows * 2 * sizeof(double)));
+    CHECK_HIP(launch_velocity_spectrum(track, rows, n_tracers, remove_mean ? 1 : 0,
+                                       static_cast<double *>(ws->twiddle.ptr), out, s));
+    return COLATUS_OK;
 }
 
 int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, double G,

@@ -166,6 +166,9 @@ struct IntegrateArgs {
     const double *box_mass;// per-box common mass or NaN (as given to the sweep)
     int part_f32;          // slots are FP32 without the common mass (see above)
     Attractor att;         // Eq. (10) term added to g (att.on == 0: none)
+    const int32_t *track_slot = nullptr; // [N]: tracer number of each particle or -1
+    double *track = nullptr;   // [rows][2][3][n_tracers]: rows n > first are written here
+    int32_t n_tracers = 0;
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and
@@ -196,11 +199,29 @@ struct HEArgs {
     int last;              // n + 1 == last step of the call
     const double *box_mass;
     Attractor att;
+    const int32_t *track_slot = nullptr; // as in IntegrateArgs: row + 1 (x^{n+1}, v^{n+1})
+    double *track = nullptr;
+    int32_t n_tracers = 0;
 };
 // v = v (1 - H tau)/(1 + H tau) + g(x^{n+1/2}) tau / (a^3 (1 + H tau)) with H, a
 // at the half time; x^{n+1} = x^{n+1/2} + tau v / 2; then the next step's
 // opening half drift unless last.
 hipError_t launch_he_step(const HEArgs &args, hipStream_t stream);
+
+// ---- tracer tracks ---------------------------------------------------------
+// slot[i] = -1 for all N particles, then slot[idx[t]] = t.
+hipError_t launch_track_slots(int32_t *slot, int64_t N, const int64_t *idx, int32_t T,
+                              hipStream_t stream);
+// One track row [2][3][T] from x and v (the start state): row[c][t] = x[c][idx[t]],
+// row[3 + c][t] = v[c][idx[t]].
+hipError_t launch_track_gather(const double *x, const double *v, int64_t N,
+                               const int64_t *idx, int32_t T, double *row, hipStream_t stream);
+
+// Velocity periodogram of each tracer over M track rows (spectrum.hip):
+// out[t][k] = (1/M) sum_c |sum_n w_c[n] e^{-2 pi i k n / M}|^2, k <= M/2,
+// w = v (less its mean if remove_mean).  twiddle: [M] double2 scratch.
+hipError_t launch_velocity_spectrum(const double *track, int64_t M, int32_t T, int remove_mean,
+                                    double *twiddle, double *out, hipStream_t stream);
 
 // Diagnostics row `row` of the state (x, v) at scale factor a_of(row):
 // row 0 -> coef[0].a0, row r > 0 -> coef[r - 1].a1; p = a^2 v; the potential

@@ -327,9 +327,19 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
         if (A.att.on)
             phe = attractor_pull(A.att, xx[0], xx[1], xx[2], blk.eps, g);
         if (n > A.first) {
-            const double k2 = A.coef[row - 1].k2;
+            const StepCoef cp = A.coef[row - 1];
             for (int c = 0; c < 3; ++c)
-                p[c] += k2 * g[c];
+                p[c] += cp.k2 * g[c];
+            // tracer row at a_n: v = p / a^2, the final conversion's formula
+            const int32_t t = A.track_slot ? A.track_slot[i] : -1;
+            if (t >= 0) {
+                const int64_t T = A.n_tracers;
+                double *out = A.track + row * 6 * T + t;
+                for (int c = 0; c < 3; ++c) {
+                    out[c * T] = xx[c];
+                    out[(3 + c) * T] = p[c] / (cp.a1 * cp.a1);
+                }
+            }
         }
         if (A.diag_part) {
             const double mi = A.m[i];
@@ -599,13 +609,53 @@ __global__ __launch_bounds__(kFinalizeThreads) void he_step_kernel(HEArgs A)
     const double drag = (1.0 - Ht) / (1.0 + Ht);
     const double kick = tau / (cf.ah * cf.ah * cf.ah * (1.0 + Ht));
     const double tnext = A.last ? 0.0 : A.coef[A.row + 1].dt;
+    const int32_t t = A.track_slot ? A.track_slot[i] : -1;
+    const int64_t T = A.n_tracers;
+    double *out = t >= 0 ? A.track + (A.row + 1) * 6 * T + t : nullptr;
     for (int c = 0; c < 3; ++c) {
         vv[c] = vv[c] * drag + g[c] * kick;
         const double xi = xx[c] + 0.5 * tau * vv[c];
         if (A.xi)
             A.xi[(int64_t)c * N + i] = xi;
+        if (out) {
+            out[c * T] = xi;
+            out[(3 + c) * T] = vv[c];
+        }
         A.x[(int64_t)c * N + i] = A.last ? xi : xi + 0.5 * tnext * vv[c];
         A.v[(int64_t)c * N + i] = vv[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tracer tracks: the particle -> tracer map read by the step kernels, and the
+// start-state row.
+// ---------------------------------------------------------------------------
+__global__ void track_slots_fill_kernel(int32_t *__restrict__ slot, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N)
+        slot[i] = -1;
+}
+
+__global__ void track_slots_set_kernel(int32_t *__restrict__ slot,
+                                       const int64_t *__restrict__ idx, int32_t T)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T)
+        slot[idx[t]] = t;
+}
+
+__global__ void track_gather_kernel(const double *__restrict__ x, const double *__restrict__ v,
+                                    int64_t N, const int64_t *__restrict__ idx, int32_t T,
+                                    double *__restrict__ row)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T)
+        return;
+    const int64_t k = idx[t];
+    for (int c = 0; c < 3; ++c) {
+        row[(int64_t)c * T + t] = x[c * N + k];
+        row[(int64_t)(3 + c) * T + t] = v[c * N + k];
     }
 }
 
@@ -786,6 +836,24 @@ hipError_t launch_he_drift(double *x, const double *v, int64_t N, const StepCoef
 {
     hipLaunchKernelGGL(he_drift_kernel, dim3(blocks_for(3 * N, 256)), dim3(256), 0, stream, x, v,
                        3 * N, coef, idx, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_slots(int32_t *slot, int64_t N, const int64_t *idx, int32_t T,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(track_slots_fill_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                       stream, slot, N);
+    hipLaunchKernelGGL(track_slots_set_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0,
+                       stream, slot, idx, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_gather(const double *x, const double *v, int64_t N, const int64_t *idx,
+                               int32_t T, double *row, hipStream_t stream)
+{
+    hipLaunchKernelGGL(track_gather_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0,
+                       stream, x, v, N, idx, T, row);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1208_3444_amd import colatus
@@ -61,7 +62,7 @@ def test_strerror_and_version():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.colatus_strerror(code)
     assert L.colatus_strerror(-99) == b"unknown error code"
-    assert L.colatus_version() == 10100
+    assert L.colatus_version() == 10200
 
 
 def test_forces_rejects_bad_arguments():
@@ -117,7 +118,7 @@ def _run(**kw):
     a.update(kw)
     return L.colatus_run(a["x"], a["v"], a["m"], a["N"], a["eps"], a["G"], *a["cos"],
                          a["a0"], a["a1"], a["n"], a["first"], a["last"], a["prec"], None, None,
-                         a.get("att"), None)
+                         a.get("att"), a.get("trk"), None)
 
 
 def test_run_rejects_bad_arguments():
@@ -134,6 +135,43 @@ def test_run_rejects_bad_arguments():
     assert _run(prec=7) == EINVAL
     pa, keep = colatus._attractor((0.5, (0.0, float("nan"), 0.0)))
     assert _run(att=pa) == EINVAL
+
+
+def _tracks(idx, n=None, out=FAKE):
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    t = colatus._Tracks(len(idx) if n is None else n,
+                        idx.ctypes.data if len(idx) else None, out)
+    return ctypes.byref(t), (t, idx)
+
+
+def test_run_rejects_bad_tracks():
+    L = colatus.lib()
+    bad = [
+        _tracks([], n=0),                 # no tracers
+        _tracks([1, 2], n=70000),         # above the limit
+        _tracks([8]),                     # out of range (N = 8)
+        _tracks([-1, 2]),                 # negative
+        _tracks([2, 5, 2]),               # repeated
+        _tracks([1, 2], out=None),        # no output
+    ]
+    for pt, keep in bad:
+        assert _run(trk=pt) == EINVAL
+        args = dict(x=FAKE, v=FAKE, m=FAKE)
+        rc = L.colatus_run_he(args["x"], args["v"], args["m"], 8, 0.01, 1.0, *LCDM, 0.1, 1.0,
+                              10, 0, 10, 1, None, None, None, pt, None)
+        assert rc == EINVAL
+    t = colatus._Tracks(2, None, FAKE)  # NULL index list
+    assert _run(trk=ctypes.byref(t)) == EINVAL
+
+
+def test_spectrum_rejects_bad_arguments():
+    L = colatus.lib()
+    assert L.colatus_velocity_spectrum(FAKE, 0, 4, 0, FAKE, None) == EINVAL
+    assert L.colatus_velocity_spectrum(FAKE, (1 << 17) + 1, 4, 0, FAKE, None) == EINVAL
+    assert L.colatus_velocity_spectrum(FAKE, 100, 0, 0, FAKE, None) == EINVAL
+    assert L.colatus_velocity_spectrum(FAKE, 100, 65537, 0, FAKE, None) == EINVAL
+    assert L.colatus_velocity_spectrum(None, 100, 4, 0, FAKE, None) == EINVAL
+    assert L.colatus_velocity_spectrum(FAKE, 100, 4, 0, None, None) == EINVAL
 
 
 def test_run_rejects_unphysical_friedmann_range():

@@ -1,0 +1,138 @@
+"""GPU parity of tracer tracks (colatus_tracks through colatus_run and
+colatus_run_he) and of the velocity power spectrum
+(colatus_velocity_spectrum) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_3444_amd import colatus, inputs
+from conftest import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _w():
+    w = inputs.eds_lattice(8, n_steps=12)
+    return w, w.velocities(oracle.hubble(w.a_begin, *w.cosmo.values()))
+
+
+@pytest.mark.parametrize("scheme", ["kdk", "he"])
+@pytest.mark.parametrize("graph", [1, 0])
+def test_fp64_tracks_match_oracle(dev, scheme, graph):
+    w, v0 = _w()
+    tr = np.array([0, 511, 77, 300, 5])
+    att = (0.3, (1.5, 0.4, 0.55))
+    fn = oracle.run if scheme == "kdk" else oracle.run_he
+    _, _, dr, tref = fn(w.x, v0, w.m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, 12, diag=True,
+                        attractor=att, tracers=tr)
+    x, v = to_dev(w.x, dev), to_dev(v0, dev)
+    colatus.set_option(colatus.OPT_GRAPH, graph)
+    try:
+        d, track = colatus.run(x, v, to_dev(w.m, dev), w.eps, w.G, w.cosmo, w.a_begin, w.a_end,
+                               12, precision="fp64", diag=True, attractor=att, scheme=scheme,
+                               tracers=tr)
+    finally:
+        colatus.set_option(colatus.OPT_GRAPH, 1)
+    t = track.cpu().numpy()
+    assert t.shape == (13, 2, 3, 5)
+    assert np.max(np.abs(t[:, 0] - tref[:, 0])) <= 1e-12
+    assert np.max(np.abs(t[:, 1] - tref[:, 1])) <= 1e-11 * np.abs(tref[:, 1]).max()
+    # row 0 is the start state as given; the last row is the returned state
+    assert np.array_equal(t[0, 0], w.x[:, tr]) and np.array_equal(t[0, 1], v0[:, tr])
+    assert np.array_equal(t[-1, 0], x.cpu().numpy()[:, tr])
+    assert np.array_equal(t[-1, 1], v.cpu().numpy()[:, tr])
+    assert np.allclose(d["K"], dr["K"], rtol=1e-11)
+
+
+def test_every_particle_traced_gives_K(dev):
+    w, v0 = _w()
+    x, v = to_dev(w.x, dev), to_dev(v0, dev)
+    d, track = colatus.run(x, v, to_dev(w.m, dev), w.eps, w.G, w.cosmo, w.a_begin, w.a_end, 12,
+                           precision="mixed_twosum", diag=True, tracers=np.arange(w.N))
+    t = track.cpu().numpy()
+    K = 0.5 * np.einsum("k,rck->r", w.m, t[:, 1] ** 2) * d["a"] ** 2
+    assert np.allclose(K, d["K"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("scheme", ["kdk", "he"])
+def test_batch_tracks(dev, scheme):
+    e = inputs.ragged_ensemble(5, 64, 600)
+    v0 = e.velocities(oracle.hubble(e.a_begin, *e.cosmo.values()))
+    n = 9
+    # one tracer in each of boxes 0, 2, 4 (first, middle and last particle)
+    tr = np.array([e.box_offsets[0], (e.box_offsets[2] + e.box_offsets[3]) // 2,
+                   e.box_offsets[5] - 1])
+    x, v = to_dev(e.x, dev), to_dev(v0, dev)
+    _, track = colatus.run(x, v, to_dev(e.m, dev), 0.0, e.G, e.cosmo, e.a_begin, e.a_end, n,
+                           precision="fp64", batch=(e.box_offsets, e.box_eps), scheme=scheme,
+                           tracers=tr)
+    t = track.cpu().numpy()
+    fn = oracle.run if scheme == "kdk" else oracle.run_he
+    for col, b in enumerate((0, 2, 4)):
+        sl = slice(e.box_offsets[b], e.box_offsets[b + 1])
+        _, _, tref = fn(e.x[:, sl], v0[:, sl], e.m[sl], e.box_eps[b], e.G, e.cosmo, e.a_begin,
+                        e.a_end, n, tracers=[tr[col] - e.box_offsets[b]])
+        assert np.max(np.abs(t[:, 0, :, col] - tref[:, 0, :, 0])) <= 1e-12
+        assert np.max(np.abs(t[:, 1, :, col] - tref[:, 1, :, 0])) <= \
+            1e-11 * np.abs(tref[:, 1]).max()
+
+
+def test_mixed_tracks_resume_and_rejects(dev):
+    w = inputs.lcdm_grf(16, seed=9)
+    v0 = w.velocities(oracle.hubble(w.a_begin, *w.cosmo.values()))
+    tr = np.array([1, 2000, 4095])
+    x, v, m = to_dev(w.x, dev), to_dev(v0, dev), to_dev(w.m, dev)
+    args = (w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps)
+    _, ta = colatus.run(x, v, m, *args, last_step=20, tracers=tr)
+    _, tb = colatus.run(x, v, m, *args, first_step=20, last_step=30, tracers=tr)
+    ta, tb = ta.cpu().numpy(), tb.cpu().numpy()
+    assert ta.shape == (21, 2, 3, 3) and tb.shape == (11, 2, 3, 3)
+    assert np.array_equal(ta[-1], tb[0])  # the seam row: returned state, then start state
+    assert np.array_equal(tb[-1, 0], x.cpu().numpy()[:, tr])
+    x3, _, tref = oracle.run(w.x, v0, w.m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
+                             last_step=3, tracers=tr)
+    assert np.max(np.abs(ta[:4, 0] - tref[:, 0])) <= 1e-8
+    for bad in ([1, 1], [4096], [-2]):
+        with pytest.raises(colatus.ColatusError):
+            colatus.run(x, v, m, *args, last_step=2, tracers=bad)
+
+
+def _random_track(M, T, seed):
+    rng = np.random.default_rng(seed)
+    tr = np.zeros((M, 2, 3, T))
+    tr[:, 0] = rng.standard_normal((M, 3, T))
+    n = np.arange(M)[:, None, None]
+    # a decaying drift, a tone and noise: the shape of a tracer's velocity
+    tr[:, 1] = (2.0 * np.exp(-n / max(M, 1)) + 0.5 * np.cos(0.7 * n)
+                + 0.3 * rng.standard_normal((M, 3, T)))
+    return tr
+
+
+@pytest.mark.parametrize("M,T", [(1, 3), (2, 1), (7, 5), (1000, 4), (1025, 3), (3001, 2),
+                                 (256, 300)])
+@pytest.mark.parametrize("remove_mean", [False, True])
+def test_spectrum_matches_oracle(dev, M, T, remove_mean):
+    tr = _random_track(M, T, M + T)
+    ref = oracle.velocity_spectrum(tr, remove_mean=remove_mean)
+    got = colatus.velocity_spectrum(to_dev(tr, dev), remove_mean=remove_mean).cpu().numpy()
+    assert got.shape == ref.shape == (T, M // 2 + 1)
+    w = tr[:, 1] - tr[:, 1].mean(axis=0) if remove_mean else tr[:, 1]
+    energy = (w ** 2).sum(axis=(0, 1))
+    err = np.abs(got - ref).max(axis=1)
+    print(f"M={M} T={T} remove_mean={remove_mean}: max |dE| {err.max():.2e}, "
+          f"energy {energy.min():.2e}..{energy.max():.2e}")
+    # a single row less its mean is zero: zero energy, and exact zeros
+    assert np.all(err <= 1e-13 * energy)
+
+
+def test_spectrum_of_a_run(dev):
+    w, v0 = _w()
+    tr = np.array([3, 100, 400])
+    _, _, tref = oracle.run(w.x, v0, w.m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, 12,
+                            tracers=tr)
+    x, v = to_dev(w.x, dev), to_dev(v0, dev)
+    _, track = colatus.run(x, v, to_dev(w.m, dev), w.eps, w.G, w.cosmo, w.a_begin, w.a_end, 12,
+                           precision="fp64", tracers=tr)
+    got = colatus.velocity_spectrum(track, remove_mean=True).cpu().numpy()
+    ref = oracle.velocity_spectrum(tref, remove_mean=True)
+    assert np.allclose(got, ref, rtol=1e-9, atol=1e-12 * ref.max())
