@@ -71,17 +71,19 @@ def _load():
     lib.oracle_attractor_vjp.argtypes = [_p, _i64, _d, _d, _p, _p, _p]
     lib.oracle_run.restype = ctypes.c_int
     lib.oracle_run.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i64, _i64, _p, _d, _p, _p, _i64, _p]
+        [_d, _d, _i64, _i64, _i64, _p, _d, _p, _d, _p, _p, _i64, _p]
     lib.oracle_run_he.restype = ctypes.c_int
     lib.oracle_run_he.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i64, _i64, _p, _d, _p, _p, _i64, _p]
+        [_d, _d, _i64, _i64, _i64, _p, _d, _p, _d, _p, _p, _i64, _p]
+    lib.oracle_background_add.restype = None
+    lib.oracle_background_add.argtypes = [_p, _i64, _d, _p, _p, _p]
     lib.oracle_velocity_spectrum.restype = None
     lib.oracle_velocity_spectrum.argtypes = [_p, _i64, _i64, ctypes.c_int, _p]
     lib.oracle_he_coefficients.restype = None
     lib.oracle_he_coefficients.argtypes = [_d] * 7 + [_i64, _i64, _p]
     lib.oracle_adjoint.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [_p, _p, _p, _i64, _d, _d] + [_d] * 5 + \
-        [_d, _d, _i64, _i32, _p, _p, _p, _p, _p, _p, _d, _p, _p]
+        [_d, _d, _i64, _i32, _p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p]
     _lib = lib
     return lib
 
@@ -138,6 +140,32 @@ def attractor_field(x, eps, attractor):
     return f, phi
 
 
+def _bg(background):
+    """(b, centre array or None) from None or (b, (cx, cy, cz))."""
+    if background is None:
+        return 0.0, None
+    b, c = background
+    return float(b), np.ascontiguousarray(c, dtype=np.float64).reshape(3)
+
+
+def background_coefficient(cosmo):
+    """b = Om_M H0^2 / 2, the Eq. (6) background coefficient consistent with
+    Eq. (2): (4 pi G / 3) times the comoving mean matter density."""
+    return 0.5 * cosmo["Om_M"] * cosmo["H0"] ** 2
+
+
+def background_field(x, background):
+    """(f, phi_ext): the Eq. (6) background term b (x - c) added to the
+    comoving sum g and its potential -b |x - c|^2 / 2."""
+    x = _c(x)
+    N = x.shape[1]
+    b, c = _bg(background)
+    f = np.zeros((3, N))
+    phi = np.zeros(N)
+    _load().oracle_background_add(_ptr(x), N, b, _ptr(c), _ptr(f), _ptr(phi))
+    return f, phi
+
+
 def attractor_vjp(x, lam, eps, attractor):
     x = _c(x)
     lam = _c(lam)
@@ -148,7 +176,7 @@ def attractor_vjp(x, lam, eps, attractor):
     return out
 
 
-def forces(x, m, eps, G=1.0, a=1.0, attractor=None):
+def forces(x, m, eps, G=1.0, a=1.0, attractor=None, background=None):
     x = _c(x)
     m = _c(m)
     N = m.shape[0]
@@ -157,6 +185,8 @@ def forces(x, m, eps, G=1.0, a=1.0, attractor=None):
     _load().oracle_forces(_ptr(x), _ptr(m), N, eps, G, a, _ptr(acc))
     if attractor is not None:
         acc += attractor_field(x, eps, attractor)[0] / a ** 3
+    if background is not None:
+        acc += background_field(x, background)[0] / a ** 3
     return acc
 
 
@@ -171,7 +201,7 @@ def forces_targets(x, m, targets, eps, G=1.0, a=1.0):
     return acc
 
 
-def potential(x, m, eps, G=1.0, attractor=None):
+def potential(x, m, eps, G=1.0, attractor=None, background=None):
     x = _c(x)
     m = _c(m)
     N = m.shape[0]
@@ -179,10 +209,12 @@ def potential(x, m, eps, G=1.0, attractor=None):
     _load().oracle_potential(_ptr(x), _ptr(m), N, eps, G, _ptr(phi))
     if attractor is not None:
         phi += attractor_field(x, eps, attractor)[1]
+    if background is not None:
+        phi += background_field(x, background)[1]
     return phi
 
 
-def force_vjp(x, m, lam, eps, G=1.0, attractor=None):
+def force_vjp(x, m, lam, eps, G=1.0, attractor=None, background=None):
     x = _c(x)
     m = _c(m)
     lam = _c(lam)
@@ -191,11 +223,13 @@ def force_vjp(x, m, lam, eps, G=1.0, attractor=None):
     _load().oracle_force_vjp(_ptr(x), _ptr(m), N, eps, G, _ptr(lam), _ptr(out))
     if attractor is not None:
         out += attractor_vjp(x, lam, eps, attractor)
+    if background is not None:
+        out += _bg(background)[0] * lam
     return out
 
 
 def _run(fn, name, x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step, last_step,
-         diag, attractor, tracers):
+         diag, attractor, tracers, background):
     if last_step is None:
         last_step = n_steps
     x = _c(x).copy()
@@ -203,6 +237,7 @@ def _run(fn, name, x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step, 
     m = _c(m)
     N = m.shape[0]
     S, xp = _att(attractor)
+    bb, bc = _bg(background)
     nr = last_step - first_step + 1
     rows = np.zeros((nr, len(DIAG_FIELDS))) if diag else None
     trk = track = None
@@ -213,7 +248,7 @@ def _run(fn, name, x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step, 
         track = np.zeros((nr, 2, 3, trk.size))
     rc = fn(_ptr(x), _ptr(v), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
             cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
-            first_step, last_step, _ptr(rows), S, _ptr(xp),
+            first_step, last_step, _ptr(rows), S, _ptr(xp), bb, _ptr(bc),
             trk.ctypes.data_as(_p) if trk is not None else None,
             0 if trk is None else trk.size, _ptr(track))
     if rc != 0:
@@ -227,24 +262,25 @@ def _run(fn, name, x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step, 
 
 
 def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
-        last_step=None, diag=False, attractor=None, tracers=None):
+        last_step=None, diag=False, attractor=None, tracers=None, background=None):
     """Kick-drift-kick run over steps first_step..last_step-1 of the grid.
 
     Returns (x, v) at a_{last_step}, then the diagnostics rows (dict of
     arrays) if diag is true, then the tracer track (rows, 2, 3, T) -- x and
     v = dx/dt of particles ``tracers`` at every grid point -- if tracers is
-    given.  attractor: None or (S, (x, y, z)), the Eq. (10) term.
+    given.  attractor: None or (S, (x, y, z)), the Eq. (10) term; background:
+    None or (b, (cx, cy, cz)), the Eq. (6) term.
     """
     return _run(_load().oracle_run, "oracle_run", x, v, m, eps, G, cosmo, a_begin, a_end,
-                n_steps, first_step, last_step, diag, attractor, tracers)
+                n_steps, first_step, last_step, diag, attractor, tracers, background)
 
 
 def run_he(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
-           last_step=None, diag=False, attractor=None, tracers=None):
+           last_step=None, diag=False, attractor=None, tracers=None, background=None):
     """Steps of the paper's difference equations (Eqs. (3)-(5)) on the same
     grid as ``run``; returns as ``run``."""
     return _run(_load().oracle_run_he, "oracle_run_he", x, v, m, eps, G, cosmo, a_begin,
-                a_end, n_steps, first_step, last_step, diag, attractor, tracers)
+                a_end, n_steps, first_step, last_step, diag, attractor, tracers, background)
 
 
 def velocity_spectrum(track, remove_mean=False):
@@ -269,7 +305,7 @@ def he_coefficients(cosmo, a_begin, a_end, n_steps, n):
 
 
 def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
-            attractor=None):
+            attractor=None, background=None):
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x0, v0).
 
     lam_xN, lam_vN: (C, 3, N) or (3, N).  Returns (grad_x0, grad_v0, xN, vN)
@@ -291,12 +327,13 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
     xN = np.empty((3, N))
     vN = np.empty((3, N))
     S, xp = _att(attractor)
+    bb, bc = _bg(background)
     ga = np.zeros((C, 4)) if attractor is not None else None
     rc = _load().oracle_adjoint(
         _ptr(x0), _ptr(v0), _ptr(m), N, eps, G, cosmo["H0"], cosmo["Om_R"],
         cosmo["Om_M"], cosmo["Om_K"], cosmo["Om_L"], a_begin, a_end, n_steps,
         C, _ptr(lx), _ptr(lv), _ptr(gx), _ptr(gv), _ptr(xN), _ptr(vN), S, _ptr(xp),
-        _ptr(ga))
+        bb, _ptr(bc), _ptr(ga))
     if rc != 0:
         raise ValueError("oracle_adjoint: invalid arguments")
     if squeeze:

@@ -23,8 +23,10 @@
  *    a^-3 factor.  This is Eq. (1) rewritten for p; the printed Eq. (8)
  *    (p^2 in the drift, phi' instead of its gradient in the kick) is read as
  *    a typesetting slip.
- *  - The background term (a^2 a_ddot |x|^2 / 2) of Eq. (6) is not added:
- *    the force is Eq. (1) exactly, in an open (non-periodic) box.
+ *  - The background term (a^2 a_ddot |x|^2 / 2) of Eq. (6) is off by
+ *    default: the force is Eq. (1) exactly, in an open (non-periodic) box.
+ *    On request it is the removal of the mean matter density's pull about
+ *    a centre, b (x - c) with b = Om_M H0^2 / 2 (see oracle_background_add).
  *  - The step is kick(half) - drift - kick(half) built from the drift and
  *    kick operators of Eq. (9); steps are uniform in ln a and the half-step
  *    point is the midpoint in ln a.
@@ -396,6 +398,47 @@ void oracle_attractor_vjp(const double *x, int64_t N, double eps, double S,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Background term of Eq. (6).  The comoving potential there is the         */
+/* particles' own plus a term a^2 (d^2 a/dt^2) |x|^2 / 2 (the |x|^2 factor  */
+/* is lost in the printed equation).  It is what makes the comoving         */
+/* equations exact Newtonian dynamics about a centre c; once the uniform    */
+/* Lambda and radiation backgrounds, which the particle sum leaves out, act */
+/* on the particles too, what remains is the removal of the mean matter     */
+/* density's pull: a comoving field added to g of                           */
+/*   f_k = b (x_k - c),   b = Om_M H0^2 / 2 = (4 pi G / 3) rho_comoving,     */
+/* with potential -b |x_k - c|^2 / 2 (external: counted once in the energy) */
+/* and derivative df_k/dx_k = b I.  It scales with a like the pair sum, so  */
+/* it joins g before the a^-3 (or kick-integral) factor.  bg_c == NULL:     */
+/* none.  Adds f into g and (phi != NULL) the potential into phi.           */
+/* ------------------------------------------------------------------------ */
+void oracle_background_add(const double *x, int64_t N, double b, const double *bg_c,
+                           double *g, double *phi)
+{
+    if (!bg_c)
+        return;
+    for (int64_t k = 0; k < N; ++k) {
+        double d[3];
+        for (int c = 0; c < 3; ++c)
+            d[c] = x[(size_t)c * N + k] - bg_c[c];
+        if (g)
+            for (int c = 0; c < 3; ++c)
+                g[(size_t)c * N + k] += b * d[c];
+        if (phi)
+            phi[k] += -0.5 * b * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+}
+
+/* out += (df/dx)^T lam = b lam (bg_c == NULL: nothing).                    */
+static void background_vjp_add(int64_t N, double b, const double *bg_c, const double *lam,
+                               double *out)
+{
+    if (!bg_c)
+        return;
+    for (size_t i = 0; i < 3 * (size_t)N; ++i)
+        out[i] += b * lam[i];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time grid and step coefficients.                                         */
 /* ------------------------------------------------------------------------ */
 
@@ -465,13 +508,14 @@ void oracle_step_coefficients(double H0, double OmR, double OmM, double OmK,
 
 static void energies(const double *x, const double *p, const double *m,
                      int64_t N, double eps, double G, double a, double S,
-                     const double *att_x, double *K, double *U, double *P,
-                     double *L)
+                     const double *att_x, double bg_b, const double *bg_c, double *K,
+                     double *U, double *P, double *L)
 {
     double *phi = (double *)malloc(sizeof(double) * (size_t)N);
     double *phe = (double *)calloc((size_t)N, sizeof(double));
     oracle_potential(x, m, N, eps, G, phi);
     oracle_attractor_add(x, N, eps, S, att_x, NULL, phe);
+    oracle_background_add(x, N, bg_b, bg_c, NULL, phe);
     ksum kk = {0, 0}, uu = {0, 0}, ue = {0, 0};
     ksum pp[3] = {{0, 0}, {0, 0}, {0, 0}}, ll[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int64_t k = 0; k < N; ++k) {
@@ -529,7 +573,8 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
                double G, double H0, double OmR, double OmM, double OmK,
                double OmL, double a_begin, double a_end, int64_t n_steps,
                int64_t first_step, int64_t last_step, double *diag, double att_S,
-               const double *att_x, const int64_t *trk, int64_t n_trk, double *track)
+               const double *att_x, double bg_b, const double *bg_c, const int64_t *trk,
+               int64_t n_trk, double *track)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
@@ -543,6 +588,7 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
         p[i] = a * a * v[i];
     oracle_forces(x, m, N, eps, G, 1.0, g);
     oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
+    oracle_background_add(x, N, bg_b, bg_c, g, NULL);
     const size_t trow = 6 * (size_t)n_trk;
     if (track)
         record_track(x, v, a, 0, N, trk, n_trk, track);
@@ -550,7 +596,7 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
     double t = 0.0, E0 = 0.0, li_int = 0.0, prev_src = 0.0;
     if (diag) {
         double K, U, P[3], L[3];
-        energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
+        energies(x, p, m, N, eps, G, a, att_S, att_x, bg_b, bg_c, &K, &U, P, L);
         E0 = K + U;
         prev_src = 2.0 * K + U;
         double *row = diag;
@@ -565,6 +611,7 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
             x[i] += s.d * p[i];
         oracle_forces(x, m, N, eps, G, 1.0, g);
         oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
+        oracle_background_add(x, N, bg_b, bg_c, g, NULL);
         for (size_t i = 0; i < n3; ++i)
             p[i] += s.k2 * g[i];
         double a_prev = a;
@@ -574,7 +621,7 @@ int oracle_run(double *x, double *v, const double *m, int64_t N, double eps,
             record_track(x, p, a, 1, N, trk, n_trk, track + (size_t)(n + 1 - first_step) * trow);
         if (diag) {
             double K, U, P[3], L[3];
-            energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
+            energies(x, p, m, N, eps, G, a, att_S, att_x, bg_b, bg_c, &K, &U, P, L);
             double src = 2.0 * K + U;
             double dlna = (c.H0 == 0.0) ? 0.0 : log(a) - log(a_prev);
             li_int += 0.5 * (prev_src + src) * dlna;
@@ -658,7 +705,8 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                   double G, double H0, double OmR, double OmM, double OmK,
                   double OmL, double a_begin, double a_end, int64_t n_steps,
                   int64_t first_step, int64_t last_step, double *diag, double att_S,
-                  const double *att_x, const int64_t *trk, int64_t n_trk, double *track)
+                  const double *att_x, double bg_b, const double *bg_c, const int64_t *trk,
+                  int64_t n_trk, double *track)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || first_step < 0 || last_step <= first_step ||
@@ -676,7 +724,7 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
         double K, U, P[3], L[3];
         for (size_t i = 0; i < n3; ++i)
             p[i] = a * a * v[i];
-        energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
+        energies(x, p, m, N, eps, G, a, att_S, att_x, bg_b, bg_c, &K, &U, P, L);
         E0 = K + U;
         prev_src = 2.0 * K + U;
         double *row = diag;
@@ -690,6 +738,7 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
             x[i] += 0.5 * tau * v[i];
         oracle_forces(x, m, N, eps, G, 1.0, g);
         oracle_attractor_add(x, N, eps, att_S, att_x, g, NULL);
+        oracle_background_add(x, N, bg_b, bg_c, g, NULL);
         double drag = (1.0 - Ht) / (1.0 + Ht);
         double kick = tau / (h.ah * h.ah * h.ah * (1.0 + Ht));
         for (size_t i = 0; i < n3; ++i)
@@ -705,7 +754,7 @@ int oracle_run_he(double *x, double *v, const double *m, int64_t N, double eps,
             double K, U, P[3], L[3];
             for (size_t i = 0; i < n3; ++i)
                 p[i] = a * a * v[i];
-            energies(x, p, m, N, eps, G, a, att_S, att_x, &K, &U, P, L);
+            energies(x, p, m, N, eps, G, a, att_S, att_x, bg_b, bg_c, &K, &U, P, L);
             double src = 2.0 * K + U;
             double dlna = (c.H0 == 0.0) ? 0.0 : log(a) - log(a_prev);
             li_int += 0.5 * (prev_src + src) * dlna;
@@ -784,7 +833,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
                    double a_end, int64_t n_steps, int32_t n_cot,
                    const double *lam_xN, const double *lam_vN, double *grad_x0,
                    double *grad_v0, double *xN, double *vN, double att_S,
-                   const double *att_x, double *grad_att)
+                   const double *att_x, double bg_b, const double *bg_c, double *grad_att)
 {
     cosmo c = {H0, OmR, OmM, OmK, OmL};
     if (N < 1 || n_steps < 1 || n_cot < 1)
@@ -802,6 +851,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
         p[i] = a0 * a0 * v0[i];
     oracle_forces(xs, m, N, eps, G, 1.0, g);
     oracle_attractor_add(xs, N, eps, att_S, att_x, g, NULL);
+    oracle_background_add(xs, N, bg_b, bg_c, g, NULL);
     for (int64_t n = 0; n < n_steps; ++n) {
         coef[n] = step_coefficients(&c, a_begin, a_end, n_steps, n);
         double *xn = xs + (size_t)n * n3, *xn1 = xs + (size_t)(n + 1) * n3;
@@ -811,6 +861,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
             xn1[i] = xn[i] + coef[n].d * p[i];
         oracle_forces(xn1, m, N, eps, G, 1.0, g);
         oracle_attractor_add(xn1, N, eps, att_S, att_x, g, NULL);
+        oracle_background_add(xn1, N, bg_b, bg_c, g, NULL);
         for (size_t i = 0; i < n3; ++i)
             p[i] += coef[n].k2 * g[i];
     }
@@ -838,6 +889,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
             double *xn = xs + (size_t)n * n3, *xn1 = xs + (size_t)(n + 1) * n3;
             oracle_force_vjp(xn1, m, N, eps, G, lp, w);
             attractor_vjp_add(xn1, N, eps, att_S, att_x, lp, w);
+            background_vjp_add(N, bg_b, bg_c, lp, w);
             attractor_grad_add(xn1, N, eps, att_S, att_x, lp, coef[n].k2, ga);
             for (size_t i = 0; i < n3; ++i)
                 lx[i] += coef[n].k2 * w[i];
@@ -845,6 +897,7 @@ int oracle_adjoint(const double *x0, const double *v0, const double *m,
                 lp[i] += coef[n].d * lx[i];
             oracle_force_vjp(xn, m, N, eps, G, lp, w);
             attractor_vjp_add(xn, N, eps, att_S, att_x, lp, w);
+            background_vjp_add(N, bg_b, bg_c, lp, w);
             attractor_grad_add(xn, N, eps, att_S, att_x, lp, coef[n].k1, ga);
             for (size_t i = 0; i < n3; ++i)
                 lx[i] += coef[n].k1 * w[i];
