@@ -111,6 +111,26 @@ typedef struct {
     double x[3];     /* x_psi, comoving */
 } colatus_attractor;
 
+/* ---- background term (Eq. (6)) ------------------------------------------ */
+/* The background term of the comoving potential of Eq. (6): with it the
+ * pull of the mean matter density is removed, so that an unperturbed
+ * distribution at that density follows the expansion a(t) of Eq. (2)
+ * instead of collapsing under its own mean density (Eq. (1) alone, in an
+ * open box).  It adds to the comoving sum g of particle k
+ *     b (x_k - c)
+ * and -b |x_k - c|^2 / 2 to its potential (an external field: counted once
+ * in the diagnostics).  b = Om_M H0^2 / 2 is the value consistent with
+ * Eq. (2) (Lambda and radiation act on every particle alike, so only the
+ * matter term remains once they are included); c is the centre of the
+ * region the particles sample (the box centre).  Scales with a like the
+ * pair sum.  HOST pointer, read during the call; NULL: no background term.
+ * coefficient and centre must be finite.  The same b and c for every box
+ * of a batch.                                                              */
+typedef struct {
+    double coefficient; /* b */
+    double centre[3];   /* c, comoving */
+} colatus_background;
+
 /* ---- tracer tracks ----------------------------------------------------- */
 /* The state of chosen particles at every grid point a run visits, so that
  * a single particle's velocity can be followed step by step (Section I and
@@ -161,11 +181,12 @@ typedef struct {
  *   eps >= 0 (eps == 0 with two coincident particles gives Inf/NaN), G finite,
  *   a > 0.  batch: see colatus_batch, or NULL.
  *   attractor: see colatus_attractor, or NULL; its field (times a^-3) and
- *   potential are added to acc and phi, in FP64 for every precision.       */
+ *   potential are added to acc and phi, in FP64 for every precision.
+ *   background: see colatus_background, or NULL; added the same way.       */
 int colatus_forces(const double *x, const double *m, int64_t N, double eps,
                    double G, double a, int precision, double *acc, double *phi,
                    const colatus_batch *batch, const colatus_attractor *attractor,
-                   void *stream);
+                   const colatus_background *background, void *stream);
 
 /* One kick-drift-kick step (Eq. (9) operators, Section II) from a to a_next,
  * in place on x and v (comoving position and dx/dt):
@@ -176,12 +197,12 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps,
  * Static limit H0 == 0: a stays fixed and a_next is read as the time step
  * dt (K = dt/(2a) each, D = dt/a^2).  Costs two force evaluations; use
  * colatus_run for many steps (one evaluation per step).  With an attractor
- * (or NULL) g includes the Eq. (10) term.                                   */
+ * or a background term (or NULL) g includes the Eq. (10) / Eq. (6) terms.  */
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
                  double G, double H0, double Om_R, double Om_M, double Om_K,
                  double Om_L, double a, double a_next, int precision,
                  const colatus_batch *batch, const colatus_attractor *attractor,
-                 void *stream);
+                 const colatus_background *background, void *stream);
 
 /* Steps first_step .. last_step-1 of the global grid a_n = a_begin
  * exp(n ln(a_end/a_begin)/n_steps), a_{n_steps} = a_end, in place on x, v.
@@ -196,14 +217,16 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
  * Requires n_steps >= 1, 0 <= first_step < last_step <= n_steps, a_begin > 0,
  * a_end > 0 (or > 0 elapsed time in the static limit), H^2 > 0 on the range
  * (else COLATUS_EFRIEDMANN).  attractor (or NULL): the Eq. (10) term joins g
- * at every kick and its energy joins U.  tracks (or NULL): see
- * colatus_tracks; rows r >= 1 hold v = p / a^2 as the final v does.        */
+ * at every kick and its energy joins U; so does the Eq. (6) background
+ * term (or NULL).  tracks (or NULL): see colatus_tracks; rows r >= 1 hold
+ * v = p / a^2 as the final v does.                                          */
 int colatus_run(double *x, double *v, const double *m, int64_t N, double eps,
                 double G, double H0, double Om_R, double Om_M, double Om_K,
                 double Om_L, double a_begin, double a_end, int64_t n_steps,
                 int64_t first_step, int64_t last_step, int precision,
                 colatus_diag *diag, const colatus_batch *batch,
-                const colatus_attractor *attractor, const colatus_tracks *tracks,
+                const colatus_attractor *attractor,
+                const colatus_background *background, const colatus_tracks *tracks,
                 void *stream);
 
 /* The paper's own difference equations, Eqs. (3)-(5) (after Hockney and
@@ -224,7 +247,8 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                    double Om_L, double a_begin, double a_end, int64_t n_steps,
                    int64_t first_step, int64_t last_step, int precision,
                    colatus_diag *diag, const colatus_batch *batch,
-                   const colatus_attractor *attractor, const colatus_tracks *tracks,
+                   const colatus_attractor *attractor,
+                   const colatus_background *background, const colatus_tracks *tracks,
                    void *stream);
 
 /* Velocity power spectrum of each tracer of a track (the power spectrum of
@@ -262,7 +286,8 @@ int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_trace
  * transpose Jacobian -S M(d) (d = x_psi - x_k) joins the pair sum's, and
  * grad_attractor ([n_cot][4] device, or NULL; requires an attractor)
  * receives d<lam, state_N>/dS and d<lam, state_N>/dx_psi per cotangent,
- * accumulated in a fixed order (deterministic).                            */
+ * accumulated in a fixed order (deterministic).  With a background term
+ * (Eq. (6), or NULL) its transpose Jacobian b I joins as well.              */
 int colatus_adjoint(const double *x0, const double *v0, const double *m,
                     int64_t N, double eps, double G, double H0, double Om_R,
                     double Om_M, double Om_K, double Om_L, double a_begin,
@@ -271,16 +296,17 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m,
                     double *grad_x0, double *grad_v0, double *xN, double *vN,
                     double *grad_attractor, int precision,
                     const colatus_batch *batch, const colatus_attractor *attractor,
-                    void *stream);
+                    const colatus_background *background, void *stream);
 
 /* Transpose-Jacobian product of the comoving sum g (Eq. (1) without a^-3,
- * plus the Eq. (10) attractor's field when attractor is non-NULL):
+ * plus the Eq. (10) attractor's field and the Eq. (6) background term when
+ * given):
  * out[c] = J(x)^T lam[c] for n_cot cotangents, arrays [n_cot][3][N]
  * device.  The building block of colatus_adjoint.                         */
 int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps,
                       double G, int32_t n_cot, const double *lam, double *out,
                       int precision, const colatus_attractor *attractor,
-                      void *stream);
+                      const colatus_background *background, void *stream);
 
 /* Hubble rate of Eq. (2) at scale factor a, on the host.  Returns
  * COLATUS_EFRIEDMANN if H^2 < 0 there.                                    */

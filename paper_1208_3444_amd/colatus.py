@@ -40,17 +40,17 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "EFRIEDMANN", -3: "ENODEV", -4: "ENOMEM", -
 _d, _i64, _i32, _i, _p = (ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
                           ctypes.c_void_p)
 SIGNATURES = {
-    "colatus_forces": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p, _p]),
+    "colatus_forces": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p, _p, _p]),
     "colatus_step": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i, _p, _p,
-                          _p]),
+                          _p, _p]),
     "colatus_run": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                         _i64, _i, _p, _p, _p, _p, _p]),
+                         _i64, _i, _p, _p, _p, _p, _p, _p]),
     "colatus_run_he": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                            _i64, _i, _p, _p, _p, _p, _p]),
+                            _i64, _i, _p, _p, _p, _p, _p, _p]),
     "colatus_velocity_spectrum": (_i, [_p, _i64, _i32, _i, _p, _p]),
     "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
-                             _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p]),
-    "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p]),
+                             _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p, _p]),
+    "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p, _p]),
     "colatus_hubble": (_i, [_d, _d, _d, _d, _d, _d, ctypes.POINTER(_d)]),
     "colatus_strerror": (ctypes.c_char_p, [_i]),
     "colatus_set_option": (_i, [_i, _i64]),
@@ -88,6 +88,28 @@ def _attractor(att):
         raise ValueError("attractor position must have 3 components")
     a = _Attractor(float(S), (_d * 3)(*xp))
     return ctypes.byref(a), a
+
+
+class _Background(ctypes.Structure):
+    _fields_ = [("coefficient", _d), ("centre", _d * 3)]
+
+
+def _background(bg):
+    """bg = (b, (cx, cy, cz)) -> pointer to a colatus_background, or None."""
+    if bg is None:
+        return None, None
+    b, c = bg
+    c = [float(v) for v in c]
+    if len(c) != 3:
+        raise ValueError("background centre must have 3 components")
+    o = _Background(float(b), (_d * 3)(*c))
+    return ctypes.byref(o), o
+
+
+def background_coefficient(cosmo):
+    """b = Om_M H0^2 / 2: the Eq. (6) background coefficient consistent with
+    the expansion of Eq. (2) (comoving mean matter density 3 Om_M H0^2 / (8 pi G))."""
+    return 0.5 * float(cosmo["Om_M"]) * float(cosmo["H0"]) ** 2
 
 
 class _Tracks(ctypes.Structure):
@@ -179,11 +201,13 @@ def _batch(batch):
 
 
 def forces(x, m, eps, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False, batch=None,
-           attractor=None):
+           attractor=None, background=None):
     """a^-3 G sum_{j != k} m_j (x_j - x_k) / (|x_j - x_k|^2 + eps^2)^{3/2}  (Eq. (1)).
 
     Returns acc (3, N), and phi (N,) (-G sum m_j / r) if with_phi.
     attractor: None or (S, (x, y, z)), the Eq. (10) deformation term.
+    background: None or (b, (cx, cy, cz)), the Eq. (6) background term
+    b (x - c) (b = background_coefficient(cosmo) for consistency with Eq. (2)).
     """
     N = m.shape[0]
     px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
@@ -191,11 +215,12 @@ def forces(x, m, eps, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False, ba
     phi = torch.empty_like(m) if with_phi else None
     b, keep = _batch(batch)
     pa, keep_a = _attractor(attractor)
+    pb, keep_b = _background(background)
     rc = lib().colatus_forces(px, pm, N, float(eps) if batch is None else 0.0, float(G),
                               float(a), _prec(precision), ctypes.c_void_p(acc.data_ptr()),
                               ctypes.c_void_p(phi.data_ptr()) if with_phi else None,
-                              ctypes.byref(b) if b is not None else None, pa, _stream(x))
-    del keep, keep_a
+                              ctypes.byref(b) if b is not None else None, pa, pb, _stream(x))
+    del keep, keep_a, keep_b
     _check("colatus_forces", rc)
     return (acc, phi) if with_phi else acc
 
@@ -206,16 +231,17 @@ def _cosmo(c):
 
 
 def step(x, v, m, eps, G, cosmo, a, a_next, precision="mixed_twosum", batch=None,
-         attractor=None):
+         attractor=None, background=None):
     """One kick-drift-kick step from a to a_next, in place on x and v."""
     N = m.shape[0]
     px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
     b, keep = _batch(batch)
     pa, keep_a = _attractor(attractor)
+    pb, keep_b = _background(background)
     rc = lib().colatus_step(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
                             *_cosmo(cosmo), float(a), float(a_next), _prec(precision),
-                            ctypes.byref(b) if b is not None else None, pa, _stream(x))
-    del keep, keep_a
+                            ctypes.byref(b) if b is not None else None, pa, pb, _stream(x))
+    del keep, keep_a, keep_b
     _check("colatus_step", rc)
 
 
@@ -235,12 +261,13 @@ def _diag_dict(rows):
 
 def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step=None,
         precision="mixed_twosum", diag=False, batch=None, attractor=None, scheme="kdk",
-        tracers=None):
+        tracers=None, background=None):
     """Kick-drift-kick steps [first_step, last_step) of the global ln-a grid, in place.
 
     Returns the diagnostics (dict of numpy arrays, one entry per grid point;
     with a batch, a list of such dicts, one per box) if diag, else None.
     attractor: None or (S, (x, y, z)), the Eq. (10) deformation term.
+    background: None or (b, (cx, cy, cz)), the Eq. (6) background term.
     scheme: 'kdk' (the Eq. (9) operators, colatus_run) or 'he' (the paper's
     difference equations, Eqs. (3)-(5), colatus_run_he).
     tracers: None or particle indices; then the return value is the pair
@@ -259,13 +286,14 @@ def run(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0, last_step
     if scheme not in ("kdk", "he"):
         raise ValueError("scheme must be 'kdk' (Eq. (9) operators) or 'he' (Eqs. (3)-(5))")
     pt, keep_t, track = _tracks(tracers, nr, x)
+    pb, keep_b = _background(background)
     fn = lib().colatus_run if scheme == "kdk" else lib().colatus_run_he
     rc = fn(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
             *_cosmo(cosmo), float(a_begin), float(a_end), int(n_steps),
             int(first_step), int(last_step), _prec(precision),
             ctypes.cast(rows, ctypes.c_void_p) if diag else None,
-            ctypes.byref(b) if b is not None else None, pa, pt, _stream(x))
-    del keep, keep_a, keep_t
+            ctypes.byref(b) if b is not None else None, pa, pb, pt, _stream(x))
+    del keep, keep_a, keep_t, keep_b
     _check("colatus_run" if scheme == "kdk" else "colatus_run_he", rc)
     d = None
     if diag:
@@ -290,32 +318,35 @@ def velocity_spectrum(track, remove_mean=False):
     return out
 
 
-def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum", attractor=None):
+def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum", attractor=None,
+              background=None):
     """J(x)^T lam for the comoving sum (pair sum, plus the Eq. (10) attractor
-    if given); lam (3, N) or (C, 3, N)."""
+    and the Eq. (6) background term if given); lam (3, N) or (C, 3, N)."""
     N = m.shape[0]
     px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
     C = 1 if lam.dim() == 2 else lam.shape[0]
     pl = _dev(lam, "lam", (3, N) if lam.dim() == 2 else (C, 3, N))
     out = torch.empty_like(lam)
     pa, keep_a = _attractor(attractor)
+    pb, keep_b = _background(background)
     rc = lib().colatus_force_vjp(px, pm, N, float(eps), float(G), C, pl,
-                                 ctypes.c_void_p(out.data_ptr()), _prec(precision), pa,
+                                 ctypes.c_void_p(out.data_ptr()), _prec(precision), pa, pb,
                                  _stream(x))
-    del keep_a
+    del keep_a, keep_b
     _check("colatus_force_vjp", rc)
     return out
 
 
 def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
             checkpoint_every=20, precision="mixed_twosum", return_state=False,
-            attractor=None):
+            attractor=None, background=None):
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x_0, v_0).
 
     lam_xN, lam_vN: (3, N) or (C, 3, N).  Returns (grad_x0, grad_v0) shaped
     like the cotangents, plus (x_N, v_N) if return_state.  With an attractor
     (S, (x, y, z)) (Eq. (10)) the run includes it and the gradient with
-    respect to (S, x_psi) is appended: (4,) or (C, 4).
+    respect to (S, x_psi) is appended: (4,) or (C, 4).  background: the
+    Eq. (6) term (b, (cx, cy, cz)) of the run, or None.
     """
     N = m.shape[0]
     px, pv, pm = _dev(x0, "x0", (3, N)), _dev(v0, "v0", (3, N)), _dev(m, "m", (N,))
@@ -326,6 +357,7 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
     xN = torch.empty_like(x0) if return_state else None
     vN = torch.empty_like(v0) if return_state else None
     pa, keep_a = _attractor(attractor)
+    pb, keep_b = _background(background)
     ga = None
     if attractor is not None:
         ga = torch.empty((4,) if lam_xN.dim() == 2 else (C, 4), dtype=torch.float64,
@@ -337,8 +369,8 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
         ctypes.c_void_p(xN.data_ptr()) if return_state else None,
         ctypes.c_void_p(vN.data_ptr()) if return_state else None,
         ctypes.c_void_p(ga.data_ptr()) if ga is not None else None,
-        _prec(precision), None, pa, _stream(x0))
-    del keep_a
+        _prec(precision), None, pa, pb, _stream(x0))
+    del keep_a, keep_b
     _check("colatus_adjoint", rc)
     out = (gx, gv) + ((xN, vN) if return_state else ())
     if ga is not None:
@@ -350,10 +382,10 @@ class ColatusRun(torch.autograd.Function):
     """(x_0, v_0) -> (x_N, v_N) of a full run, differentiable by the discrete adjoint.
 
     ``ColatusRun.apply(x0, v0, m, params)`` with params a dict holding eps, G,
-    cosmo, a_begin, a_end, n_steps and optionally checkpoint_every, precision
-    and attractor (S, (x, y, z)).  The backward pass calls colatus_adjoint,
-    which re-runs the forward with checkpoints and returns gradients for x0
-    and v0.
+    cosmo, a_begin, a_end, n_steps and optionally checkpoint_every, precision,
+    attractor (S, (x, y, z)) and background (b, (cx, cy, cz)).  The backward
+    pass calls colatus_adjoint, which re-runs the forward with checkpoints and
+    returns gradients for x0 and v0.
     """
 
     @staticmethod
@@ -362,7 +394,7 @@ class ColatusRun(torch.autograd.Function):
         v = v0.detach().clone()
         run(x, v, m, params["eps"], params["G"], params["cosmo"], params["a_begin"],
             params["a_end"], params["n_steps"], precision=params.get("precision", "mixed_twosum"),
-            attractor=params.get("attractor"))
+            attractor=params.get("attractor"), background=params.get("background"))
         ctx.save_for_backward(x0.detach(), v0.detach(), m)
         ctx.params = params
         return x, v
@@ -376,12 +408,12 @@ class ColatusRun(torch.autograd.Function):
         res = adjoint(x0, v0, m, P["eps"], P["G"], P["cosmo"], P["a_begin"], P["a_end"],
                       P["n_steps"], gx, gv, checkpoint_every=P.get("checkpoint_every", 20),
                       precision=P.get("precision", "mixed_twosum"),
-                      attractor=P.get("attractor"))
+                      attractor=P.get("attractor"), background=P.get("background"))
         return res[0], res[1], None, None
 
 
 def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_every=20,
-         precision="mixed_twosum", attractor=None):
+         precision="mixed_twosum", attractor=None, background=None):
     """Finite-time Lyapunov exponents of tracer particles.
 
     The 3x3 block d x_t(a_end) / d x_t(a_begin) of each tracer is read off
@@ -400,7 +432,8 @@ def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_
             lam_x[3 * ti + i, i, int(t)] = 1.0
     lam_v = torch.zeros_like(lam_x)
     gx = adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_x, lam_v,
-                 checkpoint_every=checkpoint_every, precision=precision, attractor=attractor)[0]
+                 checkpoint_every=checkpoint_every, precision=precision, attractor=attractor,
+                 background=background)[0]
     g = gx.cpu().numpy()
     phi = np.empty((T, 3, 3))
     for ti, t in enumerate(tracers):

@@ -204,14 +204,28 @@ int ensure(Buffer &b, size_t bytes)
 }
 
 // Host checks of the Eq. (10) attractor argument (NULL: none).
-int resolve_attractor(const colatus_attractor *a, Attractor &out)
+int resolve_external(const colatus_attractor *a, const colatus_background *bg, ExtField &out)
 {
-    out = Attractor{0, 0.0, 0.0, 0.0, 0.0};
-    if (!a)
-        return COLATUS_OK;
-    if (!is_fin(a->strength) || !is_fin(a->x[0]) || !is_fin(a->x[1]) || !is_fin(a->x[2]))
-        return COLATUS_EINVAL;
-    out = Attractor{1, a->strength, a->x[0], a->x[1], a->x[2]};
+    out = ExtField{};
+    if (a) {
+        if (!is_fin(a->strength) || !is_fin(a->x[0]) || !is_fin(a->x[1]) || !is_fin(a->x[2]))
+            return COLATUS_EINVAL;
+        out.on = 1;
+        out.S = a->strength;
+        out.x = a->x[0];
+        out.y = a->x[1];
+        out.z = a->x[2];
+    }
+    if (bg) {
+        if (!is_fin(bg->coefficient) || !is_fin(bg->centre[0]) || !is_fin(bg->centre[1]) ||
+            !is_fin(bg->centre[2]))
+            return COLATUS_EINVAL;
+        out.bg = 1;
+        out.b = bg->coefficient;
+        out.cx = bg->centre[0];
+        out.cy = bg->centre[1];
+        out.cz = bg->centre[2];
+    }
     return COLATUS_OK;
 }
 
@@ -850,7 +864,7 @@ struct RunParams {
     int precision;
     colatus_diag *diag;
     hipStream_t stream;
-    Attractor att;
+    ExtField ext;
     Tracks trk;
 };
 
@@ -984,7 +998,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     A.precision = P.precision;
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
     A.part_f32 = slots_f32(wl, P.precision);
-    A.att = P.att;
+    A.ext = P.ext;
     CHECK_RC(prepare_tracks(ws, P));
     A.track_slot = P.trk.n ? static_cast<const int32_t *>(ws->track_slot.ptr) : nullptr;
     A.track = P.trk.out;
@@ -1016,7 +1030,7 @@ int run_impl(const RunParams &P, const Boxes &b)
 // ===========================================================================
 extern "C" {
 
-int colatus_version(void) { return 10200; }
+int colatus_version(void) { return 10300; }
 
 const char *colatus_strerror(int code)
 {
@@ -1171,15 +1185,16 @@ int colatus_release(void)
 
 int colatus_forces(const double *x, const double *m, int64_t N, double eps, double G, double a,
                    int precision, double *acc, double *phi, const colatus_batch *batch,
-                   const colatus_attractor *attractor, void *stream)
+                   const colatus_attractor *attractor, const colatus_background *background,
+                   void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || !is_fin(a) || a <= 0.0)
         return COLATUS_EINVAL;
     CHECK_RC(check_ptrs({x, m, acc}));
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, batch, b));
-    Attractor att;
-    CHECK_RC(resolve_attractor(attractor, att));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
     std::lock_guard<std::mutex> lock(g_mu);
@@ -1198,7 +1213,7 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
                                      static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                      (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                      phi ? static_cast<const double *>(ws->part_phi.ptr) : nullptr,
-                                     slots_f32(wl, precision), x, m, N, G, G / (a * a * a), att,
+                                     slots_f32(wl, precision), x, m, N, G, G / (a * a * a), ext,
                                      1.0 / (a * a * a), acc, phi, s));
     return COLATUS_OK;
 }
@@ -1250,7 +1265,7 @@ int run_he_impl(const RunParams &P, const Boxes &b)
     if (diag) {
         CHECK_RC(run_forward_sweep(ws, wl, P.precision, true, mask, P.x, P.m, P.N, s, true));
         CHECK_HIP(launch_state_diag(P.x, vw, P.m, pphi, f32, blocks, n_blocks, P.N, P.G, coef,
-                                    0, P.precision, bm, P.att, dpart, s));
+                                    0, P.precision, bm, P.ext, dpart, s));
     }
     CHECK_HIP(launch_he_drift(P.x, vw, P.N, coef, 0, 0.5, s));
     HEArgs H;
@@ -1265,7 +1280,7 @@ int run_he_impl(const RunParams &P, const Boxes &b)
     H.G = P.G;
     H.coef = coef;
     H.box_mass = bm;
-    H.att = P.att;
+    H.ext = P.ext;
     H.track_slot = P.trk.n ? static_cast<const int32_t *>(ws->track_slot.ptr) : nullptr;
     H.track = P.trk.out;
     H.n_tracers = P.trk.n;
@@ -1277,7 +1292,7 @@ int run_he_impl(const RunParams &P, const Boxes &b)
         if (diag) {
             CHECK_RC(run_forward_sweep(ws, wl, P.precision, true, mask, xi, P.m, P.N, s, true));
             CHECK_HIP(launch_state_diag(xi, vw, P.m, pphi, f32, blocks, n_blocks, P.N, P.G, coef,
-                                        r + 1, P.precision, bm, P.att, dpart, s));
+                                        r + 1, P.precision, bm, P.ext, dpart, s));
         }
     }
     CHECK_HIP(hipMemcpyAsync(P.v, vw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1301,7 +1316,8 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                    double a_begin, double a_end, int64_t n_steps, int64_t first_step,
                    int64_t last_step, int precision, colatus_diag *diag,
                    const colatus_batch *batch, const colatus_attractor *attractor,
-                   const colatus_tracks *tracks, void *stream)
+                   const colatus_background *background, const colatus_tracks *tracks,
+                   void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
         return COLATUS_EINVAL;
@@ -1311,12 +1327,12 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, batch, b));
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
-    Attractor att;
-    CHECK_RC(resolve_attractor(attractor, att));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
     Tracks trk;
     CHECK_RC(resolve_tracks(tracks, N, trk));
     RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
-                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att,
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), ext,
                 trk};
     return run_he_impl(P, b);
 }
@@ -1325,7 +1341,8 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
                 double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a_begin,
                 double a_end, int64_t n_steps, int64_t first_step, int64_t last_step,
                 int precision, colatus_diag *diag, const colatus_batch *batch,
-                const colatus_attractor *attractor, const colatus_tracks *tracks,
+                const colatus_attractor *attractor, const colatus_background *background,
+                const colatus_tracks *tracks,
                 void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
@@ -1336,12 +1353,12 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, batch, b));
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
-    Attractor att;
-    CHECK_RC(resolve_attractor(attractor, att));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
     Tracks trk;
     CHECK_RC(resolve_tracks(tracks, N, trk));
     RunParams P{x, v, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
-                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), att,
+                first_step, last_step, precision, diag, static_cast<hipStream_t>(stream), ext,
                 trk};
     return run_impl(P, b);
 }
@@ -1349,10 +1366,11 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, double G,
                  double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a,
                  double a_next, int precision, const colatus_batch *batch,
-                 const colatus_attractor *attractor, void *stream)
+                 const colatus_attractor *attractor, const colatus_background *background,
+                 void *stream)
 {
     return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
-                       precision, nullptr, batch, attractor, nullptr, stream);
+                       precision, nullptr, batch, attractor, background, nullptr, stream);
 }
 
 int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_tracers,
@@ -1373,7 +1391,8 @@ int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_trace
 
 int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, double G,
                       int32_t n_cot, const double *lam, double *out, int precision,
-                      const colatus_attractor *attractor, void *stream)
+                      const colatus_attractor *attractor,
+                      const colatus_background *background, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_cot < 1 ||
         n_cot > kMaxCot)
@@ -1381,8 +1400,8 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
     CHECK_RC(check_ptrs({x, m, lam, out}));
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, nullptr, b));
-    Attractor att;
-    CHECK_RC(resolve_attractor(attractor, att));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
     std::lock_guard<std::mutex> lock(g_mu);
@@ -1396,7 +1415,7 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
     CHECK_HIP(launch_vjp_finalize(static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                   (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                   slots_f32(wl, precision),
-                                  static_cast<const double *>(ws->box_mass.ptr), x, lam, att, N,
+                                  static_cast<const double *>(ws->box_mass.ptr), x, lam, ext, N,
                                   n_cot, G, out, s));
     return COLATUS_OK;
 }
@@ -1407,7 +1426,8 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                     int32_t n_cot, const double *lam_xN, const double *lam_vN, double *grad_x0,
                     double *grad_v0, double *xN, double *vN, double *grad_attractor,
                     int precision, const colatus_batch *batch,
-                    const colatus_attractor *attractor, void *stream)
+                    const colatus_attractor *attractor,
+                    const colatus_background *background, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
         checkpoint_every < 1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
@@ -1417,8 +1437,8 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     CHECK_RC(check_ptrs({x0, v0, m, lam_xN, lam_vN, grad_x0, grad_v0}));
     Boxes b;
     CHECK_RC(resolve_boxes(N, eps, nullptr, b));
-    Attractor att;
-    CHECK_RC(resolve_attractor(attractor, att));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace *ws = nullptr;
@@ -1478,7 +1498,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     A.precision = precision;
     A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
     A.part_f32 = slots_f32(wf, precision);
-    A.att = att;
+    A.ext = ext;
     // per-block accumulators of the attractor's parameter derivatives
     double *acc_att = nullptr;
     const int n_ablk = (int)wa.blocks.size();
@@ -1549,7 +1569,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                                             n_ablk, static_cast<const double *>(ws->part.ptr),
                                             slots_f32(wa, precision),
                                             static_cast<const double *>(ws->box_mass.ptr), xs,
-                                            att, acc_att, N, n_cot, G, cw, lx, lp,
+                                            ext, acc_att, N, n_cot, G, cw, lx, lp,
                                             n > 0 ? 1 : 0, dnext, s));
         }
     }

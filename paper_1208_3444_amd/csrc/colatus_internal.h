@@ -60,14 +60,21 @@ __device__ __forceinline__ double rsqrt_refined(double s)
     return fma(0.5 * y0, e, y0);
 }
 
-// Deformation attractor of Eq. (10): a fixed point of strength S = C psi at
-// comoving (x, y, z) adding S d (|d|^2 + eps^2)^{-3/2}, d = x_psi - x_k, to
-// the comoving sum g of every particle (eps: its box's softening), with the
-// potential -S / sqrt(|d|^2 + eps^2) counted once in the energy.  on == 0:
-// no attractor (Eq. (1) alone).
-struct Attractor {
+// External terms added to the comoving sum g of every particle, each with
+// its potential counted once in the energy:
+// * the deformation attractor of Eq. (10) (on != 0): a fixed point of
+//   strength S = C psi at comoving (x, y, z) adding S d (|d|^2 + eps^2)^{-3/2},
+//   d = x_psi - x_k (eps: the particle's box softening), potential
+//   -S / sqrt(|d|^2 + eps^2);
+// * the background term of Eq. (6) (bg != 0): b (x_k - c), potential
+//   -b |x_k - c|^2 / 2 (the mean matter density's pull removed about the
+//   centre c; b = Om_M H0^2 / 2 makes it consistent with Eq. (2)).
+// Both scale with a like the pair sum.
+struct ExtField {
     int on;
     double S, x, y, z;
+    int bg;
+    double b, cx, cy, cz;
 };
 
 // Shape of one pair-sweep launch.
@@ -126,14 +133,14 @@ hipError_t launch_forces_finalize(int precision, const double *box_mass,
                                   const IntBlock *blocks, int n_blocks,
                                   const double *part, const double *part_phi, int part_f32,
                                   const double *x, const double *m, int64_t N, double G,
-                                  double scale, const Attractor &att, double inv_a3,
+                                  double scale, const ExtField &ext, double inv_a3,
                                   double *acc, double *phi, hipStream_t stream);
 
 // out = G * sum_s part[s] - S M(d) lam (attractor) for n_cot cotangents
 // ([n_cot][3][N]).
 hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
                                int part_f32, const double *box_mass, const double *x,
-                               const double *lam, const Attractor &att, int64_t N, int n_cot,
+                               const double *lam, const ExtField &ext, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream);
 
 // Step coefficients of steps [first, last) of the global grid.
@@ -165,7 +172,7 @@ struct IntegrateArgs {
     int precision;         // pair arithmetic of the sweep that wrote part_phi
     const double *box_mass;// per-box common mass or NaN (as given to the sweep)
     int part_f32;          // slots are FP32 without the common mass (see above)
-    Attractor att;         // Eq. (10) term added to g (att.on == 0: none)
+    ExtField ext;          // external terms added to g (Eqs. (10), (6))
     const int32_t *track_slot = nullptr; // [N]: tracer number of each particle or -1
     double *track = nullptr;   // [rows][2][3][n_tracers]: rows n > first are written here
     int32_t n_tracers = 0;
@@ -198,7 +205,7 @@ struct HEArgs {
     int64_t row;           // n - first
     int last;              // n + 1 == last step of the call
     const double *box_mass;
-    Attractor att;
+    ExtField ext;
     const int32_t *track_slot = nullptr; // as in IntegrateArgs: row + 1 (x^{n+1}, v^{n+1})
     double *track = nullptr;
     int32_t n_tracers = 0;
@@ -230,7 +237,7 @@ hipError_t launch_state_diag(const double *x, const double *v, const double *m,
                              const double *part_phi, int part_f32, const IntBlock *blocks,
                              int n_blocks, int64_t N, double G, const StepCoef *coef,
                              int64_t row, int precision, const double *box_mass,
-                             const Attractor &att, double *diag_part, hipStream_t stream);
+                             const ExtField &ext, double *diag_part, hipStream_t stream);
 
 // Reduce per-block diagnostics rows per box and accumulate LI / t.
 // out: [n_boxes][rows] rows of colatus_diag layout (as doubles, 14 each).
@@ -247,7 +254,7 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 // att_acc[b][c][0..4) (its own row only: deterministic, no atomics).
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
                                  int part_f32, const double *box_mass, const double *x,
-                                 const Attractor &att, double *att_acc, int64_t N, int n_cot,
+                                 const ExtField &ext, double *att_acc, int64_t N, int n_cot,
                                  double G, double cw, double *lam_x, double *lam_p,
                                  int do_drift, double dnext, hipStream_t stream);
 

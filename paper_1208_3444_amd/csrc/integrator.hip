@@ -186,7 +186,7 @@ __device__ __forceinline__ double box_mass_of(const double *box_mass, int box)
 // Eq. (10) attractor at particle position (px, py, pz), softening eps: adds
 // its field S d r^-3 (d = x_psi - x, r^2 = |d|^2 + eps^2) to f and returns
 // its potential -S / r.  FP64 with IEEE square root and division.
-__device__ __forceinline__ double attractor_pull(const Attractor &A, double px, double py,
+__device__ __forceinline__ double attractor_pull(const ExtField &A, double px, double py,
                                                  double pz, double eps, double (&f)[3])
 {
     const double dx = A.x - px, dy = A.y - py, dz = A.z - pz;
@@ -199,10 +199,34 @@ __device__ __forceinline__ double attractor_pull(const Attractor &A, double px, 
     return -A.S / r;
 }
 
+// Background term of Eq. (6): adds b (x - c) to f and returns its potential
+// -b |x - c|^2 / 2.
+__device__ __forceinline__ double background_pull(const ExtField &E, double px, double py,
+                                                  double pz, double (&f)[3])
+{
+    const double dx = px - E.cx, dy = py - E.cy, dz = pz - E.cz;
+    f[0] += E.b * dx;
+    f[1] += E.b * dy;
+    f[2] += E.b * dz;
+    return -0.5 * E.b * (dx * dx + dy * dy + dz * dz);
+}
+
+// Every external term present: field added to f, potential returned.
+__device__ __forceinline__ double ext_pull(const ExtField &E, double px, double py, double pz,
+                                           double eps, double (&f)[3])
+{
+    double ph = 0.0;
+    if (E.on)
+        ph += attractor_pull(E, px, py, pz, eps, f);
+    if (E.bg)
+        ph += background_pull(E, px, py, pz, f);
+    return ph;
+}
+
 // M(d) l with M(d) = r^-3 I - 3 r^-5 d d^T (the attractor's field derivative
 // is -S M(d) with respect to the particle, +S M(d) with respect to x_psi);
 // also returns l . d r^-3 (= l . f / S).
-__device__ __forceinline__ double attractor_m(const Attractor &A, double px, double py,
+__device__ __forceinline__ double attractor_m(const ExtField &A, double px, double py,
                                               double pz, double eps, const double (&l)[3],
                                               double (&mv)[3])
 {
@@ -323,9 +347,8 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
         double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
         double p[3] = {A.p[i], A.p[N + i], A.p[2 * N + i]};
         double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
-        double phe = 0.0;  // attractor potential (external: counted once)
-        if (A.att.on)
-            phe = attractor_pull(A.att, xx[0], xx[1], xx[2], blk.eps, g);
+        // external potential (attractor, background: counted once)
+        const double phe = ext_pull(A.ext, xx[0], xx[1], xx[2], blk.eps, g);
         if (n > A.first) {
             const StepCoef cp = A.coef[row - 1];
             for (int c = 0; c < 3; ++c)
@@ -453,7 +476,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     int precision, const double *__restrict__ box_mass, const IntBlock *__restrict__ blocks,
     const double *__restrict__ part, const double *__restrict__ part_phi, int part_f32,
     const double *__restrict__ x, const double *__restrict__ m, int64_t N, double G,
-    double scale, Attractor att, double inv_a3, double *__restrict__ acc,
+    double scale, ExtField ext, double inv_a3, double *__restrict__ acc,
     double *__restrict__ phi)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
@@ -465,8 +488,8 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     double g[3];
     slot_sum<3>(part, part_f32, i, blk.n_slices, 3 * N, N, valid, shs, mbox, g);
     double f[3] = {0.0, 0.0, 0.0}, phe = 0.0;
-    if (att.on && lead && valid)
-        phe = attractor_pull(att, x[i], x[N + i], x[2 * N + i], blk.eps, f);
+    if (lead && valid)
+        phe = ext_pull(ext, x[i], x[N + i], x[2 * N + i], blk.eps, f);
     if (lead && valid)
         for (int c = 0; c < 3; ++c)
             acc[(int64_t)c * N + i] = scale * g[c] + inv_a3 * f[c];
@@ -483,7 +506,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
 __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
     const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
     const double *__restrict__ box_mass, const double *__restrict__ x,
-    const double *__restrict__ lam, Attractor att, int64_t N, int n_cot, double G,
+    const double *__restrict__ lam, ExtField ext, int64_t N, int n_cot, double G,
     double *__restrict__ out)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
@@ -498,14 +521,19 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
                     (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
         if (lead && valid) {
             double o[3] = {G * w[0], G * w[1], G * w[2]};
-            if (att.on) {
+            if (ext.on || ext.bg) {
                 const double l[3] = {lam[((int64_t)c * 3 + 0) * N + i],
                                      lam[((int64_t)c * 3 + 1) * N + i],
                                      lam[((int64_t)c * 3 + 2) * N + i]};
-                double mv[3];
-                (void)attractor_m(att, x[i], x[N + i], x[2 * N + i], blk.eps, l, mv);
-                for (int q = 0; q < 3; ++q)
-                    o[q] -= att.S * mv[q];
+                if (ext.on) {
+                    double mv[3];
+                    (void)attractor_m(ext, x[i], x[N + i], x[2 * N + i], blk.eps, l, mv);
+                    for (int q = 0; q < 3; ++q)
+                        o[q] -= ext.S * mv[q];
+                }
+                if (ext.bg)  // the background field's Jacobian is b I
+                    for (int q = 0; q < 3; ++q)
+                        o[q] += ext.b * l[q];
             }
             for (int q = 0; q < 3; ++q)
                 out[((int64_t)c * 3 + q) * N + i] = o[q];
@@ -517,7 +545,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
 // lam_x += cw * G sum_s part[s];  then (do_drift) lam_p += dnext * lam_x.
 __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
     const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
-    const double *__restrict__ box_mass, const double *__restrict__ x, Attractor att,
+    const double *__restrict__ box_mass, const double *__restrict__ x, ExtField ext,
     double *__restrict__ att_acc, int64_t N, int n_cot, double G, double cw,
     double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift, double dnext)
 {
@@ -536,17 +564,22 @@ __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
         double gp[4] = {0.0, 0.0, 0.0, 0.0};
         if (lead && valid) {
             double o[3] = {G * w[0], G * w[1], G * w[2]};
-            if (att.on) {
+            if (ext.on || ext.bg) {
                 // lam_p as the sweep saw it (before this update's drift)
                 const double l[3] = {lam_p[((int64_t)c * 3 + 0) * N + i],
                                      lam_p[((int64_t)c * 3 + 1) * N + i],
                                      lam_p[((int64_t)c * 3 + 2) * N + i]};
-                double mv[3];
-                gp[0] = attractor_m(att, x[i], x[N + i], x[2 * N + i], blk.eps, l, mv);
-                for (int q = 0; q < 3; ++q) {
-                    o[q] -= att.S * mv[q];
-                    gp[1 + q] = att.S * mv[q];
+                if (ext.on) {
+                    double mv[3];
+                    gp[0] = attractor_m(ext, x[i], x[N + i], x[2 * N + i], blk.eps, l, mv);
+                    for (int q = 0; q < 3; ++q) {
+                        o[q] -= ext.S * mv[q];
+                        gp[1 + q] = ext.S * mv[q];
+                    }
                 }
+                if (ext.bg)
+                    for (int q = 0; q < 3; ++q)
+                        o[q] += ext.b * l[q];
             }
             for (int q = 0; q < 3; ++q) {
                 const int64_t k = ((int64_t)c * 3 + q) * N + i;
@@ -556,7 +589,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
                     lam_p[k] += dnext * lx;
             }
         }
-        if (att.on && att_acc) {
+        if (ext.on && att_acc) {
             // this block's parameter derivatives, summed in particle order
             if (lead)
                 for (int q = 0; q < 4; ++q)
@@ -603,8 +636,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void he_step_kernel(HEArgs A)
     double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
     double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
     double vv[3] = {A.v[i], A.v[N + i], A.v[2 * N + i]};
-    if (A.att.on)
-        (void)attractor_pull(A.att, xx[0], xx[1], xx[2], blk.eps, g);
+    (void)ext_pull(A.ext, xx[0], xx[1], xx[2], blk.eps, g);
     const double tau = cf.dt, Ht = cf.Hh * tau;
     const double drag = (1.0 - Ht) / (1.0 + Ht);
     const double kick = tau / (cf.ah * cf.ah * cf.ah * (1.0 + Ht));
@@ -663,7 +695,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void state_diag_kernel(
     const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ m,
     const double *__restrict__ part_phi, int part_f32, const IntBlock *__restrict__ blocks,
     int n_blocks, int64_t N, double G, const StepCoef *__restrict__ coef, int64_t row,
-    int precision, const double *__restrict__ box_mass, Attractor att,
+    int precision, const double *__restrict__ box_mass, ExtField ext,
     double *__restrict__ diag_part)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
@@ -684,7 +716,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void state_diag_kernel(
         const double xx[3] = {x[i], x[N + i], x[2 * N + i]};
         const double p[3] = {a * a * v[i], a * a * v[N + i], a * a * v[2 * N + i]};
         double f[3] = {0.0, 0.0, 0.0};
-        const double phe = att.on ? attractor_pull(att, xx[0], xx[1], xx[2], blk.eps, f) : 0.0;
+        const double phe = ext_pull(ext, xx[0], xx[1], xx[2], blk.eps, f);
         const double phi = -G * (t[0] - self_potential(precision, mi, blk.eps, mbox)) + 2.0 * phe;
         w[0] = mi * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
         w[1] = mi * phi;
@@ -783,33 +815,33 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 hipError_t launch_forces_finalize(int precision, const double *box_mass, const IntBlock *blocks,
                                   int n_blocks, const double *part, const double *part_phi,
                                   int part_f32, const double *x, const double *m, int64_t N,
-                                  double G, double scale, const Attractor &att, double inv_a3,
+                                  double G, double scale, const ExtField &ext, double inv_a3,
                                   double *acc, double *phi, hipStream_t stream)
 {
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
                        precision, box_mass, blocks, part, part_phi, part_f32, x, m, N, G, scale,
-                       att, inv_a3, acc, phi);
+                       ext, inv_a3, acc, phi);
     return hipGetLastError();
 }
 
 hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
                                int part_f32, const double *box_mass, const double *x,
-                               const double *lam, const Attractor &att, int64_t N, int n_cot,
+                               const double *lam, const ExtField &ext, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, part_f32, box_mass, x, lam, att, N, n_cot, G, out);
+                       blocks, part, part_f32, box_mass, x, lam, ext, N, n_cot, G, out);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
                                  int part_f32, const double *box_mass, const double *x,
-                                 const Attractor &att, double *att_acc, int64_t N, int n_cot,
+                                 const ExtField &ext, double *att_acc, int64_t N, int n_cot,
                                  double G, double cw, double *lam_x, double *lam_p,
                                  int do_drift, double dnext, hipStream_t stream)
 {
     hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, part_f32, box_mass, x, att, att_acc, N, n_cot, G, cw, lam_x,
+                       blocks, part, part_f32, box_mass, x, ext, att_acc, N, n_cot, G, cw, lam_x,
                        lam_p, do_drift, dnext);
     return hipGetLastError();
 }
@@ -868,11 +900,11 @@ hipError_t launch_state_diag(const double *x, const double *v, const double *m,
                              const double *part_phi, int part_f32, const IntBlock *blocks,
                              int n_blocks, int64_t N, double G, const StepCoef *coef,
                              int64_t row, int precision, const double *box_mass,
-                             const Attractor &att, double *diag_part, hipStream_t stream)
+                             const ExtField &ext, double *diag_part, hipStream_t stream)
 {
     hipLaunchKernelGGL(state_diag_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream, x,
                        v, m, part_phi, part_f32, blocks, n_blocks, N, G, coef, row, precision,
-                       box_mass, att, diag_part);
+                       box_mass, ext, diag_part);
     return hipGetLastError();
 }
 

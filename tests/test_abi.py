@@ -62,7 +62,7 @@ def test_strerror_and_version():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.colatus_strerror(code)
     assert L.colatus_strerror(-99) == b"unknown error code"
-    assert L.colatus_version() == 10200
+    assert L.colatus_version() == 10300
 
 
 def test_forces_rejects_bad_arguments():
@@ -73,7 +73,7 @@ def test_forces_rejects_bad_arguments():
     def call(**kw):
         a = dict(ok, **kw)
         return f(a["x"], a["m"], a["N"], a["eps"], a["G"], a["a"], a["prec"], a["acc"],
-                 a["phi"], None, a.get("att"), None)
+                 a["phi"], None, a.get("att"), a.get("bg"), None)
 
     assert call(N=0) == EINVAL
     assert call(N=(1 << 28) + 1) == EINVAL
@@ -89,6 +89,10 @@ def test_forces_rejects_bad_arguments():
     for bad in ((float("nan"), (0.0, 0.0, 0.0)), (1.0, (0.0, float("inf"), 0.0))):
         pa, keep = colatus._attractor(bad)
         assert call(att=pa) == EINVAL
+    # so must the Eq. (6) background term
+    for bad in ((float("inf"), (0.5, 0.5, 0.5)), (1.0, (0.5, float("nan"), 0.5))):
+        pb, keep = colatus._background(bad)
+        assert call(bg=pb) == EINVAL
 
 
 def test_batch_descriptor_checks():
@@ -98,17 +102,17 @@ def test_batch_descriptor_checks():
     eps = np.array([0.1, 0.1, 0.1])
     b = colatus._Batch(3, off.ctypes.data, eps.ctypes.data)
     rc = L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b), None,
-                          None)
+                          None, None)
     assert rc == EINVAL
     off2 = np.array([0, 10, 25], dtype=np.int64)  # does not end at N
     b2 = colatus._Batch(2, off2.ctypes.data, eps.ctypes.data)
     assert L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b2),
-                            None, None) == EINVAL
+                            None, None, None) == EINVAL
     eps3 = np.array([0.1, -0.1])
     off3 = np.array([0, 10, 30], dtype=np.int64)
     b3 = colatus._Batch(2, off3.ctypes.data, eps3.ctypes.data)
     assert L.colatus_forces(FAKE, FAKE, 30, 0.0, 1.0, 1.0, 1, FAKE, None, ctypes.byref(b3),
-                            None, None) == EINVAL
+                            None, None, None) == EINVAL
 
 
 def _run(**kw):
@@ -118,7 +122,7 @@ def _run(**kw):
     a.update(kw)
     return L.colatus_run(a["x"], a["v"], a["m"], a["N"], a["eps"], a["G"], *a["cos"],
                          a["a0"], a["a1"], a["n"], a["first"], a["last"], a["prec"], None, None,
-                         a.get("att"), a.get("trk"), None)
+                         a.get("att"), a.get("bg"), a.get("trk"), None)
 
 
 def test_run_rejects_bad_arguments():
@@ -158,10 +162,12 @@ def test_run_rejects_bad_tracks():
         assert _run(trk=pt) == EINVAL
         args = dict(x=FAKE, v=FAKE, m=FAKE)
         rc = L.colatus_run_he(args["x"], args["v"], args["m"], 8, 0.01, 1.0, *LCDM, 0.1, 1.0,
-                              10, 0, 10, 1, None, None, None, pt, None)
+                              10, 0, 10, 1, None, None, None, None, pt, None)
         assert rc == EINVAL
     t = colatus._Tracks(2, None, FAKE)  # NULL index list
     assert _run(trk=ctypes.byref(t)) == EINVAL
+    pb, keep = colatus._background((0.5, (0.0, 0.0, float("inf"))))
+    assert _run(bg=pb) == EINVAL
 
 
 def test_spectrum_rejects_bad_arguments():
@@ -190,7 +196,7 @@ def test_adjoint_rejects_bad_arguments():
         a.update(kw)
         return L.colatus_adjoint(FAKE, FAKE, FAKE, a["N"], 0.01, 1.0, *LCDM, 0.2, 1.0, 10,
                                  a["K"], a["C"], FAKE, FAKE, FAKE, FAKE, None, None, a["ga"],
-                                 a["prec"], a["batch"], a["att"], None)
+                                 a["prec"], a["batch"], a["att"], a.get("bg"), None)
 
     assert call(K=0) == EINVAL
     assert call(C=0) == EINVAL
@@ -253,4 +259,4 @@ def test_valid_call_without_device_is_enodev():
     assert _run() == ENODEV
     L = colatus.lib()
     assert L.colatus_forces(FAKE, FAKE, 16, 0.01, 1.0, 1.0, 0, FAKE, None, None, None,
-                            None) == ENODEV
+                            None, None) == ENODEV
