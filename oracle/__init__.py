@@ -77,6 +77,8 @@ def _load():
         [_d, _d, _i64, _i64, _i64, _p, _d, _p, _d, _p, _p, _i64, _p]
     lib.oracle_background_add.restype = None
     lib.oracle_background_add.argtypes = [_p, _i64, _d, _p, _p, _p]
+    lib.oracle_velocity_spectrum_bins.restype = None
+    lib.oracle_velocity_spectrum_bins.argtypes = [_p, _i64, _i64, ctypes.c_int, _p, _i64, _p]
     lib.oracle_velocity_spectrum.restype = None
     lib.oracle_velocity_spectrum.argtypes = [_p, _i64, _i64, ctypes.c_int, _p]
     lib.oracle_he_coefficients.restype = None
@@ -281,6 +283,18 @@ def run_he(x, v, m, eps, G, cosmo, a_begin, a_end, n_steps, first_step=0,
     grid as ``run``; returns as ``run``."""
     return _run(_load().oracle_run_he, "oracle_run_he", x, v, m, eps, G, cosmo, a_begin,
                 a_end, n_steps, first_step, last_step, diag, attractor, tracers, background)
+
+
+def velocity_spectrum_bins(track, bins, remove_mean=False):
+    """``velocity_spectrum`` at the given bins only: (T, len(bins))."""
+    track = _c(track)
+    M, two, three, T = track.shape
+    assert two == 2 and three == 3
+    b = np.ascontiguousarray(bins, dtype=np.int64)
+    out = np.zeros((T, b.size))
+    _load().oracle_velocity_spectrum_bins(_ptr(track), M, T, 1 if remove_mean else 0,
+                                          b.ctypes.data_as(_p), b.size, _ptr(out))
+    return out
 
 
 def velocity_spectrum(track, remove_mean=False):

@@ -816,6 +816,43 @@ void oracle_velocity_spectrum(const double *track, int64_t M, int64_t T, int rem
     }
 }
 
+/* The same periodogram at chosen bins only (n_bins values per tracer,     */
+/* out[t][b] = E(bins[b])), for series too long for every bin.             */
+void oracle_velocity_spectrum_bins(const double *track, int64_t M, int64_t T, int remove_mean,
+                                   const int64_t *bins, int64_t n_bins, double *out)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double *w = (double *)malloc(sizeof(double) * (size_t)M);
+    for (int64_t t = 0; t < T; ++t) {
+        for (int64_t b = 0; b < n_bins; ++b)
+            out[t * n_bins + b] = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            ksum mean = {0, 0};
+            for (int64_t n = 0; n < M; ++n) {
+                w[n] = track[(size_t)n * 6 * T + (size_t)(3 + c) * T + t];
+                ksum_add(&mean, w[n]);
+            }
+            double mu = remove_mean ? ksum_value(&mean) / (double)M : 0.0;
+            for (int64_t n = 0; n < M; ++n)
+                w[n] -= mu;
+#pragma omp parallel for schedule(static)
+            for (int64_t b = 0; b < n_bins; ++b) {
+                const int64_t k = bins[b];
+                ksum re = {0, 0}, im = {0, 0};
+                for (int64_t n = 0; n < M; ++n) {
+                    int64_t j = (k * n) % M;
+                    double ang = two_pi * (double)j / (double)M;
+                    ksum_add(&re, w[n] * cos(ang));
+                    ksum_add(&im, -w[n] * sin(ang));
+                }
+                double r = ksum_value(&re), i = ksum_value(&im);
+                out[t * n_bins + b] += (r * r + i * i) / (double)M;
+            }
+        }
+    }
+    free(w);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Discrete adjoint (reverse mode of the run map, every state stored).      */
 /* Forward step n:  p' = p_n + k1 g(x_n);  x_{n+1} = x_n + d p';            */

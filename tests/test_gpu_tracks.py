@@ -136,3 +136,43 @@ def test_spectrum_of_a_run(dev):
     got = colatus.velocity_spectrum(track, remove_mean=True).cpu().numpy()
     ref = oracle.velocity_spectrum(tref, remove_mean=True)
     assert np.allclose(got, ref, rtol=1e-9, atol=1e-12 * ref.max())
+
+
+def test_spectrum_at_the_row_limit(dev):
+    M, T = 1 << 17, 2
+    tr = _random_track(M, T, 17)
+    got = colatus.velocity_spectrum(to_dev(tr, dev), remove_mean=True).cpu().numpy()
+    assert got.shape == (T, M // 2 + 1)
+    bins = [0, 1, 2, 4097, M // 2 - 1, M // 2]
+    ref = oracle.velocity_spectrum_bins(tr, bins, remove_mean=True)
+    w = tr[:, 1] - tr[:, 1].mean(axis=0)
+    energy = (w ** 2).sum(axis=(0, 1))
+    assert np.all(np.abs(got[:, bins] - ref) <= 1e-12 * energy[:, None])
+    # Parseval over every bin
+    full = got[:, 0] + 2 * got[:, 1:M // 2].sum(axis=1) + got[:, M // 2]
+    assert np.allclose(full, energy, rtol=1e-11)
+    with pytest.raises(colatus.ColatusError):
+        colatus.velocity_spectrum(torch_zeros(M + 1, 1, dev))
+
+
+def torch_zeros(M, T, dev):
+    import torch
+    return torch.zeros((M, 2, 3, T), dtype=torch.float64, device=dev)
+
+
+def test_tracks_at_the_tracer_limit(dev):
+    N = 65536
+    x, m = inputs.random_cloud(N, 31, scale=0.5)
+    v0 = 0.1 * np.random.default_rng(32).standard_normal((3, N))
+    xt, vt, mt = to_dev(x, dev), to_dev(v0, dev), to_dev(m, dev)
+    _, track = colatus.run(xt, vt, mt, 0.01, 1e-3, inputs.LCDM, 0.5, 1.0, 4, last_step=2,
+                           tracers=np.arange(N)[::-1])
+    t = track.cpu().numpy()
+    assert t.shape == (3, 2, 3, N)
+    assert np.array_equal(t[0, 0], x[:, ::-1]) and np.array_equal(t[0, 1], v0[:, ::-1])
+    assert np.array_equal(t[-1, 0], xt.cpu().numpy()[:, ::-1])
+    assert np.array_equal(t[-1, 1], vt.cpu().numpy()[:, ::-1])
+    with pytest.raises(colatus.ColatusError):
+        colatus.run(to_dev(np.zeros((3, N + 1)), dev), to_dev(np.zeros((3, N + 1)), dev),
+                    to_dev(np.ones(N + 1), dev), 0.01, 1.0, inputs.LCDM, 0.5, 1.0, 4,
+                    last_step=1, tracers=np.arange(N + 1))

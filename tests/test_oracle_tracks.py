@@ -106,3 +106,23 @@ def test_spectrum_pure_tones_and_constant():
     Em = oracle.velocity_spectrum(_track_from_velocity(vel), remove_mean=True)
     assert np.all(Em[3] < tiny)
     assert Em[0, 5] == pytest.approx(E[0, 5], rel=1e-13)  # a tone has zero mean
+
+
+def test_spectrum_at_chosen_bins():
+    rng = np.random.default_rng(5)
+    M = 77
+    vel = rng.standard_normal((M, 3, 3)) - 0.4
+    tr = _track_from_velocity(vel)
+    bins = [0, 1, 38, 12]
+    for rm in (False, True):
+        full = oracle.velocity_spectrum(tr, remove_mean=rm)
+        assert np.array_equal(oracle.velocity_spectrum_bins(tr, bins, remove_mean=rm),
+                              full[:, bins])
+    # a long series (the GPU limit) against numpy's FFT at a few bins
+    M = 1 << 17
+    vel = rng.standard_normal((M, 3, 1))
+    tr = _track_from_velocity(vel)
+    bins = [0, 1, 4097, M // 2]
+    got = oracle.velocity_spectrum_bins(tr, bins)
+    ref = (np.abs(np.fft.fft(vel, axis=0)) ** 2).sum(axis=1).T[:, bins] / M
+    assert np.allclose(got, ref, rtol=1e-9, atol=1e-12 * (vel ** 2).sum())
