@@ -400,6 +400,30 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         sweep[prec] = {"ms": 1e3 * t, "gpairs_s": pairs3 / t / 1e9}
     out["precision_sweep_64cubed"] = sweep
 
+    # the integrator beyond the 256 MB Infinity Cache: at 64^3 its 1024 slots
+    # per particle are 3.2 GB (FP32 slots) or 6.4 GB (FP64 pairs) per launch
+    v3 = torch.zeros_like(x3)
+    integ = {}
+    for prec in ("mixed_twosum", "fp64"):
+        xs3 = x3.clone()
+        colatus.set_option(colatus.OPT_TIMER, 1)
+        colatus.timer_read(2, reset=True)
+        colatus.run(xs3, v3, m3, ws3.eps, ws3.G, ws3.cosmo, 0.5, 0.52, 4, precision=prec)
+        torch.cuda.synchronize()
+        ms, launches = colatus.timer_read(2, reset=True)
+        colatus.set_option(colatus.OPT_TIMER, 0)
+        R3, tpb3, s3, f3 = colatus.tile_config(ws3.N, prec)
+        sb = 12.0 if f3 == 2 and prec != "fp64" and R3 * tpb3 <= 256 else 24.0
+        nbytes = ws3.N * (sb * s3 + 96.0)
+        integ[prec] = {"launch_ms": ms / launches, "bytes_per_launch": nbytes,
+                       "achieved_GBs": nbytes / (ms / launches * 1e-3) / 1e9,
+                       "frac_hbm_peak": nbytes / (ms / launches * 1e-3) / PEAK_HBM,
+                       "slots": s3, "slot_bytes": sb}
+    out["integrator_64cubed"] = integ
+    print(f"[bench] integrator at 64^3: {integ['mixed_twosum']['achieved_GBs']:.0f} GB/s "
+          f"(FP32 slots), {integ['fp64']['achieved_GBs']:.0f} GB/s (FP64)", file=sys.stderr,
+          flush=True)
+
     # ragged ensemble: 256 boxes, N log-uniform in [512, 8192], one launch per step
     e = inputs.ragged_ensemble()
     ve = e.velocities(colatus.hubble(e.a_begin, e.cosmo))
