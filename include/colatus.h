@@ -195,12 +195,20 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps,
  * with a_h = sqrt(a a_next), K(a1,a2) = int_{a1}^{a2} da/(a^2 H),
  * D(a1,a2) = int_{a1}^{a2} da/(a^3 H), H from Eq. (2).
  * Static limit H0 == 0: a stays fixed and a_next is read as the time step
- * dt (K = dt/(2a) each, D = dt/a^2).  Costs two force evaluations; use
- * colatus_run for many steps (one evaluation per step).  With an attractor
- * or a background term (or NULL) g includes the Eq. (10) / Eq. (6) terms.  */
+ * dt (K = dt/(2a) each, D = dt/a^2).  With an attractor or a background
+ * term (or NULL) g includes the Eq. (10) / Eq. (6) terms.
+ *   g_cache: NULL, or a DEVICE [3][N] array holding g(x) at the entry
+ *            positions (the comoving sum without a^-3, external terms
+ *            included: what colatus_forces returns with a = 1, or what the
+ *            previous colatus_step left there); the step uses it for the
+ *            opening kick and overwrites it with g(x) at the new positions,
+ *            so a sequence of steps costs one force evaluation each (NULL:
+ *            two per step).  Must not alias x or v (COLATUS_EINVAL).
+ * colatus_run makes many steps in one call (one evaluation per step and a
+ * captured graph).                                                          */
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
                  double G, double H0, double Om_R, double Om_M, double Om_K,
-                 double Om_L, double a, double a_next, int precision,
+                 double Om_L, double a, double a_next, int precision, double *g_cache,
                  const colatus_batch *batch, const colatus_attractor *attractor,
                  const colatus_background *background, void *stream);
 

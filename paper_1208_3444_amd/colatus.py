@@ -42,7 +42,7 @@ _d, _i64, _i32, _i, _p = (ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctype
 SIGNATURES = {
     "colatus_forces": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p, _p, _p]),
     "colatus_step": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i, _p, _p,
-                          _p, _p]),
+                          _p, _p, _p]),
     "colatus_run": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                          _i64, _i, _p, _p, _p, _p, _p, _p]),
     "colatus_run_he": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
@@ -231,15 +231,21 @@ def _cosmo(c):
 
 
 def step(x, v, m, eps, G, cosmo, a, a_next, precision="mixed_twosum", batch=None,
-         attractor=None, background=None):
-    """One kick-drift-kick step from a to a_next, in place on x and v."""
+         attractor=None, background=None, g_cache=None):
+    """One kick-drift-kick step from a to a_next, in place on x and v.
+
+    g_cache: None, or a (3, N) tensor holding g at the current positions
+    (forces(..., a=1.0) or the previous step's); it is used for the opening
+    kick and overwritten with g at the new positions (one force evaluation
+    per step instead of two)."""
     N = m.shape[0]
     px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
     b, keep = _batch(batch)
     pa, keep_a = _attractor(attractor)
     pb, keep_b = _background(background)
+    pg = _dev(g_cache, "g_cache", (3, N)) if g_cache is not None else None
     rc = lib().colatus_step(px, pv, pm, N, float(eps) if batch is None else 0.0, float(G),
-                            *_cosmo(cosmo), float(a), float(a_next), _prec(precision),
+                            *_cosmo(cosmo), float(a), float(a_next), _prec(precision), pg,
                             ctypes.byref(b) if b is not None else None, pa, pb, _stream(x))
     del keep, keep_a, keep_b
     _check("colatus_step", rc)

@@ -1365,12 +1365,50 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
 
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, double G,
                  double H0, double Om_R, double Om_M, double Om_K, double Om_L, double a,
-                 double a_next, int precision, const colatus_batch *batch,
+                 double a_next, int precision, double *g_cache, const colatus_batch *batch,
                  const colatus_attractor *attractor, const colatus_background *background,
                  void *stream)
 {
-    return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
-                       precision, nullptr, batch, attractor, background, nullptr, stream);
+    if (!g_cache)
+        return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
+                           precision, nullptr, batch, attractor, background, nullptr, stream);
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, v, m}));
+    if (g_cache == x || g_cache == v)
+        return COLATUS_EINVAL;
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, batch, b));
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a, a_next));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(prepare_worklist(ws, 0, b, N, precision, x, m, 1, s));
+    const WorkList &wl = ws->fwd;
+    CHECK_RC(prepare_box_mass(ws, wl, m, s));
+    const size_t n3 = 3 * (size_t)N;
+    CHECK_RC(ensure(ws->coef, sizeof(StepCoef)));
+    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n3 * sizeof(double)));
+    bool mask = false;
+    for (double e : b.eps)
+        mask = mask || e == 0.0;
+    StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
+    double *p = static_cast<double *>(ws->p.ptr);
+    CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1, coef, s));
+    CHECK_HIP(launch_cached_kick(0, x, v, p, g_cache, N, coef, s));
+    CHECK_RC(run_forward_sweep(ws, wl, precision, false, mask, x, m, N, s, true));
+    // g at the new positions into the cache (the comoving sum: a = 1)
+    CHECK_HIP(launch_forces_finalize(precision, static_cast<const double *>(ws->box_mass.ptr),
+                                     static_cast<const IntBlock *>(wl.d_blocks.ptr),
+                                     (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
+                                     nullptr, slots_f32(wl, precision), x, m, N, G, G, ext, 1.0,
+                                     g_cache, nullptr, s));
+    CHECK_HIP(launch_cached_kick(1, x, v, p, g_cache, N, coef, s));
+    return COLATUS_OK;
 }
 
 int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_tracers,

@@ -215,6 +215,12 @@ struct HEArgs {
 // opening half drift unless last.
 hipError_t launch_he_step(const HEArgs &args, hipStream_t stream);
 
+// One step with a cached force g (colatus_step with g_cache), coefficients
+// coef[0]: mode 0 = opening kick and drift (p from v), mode 1 = closing kick
+// and v from p.
+hipError_t launch_cached_kick(int mode, double *x, double *v, double *p, const double *g,
+                              int64_t N, const StepCoef *coef, hipStream_t stream);
+
 // ---- tracer tracks ---------------------------------------------------------
 // slot[i] = -1 for all N particles, then slot[idx[t]] = t.
 hipError_t launch_track_slots(int32_t *slot, int64_t N, const int64_t *idx, int32_t T,

@@ -129,6 +129,30 @@ __global__ void convert_kernel(int mode, const double *__restrict__ src, double 
     }
 }
 
+// One kick-drift-kick step with the force at its start given (the step
+// with a cached force): mode 0, p = a_n^2 v, p += k1 g, x += d p; mode 1,
+// p += k2 g, v = p / a_{n+1}^2.  The same operations, in the same order, as
+// the conversion and integrate kernels of a run.  Elementwise over [3][N].
+__global__ void cached_kick_kernel(int mode, double *__restrict__ x, double *__restrict__ v,
+                                   double *__restrict__ p, const double *__restrict__ g,
+                                   int64_t n3, const StepCoef *__restrict__ coef)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3)
+        return;
+    const StepCoef cf = coef[0];
+    // explicit FMAs: the run's kernels contract their updates the same way
+    if (mode == 0) {
+        const double p0 = cf.a0 * cf.a0 * v[i];
+        const double pi = fma(cf.k1, g[i], p0);
+        x[i] = fma(cf.d, pi, x[i]);
+        p[i] = pi;
+    } else {
+        const double pi = fma(cf.k2, g[i], p[i]);
+        v[i] = pi / (cf.a1 * cf.a1);
+    }
+}
+
 // Deterministic tree sum of kDiagW values over the first kIntBlock threads
 // (every thread of the block calls it; the others contribute nothing).
 __device__ void block_sum_rows(double (&v)[kDiagW], double (*sh)[kIntBlock])
@@ -868,6 +892,15 @@ hipError_t launch_he_drift(double *x, const double *v, int64_t N, const StepCoef
 {
     hipLaunchKernelGGL(he_drift_kernel, dim3(blocks_for(3 * N, 256)), dim3(256), 0, stream, x, v,
                        3 * N, coef, idx, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_cached_kick(int mode, double *x, double *v, double *p, const double *g,
+                              int64_t N, const StepCoef *coef, hipStream_t stream)
+{
+    const int64_t n3 = 3 * N;
+    hipLaunchKernelGGL(cached_kick_kernel, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0,
+                       stream, mode, x, v, p, g, n3, coef);
     return hipGetLastError();
 }
 

@@ -170,6 +170,15 @@ def test_run_rejects_bad_tracks():
     assert _run(bg=pb) == EINVAL
 
 
+def test_step_rejects_aliased_force_cache():
+    L = colatus.lib()
+    for g in (FAKE, ctypes.c_void_p(8192)):
+        x, v = FAKE, ctypes.c_void_p(8192)
+        rc = L.colatus_step(x, v, FAKE, 8, 0.01, 1.0, *LCDM, 0.2, 0.3, 1, g, None, None, None,
+                            None)
+        assert rc == EINVAL
+
+
 def test_spectrum_rejects_bad_arguments():
     L = colatus.lib()
     assert L.colatus_velocity_spectrum(FAKE, 0, 4, 0, FAKE, None) == EINVAL
