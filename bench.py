@@ -489,9 +489,52 @@ def cpu_baseline(w, v0, args):
     sweeps = n + 1
     rate = sweeps * float(w.N) ** 2 / t / 1e9
     print(f"[bench] cpu oracle: {rate:.3f} Gpairs/s in {t:.1f} s", file=sys.stderr, flush=True)
-    return {"value": rate, "unit": "Gpairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # single FP64 force evaluations (median of 3) at the three workload sizes,
+    # and one 32^3 evaluation on a single core
+    import statistics
+    detail = {"cpu_model": _cpu_model(), "threads": cores}
+    for name, ww, tg in (("eds_lattice_16^3", _inputs().eds_lattice(16), None),
+                         ("lcdm_grf_32^3", w, None),
+                         ("precision_sweep_64^3_4096_targets", _inputs().precision_sweep(64),
+                          "targets")):
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            if tg is None:
+                oracle.forces(ww.x, ww.m, ww.eps, G=ww.G)
+            else:
+                oracle.forces_targets(ww.x, ww.m, ww.extra[tg], ww.eps, G=ww.G)
+            ts.append(time.perf_counter() - t0)
+        npairs = float(ww.N) * (ww.N if tg is None else len(ww.extra[tg]))
+        detail[name] = {"seconds_median_of_3": statistics.median(ts),
+                        "gpairs_s": npairs / statistics.median(ts) / 1e9}
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.forces(w.x, w.m, w.eps, G=w.G)
+    t1 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    detail["lcdm_grf_32^3_one_core"] = {"seconds": t1, "gpairs_s": float(w.N) ** 2 / t1 / 1e9}
+    print(f"[bench] cpu oracle, one core: {detail['lcdm_grf_32^3_one_core']['gpairs_s']:.3f} "
+          f"Gpairs/s", file=sys.stderr, flush=True)
+    return {"value": rate, "unit": "Gpairs/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} kick-drift-kick steps ({sweeps} FP64 force sweeps) of the "
-                      f"same 32^3 LCDM run", "seconds": t}
+                      f"same 32^3 LCDM run", "seconds": t, "detail": detail}
+
+
+def _inputs():
+    from paper_1208_3444_amd import inputs
+    return inputs
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -51,6 +51,8 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.restype = None
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     lib.oracle_hubble.restype = _d
     lib.oracle_hubble.argtypes = [_d] * 6
     lib.oracle_time_integral.restype = _d
@@ -101,6 +103,10 @@ def _ptr(a):
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
 
 
 def hubble(a, H0, Om_R, Om_M, Om_K, Om_L):

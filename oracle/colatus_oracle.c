@@ -74,6 +74,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads for the following calls (timing the oracle on one core). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Friedmann equation, Eq. (2):                                             */
 /*   H(a) = H0 sqrt(Om_R a^-4 + Om_M a^-3 + Om_K a^-2 + Om_L).              */
