@@ -1030,7 +1030,7 @@ int run_impl(const RunParams &P, const Boxes &b)
 // ===========================================================================
 extern "C" {
 
-int colatus_version(void) { return 10300; }
+int colatus_version(void) { return 10400; }
 
 const char *colatus_strerror(int code)
 {

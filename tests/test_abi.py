@@ -62,7 +62,7 @@ def test_strerror_and_version():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.colatus_strerror(code)
     assert L.colatus_strerror(-99) == b"unknown error code"
-    assert L.colatus_version() == 10300
+    assert L.colatus_version() == 10400
 
 
 def test_forces_rejects_bad_arguments():
