@@ -296,16 +296,21 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
 
     # tracer tracks of 64 particles at every grid point over the timed steps,
     # then the velocity power spectrum of their whole 1000-step tracks
+    # (timed back to back with the same steps untracked, from the same state)
     tr = np.random.default_rng(55).choice(N, 64, replace=False)
-    x, v, m = state()
-    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=0,
-                last_step=5, precision=args.precision, tracers=tr)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=5,
-                last_step=5 + Kg, precision=args.precision, tracers=tr)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    tt = {}
+    for key, trc in (("untracked", None), ("tracked", tr), ("untracked", None),
+                     ("tracked", tr)):
+        x, v, m = state()
+        colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=0,
+                    last_step=5, precision=args.precision, tracers=trc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps, first_step=5,
+                    last_step=5 + Kg, precision=args.precision, tracers=trc)
+        torch.cuda.synchronize()
+        tt[key] = time.perf_counter() - t0  # the second of each pair is kept
+    t = tt["tracked"]
     x, v, m = state()
     _, track = colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
                            precision=args.precision, tracers=tr)
@@ -316,6 +321,7 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         colatus.velocity_spectrum(track, remove_mean=True)
     torch.cuda.synchronize()
     out["tracks_64"] = {"gpairs_s": (Kg + 1) * pairs / t / 1e9, "ms_per_step": 1e3 * t / Kg,
+                        "untracked_ms_per_step": 1e3 * tt["untracked"] / Kg,
                         "track_rows": int(track.shape[0]),
                         "spectrum_ms": 1e3 * (time.perf_counter() - t1) / 10}
     print(f"[bench] 64 tracers: {out['tracks_64']['gpairs_s']:.1f} Gpairs/s; spectrum of "
