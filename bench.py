@@ -375,6 +375,19 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         "gpairs_s": (3 * nS + 2) * pairs / t / 1e9,
         "tflops": (FLOPS_PER_PAIR * (2 * nS + 1) + FLOPS_PER_PAIR_ADJ * (nS + 1)) * pairs / t
         / 1e12}
+    # the same run keeping every position (158 MB at 32^3) instead of
+    # recomputing the segments: one force sweep per step fewer, same bits
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colatus.adjoint(x4, v4, m4, wa.eps, wa.G, wa.cosmo, wa.a_begin, wa.a_end, wa.n_steps,
+                    lx, lv, checkpoint_every=0, precision=args.precision)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["adjoint_200_steps_all_positions_kept"] = {
+        "seconds": t, "forward_sweeps": nS + 1, "adjoint_sweeps": nS + 1,
+        "gpairs_s": (2 * nS + 2) * pairs / t / 1e9,
+        "tflops": (FLOPS_PER_PAIR * (nS + 1) + FLOPS_PER_PAIR_ADJ * (nS + 1)) * pairs / t / 1e12,
+        "position_bytes": 24.0 * wa.N * (nS + 1)}
     if args.ftle:
         tr = [int(i) for i in wa.extra["tracers"]]
         torch.cuda.synchronize()
@@ -387,7 +400,9 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         out["ftle_192_cotangents"] = {"seconds": t, "tracers": len(tr),
                                       "lambda_per_ln_a_median": float(np.median(lam_lna)),
                                       "lambda_per_ln_a_max": float(np.max(lam_lna))}
-    print(f"[bench] adjoint 200 steps: {out['adjoint_200_steps']['seconds']:.3f} s",
+    print(f"[bench] adjoint 200 steps: {out['adjoint_200_steps']['seconds']:.3f} s "
+          f"(every position kept: "
+          f"{out['adjoint_200_steps_all_positions_kept']['seconds']:.3f} s)",
           file=sys.stderr, flush=True)
 
     # single force evaluation at N = 64^3 in each precision

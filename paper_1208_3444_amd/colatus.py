@@ -349,7 +349,9 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x_0, v_0).
 
     lam_xN, lam_vN: (3, N) or (C, 3, N).  Returns (grad_x0, grad_v0) shaped
-    like the cotangents, plus (x_N, v_N) if return_state.  With an attractor
+    like the cotangents, plus (x_N, v_N) if return_state.  checkpoint_every:
+    K >= 1 stores the state every K steps and recomputes the segments; 0 keeps
+    every position (24 B per particle and step) and recomputes nothing.  With an attractor
     (S, (x, y, z)) (Eq. (10)) the run includes it and the gradient with
     respect to (S, x_psi) is appended: (4,) or (C, 4).  background: the
     Eq. (6) term (b, (cx, cy, cz)) of the run, or None.

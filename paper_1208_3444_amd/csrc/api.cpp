@@ -1468,7 +1468,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                     const colatus_background *background, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
-        checkpoint_every < 1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
+        checkpoint_every < 0 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
         return COLATUS_EINVAL;
     if (grad_attractor && !attractor)
         return COLATUS_EINVAL;
@@ -1488,7 +1488,10 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     const WorkList &wa = ws->adj;
     CHECK_RC(prepare_box_mass(ws, wf, m, s));
     const size_t n3 = 3 * (size_t)N;
-    const int64_t K = checkpoint_every;
+    // checkpoint_every == 0: every position of the forward run is kept (one
+    // segment spanning the run, filled by the forward pass itself)
+    const bool keep_all = checkpoint_every == 0;
+    const int64_t K = keep_all ? n_steps : checkpoint_every;
     const int64_t n_seg = (n_steps + K - 1) / K;
     CHECK_RC(ensure(ws->coef, (size_t)n_steps * sizeof(StepCoef)));
     CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
@@ -1553,6 +1556,17 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     CHECK_RC(set_step(ws, 0, s));
     A.x = xw;
     for (int64_t n = 0; n < n_steps; ++n) {
+        if (keep_all) {
+            // x_n stays in slot n; the step writes x_{n+1} into slot n + 1
+            double *xs = seg + (size_t)n * n3;
+            double *xn = xs + n3;
+            CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
+            CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            A.x = xn;
+            CHECK_HIP(launch_integrate(A, s));
+            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+            continue;
+        }
         CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
         if (n % K == 0) {
             double *cx = ck + (size_t)(n / K) * 2 * n3;
@@ -1562,8 +1576,11 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
         CHECK_HIP(launch_integrate(A, s));
         CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
     }
+    if (keep_all)
+        xw = seg + (size_t)n_steps * n3;  // x_N
     if (xN || vN) {
         CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
+        A.x = xw;
         CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_end
         if (xN)
             CHECK_HIP(hipMemcpyAsync(xN, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1578,12 +1595,15 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     CHECK_HIP(launch_scale(lam_vN, lp, (int64_t)n_cot * (int64_t)n3, 1.0 / (aN * aN), s));
     for (int64_t sg = n_seg - 1; sg >= 0; --sg) {
         const int64_t lo = sg * K, hi = std::min(lo + K, n_steps);
-        // recompute positions x_lo .. x_hi from the checkpoint (bitwise: same kernels)
+        // recompute positions x_lo .. x_hi from the checkpoint (bitwise: same
+        // kernels), unless the forward pass kept them all
         const double *cx = ck + (size_t)sg * 2 * n3;
-        CHECK_HIP(hipMemcpyAsync(seg, cx, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-        CHECK_HIP(hipMemcpyAsync(p, cx + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-        CHECK_RC(set_step(ws, lo, s));
-        for (int64_t n = lo; n < hi; ++n) {
+        if (!keep_all) {
+            CHECK_HIP(hipMemcpyAsync(seg, cx, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            CHECK_HIP(hipMemcpyAsync(p, cx + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            CHECK_RC(set_step(ws, lo, s));
+        }
+        for (int64_t n = lo; n < hi && !keep_all; ++n) {
             double *xs = seg + (size_t)(n - lo) * n3;
             double *xn = seg + (size_t)(n - lo + 1) * n3;
             CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
