@@ -287,8 +287,10 @@ int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_trace
  * reverse sweep (one more force sweep per step); checkpoint_every == 0
  * keeps every position of the forward run instead (24 B x N x (n_steps + 1)
  * of device memory, 158 MB for 200 steps at N = 32768) and recomputes
- * nothing: the same bits, one force sweep per step fewer.  The transpose
- * Jacobian of the pair sum,
+ * nothing: the same bits, one force sweep per step fewer; -1 chooses: every
+ * position if they take at most a quarter of the free device memory, else
+ * segments of ceil(sqrt(n_steps)) steps.  checkpoint_every < -1 is
+ * COLATUS_EINVAL.  The transpose Jacobian of the pair sum,
  *   (J^T lam)_k = G sum_{j != k} M(d)(m_k lam_j - m_j lam_k),
  *   M(d) = r^-3 I - 3 r^-5 d d^T,  d = x_j - x_k,
  * is evaluated by its own O(N^2) pair sweep in the given precision, once

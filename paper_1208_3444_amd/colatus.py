@@ -344,7 +344,7 @@ def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum", attractor=None,
 
 
 def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
-            checkpoint_every=20, precision="mixed_twosum", return_state=False,
+            checkpoint_every=-1, precision="mixed_twosum", return_state=False,
             attractor=None, background=None):
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x_0, v_0).
 
@@ -414,13 +414,13 @@ class ColatusRun(torch.autograd.Function):
         gx = torch.zeros_like(x0) if gx is None else gx.contiguous()
         gv = torch.zeros_like(v0) if gv is None else gv.contiguous()
         res = adjoint(x0, v0, m, P["eps"], P["G"], P["cosmo"], P["a_begin"], P["a_end"],
-                      P["n_steps"], gx, gv, checkpoint_every=P.get("checkpoint_every", 20),
+                      P["n_steps"], gx, gv, checkpoint_every=P.get("checkpoint_every", -1),
                       precision=P.get("precision", "mixed_twosum"),
                       attractor=P.get("attractor"), background=P.get("background"))
         return res[0], res[1], None, None
 
 
-def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_every=20,
+def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_every=-1,
          precision="mixed_twosum", attractor=None, background=None):
     """Finite-time Lyapunov exponents of tracer particles.
 

@@ -1468,7 +1468,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                     const colatus_background *background, void *stream)
 {
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
-        checkpoint_every < 0 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
+        checkpoint_every < -1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
         return COLATUS_EINVAL;
     if (grad_attractor && !attractor)
         return COLATUS_EINVAL;
@@ -1488,6 +1488,18 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     const WorkList &wa = ws->adj;
     CHECK_RC(prepare_box_mass(ws, wf, m, s));
     const size_t n3 = 3 * (size_t)N;
+    if (checkpoint_every < 0) {
+        // automatic: every position when they take at most a quarter of the
+        // free device memory, else segments of ceil(sqrt(n_steps)) steps
+        // (the least checkpoint + segment memory; the compute is the same for
+        // every segment length)
+        size_t free_b = 0, total_b = 0;
+        CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
+        const double need = (double)(n_steps + 1) * (double)n3 * sizeof(double);
+        checkpoint_every = need <= 0.25 * (double)free_b
+                               ? 0
+                               : (int64_t)std::ceil(std::sqrt((double)n_steps));
+    }
     // checkpoint_every == 0: every position of the forward run is kept (one
     // segment spanning the run, filled by the forward pass itself)
     const bool keep_all = checkpoint_every == 0;

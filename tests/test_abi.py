@@ -207,7 +207,7 @@ def test_adjoint_rejects_bad_arguments():
                                  a["K"], a["C"], FAKE, FAKE, FAKE, FAKE, None, None, a["ga"],
                                  a["prec"], a["batch"], a["att"], a.get("bg"), None)
 
-    assert call(K=-1) == EINVAL
+    assert call(K=-2) == EINVAL
     assert call(C=0) == EINVAL
     assert call(C=5000) == EINVAL
     assert call(batch=FAKE) == EINVAL

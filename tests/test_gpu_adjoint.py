@@ -44,7 +44,7 @@ def test_adjoint_fp64_matches_oracle_and_checkpoints_are_exact(dev):
     gx_r, gv_r, xN_r, vN_r = oracle.adjoint(x0, v0, m, eps, G, LCDM, 0.2, 1.0, n, lx, lv)
     args = [to_dev(a, dev) for a in (x0, v0, m)]
     outs = []
-    for K in (1, 5, 12, 0):  # 0: every position kept, nothing recomputed
+    for K in (1, 5, 12, 0, -1):  # 0: every position kept; -1: the library chooses
         gx, gv, xN, vN = colatus.adjoint(*args, eps, G, LCDM, 0.2, 1.0, n, to_dev(lx, dev),
                                          to_dev(lv, dev), checkpoint_every=K, precision="fp64",
                                          return_state=True)
