@@ -91,8 +91,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not an implementation)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
