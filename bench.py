@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--ftle", action="store_true",
                    help="also time the 64-tracer FTLE (192 cotangents, 200 steps)")
     p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--roctx", action="store_true",
+                   help="roctx ranges around every library call (rocprofv3 --marker-trace)")
     p.add_argument("--calibration-copy-mib", type=int, default=0,
                    help="first run one plain elementwise pass over this many MiB (read "
                         "and write; a known-size kernel for scaling hardware byte counters)")
@@ -98,6 +100,8 @@ def main():
     import torch
 
     from paper_1208_3444_amd import colatus, inputs
+    if args.roctx:
+        colatus.set_option(colatus.OPT_ROCTX, 1)
 
     dev = torch.device("cuda", 0)
     if args.calibration_copy_mib > 0:

@@ -369,6 +369,11 @@ const char *colatus_strerror(int code);
                                      the forward up to 2^18 particles per box and
                                      for the adjoint with up to 3 cotangents, else
                                      0).  FP64 pairs: 1 means 0                      */
+#define COLATUS_OPT_ROCTX      9  /* 1: a roctx range around every call, named after
+                                     the entry point, and one per step of the
+                                     eagerly launched loops (graph-replayed steps
+                                     fall inside their call's range), for
+                                     rocprofv3 --marker-trace; 0 (default): none */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

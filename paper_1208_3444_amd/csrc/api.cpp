@@ -6,6 +6,7 @@
 #include "colatus_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -33,9 +34,28 @@ struct Options {
     int64_t tile_slices = 0;
     int64_t persistent = 0;  // one-shot grid measured faster on gfx950
     int64_t pair_form = -1;  // -1: heuristic or tuned
+    int64_t roctx = 0;       // 1: roctx ranges around calls and eager steps
 };
 Options g_opt;
 std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
+
+// A roctx range for the lifetime of the object, when COLATUS_OPT_ROCTX is on
+// (host-side marks for rocprofv3's marker trace; names are static strings).
+struct TraceRange {
+    bool on;
+    explicit TraceRange(const char *name) : on(g_opt.roctx != 0)
+    {
+        if (on)
+            roctxRangePush(name);
+    }
+    ~TraceRange()
+    {
+        if (on)
+            roctxRangePop();
+    }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // ---------------------------------------------------------------------------
 // Validation helpers (host only; nothing touches HIP before they pass).
@@ -901,8 +921,10 @@ int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, 
     };
     const bool use_graph = g_opt.graph && !g_opt.timer && n_iter >= 8;
     if (!use_graph) {
-        for (int64_t k = 0; k < n_iter; ++k)
+        for (int64_t k = 0; k < n_iter; ++k) {
+            TraceRange step("step");
             CHECK_RC(body(s));
+        }
         return COLATUS_OK;
     }
     if (!ws->cap_stream)
@@ -1082,6 +1104,7 @@ int colatus_set_option(int key, int64_t value)
         g_opt.tile_slices = value;
         return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: g_opt.persistent = value != 0; return COLATUS_OK;
+    case COLATUS_OPT_ROCTX: g_opt.roctx = value != 0; return COLATUS_OK;
     case COLATUS_OPT_PAIR_FORM:
         if (value < -1 || value > 2)
             return COLATUS_EINVAL;
@@ -1105,6 +1128,7 @@ int colatus_get_option(int key, int64_t *value)
     case COLATUS_OPT_TILE_SLICES: *value = g_opt.tile_slices; return COLATUS_OK;
     case COLATUS_OPT_PERSISTENT: *value = g_opt.persistent; return COLATUS_OK;
     case COLATUS_OPT_PAIR_FORM: *value = g_opt.pair_form; return COLATUS_OK;
+    case COLATUS_OPT_ROCTX: *value = g_opt.roctx; return COLATUS_OK;
     }
     return COLATUS_EINVAL;
 }
@@ -1188,6 +1212,7 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps, doub
                    const colatus_attractor *attractor, const colatus_background *background,
                    void *stream)
 {
+    TraceRange trace("colatus_forces");
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || !is_fin(a) || a <= 0.0)
         return COLATUS_EINVAL;
     CHECK_RC(check_ptrs({x, m, acc}));
@@ -1285,6 +1310,7 @@ int run_he_impl(const RunParams &P, const Boxes &b)
     H.track = P.trk.out;
     H.n_tracers = P.trk.n;
     for (int64_t r = 0; r < nsteps; ++r) {
+        TraceRange step("step");
         CHECK_RC(run_forward_sweep(ws, wl, P.precision, false, mask, P.x, P.m, P.N, s, true));
         H.row = r;
         H.last = r + 1 == nsteps ? 1 : 0;
@@ -1319,6 +1345,7 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                    const colatus_background *background, const colatus_tracks *tracks,
                    void *stream)
 {
+    TraceRange trace("colatus_run_he");
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
         return COLATUS_EINVAL;
     if (n_steps < 1 || first_step < 0 || last_step <= first_step || last_step > n_steps)
@@ -1345,6 +1372,7 @@ int colatus_run(double *x, double *v, const double *m, int64_t N, double eps, do
                 const colatus_tracks *tracks,
                 void *stream)
 {
+    TraceRange trace("colatus_run");
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G))
         return COLATUS_EINVAL;
     if (n_steps < 1 || first_step < 0 || last_step <= first_step || last_step > n_steps)
@@ -1369,6 +1397,7 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, d
                  const colatus_attractor *attractor, const colatus_background *background,
                  void *stream)
 {
+    TraceRange trace("colatus_step");
     if (!g_cache)
         return colatus_run(x, v, m, N, eps, G, H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1,
                            precision, nullptr, batch, attractor, background, nullptr, stream);
@@ -1414,6 +1443,7 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, d
 int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_tracers,
                               int remove_mean, double *out, void *stream)
 {
+    TraceRange trace("colatus_velocity_spectrum");
     if (rows < 1 || rows > kMaxSpectrumRows || n_tracers < 1 || n_tracers > kMaxTracers)
         return COLATUS_EINVAL;
     CHECK_RC(check_ptrs({track, out}));
@@ -1432,6 +1462,7 @@ int colatus_force_vjp(const double *x, const double *m, int64_t N, double eps, d
                       const colatus_attractor *attractor,
                       const colatus_background *background, void *stream)
 {
+    TraceRange trace("colatus_force_vjp");
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_cot < 1 ||
         n_cot > kMaxCot)
         return COLATUS_EINVAL;
@@ -1467,6 +1498,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
                     const colatus_attractor *attractor,
                     const colatus_background *background, void *stream)
 {
+    TraceRange trace("colatus_adjoint");
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
         checkpoint_every < -1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
         return COLATUS_EINVAL;
@@ -1568,6 +1600,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     CHECK_RC(set_step(ws, 0, s));
     A.x = xw;
     for (int64_t n = 0; n < n_steps; ++n) {
+        TraceRange step("adjoint forward step");
         if (keep_all) {
             // x_n stays in slot n; the step writes x_{n+1} into slot n + 1
             double *xs = seg + (size_t)n * n3;
@@ -1630,6 +1663,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
         const int64_t top = hi;
         const int64_t bottom = (sg == 0) ? lo : lo + 1;
         for (int64_t n = top; n >= bottom; --n) {
+            TraceRange step("adjoint reverse step");
             const double *xs = seg + (size_t)(n - lo) * n3;
             CHECK_RC(run_adjoint_sweep(ws, wa, precision, mask, xs, m, N, n_cot, lp, s));
             const double cw = (n < n_steps ? hc[(size_t)n].k1 : 0.0) +

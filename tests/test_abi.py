@@ -235,6 +235,11 @@ def test_options_and_tile_config():
     assert L.colatus_set_option(4, 3) == EINVAL
     assert L.colatus_set_option(5, 32) == EINVAL
     assert L.colatus_set_option(99, 0) == EINVAL
+    # roctx ranges: off by default, any nonzero value turns them on
+    assert L.colatus_get_option(9, ctypes.byref(v)) == 0 and v.value == 0
+    assert L.colatus_set_option(9, 5) == 0
+    assert L.colatus_get_option(9, ctypes.byref(v)) == 0 and v.value == 1
+    assert L.colatus_set_option(9, 0) == 0
     # forward sweeps and the few-cotangent adjoint: symmetric form, parts of
     # 4 x 64 particles
     assert colatus.tile_config(32768, "mixed") == (4, 64, 128, 2)
