@@ -79,8 +79,8 @@ def parse():
     p.add_argument("--precision", default="mixed_twosum")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
-    p.add_argument("--ftle", action="store_true",
-                   help="also time the 64-tracer FTLE (192 cotangents, 200 steps)")
+    p.add_argument("--no-ftle", action="store_true",
+                   help="skip the 64-tracer FTLE (192 cotangents, 200 steps, about 13 s)")
     p.add_argument("--cpu-sample-steps", type=int, default=24)
     p.add_argument("--roctx", action="store_true",
                    help="roctx ranges around every library call (rocprofv3 --marker-trace)")
@@ -392,7 +392,7 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         "gpairs_s": (2 * nS + 2) * pairs / t / 1e9,
         "tflops": (FLOPS_PER_PAIR * (nS + 1) + FLOPS_PER_PAIR_ADJ * (nS + 1)) * pairs / t / 1e12,
         "position_bytes": 24.0 * wa.N * (nS + 1)}
-    if args.ftle:
+    if not args.no_ftle:
         tr = [int(i) for i in wa.extra["tracers"]]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -404,6 +404,8 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         out["ftle_192_cotangents"] = {"seconds": t, "tracers": len(tr),
                                       "lambda_per_ln_a_median": float(np.median(lam_lna)),
                                       "lambda_per_ln_a_max": float(np.max(lam_lna))}
+        print(f"[bench] FTLE of {len(tr)} tracers (192 cotangents): {t:.1f} s",
+              file=sys.stderr, flush=True)
     print(f"[bench] adjoint 200 steps: {out['adjoint_200_steps']['seconds']:.3f} s "
           f"(every position kept: "
           f"{out['adjoint_200_steps_all_positions_kept']['seconds']:.3f} s)",
