@@ -15,7 +15,12 @@
  *     trajectory sensitivities and finite-time Lyapunov exponents of the
  *     chaotic-advection study the paper motivates (Sections I and IV);
  *   - optionally the deformation term of Eq. (10), a fixed attractor, in
- *     the forces, the run and the adjoint (with its parameter gradients).
+ *     the forces, the run and the adjoint (with its parameter gradients),
+ *     and the background term of Eq. (6) (the mean density's pull removed);
+ *   - the paper's own difference equations, Eqs. (3)-(5), as a second
+ *     scheme (colatus_run_he);
+ *   - tracer tracks (the state of chosen particles at every step) and each
+ *     tracer's velocity power spectrum (Section I's stated goal).
  *
  * Conventions shared by every entry point
  *   - Arrays named x, v, acc, lam_*, grad_* are structure-of-arrays float64
@@ -44,10 +49,11 @@
  *     same input gives bitwise the same output.
  *   - Limits: 1 <= N <= 2^28 particles (per call, all boxes together).
  *
- * Readings of the paper taken by this library (see also the design notes)
+ * Readings of the paper taken by this library
  *   - Eq. (1) prints the pair term as m_j (x_k - x_j), which is repulsive;
  *     the attractive m_j (x_j - x_k) is used.  The self pair j == k is
- *     excluded.  No background (a^2 a_ddot |x|^2 / 2) term: open box.
+ *     excluded.  Open box; the background term of Eq. (6) only when a
+ *     colatus_background is passed.
  *   - The step is the symplectic kick-drift-kick of Eq. (9) with canonical
  *     momentum p = a^2 v (per unit mass): kick p += g int dt/a, drift
  *     x += p int dt/a^2, where g = G sum m_j (x_j - x_k) r^-3.  Steps are

@@ -14,7 +14,7 @@
  * Paper: Stalder et al., "A new gravitational N-body simulation algorithm
  * for investigation of cosmological chaotic advection" (arXiv:1208.3444).
  *
- * Readings of the paper taken here (each is also listed in the design notes):
+ * Readings of the paper taken here:
  *  - Eq. (1) prints the pair term as m_j (x_k - x_j); that is repulsive.  The
  *    attractive form m_j (x_j - x_k) is used.
  *  - Eqs. (6)-(9): the canonical momentum is p = a^2 v (per unit mass), the
