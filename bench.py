@@ -467,9 +467,11 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    erun(0, 5)
+    # a warm-up run as long as the timed one (the first batched runs of a
+    # process ran up to 15 % slower)
     Ke = 50
-    t = erun(5, 5 + Ke)
+    erun(0, Ke)
+    t = erun(Ke, 2 * Ke)
     ens = {"boxes": int(len(sizes)), "particles": int(sizes.sum()),
            "pairs_per_step": pairs_e, "gpairs_s": (Ke + 1) * pairs_e / t / 1e9,
            "ms_per_step": 1e3 * t / Ke}
@@ -481,7 +483,7 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     t0 = time.perf_counter()
     for b, (xb, vb, mb) in enumerate(xs):
         colatus.run(xb, vb, mb, float(e.box_eps[b]), e.G, e.cosmo, e.a_begin, e.a_end,
-                    e.n_steps, first_step=5 + Ke, last_step=5 + Ke + Kl,
+                    e.n_steps, first_step=2 * Ke, last_step=2 * Ke + Kl,
                     precision=args.precision)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -490,16 +492,15 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     # the same batched step with the persistent grid (work items pulled from a
     # device counter), and with tile shapes from the autotuner
     colatus.set_option(colatus.OPT_PERSISTENT, 1)
-    erun(5 + Ke, 10 + Ke)
-    t = erun(10 + Ke, 10 + 2 * Ke)
+    erun(2 * Ke, 2 * Ke + 5)
+    t = erun(2 * Ke + 5, 3 * Ke + 5)
     colatus.set_option(colatus.OPT_PERSISTENT, 0)
     ens["persistent_grid_gpairs_s"] = (Ke + 1) * pairs_e / t / 1e9
     colatus.set_option(colatus.OPT_AUTOTUNE, 1)
-    erun(10 + 2 * Ke, 15 + 2 * Ke)
-    t = erun(15 + 2 * Ke, 15 + 3 * Ke)
+    erun(3 * Ke + 5, 3 * Ke + 10)
+    t = erun(3 * Ke + 10, 4 * Ke + 10)
     colatus.set_option(colatus.OPT_AUTOTUNE, 0)
     ens["autotuned_gpairs_s"] = (Ke + 1) * pairs_e / t / 1e9
-    ens["autotuned_tile"] = list(colatus.tile_config(int(sizes.max()), args.precision))
     out["ensemble_256"] = ens
     print(f"[bench] ensemble: {ens['gpairs_s']:.1f} Gpairs/s "
           f"({ens['speedup_vs_per_box_loop']:.1f}x per-box loop)", file=sys.stderr, flush=True)
