@@ -299,13 +299,24 @@ int get_workspace(hipStream_t stream, Workspace *&ws)
         ws = it->second;
         return COLATUS_OK;
     }
-    ws = new Workspace();
-    ws->device = dev;
-    ws->stream = stream;
-    g_ws[key] = ws;
-    // counters: [0] work-item counter (int), [8..16) step counter (int64)
-    CHECK_RC(ensure(ws->counters, 256));
-    CHECK_HIP(launch_zero_counter(static_cast<int *>(ws->counters.ptr), stream));
+    // registered only once its counters exist, so that a failed set-up is
+    // retried by the next call instead of leaving a workspace without them
+    Workspace *fresh = new Workspace();
+    fresh->device = dev;
+    fresh->stream = stream;
+    // counters: [0] work-item counter (int), [64..72) step counter (int64),
+    // [128] completion counter (int)
+    int rc = ensure(fresh->counters, 256);
+    if (rc == COLATUS_OK)
+        rc = hip_err(launch_zero_counter(static_cast<int *>(fresh->counters.ptr), stream));
+    if (rc != COLATUS_OK) {
+        if (fresh->counters.ptr)
+            (void)hipFree(fresh->counters.ptr);
+        delete fresh;
+        return rc;
+    }
+    g_ws[key] = fresh;
+    ws = fresh;
     return COLATUS_OK;
 }
 
@@ -624,15 +635,13 @@ int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, cons
         return COLATUS_OK;
     // the previous list may still be read by queued work
     CHECK_HIP(hipStreamSynchronize(s));
+    // the key is recorded last: a list whose upload failed is rebuilt
+    wl.N = -1;
     build_worklist(b, N, cfg, wl);
-    wl.N = N;
-    wl.off = b.off;
-    wl.eps = b.eps;
-    wl.cfg = cfg;
     CHECK_RC(ensure(wl.d_items, wl.items.size() * sizeof(WorkItem)));
     CHECK_RC(ensure(wl.d_blocks, wl.blocks.size() * sizeof(IntBlock)));
     CHECK_RC(ensure(wl.d_box_first, wl.box_first_block.size() * sizeof(int32_t)));
-    CHECK_RC(ensure(wl.d_off, wl.off.size() * sizeof(int64_t)));
+    CHECK_RC(ensure(wl.d_off, b.off.size() * sizeof(int64_t)));
     CHECK_HIP(hipMemcpyAsync(wl.d_items.ptr, wl.items.data(), wl.items.size() * sizeof(WorkItem),
                              hipMemcpyHostToDevice, s));
     CHECK_HIP(hipMemcpyAsync(wl.d_blocks.ptr, wl.blocks.data(),
@@ -640,9 +649,13 @@ int ensure_worklist(Workspace *ws, WorkList &wl, const Boxes &b, int64_t N, cons
     CHECK_HIP(hipMemcpyAsync(wl.d_box_first.ptr, wl.box_first_block.data(),
                              wl.box_first_block.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                              s));
-    CHECK_HIP(hipMemcpyAsync(wl.d_off.ptr, wl.off.data(), wl.off.size() * sizeof(int64_t),
+    CHECK_HIP(hipMemcpyAsync(wl.d_off.ptr, b.off.data(), b.off.size() * sizeof(int64_t),
                              hipMemcpyHostToDevice, s));
     CHECK_HIP(hipStreamSynchronize(s));
+    wl.N = N;
+    wl.off = b.off;
+    wl.eps = b.eps;
+    wl.cfg = cfg;
     (void)ws;
     return COLATUS_OK;
 }
