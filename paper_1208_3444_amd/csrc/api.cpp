@@ -176,6 +176,16 @@ struct Workspace {
     Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
         box_mass, att_acc, he_x, track_idx, track_slot, twiddle;
     WorkList fwd, adj;
+    // every device allocation the workspace owns
+    std::vector<Buffer *> buffers()
+    {
+        return {&part,          &part_phi,      &coef,           &p,          &diag_part,
+                &diag_out,      &counters,      &lam_x,          &lam_p,      &ckpt,
+                &seg,           &box_mass,      &att_acc,        &he_x,       &track_idx,
+                &track_slot,    &twiddle,       &fwd.d_items,    &fwd.d_blocks,
+                &fwd.d_box_first, &fwd.d_off,   &adj.d_items,    &adj.d_blocks,
+                &adj.d_box_first, &adj.d_off};
+    }
 };
 
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
@@ -846,7 +856,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                 }
                 for (Buffer *bb : {&tmp.d_items, &tmp.d_blocks, &tmp.d_box_first, &tmp.d_off})
                     if (bb->ptr)
-                        hipFree(bb->ptr);
+                        (void)hipFree(bb->ptr);
                 if (ms_total < best) {
                     best = ms_total;
                     cfg = c;
@@ -952,18 +962,18 @@ int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, 
     hipError_t ec = hipStreamEndCapture(ws->cap_stream, &graph);
     if (rc != COLATUS_OK) {
         if (graph)
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
         return rc;
     }
     CHECK_HIP(ec);
     hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     CHECK_HIP(ei);
     int64_t done = 0;
     while (done + per_graph <= n_iter) {
         hipError_t el = hipGraphLaunch(exec, s);
         if (el != hipSuccess) {
-            hipGraphExecDestroy(exec);
+            (void)hipGraphExecDestroy(exec);
             return hip_err(el);
         }
         done += per_graph;
@@ -975,7 +985,7 @@ int enqueue_steps(Workspace *ws, const RunParams &P, const IntegrateArgs &base, 
             break;
     }
     hipError_t es = hipStreamSynchronize(s);
-    hipGraphExecDestroy(exec);
+    (void)hipGraphExecDestroy(exec);
     CHECK_HIP(es);
     return rc;
 }
@@ -1200,23 +1210,26 @@ int colatus_release(void)
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
         return COLATUS_OK;
+    int current = 0;
+    const bool restore = hipGetDevice(&current) == hipSuccess;
     for (auto &kv : g_ws) {
         Workspace *ws = kv.second;
-        hipSetDevice(ws->device);
-        hipStreamSynchronize(ws->stream);
-        for (Buffer *bb : {&ws->part, &ws->part_phi, &ws->coef, &ws->p, &ws->diag_part,
-                           &ws->diag_out, &ws->counters, &ws->lam_x, &ws->lam_p, &ws->ckpt,
-                           &ws->seg, &ws->fwd.d_items, &ws->fwd.d_blocks, &ws->fwd.d_box_first,
-                           &ws->adj.d_items, &ws->adj.d_blocks, &ws->adj.d_box_first,
-                           &ws->fwd.d_off, &ws->adj.d_off, &ws->box_mass, &ws->att_acc,
-                           &ws->he_x})
+        (void)hipSetDevice(ws->device);
+        (void)hipStreamSynchronize(ws->stream);
+        for (Buffer *bb : ws->buffers())
             if (bb->ptr)
-                hipFree(bb->ptr);
+                (void)hipFree(bb->ptr);
         if (ws->cap_stream)
-            hipStreamDestroy(ws->cap_stream);
+            (void)hipStreamDestroy(ws->cap_stream);
         delete ws;
     }
     g_ws.clear();
+    // pooled timer events (those still held by unread timers stay valid)
+    for (hipEvent_t e : g_event_pool)
+        (void)hipEventDestroy(e);
+    g_event_pool.clear();
+    if (restore)
+        (void)hipSetDevice(current);
     return COLATUS_OK;
 }
 
