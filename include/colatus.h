@@ -395,7 +395,12 @@ int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset)
  * COLATUS_OPT_PAIR_FORM).  kind 0 = forward, 1 = adjoint.                 */
 int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[4]);
 
-/* Release all cached device scratch of all streams (synchronises them).  */
+/* Release all cached device scratch of every (device, stream) workspace,
+ * after synchronising each of those streams, and the pooled timer events.
+ * Tuned tile shapes, options and unread timer records are kept.  The next
+ * call on a stream allocates its scratch again.  The calling thread's
+ * current device is restored before return.  Always returns COLATUS_OK
+ * (cleanup errors are ignored); with no HIP device it does nothing.        */
 int colatus_release(void);
 
 /* Library version, major*10000 + minor*100 + patch.                      */
