@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--no-ftle", action="store_true",
                    help="skip the 64-tracer FTLE (192 cotangents, 200 steps, about 13 s)")
     p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--integrator-64-only", action="store_true",
+                   help="run only the integrator measurement at 64^3 (5 launches per precision) and print it as one JSON object, for counter runs")
     p.add_argument("--roctx", action="store_true",
                    help="roctx ranges around every library call (rocprofv3 --marker-trace)")
     p.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -113,6 +115,11 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.integrator_64_only:
+        ws3 = inputs.precision_sweep(64)
+        x3, m3 = torch.from_numpy(ws3.x).to(dev), torch.from_numpy(ws3.m).to(dev)
+        print(json.dumps({"integrator_64cubed": integrator_64cubed(ws3, x3, m3, colatus, torch)}), flush=True)
+        return
     w = inputs.lcdm_grf(32)
     H_i = colatus.hubble(w.a_begin, w.cosmo)
     v0 = w.velocities(H_i)
@@ -417,35 +424,18 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     pairs3 = float(ws3.N) ** 2
     sweep = {}
     for prec in ("fp32", "mixed_twosum", "mixed_f64acc", "fp64"):
-        colatus.forces(x3, m3, ws3.eps, a=0.5, precision=prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         for _ in range(3):
             colatus.forces(x3, m3, ws3.eps, a=0.5, precision=prec)
         torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / 3
+        t0 = time.perf_counter()
+        for _ in range(10):
+            colatus.forces(x3, m3, ws3.eps, a=0.5, precision=prec)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 10
         sweep[prec] = {"ms": 1e3 * t, "gpairs_s": pairs3 / t / 1e9}
     out["precision_sweep_64cubed"] = sweep
 
-    # the integrator beyond the 256 MB Infinity Cache: at 64^3 its 1024 slots
-    # per particle are 3.2 GB (FP32 slots) or 6.4 GB (FP64 pairs) per launch
-    v3 = torch.zeros_like(x3)
-    integ = {}
-    for prec in ("mixed_twosum", "fp64"):
-        xs3 = x3.clone()
-        colatus.set_option(colatus.OPT_TIMER, 1)
-        colatus.timer_read(2, reset=True)
-        colatus.run(xs3, v3, m3, ws3.eps, ws3.G, ws3.cosmo, 0.5, 0.52, 4, precision=prec)
-        torch.cuda.synchronize()
-        ms, launches = colatus.timer_read(2, reset=True)
-        colatus.set_option(colatus.OPT_TIMER, 0)
-        R3, tpb3, s3, f3 = colatus.tile_config(ws3.N, prec)
-        sb = 12.0 if f3 == 2 and prec != "fp64" and R3 * tpb3 <= 256 else 24.0
-        nbytes = ws3.N * (sb * s3 + 96.0)
-        integ[prec] = {"launch_ms": ms / launches, "bytes_per_launch": nbytes,
-                       "achieved_GBs": nbytes / (ms / launches * 1e-3) / 1e9,
-                       "frac_hbm_peak": nbytes / (ms / launches * 1e-3) / PEAK_HBM,
-                       "slots": s3, "slot_bytes": sb}
+    integ = integrator_64cubed(ws3, x3, m3, colatus, torch)
     out["integrator_64cubed"] = integ
     print(f"[bench] integrator at 64^3: {integ['mixed_twosum']['achieved_GBs']:.0f} GB/s "
           f"(FP32 slots), {integ['fp64']['achieved_GBs']:.0f} GB/s (FP64)", file=sys.stderr,
@@ -505,6 +495,30 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     print(f"[bench] ensemble: {ens['gpairs_s']:.1f} Gpairs/s "
           f"({ens['speedup_vs_per_box_loop']:.1f}x per-box loop)", file=sys.stderr, flush=True)
     return out
+
+
+def integrator_64cubed(ws3, x3, m3, colatus, torch):
+    """The integrator beyond the 256 MB Infinity Cache: at 64^3 its 1024 slots
+    per particle are 3.2 GB (FP32 slots) or 6.4 GB (FP64 pairs) per launch.
+    A 4-step run per precision, its integrator launches timed with hipEvents."""
+    v3 = torch.zeros_like(x3)
+    integ = {}
+    for prec in ("mixed_twosum", "fp64"):
+        xs3 = x3.clone()
+        colatus.set_option(colatus.OPT_TIMER, 1)
+        colatus.timer_read(2, reset=True)
+        colatus.run(xs3, v3, m3, ws3.eps, ws3.G, ws3.cosmo, 0.5, 0.52, 4, precision=prec)
+        torch.cuda.synchronize()
+        ms, launches = colatus.timer_read(2, reset=True)
+        colatus.set_option(colatus.OPT_TIMER, 0)
+        R3, tpb3, s3, f3 = colatus.tile_config(ws3.N, prec)
+        sb = 12.0 if f3 == 2 and prec != "fp64" and R3 * tpb3 <= 256 else 24.0
+        nbytes = ws3.N * (sb * s3 + 96.0)
+        integ[prec] = {"launch_ms": ms / launches, "bytes_per_launch": nbytes,
+                       "achieved_GBs": nbytes / (ms / launches * 1e-3) / 1e9,
+                       "frac_hbm_peak": nbytes / (ms / launches * 1e-3) / PEAK_HBM,
+                       "slots": s3, "slot_bytes": sb, "launches": launches}
+    return integ
 
 
 def cpu_baseline(w, v0, args):
