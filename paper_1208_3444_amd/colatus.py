@@ -183,6 +183,10 @@ def _dev(t, name, shape=None):
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    current = torch.cuda.current_device()
+    if t.device.index is not None and t.device.index != current:
+        raise ValueError(f"{name} is on {t.device}, but the library runs on the current "
+                         f"HIP device (cuda:{current})")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -195,9 +199,13 @@ def _batch(batch):
     if batch is None:
         return None, None
     import numpy as np
-    off = np.ascontiguousarray(np.asarray(batch[0], dtype=np.int64))
-    eps = np.ascontiguousarray(np.asarray(batch[1], dtype=np.float64))
-    b = _Batch(int(eps.shape[0]), off.ctypes.data, eps.ctypes.data)
+    off = np.ascontiguousarray(np.asarray(batch[0], dtype=np.int64).reshape(-1))
+    eps = np.ascontiguousarray(np.asarray(batch[1], dtype=np.float64).reshape(-1))
+    if eps.size < 1 or off.size != eps.size + 1:
+        # the library reads n_boxes + 1 offsets and n_boxes softenings
+        raise ValueError(f"batch needs B + 1 box offsets for B softenings (got {off.size} "
+                         f"offsets, {eps.size} softenings)")
+    b = _Batch(int(eps.size), off.ctypes.data, eps.ctypes.data)
     return b, (off, eps)
 
 

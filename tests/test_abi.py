@@ -115,6 +115,16 @@ def test_batch_descriptor_checks():
                             None, None, None) == EINVAL
 
 
+
+def test_binding_batch_lengths():
+    """The binding checks the batch arrays' lengths before they reach the
+    library, which reads B + 1 offsets and B softenings."""
+    off, keep = colatus._batch(([0, 10, 30], [0.1, 0.2]))
+    assert off.n_boxes == 2 and keep[0].size == 3
+    for bad in (([0, 30], [0.1, 0.2]), ([0, 10, 20, 30], [0.1, 0.2]), ([0], [])):
+        with pytest.raises(ValueError, match="offsets"):
+            colatus._batch(bad)
+
 def _run(**kw):
     L = colatus.lib()
     a = dict(x=FAKE, v=FAKE, m=FAKE, N=8, eps=0.01, G=1.0, cos=LCDM, a0=0.1, a1=1.0,
