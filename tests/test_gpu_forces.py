@@ -22,7 +22,8 @@ def _term_scale(x, m, eps, G=1.0):
     """sum_j |G m_j (x_j - x_k) r^-3| per target (conditioning of the sum)."""
     d = x[:, None, :] - x[:, :, None]
     s = (d ** 2).sum(axis=0) + eps * eps
-    w = G * m[None, :] * s ** -1.5
+    with np.errstate(divide="ignore"):  # eps = 0: the diagonal, cleared below
+        w = G * m[None, :] * s ** -1.5
     np.fill_diagonal(w, 0.0)
     return (w * np.sqrt((d ** 2).sum(axis=0))).sum(axis=1)
 

@@ -31,7 +31,8 @@ SHAPES = [(4, 64), (8, 64), (4, 128)]
 def _term_scale(x, m, eps):
     d = x[:, None, :] - x[:, :, None]
     s = (d ** 2).sum(axis=0) + eps * eps
-    w = m[None, :] * s ** -1.5
+    with np.errstate(divide="ignore"):  # eps = 0: the diagonal, cleared below
+        w = m[None, :] * s ** -1.5
     np.fill_diagonal(w, 0.0)
     return (w * np.sqrt((d ** 2).sum(axis=0))).sum(axis=1)
 
