@@ -9,6 +9,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -25,16 +26,17 @@ constexpr int kMaxCot = 4096;
 // ---------------------------------------------------------------------------
 // Options.
 // ---------------------------------------------------------------------------
+// Atomic: the roctx switch is read before an entry point takes the lock.
 struct Options {
-    int64_t graph = 1;
-    int64_t timer = 0;
-    int64_t autotune = 0;
-    int64_t tile_r = 0;
-    int64_t tile_tpb = 0;
-    int64_t tile_slices = 0;
-    int64_t persistent = 0;  // one-shot grid measured faster on gfx950
-    int64_t pair_form = -1;  // -1: heuristic or tuned
-    int64_t roctx = 0;       // 1: roctx ranges around calls and eager steps
+    std::atomic<int64_t> graph{1};
+    std::atomic<int64_t> timer{0};
+    std::atomic<int64_t> autotune{0};
+    std::atomic<int64_t> tile_r{0};
+    std::atomic<int64_t> tile_tpb{0};
+    std::atomic<int64_t> tile_slices{0};
+    std::atomic<int64_t> persistent{0};  // one-shot grid measured faster on gfx950
+    std::atomic<int64_t> pair_form{-1};  // -1: heuristic or tuned
+    std::atomic<int64_t> roctx{0};       // 1: roctx ranges around calls and eager steps
 };
 Options g_opt;
 std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
