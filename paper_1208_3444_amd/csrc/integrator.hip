@@ -441,57 +441,69 @@ __global__ void tick_kernel(int64_t *step, int *counter)
 
 // One block per box: sum the per-block rows in block order, then the
 // Layzer-Irvine residual and elapsed time by a sequential pass.
-__global__ void diag_reduce_kernel(const double *__restrict__ diag_part, int rows,
-                                   const IntBlock *__restrict__ blocks, int n_blocks,
-                                   const int32_t *__restrict__ box_first_block,
-                                   const StepCoef *__restrict__ coef, double H0,
-                                   colatus_diag *__restrict__ out)
+// Diagnostics rows: one thread per (box, row) sums the row's block partials
+// over the box's blocks in block order (the order, and so the bits, do not
+// depend on the launch shape); the grid is flattened over (box, row chunk).
+constexpr int kDiagRowThreads = 64;
+
+__global__ __launch_bounds__(kDiagRowThreads) void diag_rows_kernel(
+    const double *__restrict__ diag_part, int rows, int chunks, int n_blocks,
+    const int32_t *__restrict__ box_first_block, const StepCoef *__restrict__ coef,
+    colatus_diag *__restrict__ out)
 {
-    const int box = blockIdx.x;
+    const int box = (int)(blockIdx.x / (unsigned)chunks);
+    const int r = (int)(blockIdx.x % (unsigned)chunks) * kDiagRowThreads + (int)threadIdx.x;
+    if (r >= rows)
+        return;
     const int b0 = box_first_block[box], b1 = box_first_block[box + 1];
-    colatus_diag *o = out + (int64_t)box * rows;
-    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-        double s[kDiagW];
-        for (int q = 0; q < kDiagW; ++q)
-            s[q] = 0.0;
-        for (int b = b0; b < b1; ++b) {
-            const double *d = diag_part + ((int64_t)r * n_blocks + b) * kDiagW;
-            for (int q = 0; q < kDiagW - 1; ++q)
-                s[q] += d[q];
-            s[kDiagW - 1] = fmax(s[kDiagW - 1], d[kDiagW - 1]);
-        }
-        const double a = (r < rows - 1) ? coef[r].a0 : coef[r - 1].a1;
-        colatus_diag row;
-        row.a = a;
-        row.t = 0.0;
-        row.K = 0.5 * s[0] / (a * a);
-        row.U = 0.5 * s[1] / a;
-        row.LI = 0.0;
-        row.P[0] = s[2];
-        row.P[1] = s[3];
-        row.P[2] = s[4];
-        row.L[0] = s[5];
-        row.L[1] = s[6];
-        row.L[2] = s[7];
-        const bool bad = s[kDiagW - 1] != 0.0 || !isfinite(row.K) || !isfinite(row.U);
-        row.flags = bad ? 1u : 0u;
-        row.reserved = 0u;
-        o[r] = row;
+    double s[kDiagW];
+    for (int q = 0; q < kDiagW; ++q)
+        s[q] = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const double *d = diag_part + ((int64_t)r * n_blocks + b) * kDiagW;
+        for (int q = 0; q < kDiagW - 1; ++q)
+            s[q] += d[q];
+        s[kDiagW - 1] = fmax(s[kDiagW - 1], d[kDiagW - 1]);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double E0 = o[0].K + o[0].U;
-        double t = 0.0, li = 0.0;
-        double prev = 2.0 * o[0].K + o[0].U;
-        for (int r = 1; r < rows; ++r) {
-            t += coef[r - 1].dt;
-            const double src = 2.0 * o[r].K + o[r].U;
-            const double dlna = (H0 == 0.0) ? 0.0 : log(o[r].a) - log(o[r - 1].a);
-            li += 0.5 * (prev + src) * dlna;
-            prev = src;
-            o[r].t = t;
-            o[r].LI = o[r].K + o[r].U - E0 + li;
-        }
+    const double a = (r < rows - 1) ? coef[r].a0 : coef[r - 1].a1;
+    colatus_diag row;
+    row.a = a;
+    row.t = 0.0;
+    row.K = 0.5 * s[0] / (a * a);
+    row.U = 0.5 * s[1] / a;
+    row.LI = 0.0;
+    row.P[0] = s[2];
+    row.P[1] = s[3];
+    row.P[2] = s[4];
+    row.L[0] = s[5];
+    row.L[1] = s[6];
+    row.L[2] = s[7];
+    const bool bad = s[kDiagW - 1] != 0.0 || !isfinite(row.K) || !isfinite(row.U);
+    row.flags = bad ? 1u : 0u;
+    row.reserved = 0u;
+    out[(int64_t)box * rows + r] = row;
+}
+
+// Cosmic time and the Layzer-Irvine residual along each box's rows
+// (trapezoid in ln a), one thread per box, rows in order.
+__global__ void diag_prefix_kernel(int rows, int n_boxes, const StepCoef *__restrict__ coef,
+                                   double H0, colatus_diag *__restrict__ out)
+{
+    const int box = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (box >= n_boxes)
+        return;
+    colatus_diag *o = out + (int64_t)box * rows;
+    const double E0 = o[0].K + o[0].U;
+    double t = 0.0, li = 0.0;
+    double prev = 2.0 * o[0].K + o[0].U;
+    for (int r = 1; r < rows; ++r) {
+        t += coef[r - 1].dt;
+        const double src = 2.0 * o[r].K + o[r].U;
+        const double dlna = (H0 == 0.0) ? 0.0 : log(o[r].a) - log(o[r - 1].a);
+        li += 0.5 * (prev + src) * dlna;
+        prev = src;
+        o[r].t = t;
+        o[r].LI = o[r].K + o[r].U - E0 + li;
     }
 }
 
@@ -830,9 +842,21 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
                               int n_blocks, int n_boxes, const int32_t *box_first_block,
                               const StepCoef *coef, double H0, double *out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(diag_reduce_kernel, dim3(n_boxes), dim3(256), 0, stream, diag_part, rows,
-                       blocks, n_blocks, box_first_block, coef, H0,
-                       reinterpret_cast<colatus_diag *>(out));
+    (void)blocks;
+    if (rows < 2 || n_boxes < 1)  // a run has at least its start and end rows
+        return hipErrorInvalidValue;
+    const int64_t chunks = (rows + kDiagRowThreads - 1) / kDiagRowThreads;
+    const int64_t grid = chunks * (int64_t)n_boxes;
+    if (grid > 0x7fffffff)
+        return hipErrorInvalidValue;
+    colatus_diag *o = reinterpret_cast<colatus_diag *>(out);
+    hipLaunchKernelGGL(diag_rows_kernel, dim3((unsigned)grid), dim3(kDiagRowThreads), 0, stream,
+                       diag_part, rows, (int)chunks, n_blocks, box_first_block, coef, o);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(diag_prefix_kernel, dim3((unsigned)((n_boxes + 63) / 64)), dim3(64), 0,
+                       stream, rows, n_boxes, coef, H0, o);
     return hipGetLastError();
 }
 
