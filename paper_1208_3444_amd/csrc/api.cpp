@@ -1021,7 +1021,7 @@ int run_impl(const RunParams &P, const Boxes &b)
     StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
     double *p = static_cast<double *>(ws->p.ptr);
     CHECK_HIP(launch_coefficients(P.H0, P.OmR, P.OmM, P.OmK, P.OmL, P.a_begin, P.a_end,
-                                  P.n_steps, P.first, P.last, coef, s));
+                                  P.n_steps, P.first, P.last, 0, coef, s));
     CHECK_HIP(launch_convert(0, P.v, p, P.N, coef, 0, s));
     CHECK_RC(set_step(ws, P.first, s));
     CHECK_RC(run_forward_sweep(ws, wl, P.precision, diag, mask, P.x, P.m, P.N, s, false));
@@ -1312,7 +1312,7 @@ int run_he_impl(const RunParams &P, const Boxes &b)
     double *dpart = diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
     const double *pphi = static_cast<const double *>(ws->part_phi.ptr);
     CHECK_HIP(launch_coefficients(P.H0, P.OmR, P.OmM, P.OmK, P.OmL, P.a_begin, P.a_end,
-                                  P.n_steps, P.first, P.last, coef, s));
+                                  P.n_steps, P.first, P.last, 1, coef, s));
     CHECK_HIP(hipMemcpyAsync(vw, P.v, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     CHECK_RC(prepare_tracks(ws, P));
     if (diag) {
@@ -1455,7 +1455,7 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, d
         mask = mask || e == 0.0;
     StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
     double *p = static_cast<double *>(ws->p.ptr);
-    CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1, coef, s));
+    CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1, 0, coef, s));
     CHECK_HIP(launch_cached_kick(0, x, v, p, g_cache, N, coef, s));
     CHECK_RC(run_forward_sweep(ws, wl, precision, false, mask, x, m, N, s, true));
     // g at the new positions into the cache (the comoving sum: a = 1)
@@ -1587,7 +1587,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     double *xw = seg;
 
     CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps, 0,
-                                  n_steps, coef, s));
+                                  n_steps, 0, coef, s));
     std::vector<StepCoef> hc((size_t)n_steps);
     CHECK_HIP(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(StepCoef), hipMemcpyDeviceToHost,
                              s));

@@ -143,10 +143,11 @@ hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const doubl
                                const double *lam, const ExtField &ext, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream);
 
-// Step coefficients of steps [first, last) of the global grid.
+// Step coefficients of steps [first, last) of the global grid.  half_time:
+// also solve the half-time point (ah, Hh) of Eqs. (3)-(5), else leave it NaN.
 hipError_t launch_coefficients(double H0, double OmR, double OmM, double OmK, double OmL,
                                double a_begin, double a_end, int64_t n_steps,
-                               int64_t first, int64_t last, StepCoef *coef,
+                               int64_t first, int64_t last, int half_time, StepCoef *coef,
                                hipStream_t stream);
 
 // p = a_first^2 v (mode 0) or v = p / a^2 (mode 1) over all particles.

@@ -65,7 +65,7 @@ __device__ void time_integrals(const Cosmo &c, double s0, double s1, double out[
 }
 
 __global__ void coefficients_kernel(Cosmo c, double a_begin, double a_end, int64_t n_steps,
-                                    int64_t first, int64_t last, StepCoef *coef)
+                                    int64_t first, int64_t last, int half_time, StepCoef *coef)
 {
     const int64_t n = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= last)
@@ -97,6 +97,13 @@ __global__ void coefficients_kernel(Cosmo c, double a_begin, double a_end, int64
         s.dt = lo[0] + hi[0];
         s.a0 = a0;
         s.a1 = a1;
+        // only the Eqs. (3)-(5) scheme reads ah and Hh
+        s.ah = NAN;
+        s.Hh = NAN;
+        if (!half_time) {
+            coef[n - first] = s;
+            return;
+        }
         // half time of Eqs. (3)-(5): solve int_{s0}^{u} ds / H = dt / 2 for
         // u = ln a by Newton's method (derivative 1/H), from the ln-a midpoint
         double u = sh;
@@ -808,12 +815,12 @@ inline unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1)
 
 hipError_t launch_coefficients(double H0, double OmR, double OmM, double OmK, double OmL,
                                double a_begin, double a_end, int64_t n_steps, int64_t first,
-                               int64_t last, StepCoef *coef, hipStream_t stream)
+                               int64_t last, int half_time, StepCoef *coef, hipStream_t stream)
 {
     Cosmo c{H0, OmR, OmM, OmK, OmL};
     const int64_t n = last - first;
     hipLaunchKernelGGL(coefficients_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, stream, c,
-                       a_begin, a_end, n_steps, first, last, coef);
+                       a_begin, a_end, n_steps, first, last, half_time, coef);
     return hipGetLastError();
 }
 
