@@ -885,7 +885,7 @@ int prepare_box_mass(Workspace *ws, const WorkList &wl, const double *m, hipStre
     const int n_boxes = (int)wl.off.size() - 1;
     CHECK_RC(ensure(ws->box_mass, (size_t)n_boxes * sizeof(double)));
     CHECK_HIP(launch_box_mass(m, static_cast<const int64_t *>(wl.d_off.ptr), n_boxes,
-                              static_cast<double *>(ws->box_mass.ptr), s));
+                              wl.off.back(), static_cast<double *>(ws->box_mass.ptr), s));
     return COLATUS_OK;
 }
 

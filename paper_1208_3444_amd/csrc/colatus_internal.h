@@ -106,8 +106,9 @@ hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool w
                              double *part, double *part_phi, int64_t *step_inc,
                              hipStream_t stream);
 
-// box_mass[b] = m of box b if all its masses are equal and positive, else NaN.
-hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes,
+// box_mass[b] = m of box b if all its masses are equal and positive, else NaN
+// (box_offsets: device, n_boxes + 1 entries ending at N).
+hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes, int64_t N,
                            double *box_mass, hipStream_t stream);
 
 // Adjoint pair sweep for n_cot cotangents lam [n_cot][3][N]:

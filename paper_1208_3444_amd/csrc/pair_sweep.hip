@@ -1359,26 +1359,55 @@ hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool w
     return hipErrorInvalidValue;
 }
 
-// box_mass[b] = the common mass of box b, or NaN if its masses differ.
-__global__ void box_mass_kernel(const double *__restrict__ m, const int64_t *__restrict__ off,
-                                double *__restrict__ box_mass)
+// box_mass[b] = the common mass of box b, or NaN if its masses differ (or one
+// is not positive).  Two passes over the whole grid: every box takes its first
+// mass, then every particle whose mass differs from its box's first marks the
+// box NaN.  Those marks all store the same value, so the result does not
+// depend on their order.
+__global__ void box_mass_seed_kernel(const double *__restrict__ m,
+                                     const int64_t *__restrict__ off, int n_boxes,
+                                     double *__restrict__ box_mass)
 {
-    const int b = blockIdx.x;
-    const int64_t o0 = off[b], o1 = off[b + 1];
-    const double m0 = m[o0];
-    int differ = 0;
-    for (int64_t i = o0 + threadIdx.x; i < o1; i += blockDim.x)
-        differ |= (m[i] != m0) || !(m[i] > 0.0);
-    differ = __syncthreads_or(differ);
-    if (threadIdx.x == 0)
-        box_mass[b] = differ ? NAN : m0;
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= n_boxes)
+        return;
+    const double m0 = m[off[b]];
+    box_mass[b] = m0 > 0.0 ? m0 : NAN;
 }
 
-hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes,
+__global__ void box_mass_check_kernel(const double *__restrict__ m,
+                                      const int64_t *__restrict__ off, int n_boxes, int64_t N,
+                                      double *__restrict__ box_mass)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    // the box holding particle i: the last b with off[b] <= i
+    int lo = 0, hi = n_boxes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const double mi = m[i];
+    if (mi != m[off[lo]] || !(mi > 0.0))
+        box_mass[lo] = NAN;
+}
+
+hipError_t launch_box_mass(const double *m, const int64_t *box_offsets, int n_boxes, int64_t N,
                            double *box_mass, hipStream_t stream)
 {
-    hipLaunchKernelGGL(box_mass_kernel, dim3(n_boxes), dim3(1024), 0, stream, m, box_offsets,
-                       box_mass);
+    if (n_boxes < 1 || N < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(box_mass_seed_kernel, dim3((unsigned)((n_boxes + 63) / 64)), dim3(64), 0,
+                       stream, m, box_offsets, n_boxes, box_mass);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(box_mass_check_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                       stream, m, box_offsets, n_boxes, N, box_mass);
     return hipGetLastError();
 }
 
