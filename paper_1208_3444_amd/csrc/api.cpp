@@ -1458,13 +1458,13 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, d
     CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a, a_next, 1, 0, 1, 0, coef, s));
     CHECK_HIP(launch_cached_kick(0, x, v, p, g_cache, N, coef, s));
     CHECK_RC(run_forward_sweep(ws, wl, precision, false, mask, x, m, N, s, true));
-    // g at the new positions into the cache (the comoving sum: a = 1)
+    // g at the new positions into the cache (the comoving sum: a = 1), and
+    // the closing half kick from it in the same kernel
     CHECK_HIP(launch_forces_finalize(precision, static_cast<const double *>(ws->box_mass.ptr),
                                      static_cast<const IntBlock *>(wl.d_blocks.ptr),
                                      (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                      nullptr, slots_f32(wl, precision), x, m, N, G, G, ext, 1.0,
-                                     g_cache, nullptr, s));
-    CHECK_HIP(launch_cached_kick(1, x, v, p, g_cache, N, coef, s));
+                                     g_cache, nullptr, s, p, v, coef));
     return COLATUS_OK;
 }
 

@@ -129,13 +129,16 @@ hipError_t launch_zero_counter(int *counter, hipStream_t stream);
 // FP64 and apply the mass.
 
 // acc = scale * sum_s part[s] + inv_a3 f_att(x), phi = -G (sum_s part_phi[s] -
-// m/eps) + phi_att(x).
+// m/eps) + phi_att(x).  With kick_v: also the closing half kick of a cached
+// step from that acc, kick_v = (kick_p + k2 acc) / a1^2 (kick_coef[0]).
 hipError_t launch_forces_finalize(int precision, const double *box_mass,
                                   const IntBlock *blocks, int n_blocks,
                                   const double *part, const double *part_phi, int part_f32,
                                   const double *x, const double *m, int64_t N, double G,
                                   double scale, const ExtField &ext, double inv_a3,
-                                  double *acc, double *phi, hipStream_t stream);
+                                  double *acc, double *phi, hipStream_t stream,
+                                  const double *kick_p = nullptr, double *kick_v = nullptr,
+                                  const StepCoef *kick_coef = nullptr);
 
 // out = G * sum_s part[s] - S M(d) lam (attractor) for n_cot cotangents
 // ([n_cot][3][N]).

@@ -520,7 +520,8 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     const double *__restrict__ part, const double *__restrict__ part_phi, int part_f32,
     const double *__restrict__ x, const double *__restrict__ m, int64_t N, double G,
     double scale, ExtField ext, double inv_a3, double *__restrict__ acc,
-    double *__restrict__ phi)
+    double *__restrict__ phi, const double *__restrict__ kick_p, double *__restrict__ kick_v,
+    const StepCoef *__restrict__ kick_coef)
 {
     __shared__ double shs[4][kSliceGroups][kIntBlock];
     const IntBlock blk = blocks[blockIdx.x];
@@ -534,8 +535,17 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     if (lead && valid)
         phe = ext_pull(ext, x[i], x[N + i], x[2 * N + i], blk.eps, f);
     if (lead && valid)
-        for (int c = 0; c < 3; ++c)
-            acc[(int64_t)c * N + i] = scale * g[c] + inv_a3 * f[c];
+        for (int c = 0; c < 3; ++c) {
+            const double gc = scale * g[c] + inv_a3 * f[c];
+            acc[(int64_t)c * N + i] = gc;
+            if (kick_v) {
+                // closing half kick of a cached step: v = (p + k2 g) / a1^2,
+                // the same operations on the same g as the separate kick
+                const StepCoef cf = kick_coef[0];
+                const double pi = fma(cf.k2, gc, kick_p[(int64_t)c * N + i]);
+                kick_v[(int64_t)c * N + i] = pi / (cf.a1 * cf.a1);
+            }
+        }
     if (phi) {
         __syncthreads();
         double t[1];
@@ -871,11 +881,12 @@ hipError_t launch_forces_finalize(int precision, const double *box_mass, const I
                                   int n_blocks, const double *part, const double *part_phi,
                                   int part_f32, const double *x, const double *m, int64_t N,
                                   double G, double scale, const ExtField &ext, double inv_a3,
-                                  double *acc, double *phi, hipStream_t stream)
+                                  double *acc, double *phi, hipStream_t stream,
+                                  const double *kick_p, double *kick_v, const StepCoef *kick_coef)
 {
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
                        precision, box_mass, blocks, part, part_phi, part_f32, x, m, N, G, scale,
-                       ext, inv_a3, acc, phi);
+                       ext, inv_a3, acc, phi, kick_p, kick_v, kick_coef);
     return hipGetLastError();
 }
 
