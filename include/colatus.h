@@ -35,7 +35,9 @@
  *     of Eq. (2) (no renormalisation of their sum), a the scale factor.
  *   - stream is a hipStream_t (NULL = the default stream).  Work is queued
  *     on it and the call returns without waiting, except where a host
- *     output (diagnostics) is requested.
+ *     output (diagnostics) is requested, or where the library grows one of
+ *     its scratch buffers (the old buffer is freed after the device is idle)
+ *     or reads back a coefficient table it needs on the host (the adjoint).
  *   - Every argument check runs on the host before any HIP call; on an error
  *     nothing has been queued.  Return value 0 on success, else one of the
  *     negative COLATUS_E* codes; colatus_strerror() names it.
@@ -79,13 +81,17 @@ extern "C" {
 #define COLATUS_ENONFINITE -6  /* diagnostics found a NaN or Inf in the state             */
 
 /* ---- pair arithmetic --------------------------------------------------- */
+/* The FP32 forms evaluate each pair in FP32 on coordinates taken relative to
+ * the centre of the target tile (FP64 subtraction, then rounding), sum the
+ * pair terms of one tile in FP32 (a tile: a part of at most 256 sources in
+ * the default symmetric loop, 256 sources in the ordered loop), and then
+ * accumulate the tiles' FP32 partials per target as follows.               */
 #define COLATUS_FP64         0  /* FP64 pairs, FP64 running sums                            */
-#define COLATUS_MIXED_TWOSUM 1  /* FP32 pairs on coordinates relative to the target block's
-                                   centre; per-tile FP32 partials folded by TwoSum into an
-                                   unevaluated (hi, lo) FP32 pair                          */
-#define COLATUS_MIXED_F64ACC 2  /* FP32 pairs as above; per-tile partials folded into FP64  */
-#define COLATUS_FP32         3  /* FP32 pairs as above, one FP32 running sum per target and
-                                   source slice (no compensation)                          */
+#define COLATUS_MIXED_TWOSUM 1  /* FP32 pairs; tile partials accumulated by TwoSum into an
+                                   unevaluated (hi, lo) FP32 pair (compensated)            */
+#define COLATUS_MIXED_F64ACC 2  /* FP32 pairs; tile partials accumulated in FP64           */
+#define COLATUS_FP32         3  /* FP32 pairs; tile partials accumulated in one FP32
+                                   running sum (no compensation)                           */
 
 /* ---- ensembles of independent boxes ------------------------------------ */
 /* Particles of box b are [box_offsets[b], box_offsets[b+1]) of the [3][N]
@@ -210,8 +216,7 @@ int colatus_forces(const double *x, const double *m, int64_t N, double eps,
  *            opening kick and overwrites it with g(x) at the new positions,
  *            so a sequence of steps costs one force evaluation each (NULL:
  *            two per step).  Must not alias x or v (COLATUS_EINVAL).
- * colatus_run makes many steps in one call (one evaluation per step and a
- * captured graph).                                                          */
+ * colatus_run makes many steps in one call (one evaluation per step).     */
 int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
                  double G, double H0, double Om_R, double Om_M, double Om_K,
                  double Om_L, double a, double a_next, int precision, double *g_cache,
@@ -230,7 +235,11 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
  *         holds n_boxes consecutive blocks of rows (box-major).
  * Requires n_steps >= 1, 0 <= first_step < last_step <= n_steps, a_begin > 0,
  * a_end > 0 (or > 0 elapsed time in the static limit), H^2 > 0 on the range
- * (else COLATUS_EFRIEDMANN).  attractor (or NULL): the Eq. (10) term joins g
+ * (else COLATUS_EFRIEDMANN).  The steps are launched on the stream as they
+ * are queued; a call of 256 steps or more also captures 16 steps in a graph
+ * that this and later calls with the same arguments and buffers replay (the
+ * same kernels and arguments, so the same bits; COLATUS_OPT_GRAPH = 0 turns
+ * this off).  attractor (or NULL): the Eq. (10) term joins g
  * at every kick and its energy joins U; so does the Eq. (6) background
  * term (or NULL).  tracks (or NULL): see colatus_tracks; rows r >= 1 hold
  * v = p / a^2 as the final v does.                                          */
@@ -337,8 +346,10 @@ int colatus_hubble(double a, double H0, double Om_R, double Om_M, double Om_K,
 const char *colatus_strerror(int code);
 
 /* ---- tuning, timing and housekeeping ----------------------------------- */
-#define COLATUS_OPT_GRAPH      1  /* 1: capture the repeated step of colatus_run in a
-                                     hipGraph and replay it (default 1)              */
+#define COLATUS_OPT_GRAPH      1  /* 1: colatus_run calls of 256 steps or more capture
+                                     16 steps in a hipGraph, kept per (stream, kernel
+                                     arguments) and replayed by later calls of 16
+                                     steps or more (default 1)                       */
 #define COLATUS_OPT_TIMER      2  /* 1: bracket every pair-sweep and integrator launch
                                      with hipEvents on its stream (default 0; the run
                                      then launches eagerly instead of from a graph)  */

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "colatus.h"
+
 namespace colatus {
 
 // One unit of the O(N^2) pair sweep: a block of target particles of one box
@@ -48,6 +50,28 @@ struct StepCoef {
 
 enum Precision { kFP64 = 0, kMixedTwoSum = 1, kMixedF64Acc = 2, kFP32 = 3 };
 
+// How the O(N) readers add a particle's partial-sum slots (one slot per part
+// or source slice):
+//   kSlotF64        FP64 slots (already scaled by the box's common mass),
+//                   summed in FP64;
+//   kSlotF32Fold64  FP32 slots (one FP32 sum of at most 256 pair terms each,
+//                   without the mass), summed in FP64;
+//   kSlotF32TwoSum  FP32 slots, summed in an unevaluated FP32 pair (hi, lo)
+//                   by TwoSum (compensated FP32 accumulation);
+//   kSlotF32Direct  FP32 slots, summed in one FP32 running sum.
+enum SlotMode { kSlotF64 = 0, kSlotF32Fold64 = 1, kSlotF32TwoSum = 2, kSlotF32Direct = 3 };
+
+// hi + lo += v with the rounding error of hi + v carried into lo (TwoSum,
+// Knuth): hi + lo then holds the running sum to about twice FP32 precision.
+__device__ __forceinline__ void two_sum_add(float &hi, float &lo, float v)
+{
+    float s = hi + v;
+    float bp = s - hi;
+    float err = (hi - (s - bp)) + (v - bp);
+    hi = s;
+    lo += err;
+}
+
 // FP64 1/sqrt(s) for s > 0 finite: the hardware estimate (v_rsq_f64, about
 // 5e-8 relative on gfx950) refined by one Newton step,
 //   y1 = y0 + (y0 / 2) (1 - s y0^2),
@@ -77,6 +101,10 @@ struct ExtField {
     double b, cx, cy, cz;
 };
 
+// Host checks of the Eq. (10) attractor and Eq. (6) background arguments of
+// an entry point (NULL: none); COLATUS_EINVAL on a non-finite value.
+int resolve_external(const colatus_attractor *a, const colatus_background *bg, ExtField &out);
+
 // Shape of one pair-sweep launch.
 struct TileCfg {
     int R;        // targets per lane
@@ -84,6 +112,23 @@ struct TileCfg {
     int slices;   // source slices per box (form 2: parts of R * tpb particles)
     int form;     // FP32 pair-loop form (see launch_pair_sweep); 0 for FP64
 };
+
+// How the readers add the slots a sweep of this shape writes (SlotMode).
+// The symmetric form with FP32 pairs and parts of at most 256 particles
+// writes FP32 slots (each one FP32 sum of at most 256 terms), and the
+// precision then chooses the accumulation over the slots: TwoSum
+// (MIXED_TWOSUM), FP64 (MIXED_F64ACC) or plain FP32 (FP32); every other
+// sweep writes FP64 slots, summed in FP64.
+inline int slot_mode_for(const TileCfg &cfg, int precision)
+{
+    if (!(cfg.form == 2 && precision != kFP64 && cfg.R * cfg.tpb <= 256))
+        return kSlotF64;
+    if (precision == kMixedTwoSum)
+        return kSlotF32TwoSum;
+    if (precision == kFP32)
+        return kSlotF32Direct;
+    return kSlotF32Fold64;
+}
 
 // Diagnostics partial row written per IntBlock: K*a^2*2, sum m phi, P[3], L[3],
 // non-finite flag (as a double), padding.
@@ -124,16 +169,16 @@ hipError_t launch_adjoint_sweep(int precision, const TileCfg &cfg, bool mask_sel
 hipError_t launch_zero_counter(int *counter, hipStream_t stream);
 
 // Partial-sum slots: FP64, already multiplied by the box's common mass, or
-// (part_f32 != 0: the symmetric loop with FP32 pairs and parts of at most 256)
-// FP32 without it, the buffer then read as float; readers add the slots in
-// FP64 and apply the mass.
+// (slot_mode != kSlotF64: the symmetric loop with FP32 pairs and parts of at
+// most 256) FP32 without it, the buffer then read as float; readers add the
+// slots as the SlotMode slot_mode says and apply the mass in FP64.
 
 // acc = scale * sum_s part[s] + inv_a3 f_att(x), phi = -G (sum_s part_phi[s] -
 // m/eps) + phi_att(x).  With kick_v: also the closing half kick of a cached
 // step from that acc, kick_v = (kick_p + k2 acc) / a1^2 (kick_coef[0]).
 hipError_t launch_forces_finalize(int precision, const double *box_mass,
                                   const IntBlock *blocks, int n_blocks,
-                                  const double *part, const double *part_phi, int part_f32,
+                                  const double *part, const double *part_phi, int slot_mode,
                                   const double *x, const double *m, int64_t N, double G,
                                   double scale, const ExtField &ext, double inv_a3,
                                   double *acc, double *phi, hipStream_t stream,
@@ -143,7 +188,7 @@ hipError_t launch_forces_finalize(int precision, const double *box_mass,
 // out = G * sum_s part[s] - S M(d) lam (attractor) for n_cot cotangents
 // ([n_cot][3][N]).
 hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
-                               int part_f32, const double *box_mass, const double *x,
+                               int slot_mode, const double *box_mass, const double *x,
                                const double *lam, const ExtField &ext, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream);
 
@@ -169,14 +214,16 @@ struct IntegrateArgs {
     int64_t N;
     double G;
     const StepCoef *coef;  // indexed by (n - first)
-    const int64_t *step;   // device step counter n (absolute), advanced by the
-                           // next pair sweep (or a tick kernel)
+    const int64_t *step;   // device run descriptor {n, first, last}: the
+                           // absolute step counter n (advanced by the next
+                           // pair sweep or a tick kernel) and the call's step
+                           // range; kept in device memory so that a captured
+                           // step graph does not depend on the range
     int *work_counter;     // pair-sweep work counter, re-armed here (or null)
-    int64_t first, last;
     double *diag_part;     // [rows][n_blocks][kDiagW] or null
     int precision;         // pair arithmetic of the sweep that wrote part_phi
     const double *box_mass;// per-box common mass or NaN (as given to the sweep)
-    int part_f32;          // slots are FP32 without the common mass (see above)
+    int slot_mode;          // SlotMode of the slots (see above)
     ExtField ext;          // external terms added to g (Eqs. (10), (6))
     const int32_t *track_slot = nullptr; // [N]: tracer number of each particle or -1
     double *track = nullptr;   // [rows][2][3][n_tracers]: rows n > first are written here
@@ -201,7 +248,7 @@ struct HEArgs {
     double *v;             // [3][N]: v^n in, v^{n+1} out
     double *xi;            // [3][N] or null: receives x^{n+1}
     const double *part;    // slots of the sweep at x^{n+1/2}
-    int part_f32;
+    int slot_mode;
     const IntBlock *blocks;
     int n_blocks;
     int64_t N;
@@ -245,7 +292,7 @@ hipError_t launch_velocity_spectrum(const double *track, int64_t M, int32_t T, i
 // row 0 -> coef[0].a0, row r > 0 -> coef[r - 1].a1; p = a^2 v; the potential
 // from the PHI slots of a sweep at x (plus the attractor).
 hipError_t launch_state_diag(const double *x, const double *v, const double *m,
-                             const double *part_phi, int part_f32, const IntBlock *blocks,
+                             const double *part_phi, int slot_mode, const IntBlock *blocks,
                              int n_blocks, int64_t N, double G, const StepCoef *coef,
                              int64_t row, int precision, const double *box_mass,
                              const ExtField &ext, double *diag_part, hipStream_t stream);
@@ -264,7 +311,7 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 // cw * (sum_k lam_p . f_k / S, sum_k S M(d_k) lam_p) over its particles to
 // att_acc[b][c][0..4) (its own row only: deterministic, no atomics).
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
-                                 int part_f32, const double *box_mass, const double *x,
+                                 int slot_mode, const double *box_mass, const double *x,
                                  const ExtField &ext, double *att_acc, int64_t N, int n_cot,
                                  double G, double cw, double *lam_x, double *lam_p,
                                  int do_drift, double dnext, hipStream_t stream);

@@ -289,61 +289,133 @@ __device__ __forceinline__ double attractor_m(const ExtField &A, double px, doub
 constexpr int kSliceGroups = 4;
 constexpr int kFinalizeThreads = kIntBlock * kSliceGroups;
 
-// Sum of n_comp strided planes (k * stride + c * N) over this thread's slice
-// group, then the fixed-order combine; valid in wave 0 afterwards.
-template <int NC, typename P>
+// Sum of NC strided planes (k * stride + c * N) over this thread's slice
+// group, then the fixed-order combine of the groups; valid in wave 0
+// afterwards.  The accumulation follows the slot mode:
+//   kSlotF64, kSlotF32Fold64: FP64 running sums, FP64 combine;
+//   kSlotF32TwoSum: an unevaluated FP32 pair (hi, lo), each slot added by
+//     TwoSum, the groups' pairs combined by TwoSum, hi + lo taken in FP64;
+//   kSlotF32Direct: one FP32 running sum, FP32 combine.
+template <int NC, int MODE, typename P>
 __device__ __forceinline__ void grouped_slice_sum(const P *__restrict__ base, int S,
                                                   int64_t stride, int64_t N, bool valid,
                                                   double (*sh)[kSliceGroups][kIntBlock],
                                                   double (&out)[NC])
 {
     const int p = threadIdx.x & (kIntBlock - 1), q = threadIdx.x / kIntBlock;
-    double acc[NC];
+    if constexpr (MODE == kSlotF32TwoSum) {
+        float hi[NC], lo[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        acc[c] = 0.0;
-    if (valid) {
+        for (int c = 0; c < NC; ++c)
+            hi[c] = lo[c] = 0.0f;
+        if (valid) {
 #pragma unroll 4
-        for (int k = q; k < S; k += kSliceGroups) {
+            for (int k = q; k < S; k += kSliceGroups) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                acc[c] += (double)base[(int64_t)k * stride + (int64_t)c * N];
+                for (int c = 0; c < NC; ++c)
+                    two_sum_add(hi[c], lo[c], base[(int64_t)k * stride + (int64_t)c * N]);
+            }
         }
-    }
+        // (hi, lo) travel through LDS as the two halves of one 8-byte word
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        sh[c][q][p] = acc[c];
-    __syncthreads();
+        for (int c = 0; c < NC; ++c)
+            sh[c][q][p] = __builtin_bit_cast(double, make_float2(hi[c], lo[c]));
+        __syncthreads();
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double t = sh[c][0][p];
+        for (int c = 0; c < NC; ++c) {
+            float2 h = __builtin_bit_cast(float2, sh[c][0][p]);
+            float H = h.x, L = h.y;
 #pragma unroll
-        for (int g = 1; g < kSliceGroups; ++g)
-            t += sh[c][g][p];
-        out[c] = t;
+            for (int g = 1; g < kSliceGroups; ++g) {
+                const float2 o = __builtin_bit_cast(float2, sh[c][g][p]);
+                two_sum_add(H, L, o.x);
+                L += o.y;
+            }
+            out[c] = (double)H + (double)L;
+        }
+    } else if constexpr (MODE == kSlotF32Direct) {
+        float acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            acc[c] = 0.0f;
+        if (valid) {
+#pragma unroll 4
+            for (int k = q; k < S; k += kSliceGroups) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[c] += base[(int64_t)k * stride + (int64_t)c * N];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            sh[c][q][p] = (double)acc[c];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            float t = (float)sh[c][0][p];
+#pragma unroll
+            for (int g = 1; g < kSliceGroups; ++g)
+                t += (float)sh[c][g][p];
+            out[c] = (double)t;
+        }
+    } else {
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            acc[c] = 0.0;
+        if (valid) {
+#pragma unroll 4
+            for (int k = q; k < S; k += kSliceGroups) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[c] += (double)base[(int64_t)k * stride + (int64_t)c * N];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            sh[c][q][p] = acc[c];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double t = sh[c][0][p];
+#pragma unroll
+            for (int g = 1; g < kSliceGroups; ++g)
+                t += sh[c][g][p];
+            out[c] = t;
+        }
     }
 }
 
-// Slot sums at element offset `off`.  FP64 slots hold partial sums already
-// multiplied by the box's common mass; FP32 slots (the symmetric loop with
-// FP32 pairs, one FP32 sum per slot) hold them without it, and the mass
-// (1 when the masses differ) multiplies the FP64 total here.
+// Slot sums at element offset `off`.  FP64 slots (mode kSlotF64) hold
+// partial sums already multiplied by the box's common mass; FP32 slots (the
+// symmetric loop with FP32 pairs: one FP32 sum of at most 256 terms per
+// slot) hold them without it, and the mass (1 when the masses differ)
+// multiplies the total here in FP64.
 template <int NC>
-__device__ __forceinline__ void slot_sum(const double *part, int f32, int64_t off, int S,
+__device__ __forceinline__ void slot_sum(const double *part, int mode, int64_t off, int S,
                                          int64_t stride, int64_t N, bool valid,
                                          double (*sh)[kSliceGroups][kIntBlock], double mbox,
                                          double (&out)[NC])
 {
-    if (f32) {
-        grouped_slice_sum<NC>(reinterpret_cast<const float *>(part) + off, S, stride, N, valid,
-                              sh, out);
-        const double f = isnan(mbox) ? 1.0 : mbox;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            out[c] *= f;
-    } else {
-        grouped_slice_sum<NC>(part + off, S, stride, N, valid, sh, out);
+    const float *pf = reinterpret_cast<const float *>(part) + off;
+    switch (mode) {
+    case kSlotF64:
+        grouped_slice_sum<NC, kSlotF64>(part + off, S, stride, N, valid, sh, out);
+        return;
+    case kSlotF32TwoSum:
+        grouped_slice_sum<NC, kSlotF32TwoSum>(pf, S, stride, N, valid, sh, out);
+        break;
+    case kSlotF32Direct:
+        grouped_slice_sum<NC, kSlotF32Direct>(pf, S, stride, N, valid, sh, out);
+        break;
+    default:
+        grouped_slice_sum<NC, kSlotF32Fold64>(pf, S, stride, N, valid, sh, out);
+        break;
     }
+    const double f = isnan(mbox) ? 1.0 : mbox;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        out[c] *= f;
 }
 
 __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateArgs A)
@@ -355,19 +427,19 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
     const bool lead = threadIdx.x < kIntBlock;
     const int64_t i = blk.i0 + pl;
     const bool valid = i < blk.i1;
-    const int64_t n = *A.step;
-    const int64_t row = n - A.first;
+    const int64_t n = A.step[0], first = A.step[1], last = A.step[2];
+    const int64_t row = n - first;
     const int64_t N = A.N;
     const int S = blk.n_slices;
 
     const double mbox = box_mass_of(A.box_mass, blk.box);
     double gs[3];
-    slot_sum<3>(A.part, A.part_f32, i, S, 3 * N, N, valid, shs, mbox, gs);
+    slot_sum<3>(A.part, A.slot_mode, i, S, 3 * N, N, valid, shs, mbox, gs);
     double phs = 0.0;
     if (A.diag_part) {
         __syncthreads();
         double t[1];
-        slot_sum<1>(A.part_phi, A.part_f32, i, S, N, N, valid, shs, mbox, t);
+        slot_sum<1>(A.part_phi, A.slot_mode, i, S, N, N, valid, shs, mbox, t);
         phs = t[0];
     }
 
@@ -380,7 +452,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
         double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
         // external potential (attractor, background: counted once)
         const double phe = ext_pull(A.ext, xx[0], xx[1], xx[2], blk.eps, g);
-        if (n > A.first) {
+        if (n > first) {
             const StepCoef cp = A.coef[row - 1];
             for (int c = 0; c < 3; ++c)
                 p[c] += cp.k2 * g[c];
@@ -414,7 +486,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
                        ? 0.0
                        : 1.0;
         }
-        if (n < A.last) {
+        if (n < last) {
             const StepCoef cf = A.coef[row];
             for (int c = 0; c < 3; ++c) {
                 p[c] += cf.k1 * g[c];
@@ -517,7 +589,7 @@ __global__ void diag_prefix_kernel(int rows, int n_boxes, const StepCoef *__rest
 // acc = scale * sum_s part[s];  phi = -G (sum_s part_phi[s] - self term).
 __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     int precision, const double *__restrict__ box_mass, const IntBlock *__restrict__ blocks,
-    const double *__restrict__ part, const double *__restrict__ part_phi, int part_f32,
+    const double *__restrict__ part, const double *__restrict__ part_phi, int slot_mode,
     const double *__restrict__ x, const double *__restrict__ m, int64_t N, double G,
     double scale, ExtField ext, double inv_a3, double *__restrict__ acc,
     double *__restrict__ phi, const double *__restrict__ kick_p, double *__restrict__ kick_v,
@@ -530,7 +602,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     const bool lead = threadIdx.x < kIntBlock;
     const double mbox = box_mass_of(box_mass, blk.box);
     double g[3];
-    slot_sum<3>(part, part_f32, i, blk.n_slices, 3 * N, N, valid, shs, mbox, g);
+    slot_sum<3>(part, slot_mode, i, blk.n_slices, 3 * N, N, valid, shs, mbox, g);
     double f[3] = {0.0, 0.0, 0.0}, phe = 0.0;
     if (lead && valid)
         phe = ext_pull(ext, x[i], x[N + i], x[2 * N + i], blk.eps, f);
@@ -549,7 +621,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
     if (phi) {
         __syncthreads();
         double t[1];
-        slot_sum<1>(part_phi, part_f32, i, blk.n_slices, N, N, valid, shs, mbox, t);
+        slot_sum<1>(part_phi, slot_mode, i, blk.n_slices, N, N, valid, shs, mbox, t);
         if (lead && valid)
             phi[i] = -G * (t[0] - self_potential(precision, m[i], blk.eps, mbox)) + phe;
     }
@@ -557,7 +629,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void forces_finalize_kernel(
 
 // out[c] = G * sum_s part[s][c]  (part [S][n_cot][3][N]).
 __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
-    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int slot_mode,
     const double *__restrict__ box_mass, const double *__restrict__ x,
     const double *__restrict__ lam, ExtField ext, int64_t N, int n_cot, double G,
     double *__restrict__ out)
@@ -570,7 +642,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
     const double mbox = box_mass_of(box_mass, blk.box);
     for (int c = 0; c < n_cot; ++c) {
         double w[3];
-        slot_sum<3>(part, part_f32, (int64_t)c * 3 * N + i, blk.n_slices,
+        slot_sum<3>(part, slot_mode, (int64_t)c * 3 * N + i, blk.n_slices,
                     (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
         if (lead && valid) {
             double o[3] = {G * w[0], G * w[1], G * w[2]};
@@ -597,7 +669,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void vjp_finalize_kernel(
 
 // lam_x += cw * G sum_s part[s];  then (do_drift) lam_p += dnext * lam_x.
 __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
-    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int part_f32,
+    const IntBlock *__restrict__ blocks, const double *__restrict__ part, int slot_mode,
     const double *__restrict__ box_mass, const double *__restrict__ x, ExtField ext,
     double *__restrict__ att_acc, int64_t N, int n_cot, double G, double cw,
     double *__restrict__ lam_x, double *__restrict__ lam_p, int do_drift, double dnext)
@@ -612,7 +684,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void adjoint_update_kernel(
     const double mbox = box_mass_of(box_mass, blk.box);
     for (int c = 0; c < n_cot; ++c) {
         double w[3];
-        slot_sum<3>(part, part_f32, (int64_t)c * 3 * N + i, blk.n_slices,
+        slot_sum<3>(part, slot_mode, (int64_t)c * 3 * N + i, blk.n_slices,
                     (int64_t)n_cot * 3 * N, N, valid, shs, mbox, w);
         double gp[4] = {0.0, 0.0, 0.0, 0.0};
         if (lead && valid) {
@@ -682,7 +754,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void he_step_kernel(HEArgs A)
     const int64_t N = A.N;
     const double mbox = box_mass_of(A.box_mass, blk.box);
     double gs[3];
-    slot_sum<3>(A.part, A.part_f32, i, blk.n_slices, 3 * N, N, valid, shs, mbox, gs);
+    slot_sum<3>(A.part, A.slot_mode, i, blk.n_slices, 3 * N, N, valid, shs, mbox, gs);
     if (!(lead && valid))
         return;
     const StepCoef cf = A.coef[A.row];
@@ -746,7 +818,7 @@ __global__ void track_gather_kernel(const double *__restrict__ x, const double *
 
 __global__ __launch_bounds__(kFinalizeThreads) void state_diag_kernel(
     const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ m,
-    const double *__restrict__ part_phi, int part_f32, const IntBlock *__restrict__ blocks,
+    const double *__restrict__ part_phi, int slot_mode, const IntBlock *__restrict__ blocks,
     int n_blocks, int64_t N, double G, const StepCoef *__restrict__ coef, int64_t row,
     int precision, const double *__restrict__ box_mass, ExtField ext,
     double *__restrict__ diag_part)
@@ -759,7 +831,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void state_diag_kernel(
     const bool lead = threadIdx.x < kIntBlock;
     const double mbox = box_mass_of(box_mass, blk.box);
     double t[1];
-    slot_sum<1>(part_phi, part_f32, i, blk.n_slices, N, N, valid, shs, mbox, t);
+    slot_sum<1>(part_phi, slot_mode, i, blk.n_slices, N, N, valid, shs, mbox, t);
     double w[kDiagW];
     for (int q = 0; q < kDiagW; ++q)
         w[q] = 0.0;
@@ -879,35 +951,35 @@ hipError_t launch_diag_reduce(const double *diag_part, int rows, const IntBlock 
 
 hipError_t launch_forces_finalize(int precision, const double *box_mass, const IntBlock *blocks,
                                   int n_blocks, const double *part, const double *part_phi,
-                                  int part_f32, const double *x, const double *m, int64_t N,
+                                  int slot_mode, const double *x, const double *m, int64_t N,
                                   double G, double scale, const ExtField &ext, double inv_a3,
                                   double *acc, double *phi, hipStream_t stream,
                                   const double *kick_p, double *kick_v, const StepCoef *kick_coef)
 {
     hipLaunchKernelGGL(forces_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       precision, box_mass, blocks, part, part_phi, part_f32, x, m, N, G, scale,
+                       precision, box_mass, blocks, part, part_phi, slot_mode, x, m, N, G, scale,
                        ext, inv_a3, acc, phi, kick_p, kick_v, kick_coef);
     return hipGetLastError();
 }
 
 hipError_t launch_vjp_finalize(const IntBlock *blocks, int n_blocks, const double *part,
-                               int part_f32, const double *box_mass, const double *x,
+                               int slot_mode, const double *box_mass, const double *x,
                                const double *lam, const ExtField &ext, int64_t N, int n_cot,
                                double G, double *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(vjp_finalize_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, part_f32, box_mass, x, lam, ext, N, n_cot, G, out);
+                       blocks, part, slot_mode, box_mass, x, lam, ext, N, n_cot, G, out);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const double *part,
-                                 int part_f32, const double *box_mass, const double *x,
+                                 int slot_mode, const double *box_mass, const double *x,
                                  const ExtField &ext, double *att_acc, int64_t N, int n_cot,
                                  double G, double cw, double *lam_x, double *lam_p,
                                  int do_drift, double dnext, hipStream_t stream)
 {
     hipLaunchKernelGGL(adjoint_update_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream,
-                       blocks, part, part_f32, box_mass, x, ext, att_acc, N, n_cot, G, cw, lam_x,
+                       blocks, part, slot_mode, box_mass, x, ext, att_acc, N, n_cot, G, cw, lam_x,
                        lam_p, do_drift, dnext);
     return hipGetLastError();
 }
@@ -972,13 +1044,13 @@ hipError_t launch_he_step(const HEArgs &args, hipStream_t stream)
 }
 
 hipError_t launch_state_diag(const double *x, const double *v, const double *m,
-                             const double *part_phi, int part_f32, const IntBlock *blocks,
+                             const double *part_phi, int slot_mode, const IntBlock *blocks,
                              int n_blocks, int64_t N, double G, const StepCoef *coef,
                              int64_t row, int precision, const double *box_mass,
                              const ExtField &ext, double *diag_part, hipStream_t stream)
 {
     hipLaunchKernelGGL(state_diag_kernel, dim3(n_blocks), dim3(kFinalizeThreads), 0, stream, x,
-                       v, m, part_phi, part_f32, blocks, n_blocks, N, G, coef, row, precision,
+                       v, m, part_phi, slot_mode, blocks, n_blocks, N, G, coef, row, precision,
                        box_mass, ext, diag_part);
     return hipGetLastError();
 }

@@ -50,15 +50,6 @@ __device__ __forceinline__ double rsqrt_t(double s) { return rsqrt_refined(s); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 
-// hi + lo += v with the rounding error of hi + v carried into lo (TwoSum).
-__device__ __forceinline__ void two_sum_add(float &hi, float &lo, float v)
-{
-    float s = hi + v;
-    float bp = s - hi;
-    float err = (hi - (s - bp)) + (v - bp);
-    hi = s;
-    lo += err;
-}
 
 // Centre of the bounding box of the block's valid targets, for every thread.
 template <int TPB, int R>
