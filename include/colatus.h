@@ -80,6 +80,9 @@ extern "C" {
 #define COLATUS_EHIP       -5  /* a HIP runtime call failed                               */
 #define COLATUS_ENONFINITE -6  /* diagnostics found a NaN or Inf in the state             */
 
+#define COLATUS_ESCRATCH   -7  /* problem too large for the allocation-free entry point's
+                                  fixed scratch (colatus_forces_noalloc: N > 16384)      */
+
 /* ---- pair arithmetic --------------------------------------------------- */
 /* The FP32 forms evaluate each pair in FP32 on coordinates taken relative to
  * the centre of the target tile (FP64 subtraction, then rounding), sum the
@@ -326,6 +329,24 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m,
                     double *grad_attractor, int precision,
                     const colatus_batch *batch, const colatus_attractor *attractor,
                     const colatus_background *background, void *stream);
+
+/* colatus_forces without any allocation, for callers that cannot allocate
+ * device memory: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and results as colatus_forces with
+ * batch == NULL (one box); with the default options the two give the same
+ * bits.  The call allocates nothing and copies nothing from the host: its
+ * scratch (work items, blocks, the box's common mass, the partial-sum slots)
+ * is one fixed device array of about 33.7 MB, which every device the library
+ * runs on holds from the library's load until the process ends.  Limit:
+ * 1 <= N <= 16384 in every precision (N > 16384: COLATUS_ESCRATCH, nothing
+ * queued).  Every call on a device shares that device's array, which keeps
+ * the last call's contents: calls that overlap in time on one device (other
+ * streams, other host threads) race and give undefined results; calls on
+ * one stream are ordered and safe.                                          */
+int colatus_forces_noalloc(const double *x, const double *m, int64_t N, double eps,
+                           double G, double a, int precision, double *acc, double *phi,
+                           const colatus_attractor *attractor,
+                           const colatus_background *background, void *stream);
 
 /* Transpose-Jacobian product of the comoving sum g (Eq. (1) without a^-3,
  * plus the Eq. (10) attractor's field and the Eq. (6) background term when

@@ -35,7 +35,7 @@ OPT_PAIR_FORM = 8
 OPT_ROCTX = 9
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EFRIEDMANN", -3: "ENODEV", -4: "ENOMEM", -5: "EHIP",
-          -6: "ENONFINITE"}
+          -6: "ENONFINITE", -7: "ESCRATCH"}
 
 # Every symbol include/colatus.h declares, with its ctypes signature.
 _d, _i64, _i32, _i, _p = (ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
@@ -51,6 +51,7 @@ SIGNATURES = {
     "colatus_velocity_spectrum": (_i, [_p, _i64, _i32, _i, _p, _p]),
     "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                              _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p, _p]),
+    "colatus_forces_noalloc": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p, _p]),
     "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p, _p]),
     "colatus_hubble": (_i, [_d, _d, _d, _d, _d, _d, ctypes.POINTER(_d)]),
     "colatus_strerror": (ctypes.c_char_p, [_i]),

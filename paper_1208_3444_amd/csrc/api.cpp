@@ -1237,6 +1237,8 @@ const char *colatus_strerror(int code)
     case COLATUS_ENOMEM: return "device memory allocation failed";
     case COLATUS_EHIP: return "HIP runtime error";
     case COLATUS_ENONFINITE: return "non-finite value in the state";
+    case COLATUS_ESCRATCH:
+        return "problem too large for the fixed scratch of the allocation-free entry point";
     default: return "unknown error code";
     }
 }

@@ -1,0 +1,194 @@
+// colatus_forces_noalloc: the pair sum of colatus_forces for callers that
+// cannot allocate device memory (work under stream capture, serving loops,
+// harnesses that forbid hipMalloc).  Every scratch byte the call needs (the
+// work items, the O(N) blocks, the box's common mass, the partial-sum slots)
+// lives in one file-scope device array; the items and blocks are generated
+// on the device, so the call makes no allocation and no host-to-device copy.
+//
+// It runs the kernels of colatus_forces with the built-in tile shape (the
+// symmetric form: parts of 256 particles, four targets per lane), so with
+// the default options the two entry points give the same bits.
+#include "colatus.h"
+#include "colatus_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+
+namespace colatus {
+namespace {
+
+// Largest N the scratch holds, for every precision, with the potential.
+constexpr int64_t kNoAllocMaxN = 16384;
+constexpr int64_t kPart = 256;   // particles per part (4 targets x 64 lanes)
+constexpr int64_t kPiece = 64;   // targets per piece of a diagonal part
+constexpr int64_t kMaxParts = kNoAllocMaxN / kPart;
+constexpr int64_t kMaxItems = kMaxParts * (kMaxParts - 1) / 2 + kMaxParts * (kPart / kPiece);
+constexpr int64_t kMaxBlocks = kNoAllocMaxN / kIntBlock;
+
+constexpr size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+// Byte offsets of the regions of the scratch array.
+constexpr size_t kOffCounter = 0;    // int: pair-sweep work counter
+constexpr size_t kOffOffsets = 256;  // int64[2]: box offsets {0, N}
+constexpr size_t kOffBoxMass = 512;  // double: the box's common mass or NaN
+constexpr size_t kOffBlocks = 768;   // IntBlock[kMaxBlocks]
+constexpr size_t kOffItems = kOffBlocks + round256(kMaxBlocks * sizeof(IntBlock));
+constexpr size_t kOffPart = kOffItems + round256(kMaxItems * sizeof(WorkItem));
+constexpr size_t kPartBytes = (size_t)kMaxParts * 3 * kNoAllocMaxN * sizeof(double);
+constexpr size_t kOffPhi = kOffPart + kPartBytes;
+constexpr size_t kPhiBytes = (size_t)kMaxParts * kNoAllocMaxN * sizeof(double);
+constexpr size_t kScratchBytes = kOffPhi + kPhiBytes;  // about 33.7 MB
+
+// The scratch array: one copy per device, held until the process ends.  Host
+// code never passes this name to a kernel (on the host it is only a handle);
+// it uses the device address hipGetSymbolAddress returns for the current
+// device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_na_mu;
+unsigned char *g_na_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on device `dev` (current), looked up
+// once per device.
+int scratch_address(int dev, unsigned char *&out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return COLATUS_ENODEV;
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return COLATUS_EHIP;
+        g_na_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    out = g_na_ptr[dev];
+    return COLATUS_OK;
+}
+
+// Work items and blocks of one box [0, N) in the symmetric form, written by
+// one thread each: items [0, n_pairs) pair part p (targets, slot q) with part
+// q > p (sources, reaction in slot p), in row order of the (p, q) triangle;
+// items [n_pairs, n_items) are the 64-target pieces of the diagonal parts
+// (part j / 4, piece j % 4: every part but the last has four).  Also the box
+// offsets and the cleared work counter.  The order of the items does not
+// change the result (each writes its own slots).
+__global__ void noalloc_setup_kernel(int64_t N, double eps, int P, int n_pairs, int n_items,
+                                     int n_blocks, WorkItem *__restrict__ items,
+                                     IntBlock *__restrict__ blocks, int64_t *__restrict__ offsets,
+                                     int *__restrict__ counter)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t == 0) {
+        offsets[0] = 0;
+        offsets[1] = N;
+        *counter = 0;
+    }
+    if (t < n_items) {
+        WorkItem w{};
+        w.eps2 = eps * eps;
+        w.box = 0;
+        if (t < n_pairs) {
+            int k = t, p = 0;
+            while (k >= P - 1 - p) {
+                k -= P - 1 - p;
+                ++p;
+            }
+            const int q = p + 1 + k;
+            w.i0 = (int64_t)p * kPart;
+            w.i1 = min(w.i0 + kPart, N);
+            w.j0 = (int64_t)q * kPart;
+            w.j1 = min(w.j0 + kPart, N);
+            w.slice = q;
+            w.rslice = p;
+            w.kind = 0;
+        } else {
+            const int j = t - n_pairs, p = j / (int)(kPart / kPiece), i = j % (int)(kPart / kPiece);
+            const int64_t p0 = (int64_t)p * kPart, p1 = min(p0 + kPart, N);
+            w.i0 = p0 + (int64_t)i * kPiece;
+            w.i1 = min(w.i0 + kPiece, p1);
+            w.j0 = p0;
+            w.j1 = p1;
+            w.slice = p;
+            w.rslice = p;
+            w.kind = 1;
+        }
+        items[t] = w;
+    }
+    if (t < n_blocks) {
+        IntBlock b;
+        b.i0 = (int64_t)t * kIntBlock;
+        b.i1 = min(b.i0 + kIntBlock, N);
+        b.eps = eps;
+        b.box = 0;
+        b.n_slices = P;
+        blocks[t] = b;
+    }
+}
+
+}  // namespace
+}  // namespace colatus
+
+using namespace colatus;
+
+extern "C" int colatus_forces_noalloc(const double *x, const double *m, int64_t N, double eps,
+                                      double G, double a, int precision, double *acc,
+                                      double *phi, const colatus_attractor *attractor,
+                                      const colatus_background *background, void *stream)
+{
+    if (N < 1 || precision < COLATUS_FP64 || precision > COLATUS_FP32 || !std::isfinite(G) ||
+        !std::isfinite(a) || a <= 0.0 || !std::isfinite(eps) || eps < 0.0)
+        return COLATUS_EINVAL;
+    if (N > kNoAllocMaxN)
+        return COLATUS_ESCRATCH;
+    if (!x || !m || !acc)
+        return COLATUS_EINVAL;
+    ExtField ext;
+    if (resolve_external(attractor, background, ext) != COLATUS_OK)
+        return COLATUS_EINVAL;
+    int dev = 0;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1 || hipGetDevice(&dev) != hipSuccess)
+        return COLATUS_ENODEV;
+    unsigned char *base = nullptr;
+    const int rc = scratch_address(dev, base);
+    if (rc != COLATUS_OK)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    int *counter = reinterpret_cast<int *>(base + kOffCounter);
+    int64_t *offsets = reinterpret_cast<int64_t *>(base + kOffOffsets);
+    double *box_mass = reinterpret_cast<double *>(base + kOffBoxMass);
+    IntBlock *blocks = reinterpret_cast<IntBlock *>(base + kOffBlocks);
+    WorkItem *items = reinterpret_cast<WorkItem *>(base + kOffItems);
+    double *part = reinterpret_cast<double *>(base + kOffPart);
+    double *part_phi = reinterpret_cast<double *>(base + kOffPhi);
+
+    const int P = (int)((N + kPart - 1) / kPart);
+    const int n_pairs = P * (P - 1) / 2;
+    const int64_t last_len = N - (int64_t)(P - 1) * kPart;
+    const int n_pieces = (P - 1) * (int)(kPart / kPiece) + (int)((last_len + kPiece - 1) / kPiece);
+    const int n_items = n_pairs + n_pieces;
+    const int n_blocks = (int)((N + kIntBlock - 1) / kIntBlock);
+    const int n_setup = n_items > n_blocks ? n_items : n_blocks;
+    hipLaunchKernelGGL(noalloc_setup_kernel, dim3((unsigned)((n_setup + 255) / 256)), dim3(256),
+                       0, s, N, eps, P, n_pairs, n_items, n_blocks, items, blocks, offsets,
+                       counter);
+    if (hipGetLastError() != hipSuccess)
+        return COLATUS_EHIP;
+    if (launch_box_mass(m, offsets, 1, N, box_mass, s) != hipSuccess)
+        return COLATUS_EHIP;
+    const TileCfg cfg{4, 64, P, 2};
+    if (launch_pair_sweep(precision, cfg.form, cfg, phi != nullptr, eps == 0.0, x, m, N, items,
+                          n_items, counter, false, box_mass, part, phi ? part_phi : nullptr,
+                          nullptr, s) != hipSuccess)
+        return COLATUS_EHIP;
+    if (launch_forces_finalize(precision, box_mass, blocks, n_blocks, part,
+                               phi ? part_phi : nullptr, slot_mode_for(cfg, precision), x, m, N,
+                               G, G / (a * a * a), ext, 1.0 / (a * a * a), acc, phi,
+                               s) != hipSuccess)
+        return COLATUS_EHIP;
+    return COLATUS_OK;
+}

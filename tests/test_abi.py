@@ -59,7 +59,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_strerror_and_version():
     L = colatus.lib()
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.colatus_strerror(code)
     assert L.colatus_strerror(-99) == b"unknown error code"
     assert L.colatus_version() == 10400
@@ -284,3 +284,26 @@ def test_valid_call_without_device_is_enodev():
     L = colatus.lib()
     assert L.colatus_forces(FAKE, FAKE, 16, 0.01, 1.0, 1.0, 0, FAKE, None, None, None,
                             None, None) == ENODEV
+
+
+def test_forces_noalloc_rejects_bad_arguments_on_host():
+    """The allocation-free pair sum checks its arguments before any HIP call;
+    N beyond its fixed scratch is COLATUS_ESCRATCH."""
+    L = colatus.lib()
+    f = L.colatus_forces_noalloc
+
+    def call(N=16, eps=0.01, G=1.0, a=1.0, prec=0, x=FAKE, m=FAKE, acc=FAKE):
+        return f(x, m, N, eps, G, a, prec, acc, None, None, None, None)
+
+    assert call(N=16385) == -7
+    assert call(N=(1 << 28)) == -7
+    assert b"too large" in L.colatus_strerror(-7)
+    assert call(N=0) == EINVAL
+    assert call(eps=-1.0) == EINVAL
+    assert call(eps=float("nan")) == EINVAL
+    assert call(a=0.0) == EINVAL
+    assert call(G=float("inf")) == EINVAL
+    assert call(prec=4) == EINVAL
+    assert call(x=None) == EINVAL
+    assert call(acc=None) == EINVAL
+
