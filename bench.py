@@ -422,7 +422,9 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
                                          wa.a_end, wa.n_steps, tr,
                                          checkpoint_every=wa.extra["checkpoint_every"],
                                          precision=args.precision)
+        torch.cuda.synchronize()
         t = time.perf_counter() - t0
+        lam_lna = lam_lna.cpu().numpy()
         out["ftle_192_cotangents"] = {"seconds": t, "tracers": len(tr),
                                       "lambda_per_ln_a_median": float(np.median(lam_lna)),
                                       "lambda_per_ln_a_max": float(np.max(lam_lna))}

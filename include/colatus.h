@@ -79,7 +79,6 @@ extern "C" {
 #define COLATUS_ENOMEM     -4  /* device scratch allocation failed                        */
 #define COLATUS_EHIP       -5  /* a HIP runtime call failed                               */
 #define COLATUS_ENONFINITE -6  /* diagnostics found a NaN or Inf in the state             */
-
 #define COLATUS_ESCRATCH   -7  /* problem too large for the allocation-free entry point's
                                   fixed scratch (colatus_forces_noalloc: N > 16384)      */
 
@@ -312,8 +311,9 @@ int colatus_velocity_spectrum(const double *track, int64_t rows, int32_t n_trace
  *   (J^T lam)_k = G sum_{j != k} M(d)(m_k lam_j - m_j lam_k),
  *   M(d) = r^-3 I - 3 r^-5 d d^T,  d = x_j - x_k,
  * is evaluated by its own O(N^2) pair sweep in the given precision, once
- * per step for all cotangents together.  1 <= n_cot <= 4096; batch must be
- * NULL (single box).
+ * per step for all cotangents together.  1 <= n_cot <= 4096.  batch: see
+ * colatus_batch, or NULL (the boxes do not interact, so each box's
+ * cotangents move only its own particles' gradients).
  * With an attractor (Eq. (10), or NULL) the run is the attractor's run; its
  * transpose Jacobian -S M(d) (d = x_psi - x_k) joins the pair sum's, and
  * grad_attractor ([n_cot][4] device, or NULL; requires an attractor)
@@ -347,6 +347,44 @@ int colatus_forces_noalloc(const double *x, const double *m, int64_t N, double e
                            double G, double a, int precision, double *acc, double *phi,
                            const colatus_attractor *attractor,
                            const colatus_background *background, void *stream);
+
+/* Finite-time Lyapunov exponents of tracer particles, the measure of the
+ * chaotic advection that Sections I and IV motivate the method with.  For
+ * tracer t (HOST array tracers[n_tracers] of particle indices, global with a
+ * batch), the 3x3 block B_t = d x_t(a_end) / d x_t(a_begin) of the run's
+ * flow map is read off the discrete adjoint of colatus_run [0, n_steps)
+ * seeded with the unit vectors on x_t(a_end) (3 cotangents per tracer, all
+ * tracers in one adjoint pass); then, in the library, in FP64:
+ *   sigma_t = largest singular value of B_t (square root of the largest
+ *             eigenvalue of B_t^T B_t, cyclic Jacobi rotations),
+ *   lambda_t[t]   = ln sigma_t / (t(a_end) - t(a_begin)),
+ *   lambda_lna[t] = ln sigma_t / ln(a_end / a_begin)   (NaN if H0 == 0),
+ *   blocks[t][i][j] = (B_t)_{ij}.
+ * The cosmic time span is the sum of the run's step times in grid order
+ * (what the diagnostics' t reports; a_end itself in the static limit).
+ *   lambda_t: DEVICE [n_tracers], written; lambda_lna, blocks: DEVICE
+ *   [n_tracers] and [n_tracers][3][3], or NULL.
+ * Other arguments, precision, checkpointing and the external terms as in
+ * colatus_adjoint.  1 <= n_tracers <= 1365 and every index in [0, N), else
+ * COLATUS_EINVAL.  Device scratch: the adjoint's, with 3 n_tracers
+ * cotangents (about 0.45 GB at N = 32768 and 64 tracers).                  */
+int colatus_ftle(const double *x0, const double *v0, const double *m, int64_t N,
+                 double eps, double G, double H0, double Om_R, double Om_M,
+                 double Om_K, double Om_L, double a_begin, double a_end, int64_t n_steps,
+                 int64_t checkpoint_every, int32_t n_tracers, const int64_t *tracers,
+                 double *lambda_t, double *lambda_lna, double *blocks, int precision,
+                 const colatus_batch *batch, const colatus_attractor *attractor,
+                 const colatus_background *background, void *stream);
+
+/* Cosmic time elapsed over the grid of colatus_run, t(a_end) - t(a_begin) =
+ * sum over steps of int dt (Eq. (2), Gauss-Legendre in ln a per step, the
+ * same arithmetic as the run's coefficients), summed in grid order: the
+ * value the last diagnostics row's t holds after a full run.  Static limit
+ * H0 == 0: a_end (the elapsed time as given).  *t: HOST, written.  The call
+ * synchronises the stream.  Arguments as colatus_run.                      */
+int colatus_cosmic_time(double a_begin, double a_end, int64_t n_steps, double H0,
+                        double Om_R, double Om_M, double Om_K, double Om_L, double *t,
+                        void *stream);
 
 /* Transpose-Jacobian product of the comoving sum g (Eq. (1) without a^-3,
  * plus the Eq. (10) attractor's field and the Eq. (6) background term when

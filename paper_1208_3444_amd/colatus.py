@@ -52,6 +52,9 @@ SIGNATURES = {
     "colatus_adjoint": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                              _i32, _p, _p, _p, _p, _p, _p, _p, _i, _p, _p, _p, _p]),
     "colatus_forces_noalloc": (_i, [_p, _p, _i64, _d, _d, _d, _i, _p, _p, _p, _p, _p]),
+    "colatus_ftle": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
+                          _i32, _p, _p, _p, _p, _i, _p, _p, _p, _p]),
+    "colatus_cosmic_time": (_i, [_d, _d, _i64, _d, _d, _d, _d, _d, ctypes.POINTER(_d), _p]),
     "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p, _p]),
     "colatus_hubble": (_i, [_d, _d, _d, _d, _d, _d, ctypes.POINTER(_d)]),
     "colatus_strerror": (ctypes.c_char_p, [_i]),
@@ -355,7 +358,7 @@ def force_vjp(x, m, lam, eps, G=1.0, precision="mixed_twosum", attractor=None,
 
 def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
             checkpoint_every=-1, precision="mixed_twosum", return_state=False,
-            attractor=None, background=None):
+            attractor=None, background=None, batch=None):
     """Gradients of <lam_xN, x_N> + <lam_vN, v_N> with respect to (x_0, v_0).
 
     lam_xN, lam_vN: (3, N) or (C, 3, N).  Returns (grad_x0, grad_v0) shaped
@@ -364,10 +367,11 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
     every position (24 B per particle and step) and recomputes nothing.  With an attractor
     (S, (x, y, z)) (Eq. (10)) the run includes it and the gradient with
     respect to (S, x_psi) is appended: (4,) or (C, 4).  background: the
-    Eq. (6) term (b, (cx, cy, cz)) of the run, or None.
+    Eq. (6) term (b, (cx, cy, cz)) of the run, or None.  batch: as in run().
     """
     N = m.shape[0]
     px, pv, pm = _dev(x0, "x0", (3, N)), _dev(v0, "v0", (3, N)), _dev(m, "m", (N,))
+    b, keep = _batch(batch)
     C = 1 if lam_xN.dim() == 2 else lam_xN.shape[0]
     shp = (3, N) if lam_xN.dim() == 2 else (C, 3, N)
     plx, plv = _dev(lam_xN, "lam_xN", shp), _dev(lam_vN, "lam_vN", shp)
@@ -381,14 +385,15 @@ def adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_xN, lam_vN,
         ga = torch.empty((4,) if lam_xN.dim() == 2 else (C, 4), dtype=torch.float64,
                          device=x0.device)
     rc = lib().colatus_adjoint(
-        px, pv, pm, N, float(eps), float(G), *_cosmo(cosmo), float(a_begin), float(a_end),
+        px, pv, pm, N, float(eps) if batch is None else 0.0, float(G), *_cosmo(cosmo),
+        float(a_begin), float(a_end),
         int(n_steps), int(checkpoint_every), C, plx, plv, ctypes.c_void_p(gx.data_ptr()),
         ctypes.c_void_p(gv.data_ptr()),
         ctypes.c_void_p(xN.data_ptr()) if return_state else None,
         ctypes.c_void_p(vN.data_ptr()) if return_state else None,
         ctypes.c_void_p(ga.data_ptr()) if ga is not None else None,
-        _prec(precision), None, pa, pb, _stream(x0))
-    del keep_a, keep_b
+        _prec(precision), ctypes.byref(b) if b is not None else None, pa, pb, _stream(x0))
+    del keep, keep_a, keep_b
     _check("colatus_adjoint", rc)
     out = (gx, gv) + ((xN, vN) if return_state else ())
     if ga is not None:
@@ -431,46 +436,47 @@ class ColatusRun(torch.autograd.Function):
 
 
 def ftle(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, tracers, checkpoint_every=-1,
-         precision="mixed_twosum", attractor=None, background=None):
-    """Finite-time Lyapunov exponents of tracer particles.
+         precision="mixed_twosum", attractor=None, background=None, batch=None):
+    """Finite-time Lyapunov exponents of tracer particles (colatus_ftle).
 
-    The 3x3 block d x_t(a_end) / d x_t(a_begin) of each tracer is read off
-    3 reverse sweeps (cotangents e_i on x_t(a_end)), all tracers batched in
-    one adjoint call; lambda_t = ln sigma_max / elapsed cosmic time, with the
-    elapsed time from the library's coefficient integrals.  Returns
-    (lambda per unit cosmic time, lambda per unit ln a, blocks (T, 3, 3)).
+    The library reads the 3x3 block d x_t(a_end) / d x_t(a_begin) of each
+    tracer off one adjoint pass (3 unit cotangents per tracer) and takes
+    ln sigma_max over the elapsed cosmic time and over ln(a_end / a_begin).
+    Returns device tensors (lambda per unit cosmic time (T,), lambda per unit
+    ln a (T,), blocks (T, 3, 3)).
     """
-    import math
     import numpy as np
     N = m.shape[0]
-    T = len(tracers)
-    lam_x = torch.zeros((3 * T, 3, N), dtype=torch.float64, device=x0.device)
-    for ti, t in enumerate(tracers):
-        for i in range(3):
-            lam_x[3 * ti + i, i, int(t)] = 1.0
-    lam_v = torch.zeros_like(lam_x)
-    gx = adjoint(x0, v0, m, eps, G, cosmo, a_begin, a_end, n_steps, lam_x, lam_v,
-                 checkpoint_every=checkpoint_every, precision=precision, attractor=attractor,
-                 background=background)[0]
-    g = gx.cpu().numpy()
-    phi = np.empty((T, 3, 3))
-    for ti, t in enumerate(tracers):
-        for i in range(3):
-            phi[ti, i, :] = g[3 * ti + i, :, int(t)]
-    smax = np.linalg.svd(phi, compute_uv=False)[:, 0]
-    span_t = elapsed_time(cosmo, a_begin, a_end, n_steps, x0.device)
-    span_lna = math.log(a_end / a_begin) if cosmo["H0"] != 0 else float("nan")
-    lam = np.log(smax)
-    return lam / span_t, lam / span_lna, phi
+    px, pv, pm = _dev(x0, "x0", (3, N)), _dev(v0, "v0", (3, N)), _dev(m, "m", (N,))
+    idx = np.ascontiguousarray(np.asarray(tracers, dtype=np.int64).reshape(-1))
+    T = int(idx.size)
+    lam_t = torch.empty(T, dtype=torch.float64, device=x0.device)
+    lam_lna = torch.empty_like(lam_t)
+    blocks = torch.empty((T, 3, 3), dtype=torch.float64, device=x0.device)
+    b, keep = _batch(batch)
+    pa, keep_a = _attractor(attractor)
+    pb, keep_b = _background(background)
+    rc = lib().colatus_ftle(
+        px, pv, pm, N, float(eps) if batch is None else 0.0, float(G), *_cosmo(cosmo),
+        float(a_begin), float(a_end), int(n_steps), int(checkpoint_every), T,
+        idx.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(lam_t.data_ptr()),
+        ctypes.c_void_p(lam_lna.data_ptr()), ctypes.c_void_p(blocks.data_ptr()),
+        _prec(precision), ctypes.byref(b) if b is not None else None, pa, pb, _stream(x0))
+    del keep, keep_a, keep_b, idx
+    _check("colatus_ftle", rc)
+    return lam_t, lam_lna, blocks
 
 
-def elapsed_time(cosmo, a_begin, a_end, n_steps, device):
-    """Cosmic time from a_begin to a_end, from a 2-particle diagnostic run."""
-    x = torch.tensor([[0.0, 100.0], [0.0, 0.0], [0.0, 0.0]], dtype=torch.float64, device=device)
-    v = torch.zeros_like(x)
-    m = torch.zeros(2, dtype=torch.float64, device=device)
-    d = run(x, v, m, 1.0, 0.0, cosmo, a_begin, a_end, n_steps, precision="fp64", diag=True)
-    return float(d["t"][-1])
+def cosmic_time(cosmo, a_begin, a_end, n_steps, device=None):
+    """Cosmic time elapsed over the run's grid (colatus_cosmic_time): the sum
+    of the steps' Friedmann time integrals, as the diagnostics' t reports."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = ctypes.c_double()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check("colatus_cosmic_time",
+           lib().colatus_cosmic_time(float(a_begin), float(a_end), int(n_steps), *_cosmo(cosmo),
+                                     ctypes.byref(out), stream))
+    return out.value
 
 
 def hubble(a, cosmo):

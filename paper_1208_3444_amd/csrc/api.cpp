@@ -205,7 +205,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
-        box_mass, att_acc, he_x, track_idx, track_slot, twiddle;
+        box_mass, att_acc, he_x, track_idx, track_slot, twiddle, ftle_idx;
     // work lists by (N, boxes, softenings, tile shape); fwd / adj: the lists
     // selected by the current call's forward and adjoint set-up
     std::vector<WorkList *> lists;
@@ -214,12 +214,14 @@ struct Workspace {
     uint64_t clock = 0;
     std::vector<int64_t> track_host;  // tracer list being uploaded
     hipEvent_t track_ev = nullptr;    // recorded after its upload
+    std::vector<int64_t> ftle_host;   // FTLE tracer list being uploaded
+    hipEvent_t ftle_ev = nullptr;     // recorded after its upload
     // every device allocation the workspace owns, work lists aside
     std::vector<Buffer *> buffers()
     {
         return {&part,     &part_phi,   &coef,  &p,        &diag_part,  &diag_out,
                 &counters, &lam_x,      &lam_p, &ckpt,     &seg,        &box_mass,
-                &att_acc,  &he_x,       &track_idx, &track_slot, &twiddle};
+                &att_acc,  &he_x,       &track_idx, &track_slot, &twiddle, &ftle_idx};
     }
 };
 
@@ -1220,6 +1222,223 @@ int resolve_external(const colatus_attractor *a, const colatus_background *bg, E
 
 }  // namespace colatus
 
+namespace {
+
+// The discrete adjoint of a kick-drift-kick run (colatus_adjoint and
+// colatus_ftle), on the calling entry point's workspace, lock held.
+struct AdjointParams {
+    const double *x0, *v0, *m;
+    int64_t N;
+    double G, H0, OmR, OmM, OmK, OmL, a_begin, a_end;
+    int64_t n_steps, checkpoint_every;
+    int32_t n_cot;
+    const double *lam_xN, *lam_vN;  // the caller's cotangents, or lam_xN null:
+    const int64_t *seed_idx;        // unit cotangents e_i on x of these
+                                    // n_cot / 3 particles (device), none on v
+    double *grad_x0, *grad_v0;      // outputs, or null (left in lam_x / lam_p)
+    double *xN, *vN, *grad_attractor;
+    int precision;
+    ExtField ext;
+    hipStream_t stream;
+    std::vector<StepCoef> *coef_host;  // receives the coefficient table, or null
+};
+
+int adjoint_impl(Workspace *ws, const AdjointParams &P, const Boxes &b)
+{
+    const double *x0 = P.x0, *v0 = P.v0, *m = P.m, *lam_xN = P.lam_xN, *lam_vN = P.lam_vN;
+    const int64_t N = P.N, n_steps = P.n_steps;
+    int64_t checkpoint_every = P.checkpoint_every;
+    const int32_t n_cot = P.n_cot;
+    const double G = P.G;
+    double *grad_x0 = P.grad_x0, *grad_v0 = P.grad_v0, *xN = P.xN, *vN = P.vN,
+           *grad_attractor = P.grad_attractor;
+    const int precision = P.precision;
+    const ExtField &ext = P.ext;
+    hipStream_t s = P.stream;
+    bool mask = false;
+    for (double e : b.eps)
+        mask = mask || e == 0.0;
+    CHECK_RC(prepare_worklist(ws, 0, b, N, precision, x0, m, 1, s));
+    CHECK_RC(prepare_worklist(ws, 1, b, N, precision, x0, m, n_cot, s));
+    const WorkList &wf = *ws->fwd;
+    const WorkList &wa = *ws->adj;
+    CHECK_RC(prepare_box_mass(ws, wf, m, s));
+    const size_t n3 = 3 * (size_t)N;
+    if (checkpoint_every < 0) {
+        // automatic: every position when they take at most a quarter of the
+        // free device memory, else segments of ceil(sqrt(n_steps)) steps
+        // (the least checkpoint + segment memory; the compute is the same for
+        // every segment length)
+        size_t free_b = 0, total_b = 0;
+        CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
+        const double need = (double)(n_steps + 1) * (double)n3 * sizeof(double);
+        checkpoint_every = need <= 0.25 * (double)free_b
+                               ? 0
+                               : (int64_t)std::ceil(std::sqrt((double)n_steps));
+    }
+    // checkpoint_every == 0: every position of the forward run is kept (one
+    // segment spanning the run, filled by the forward pass itself)
+    const bool keep_all = checkpoint_every == 0;
+    const int64_t K = keep_all ? n_steps : checkpoint_every;
+    const int64_t n_seg = (n_steps + K - 1) / K;
+    CHECK_RC(ensure(ws->coef, (size_t)n_steps * sizeof(StepCoef)));
+    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
+    const size_t part_fwd = (size_t)wf.max_slices * n3;
+    const size_t part_adj = (size_t)wa.max_slices * n3 * (size_t)n_cot;
+    CHECK_RC(ensure(ws->part, std::max(part_fwd, part_adj) * sizeof(double)));
+    CHECK_RC(ensure(ws->lam_x, (size_t)n_cot * n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->lam_p, (size_t)n_cot * n3 * sizeof(double)));
+    // checkpoints: (x, p) at n = 0, K, 2K, ... ; segment states: K + 1 positions
+    CHECK_RC(ensure(ws->ckpt, (size_t)n_seg * 2 * n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->seg, (size_t)(K + 1) * n3 * sizeof(double)));
+
+    StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
+    double *p = static_cast<double *>(ws->p.ptr);
+    double *ck = static_cast<double *>(ws->ckpt.ptr);
+    double *seg = static_cast<double *>(ws->seg.ptr);
+    double *lx = static_cast<double *>(ws->lam_x.ptr);
+    double *lp = static_cast<double *>(ws->lam_p.ptr);
+    // the working position buffer is the first segment slot
+    double *xw = seg;
+
+    CHECK_HIP(launch_coefficients(P.H0, P.OmR, P.OmM, P.OmK, P.OmL, P.a_begin, P.a_end, n_steps, 0,
+                                  n_steps, 0, coef, s));
+    std::vector<StepCoef> hc((size_t)n_steps);
+    CHECK_HIP(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(StepCoef), hipMemcpyDeviceToHost,
+                             s));
+    CHECK_HIP(hipStreamSynchronize(s));
+
+    IntegrateArgs A;
+    A.p = p;
+    A.m = m;
+    A.part = static_cast<const double *>(ws->part.ptr);
+    A.part_phi = nullptr;
+    A.blocks = static_cast<const IntBlock *>(wf.d_blocks.ptr);
+    A.n_blocks = (int)wf.blocks.size();
+    A.N = N;
+    A.G = G;
+    A.coef = coef;
+    A.step = step_counter(ws);
+    A.work_counter = work_counter(ws);
+    A.diag_part = nullptr;
+    A.precision = precision;
+    A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
+    A.slot_mode = slot_mode_of(wf, precision);
+    A.ext = ext;
+    // per-block accumulators of the attractor's parameter derivatives
+    double *acc_att = nullptr;
+    const int n_ablk = (int)wa.blocks.size();
+    if (grad_attractor) {
+        const size_t n_acc = (size_t)n_ablk * (size_t)n_cot * 4;
+        CHECK_RC(ensure(ws->att_acc, n_acc * sizeof(double)));
+        acc_att = static_cast<double *>(ws->att_acc.ptr);
+        CHECK_HIP(launch_fill(acc_att, (int64_t)n_acc, 0.0, s));
+    }
+
+    // ---- forward with checkpoints --------------------------------------
+    CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CHECK_HIP(launch_convert(0, v0, p, N, coef, 0, s));
+    CHECK_RC(set_step(ws, 0, 0, n_steps, s));
+    A.x = xw;
+    for (int64_t n = 0; n < n_steps; ++n) {
+        TraceRange step("adjoint forward step");
+        if (keep_all) {
+            // x_n stays in slot n; the step writes x_{n+1} into slot n + 1
+            double *xs = seg + (size_t)n * n3;
+            double *xn = xs + n3;
+            CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
+            CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            A.x = xn;
+            CHECK_HIP(launch_integrate(A, s));
+            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+            continue;
+        }
+        CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
+        if (n % K == 0) {
+            double *cx = ck + (size_t)(n / K) * 2 * n3;
+            CHECK_HIP(hipMemcpyAsync(cx, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            CHECK_HIP(hipMemcpyAsync(cx + n3, p, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        CHECK_HIP(launch_integrate(A, s));
+        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+    }
+    if (keep_all)
+        xw = seg + (size_t)n_steps * n3;  // x_N
+    if (xN || vN) {
+        CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
+        A.x = xw;
+        CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_end
+        if (xN)
+            CHECK_HIP(hipMemcpyAsync(xN, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (vN)
+            CHECK_HIP(launch_convert(1, p, vN, N, coef, n_steps - 1, s));
+    }
+
+    // ---- reverse sweep ---------------------------------------------------
+    const double aN = hc[(size_t)n_steps - 1].a1, a0 = hc[0].a0;
+    if (lam_xN) {
+        CHECK_HIP(hipMemcpyAsync(lx, lam_xN, (size_t)n_cot * n3 * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+        CHECK_HIP(launch_scale(lam_vN, lp, (int64_t)n_cot * (int64_t)n3, 1.0 / (aN * aN), s));
+    } else {
+        // unit cotangents on the tracers' final positions, none on velocities
+        CHECK_HIP(launch_fill(lp, (int64_t)n_cot * (int64_t)n3, 0.0, s));
+        CHECK_HIP(launch_ftle_seed(lx, (int64_t)n_cot * (int64_t)n3, P.seed_idx, n_cot / 3, N,
+                                   s));
+    }
+    for (int64_t sg = n_seg - 1; sg >= 0; --sg) {
+        const int64_t lo = sg * K, hi = std::min(lo + K, n_steps);
+        // recompute positions x_lo .. x_hi from the checkpoint (bitwise: same
+        // kernels), unless the forward pass kept them all
+        const double *cx = ck + (size_t)sg * 2 * n3;
+        if (!keep_all) {
+            CHECK_HIP(hipMemcpyAsync(seg, cx, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            CHECK_HIP(hipMemcpyAsync(p, cx + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            CHECK_RC(set_step(ws, lo, 0, n_steps, s));
+        }
+        for (int64_t n = lo; n < hi && !keep_all; ++n) {
+            double *xs = seg + (size_t)(n - lo) * n3;
+            double *xn = seg + (size_t)(n - lo + 1) * n3;
+            CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
+            CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            IntegrateArgs B = A;
+            B.x = xn;
+            CHECK_HIP(launch_integrate(B, s));
+            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
+        }
+        // visit x_n for n = hi .. lo+1 (and lo itself in segment 0): every grid
+        // point is visited once, x_hi being the unvisited bottom of the segment above
+        const int64_t top = hi;
+        const int64_t bottom = (sg == 0) ? lo : lo + 1;
+        for (int64_t n = top; n >= bottom; --n) {
+            TraceRange step("adjoint reverse step");
+            const double *xs = seg + (size_t)(n - lo) * n3;
+            CHECK_RC(run_adjoint_sweep(ws, wa, precision, mask, xs, m, N, n_cot, lp, s));
+            const double cw = (n < n_steps ? hc[(size_t)n].k1 : 0.0) +
+                              (n > 0 ? hc[(size_t)n - 1].k2 : 0.0);
+            const double dnext = n > 0 ? hc[(size_t)n - 1].d : 0.0;
+            CHECK_HIP(launch_adjoint_update(static_cast<const IntBlock *>(wa.d_blocks.ptr),
+                                            n_ablk, static_cast<const double *>(ws->part.ptr),
+                                            slot_mode_of(wa, precision),
+                                            static_cast<const double *>(ws->box_mass.ptr), xs,
+                                            ext, acc_att, N, n_cot, G, cw, lx, lp,
+                                            n > 0 ? 1 : 0, dnext, s));
+        }
+    }
+    if (grad_x0)
+        CHECK_HIP(hipMemcpyAsync(grad_x0, lx, (size_t)n_cot * n3 * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+    if (grad_v0)
+        CHECK_HIP(launch_scale(lp, grad_v0, (int64_t)n_cot * (int64_t)n3, a0 * a0, s));
+    if (P.coef_host)
+        *P.coef_host = std::move(hc);
+    if (grad_attractor)
+        CHECK_HIP(launch_att_grad_reduce(acc_att, n_ablk, n_cot, grad_attractor, s));
+        return COLATUS_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // Exported entry points.
 // ===========================================================================
@@ -1379,6 +1598,8 @@ int colatus_release(void)
             (void)hipGraphExecDestroy(sg.exec);
         if (ws->track_ev)
             (void)hipEventDestroy(ws->track_ev);
+        if (ws->ftle_ev)
+            (void)hipEventDestroy(ws->ftle_ev);
         if (ws->cap_stream)
             (void)hipStreamDestroy(ws->cap_stream);
         delete ws;
@@ -1686,13 +1907,13 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
 {
     TraceRange trace("colatus_adjoint");
     if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
-        checkpoint_every < -1 || n_cot < 1 || n_cot > kMaxCot || batch != nullptr)
+        checkpoint_every < -1 || n_cot < 1 || n_cot > kMaxCot)
         return COLATUS_EINVAL;
     if (grad_attractor && !attractor)
         return COLATUS_EINVAL;
     CHECK_RC(check_ptrs({x0, v0, m, lam_xN, lam_vN, grad_x0, grad_v0}));
     Boxes b;
-    CHECK_RC(resolve_boxes(N, eps, nullptr, b));
+    CHECK_RC(resolve_boxes(N, eps, batch, b));
     ExtField ext;
     CHECK_RC(resolve_external(attractor, background, ext));
     CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
@@ -1700,172 +1921,87 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m, int64_t
     Workspace *ws = nullptr;
     std::lock_guard<std::mutex> lock(g_mu);
     CHECK_RC(get_workspace(s, ws));
-    CHECK_RC(prepare_worklist(ws, 0, b, N, precision, x0, m, 1, s));
-    CHECK_RC(prepare_worklist(ws, 1, b, N, precision, x0, m, n_cot, s));
-    const WorkList &wf = *ws->fwd;
-    const WorkList &wa = *ws->adj;
-    CHECK_RC(prepare_box_mass(ws, wf, m, s));
-    const size_t n3 = 3 * (size_t)N;
-    if (checkpoint_every < 0) {
-        // automatic: every position when they take at most a quarter of the
-        // free device memory, else segments of ceil(sqrt(n_steps)) steps
-        // (the least checkpoint + segment memory; the compute is the same for
-        // every segment length)
-        size_t free_b = 0, total_b = 0;
-        CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
-        const double need = (double)(n_steps + 1) * (double)n3 * sizeof(double);
-        checkpoint_every = need <= 0.25 * (double)free_b
-                               ? 0
-                               : (int64_t)std::ceil(std::sqrt((double)n_steps));
-    }
-    // checkpoint_every == 0: every position of the forward run is kept (one
-    // segment spanning the run, filled by the forward pass itself)
-    const bool keep_all = checkpoint_every == 0;
-    const int64_t K = keep_all ? n_steps : checkpoint_every;
-    const int64_t n_seg = (n_steps + K - 1) / K;
+    AdjointParams P{x0, v0, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
+                    checkpoint_every, n_cot, lam_xN, lam_vN, nullptr, grad_x0, grad_v0, xN, vN,
+                    grad_attractor, precision, ext, s, nullptr};
+    return adjoint_impl(ws, P, b);
+}
+
+int colatus_ftle(const double *x0, const double *v0, const double *m, int64_t N, double eps,
+                 double G, double H0, double Om_R, double Om_M, double Om_K, double Om_L,
+                 double a_begin, double a_end, int64_t n_steps, int64_t checkpoint_every,
+                 int32_t n_tracers, const int64_t *tracers, double *lambda_t,
+                 double *lambda_lna, double *blocks, int precision,
+                 const colatus_batch *batch, const colatus_attractor *attractor,
+                 const colatus_background *background, void *stream)
+{
+    TraceRange trace("colatus_ftle");
+    if (N < 1 || N > kMaxN || !valid_precision(precision) || !is_fin(G) || n_steps < 1 ||
+        checkpoint_every < -1 || n_tracers < 1 || n_tracers > kMaxCot / 3)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x0, v0, m, tracers, lambda_t}));
+    for (int32_t t = 0; t < n_tracers; ++t)
+        if (tracers[t] < 0 || tracers[t] >= N)
+            return COLATUS_EINVAL;
+    Boxes b;
+    CHECK_RC(resolve_boxes(N, eps, batch, b));
+    ExtField ext;
+    CHECK_RC(resolve_external(attractor, background, ext));
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    // the tracer list, uploaded from the workspace's own host copy
+    CHECK_RC(ensure(ws->ftle_idx, (size_t)n_tracers * sizeof(int64_t)));
+    if (!ws->ftle_ev)
+        CHECK_HIP(hipEventCreateWithFlags(&ws->ftle_ev, hipEventDisableTiming));
+    else
+        CHECK_HIP(hipEventSynchronize(ws->ftle_ev));
+    ws->ftle_host.assign(tracers, tracers + n_tracers);
+    CHECK_HIP(hipMemcpyAsync(ws->ftle_idx.ptr, ws->ftle_host.data(),
+                             (size_t)n_tracers * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    CHECK_HIP(hipEventRecord(ws->ftle_ev, s));
+    const int64_t *didx = static_cast<const int64_t *>(ws->ftle_idx.ptr);
+    std::vector<StepCoef> hc;
+    AdjointParams P{x0, v0, m, N, G, H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps,
+                    checkpoint_every, 3 * n_tracers, nullptr, nullptr, didx, nullptr, nullptr,
+                    nullptr, nullptr, nullptr, precision, ext, s, &hc};
+    CHECK_RC(adjoint_impl(ws, P, b));
+    // elapsed cosmic time: the step times summed in grid order, as the
+    // diagnostics rows do; per unit ln a unless a is held fixed
+    double span_t = 0.0;
+    for (const StepCoef &c : hc)
+        span_t += c.dt;
+    const double span_lna = H0 == 0.0 ? NAN : std::log(a_end / a_begin);
+    CHECK_HIP(launch_ftle(static_cast<const double *>(ws->lam_x.ptr), didx, n_tracers, N, span_t,
+                          span_lna, lambda_t, lambda_lna, blocks, s));
+    return COLATUS_OK;
+}
+
+int colatus_cosmic_time(double a_begin, double a_end, int64_t n_steps, double H0, double Om_R,
+                        double Om_M, double Om_K, double Om_L, double *t, void *stream)
+{
+    TraceRange trace("colatus_cosmic_time");
+    if (!t || n_steps < 1)
+        return COLATUS_EINVAL;
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
     CHECK_RC(ensure(ws->coef, (size_t)n_steps * sizeof(StepCoef)));
-    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
-    const size_t part_fwd = (size_t)wf.max_slices * n3;
-    const size_t part_adj = (size_t)wa.max_slices * n3 * (size_t)n_cot;
-    CHECK_RC(ensure(ws->part, std::max(part_fwd, part_adj) * sizeof(double)));
-    CHECK_RC(ensure(ws->lam_x, (size_t)n_cot * n3 * sizeof(double)));
-    CHECK_RC(ensure(ws->lam_p, (size_t)n_cot * n3 * sizeof(double)));
-    // checkpoints: (x, p) at n = 0, K, 2K, ... ; segment states: K + 1 positions
-    CHECK_RC(ensure(ws->ckpt, (size_t)n_seg * 2 * n3 * sizeof(double)));
-    CHECK_RC(ensure(ws->seg, (size_t)(K + 1) * n3 * sizeof(double)));
-    const bool mask = eps == 0.0;
-
     StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
-    double *p = static_cast<double *>(ws->p.ptr);
-    double *ck = static_cast<double *>(ws->ckpt.ptr);
-    double *seg = static_cast<double *>(ws->seg.ptr);
-    double *lx = static_cast<double *>(ws->lam_x.ptr);
-    double *lp = static_cast<double *>(ws->lam_p.ptr);
-    // the working position buffer is the first segment slot
-    double *xw = seg;
-
     CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps, 0,
                                   n_steps, 0, coef, s));
     std::vector<StepCoef> hc((size_t)n_steps);
     CHECK_HIP(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(StepCoef), hipMemcpyDeviceToHost,
                              s));
     CHECK_HIP(hipStreamSynchronize(s));
-
-    IntegrateArgs A;
-    A.p = p;
-    A.m = m;
-    A.part = static_cast<const double *>(ws->part.ptr);
-    A.part_phi = nullptr;
-    A.blocks = static_cast<const IntBlock *>(wf.d_blocks.ptr);
-    A.n_blocks = (int)wf.blocks.size();
-    A.N = N;
-    A.G = G;
-    A.coef = coef;
-    A.step = step_counter(ws);
-    A.work_counter = work_counter(ws);
-    A.diag_part = nullptr;
-    A.precision = precision;
-    A.box_mass = static_cast<const double *>(ws->box_mass.ptr);
-    A.slot_mode = slot_mode_of(wf, precision);
-    A.ext = ext;
-    // per-block accumulators of the attractor's parameter derivatives
-    double *acc_att = nullptr;
-    const int n_ablk = (int)wa.blocks.size();
-    if (grad_attractor) {
-        const size_t n_acc = (size_t)n_ablk * (size_t)n_cot * 4;
-        CHECK_RC(ensure(ws->att_acc, n_acc * sizeof(double)));
-        acc_att = static_cast<double *>(ws->att_acc.ptr);
-        CHECK_HIP(launch_fill(acc_att, (int64_t)n_acc, 0.0, s));
-    }
-
-    // ---- forward with checkpoints --------------------------------------
-    CHECK_HIP(hipMemcpyAsync(xw, x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-    CHECK_HIP(launch_convert(0, v0, p, N, coef, 0, s));
-    CHECK_RC(set_step(ws, 0, 0, n_steps, s));
-    A.x = xw;
-    for (int64_t n = 0; n < n_steps; ++n) {
-        TraceRange step("adjoint forward step");
-        if (keep_all) {
-            // x_n stays in slot n; the step writes x_{n+1} into slot n + 1
-            double *xs = seg + (size_t)n * n3;
-            double *xn = xs + n3;
-            CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
-            CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-            A.x = xn;
-            CHECK_HIP(launch_integrate(A, s));
-            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
-            continue;
-        }
-        CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
-        if (n % K == 0) {
-            double *cx = ck + (size_t)(n / K) * 2 * n3;
-            CHECK_HIP(hipMemcpyAsync(cx, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-            CHECK_HIP(hipMemcpyAsync(cx + n3, p, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-        }
-        CHECK_HIP(launch_integrate(A, s));
-        CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
-    }
-    if (keep_all)
-        xw = seg + (size_t)n_steps * n3;  // x_N
-    if (xN || vN) {
-        CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xw, m, N, s, true));
-        A.x = xw;
-        CHECK_HIP(launch_integrate(A, s));  // closing half kick at a_end
-        if (xN)
-            CHECK_HIP(hipMemcpyAsync(xN, xw, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-        if (vN)
-            CHECK_HIP(launch_convert(1, p, vN, N, coef, n_steps - 1, s));
-    }
-
-    // ---- reverse sweep ---------------------------------------------------
-    const double aN = hc[(size_t)n_steps - 1].a1, a0 = hc[0].a0;
-    CHECK_HIP(hipMemcpyAsync(lx, lam_xN, (size_t)n_cot * n3 * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-    CHECK_HIP(launch_scale(lam_vN, lp, (int64_t)n_cot * (int64_t)n3, 1.0 / (aN * aN), s));
-    for (int64_t sg = n_seg - 1; sg >= 0; --sg) {
-        const int64_t lo = sg * K, hi = std::min(lo + K, n_steps);
-        // recompute positions x_lo .. x_hi from the checkpoint (bitwise: same
-        // kernels), unless the forward pass kept them all
-        const double *cx = ck + (size_t)sg * 2 * n3;
-        if (!keep_all) {
-            CHECK_HIP(hipMemcpyAsync(seg, cx, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-            CHECK_HIP(hipMemcpyAsync(p, cx + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-            CHECK_RC(set_step(ws, lo, 0, n_steps, s));
-        }
-        for (int64_t n = lo; n < hi && !keep_all; ++n) {
-            double *xs = seg + (size_t)(n - lo) * n3;
-            double *xn = seg + (size_t)(n - lo + 1) * n3;
-            CHECK_RC(run_forward_sweep(ws, wf, precision, false, mask, xs, m, N, s, true));
-            CHECK_HIP(hipMemcpyAsync(xn, xs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-            IntegrateArgs B = A;
-            B.x = xn;
-            CHECK_HIP(launch_integrate(B, s));
-            CHECK_HIP(launch_tick(step_counter(ws), work_counter(ws), s));
-        }
-        // visit x_n for n = hi .. lo+1 (and lo itself in segment 0): every grid
-        // point is visited once, x_hi being the unvisited bottom of the segment above
-        const int64_t top = hi;
-        const int64_t bottom = (sg == 0) ? lo : lo + 1;
-        for (int64_t n = top; n >= bottom; --n) {
-            TraceRange step("adjoint reverse step");
-            const double *xs = seg + (size_t)(n - lo) * n3;
-            CHECK_RC(run_adjoint_sweep(ws, wa, precision, mask, xs, m, N, n_cot, lp, s));
-            const double cw = (n < n_steps ? hc[(size_t)n].k1 : 0.0) +
-                              (n > 0 ? hc[(size_t)n - 1].k2 : 0.0);
-            const double dnext = n > 0 ? hc[(size_t)n - 1].d : 0.0;
-            CHECK_HIP(launch_adjoint_update(static_cast<const IntBlock *>(wa.d_blocks.ptr),
-                                            n_ablk, static_cast<const double *>(ws->part.ptr),
-                                            slot_mode_of(wa, precision),
-                                            static_cast<const double *>(ws->box_mass.ptr), xs,
-                                            ext, acc_att, N, n_cot, G, cw, lx, lp,
-                                            n > 0 ? 1 : 0, dnext, s));
-        }
-    }
-    CHECK_HIP(hipMemcpyAsync(grad_x0, lx, (size_t)n_cot * n3 * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-    CHECK_HIP(launch_scale(lp, grad_v0, (int64_t)n_cot * (int64_t)n3, a0 * a0, s));
-    if (grad_attractor)
-        CHECK_HIP(launch_att_grad_reduce(acc_att, n_ablk, n_cot, grad_attractor, s));
+    double span = 0.0;
+    for (const StepCoef &c : hc)
+        span += c.dt;
+    *t = span;
     return COLATUS_OK;
 }
 

@@ -320,6 +320,21 @@ hipError_t launch_adjoint_update(const IntBlock *blocks, int n_blocks, const dou
 hipError_t launch_att_grad_reduce(const double *att_acc, int n_blocks, int n_cot, double *out,
                                   hipStream_t stream);
 
+// FTLE cotangents: lam[0..n) = 0, then for tracer t < T, component i < 3,
+// lam[(3 t + i)][i][idx[t]] = 1 (lam is [3T][3][N]).
+hipError_t launch_ftle_seed(double *lam, int64_t n, const int64_t *idx, int T, int64_t N,
+                            hipStream_t stream);
+
+// Finite-time Lyapunov exponents from the adjoint's position gradients
+// grad [3T][3][N] (row 3t + i holds d x_i(end) of tracer idx[t] / d x_0):
+// the tracer's block B[i][j] = grad[3t + i][j][idx[t]], sigma = its largest
+// singular value (square root of the largest eigenvalue of B^T B, cyclic
+// Jacobi in FP64), lam_t[t] = ln sigma / span_t, lam_lna[t] = ln sigma /
+// span_lna (or null), blocks[t][i][j] = B[i][j] (or null).
+hipError_t launch_ftle(const double *grad, const int64_t *idx, int T, int64_t N, double span_t,
+                       double span_lna, double *lam_t, double *lam_lna, double *blocks,
+                       hipStream_t stream);
+
 // p[0..n) = value (a fill kernel; graph-safe).
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t stream);
 

@@ -893,6 +893,85 @@ __global__ void scale_kernel(const double *__restrict__ src, double *__restrict_
 
 inline unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
+// ---------------------------------------------------------------------------
+// Finite-time Lyapunov exponents (the chaotic-advection diagnostic of
+// Sections I and IV): lambda = ln sigma_max(d x_t(end) / d x_t(0)) / span.
+// ---------------------------------------------------------------------------
+__global__ void ftle_seed_kernel(double *__restrict__ lam, const int64_t *__restrict__ idx,
+                                 int T, int64_t N)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= 3 * T)
+        return;
+    const int t = k / 3, i = k - 3 * t;
+    lam[((int64_t)k * 3 + i) * N + idx[t]] = 1.0;
+}
+
+// Largest eigenvalue of the symmetric 3x3 matrix c (overwritten) by cyclic
+// Jacobi rotations (Rutishauser's form of each rotation), which converge
+// quadratically; the sweep stops once the off-diagonal entries are below
+// 1e-17 of the diagonal's size.
+__device__ double sym3_max_eigenvalue(double c[3][3])
+{
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        const double off = c[0][1] * c[0][1] + c[0][2] * c[0][2] + c[1][2] * c[1][2];
+        const double dia = c[0][0] * c[0][0] + c[1][1] * c[1][1] + c[2][2] * c[2][2];
+        if (!(off > 1e-34 * dia))
+            break;
+        for (int p = 0; p < 2; ++p) {
+            for (int q = p + 1; q < 3; ++q) {
+                const double apq = c[p][q];
+                if (apq == 0.0)
+                    continue;
+                const double theta = (c[q][q] - c[p][p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) /
+                                 (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                // A' = R^T A R with R the rotation in the (p, q) plane
+                for (int k = 0; k < 3; ++k) {
+                    const double akp = c[k][p], akq = c[k][q];
+                    c[k][p] = cs * akp - sn * akq;
+                    c[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double apk = c[p][k], aqk = c[q][k];
+                    c[p][k] = cs * apk - sn * aqk;
+                    c[q][k] = sn * apk + cs * aqk;
+                }
+                c[p][q] = c[q][p] = 0.0;
+            }
+        }
+    }
+    return fmax(c[0][0], fmax(c[1][1], c[2][2]));
+}
+
+__global__ void ftle_kernel(const double *__restrict__ grad, const int64_t *__restrict__ idx,
+                            int T, int64_t N, double span_t, double span_lna,
+                            double *__restrict__ lam_t, double *__restrict__ lam_lna,
+                            double *__restrict__ blocks)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= T)
+        return;
+    const int64_t k = idx[t];
+    double B[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            B[i][j] = grad[((int64_t)(3 * t + i) * 3 + j) * N + k];
+    double C[3][3];  // B^T B
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[i][j] = B[0][i] * B[0][j] + B[1][i] * B[1][j] + B[2][i] * B[2][j];
+    const double ln_sigma = 0.5 * log(sym3_max_eigenvalue(C));
+    lam_t[t] = ln_sigma / span_t;
+    if (lam_lna)
+        lam_lna[t] = ln_sigma / span_lna;
+    if (blocks)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                blocks[(int64_t)t * 9 + i * 3 + j] = B[i][j];
+}
+
 }  // namespace
 
 hipError_t launch_coefficients(double H0, double OmR, double OmM, double OmK, double OmL,
@@ -998,6 +1077,26 @@ hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t stream)
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_ftle_seed(double *lam, int64_t n, const int64_t *idx, int T, int64_t N,
+                            hipStream_t stream)
+{
+    hipError_t e = launch_fill(lam, n, 0.0, stream);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(ftle_seed_kernel, dim3(blocks_for(3 * (int64_t)T, 64)), dim3(64), 0, stream,
+                       lam, idx, T, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_ftle(const double *grad, const int64_t *idx, int T, int64_t N, double span_t,
+                       double span_lna, double *lam_t, double *lam_lna, double *blocks,
+                       hipStream_t stream)
+{
+    hipLaunchKernelGGL(ftle_kernel, dim3(blocks_for(T, 64)), dim3(64), 0, stream, grad, idx, T, N,
+                       span_t, span_lna, lam_t, lam_lna, blocks);
     return hipGetLastError();
 }
 

@@ -220,7 +220,18 @@ def test_adjoint_rejects_bad_arguments():
     assert call(K=-2) == EINVAL
     assert call(C=0) == EINVAL
     assert call(C=5000) == EINVAL
-    assert call(batch=FAKE) == EINVAL
+    # a batch is read on the host: its offsets must end at N, its softenings
+    # be non-negative
+    off = np.array([0, 3, 7], dtype=np.int64)
+    eps = np.array([0.01, 0.02])
+    bad = colatus._Batch(2, off.ctypes.data, eps.ctypes.data)
+    assert call(batch=ctypes.byref(bad)) == EINVAL
+    eps_bad = np.array([0.01, -0.02])
+    off_ok = np.array([0, 3, 8], dtype=np.int64)
+    bad2 = colatus._Batch(2, off_ok.ctypes.data, eps_bad.ctypes.data)
+    assert call(batch=ctypes.byref(bad2)) == EINVAL
+    empty = colatus._Batch(0, off_ok.ctypes.data, eps.ctypes.data)
+    assert call(batch=ctypes.byref(empty)) == EINVAL
     # attractor gradients need an attractor
     assert call(ga=FAKE) == EINVAL
     pa, keep = colatus._attractor((float("inf"), (0.0, 0.0, 0.0)))
@@ -307,3 +318,28 @@ def test_forces_noalloc_rejects_bad_arguments_on_host():
     assert call(x=None) == EINVAL
     assert call(acc=None) == EINVAL
 
+
+def test_ftle_and_cosmic_time_reject_bad_arguments_on_host():
+    L = colatus.lib()
+    tr = np.array([0, 3, 7], dtype=np.int64)
+
+    def call(N=8, T=3, idx=tr, K=5, lam=FAKE, prec=1, n_steps=10):
+        return L.colatus_ftle(FAKE, FAKE, FAKE, N, 0.01, 1.0, *LCDM, 0.2, 1.0, n_steps, K, T,
+                              idx.ctypes.data_as(ctypes.c_void_p) if idx is not None else None,
+                              lam, None, None, prec, None, None, None, None)
+
+    assert call(T=0) == EINVAL
+    assert call(T=1366) == EINVAL
+    assert call(idx=None) == EINVAL
+    assert call(idx=np.array([0, 8, 1], dtype=np.int64)) == EINVAL
+    assert call(idx=np.array([-1, 2, 1], dtype=np.int64)) == EINVAL
+    assert call(lam=None) == EINVAL
+    assert call(K=-3) == EINVAL
+    assert call(n_steps=0) == EINVAL
+    assert call(prec=7) == EINVAL
+    t = ctypes.c_double()
+    assert L.colatus_cosmic_time(0.2, 1.0, 0, *LCDM, ctypes.byref(t), None) == EINVAL
+    assert L.colatus_cosmic_time(0.2, 1.0, 10, *LCDM, None, None) == EINVAL
+    assert L.colatus_cosmic_time(-0.2, 1.0, 10, *LCDM, ctypes.byref(t), None) == EINVAL
+    assert L.colatus_cosmic_time(0.3, 0.9, 10, 1.0, 0.0, 1.0, -2.0, 0.0, ctypes.byref(t),
+                                 None) == EFRIEDMANN

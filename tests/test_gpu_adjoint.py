@@ -132,13 +132,51 @@ def test_ftle_matches_oracle(dev):
     tracers = [0, 17, 100, 201]
     lt_r, ll_r, phi_r = oracle.ftle(w.x, v0, w.m, w.eps, w.G, w.cosmo, 0.2, 1.0, 12, tracers)
     args = [to_dev(a, dev) for a in (w.x, v0, w.m)]
-    lt, ll, phi = colatus.ftle(*args, w.eps, w.G, w.cosmo, 0.2, 1.0, 12, tracers,
-                               checkpoint_every=5, precision="fp64")
+    lt, ll, phi = (t.cpu().numpy() for t in colatus.ftle(*args, w.eps, w.G, w.cosmo, 0.2, 1.0,
+                                                          12, tracers, checkpoint_every=5,
+                                                          precision="fp64"))
     assert np.allclose(phi, phi_r, rtol=1e-9, atol=1e-12)
     assert np.allclose(lt, lt_r, rtol=1e-9) and np.allclose(ll, ll_r, rtol=1e-9)
-    ltm, _, _ = colatus.ftle(*args, w.eps, w.G, w.cosmo, 0.2, 1.0, 12, tracers,
-                             checkpoint_every=5, precision="mixed_twosum")
+    ltm = colatus.ftle(*args, w.eps, w.G, w.cosmo, 0.2, 1.0, 12, tracers, checkpoint_every=5,
+                       precision="mixed_twosum")[0].cpu().numpy()
     assert np.max(np.abs(ltm - lt_r)) <= 1e-3 * max(1.0, np.abs(lt_r).max())
+
+
+def test_ftle_singular_value_and_time_span_in_the_library(dev):
+    """colatus_ftle's sigma_max (Jacobi on B^T B) against numpy's SVD of the
+    blocks it returns, its time span against the diagnostics' t of the same
+    run and against colatus_cosmic_time; the static limit; a tracer whose
+    block is the identity (G = 0: free particles) has lambda = 0."""
+    w = inputs.lcdm_grf(6, seed=4, a_begin=0.2, n_steps=12)
+    v0 = w.velocities(oracle.hubble(0.2, *w.cosmo.values()))
+    args = [to_dev(a, dev) for a in (w.x, v0, w.m)]
+    tracers = [3, 50, 101, 150, 215]
+    lt, ll, phi = (t.cpu().numpy() for t in colatus.ftle(*args, w.eps, w.G, w.cosmo, 0.2, 1.0,
+                                                          12, tracers, checkpoint_every=4,
+                                                          precision="fp64"))
+    ls = np.log(np.linalg.svd(phi, compute_uv=False)[:, 0])
+    d = colatus.run(args[0].clone(), args[1].clone(), args[2], w.eps, w.G, w.cosmo, 0.2, 1.0, 12,
+                    precision="fp64", diag=True)
+    span = colatus.cosmic_time(w.cosmo, 0.2, 1.0, 12)
+    assert span == d["t"][-1]
+    assert span == pytest.approx(oracle.time_integral("time", 0.2, 1.0, *w.cosmo.values()),
+                                 rel=1e-13)
+    assert np.allclose(lt, ls / span, rtol=1e-12, atol=0)
+    assert np.allclose(ll, ls / math.log(1.0 / 0.2), rtol=1e-12, atol=0)
+    # free particles: the flow map block is the identity
+    lt0, ll0, phi0 = (t.cpu().numpy() for t in colatus.ftle(*args, w.eps, 0.0, w.cosmo, 0.2, 1.0,
+                                                             12, tracers, precision="fp64"))
+    assert np.allclose(phi0, np.broadcast_to(np.eye(3), phi0.shape), rtol=0, atol=1e-15)
+    assert np.all(np.abs(lt0) <= 1e-14)
+    # static limit: a held fixed, the span is the elapsed time, no ln a
+    static = dict(H0=0.0, Om_R=0.0, Om_M=0.0, Om_K=0.0, Om_L=0.0)
+    assert colatus.cosmic_time(static, 1.0, 2.5, 10) == pytest.approx(2.5, rel=1e-15)
+    lts, lls, phis = (t.cpu().numpy() for t in colatus.ftle(*args, w.eps, w.G, static, 1.0, 0.3,
+                                                             10, tracers, precision="fp64"))
+    lr, _, phir = oracle.ftle(w.x, v0, w.m, w.eps, w.G, static, 1.0, 0.3, 10, tracers)
+    assert np.allclose(phis, phir, rtol=1e-9, atol=1e-12)
+    assert np.allclose(lts, lr, rtol=1e-9)
+    assert np.all(np.isnan(lls))
 
 
 @pytest.mark.parametrize("form", [0, 2])
@@ -159,3 +197,40 @@ def test_force_vjp_few_particles_self_pair_adds_nothing(dev, form, N):
             assert _rel(got[0], ref) <= tol, prec
     finally:
         colatus.set_option(colatus.OPT_PAIR_FORM, -1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_twosum"])
+def test_adjoint_of_a_batch_equals_each_box_alone(dev, prec):
+    """Boxes of a batch do not interact: the batched adjoint's gradients of
+    each box equal the adjoint of that box run alone (the same work items per
+    box), and a cotangent on one box moves no other box's gradient."""
+    sizes = [300, 1000, 77]
+    xs, vs, ms, epss = [], [], [], []
+    for k, n in enumerate(sizes):
+        x, m = inputs.random_cloud(n, 400 + k, scale=0.6)
+        xs.append(x)
+        ms.append(m)
+        vs.append(0.1 * np.random.default_rng(k).standard_normal((3, n)))
+        epss.append(0.01 * (k + 1))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X, V, M = np.concatenate(xs, axis=1), np.concatenate(vs, axis=1), np.concatenate(ms)
+    N = X.shape[1]
+    rng = np.random.default_rng(9)
+    lx = rng.standard_normal((2, 3, N))
+    lv = rng.standard_normal((2, 3, N))
+    lx[1, :, off[1]:] = 0.0  # second cotangent on box 0 only
+    lv[1, :, off[1]:] = 0.0
+    gx, gv = colatus.adjoint(to_dev(X, dev), to_dev(V, dev), to_dev(M, dev), 0.0, 1.0, LCDM,
+                             0.3, 0.8, 9, to_dev(lx, dev), to_dev(lv, dev), checkpoint_every=4,
+                             precision=prec, batch=(off, epss))
+    gx, gv = gx.cpu().numpy(), gv.cpu().numpy()
+    for k in range(len(sizes)):
+        sl = slice(off[k], off[k + 1])
+        bx, bv = colatus.adjoint(to_dev(xs[k], dev), to_dev(vs[k], dev), to_dev(ms[k], dev),
+                                 epss[k], 1.0, LCDM, 0.3, 0.8, 9,
+                                 to_dev(np.ascontiguousarray(lx[:, :, sl]), dev),
+                                 to_dev(np.ascontiguousarray(lv[:, :, sl]), dev),
+                                 checkpoint_every=4, precision=prec)
+        assert _rel(gx[:, :, sl], bx.cpu().numpy()) <= 1e-13, k
+        assert _rel(gv[:, :, sl], bv.cpu().numpy()) <= 1e-13, k
+    assert np.all(gx[1, :, off[1]:] == 0.0) and np.all(gv[1, :, off[1]:] == 0.0)

@@ -74,8 +74,10 @@ def test_mixed_lattice_4096(dev, prec):
     assert np.median(ep) <= 1e-6 and ep.max() <= 1e-5
 
 
-@pytest.mark.parametrize("prec,med,mx", [("fp64", 1e-12, 1e-12), ("mixed_twosum", 1e-6, 1e-4),
-                                         ("mixed_f64acc", 1e-6, 1e-4), ("fp32", 1e-5, 1e-3)])
+# the scope's bars, and (measured at 32^3 on 1024 targets: TwoSum and FP64
+# accumulation 8.9e-8 / 9.6e-7, plain FP32 1.13e-7 / 1.22e-6) about twice that
+@pytest.mark.parametrize("prec,med,mx", [("fp64", 1e-15, 1e-14), ("mixed_twosum", 2e-7, 2e-6),
+                                         ("mixed_f64acc", 2e-7, 2e-6), ("fp32", 3e-7, 3e-6)])
 def test_paper_scale_32cubed_sampled(dev, prec, med, mx):
     w = inputs.lcdm_grf(32)
     targets = np.sort(np.random.Generator(np.random.PCG64(22)).choice(w.N, 1024, replace=False))

@@ -4,10 +4,11 @@ at any size (finite differences of the GPU forward, batching identities).
 
 * precision sweep: N = 64^3 at a = 0.5, all 4096 seeded targets, four
   precisions, against the FP64 oracle on those targets;
-* adjoint: N = 32^3 LCDM from a = 0.2, gradient of the tracers' summed
-  squared final velocity against central differences of the FP64 forward
-  along seeded directions (h = 1e-6 and h/2 must agree first: chaotic growth
-  can leave the linear regime), mixed vs FP64 gradient;
+* adjoint: N = 32^3 LCDM, the whole 200-step run from a = 0.2 to 1, the
+  gradient of the tracers' summed squared final velocity against central
+  differences of the FP64 forward along 16 seeded directions (h = 1e-6 and
+  10 h must agree first: chaotic growth can leave the linear regime), mixed
+  vs FP64 gradient;
 * FTLE: 3 cotangents per tracer in one batched adjoint call equal the
   separate calls; mixed and FP64 exponents agree.
 """
@@ -24,18 +25,35 @@ from conftest import rel_err_per_particle, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec,med,mx", [("fp64", 1e-12, 1e-12), ("mixed_twosum", 1e-6, 1e-4),
-                                         ("mixed_f64acc", 1e-6, 1e-4), ("fp32", 1e-5, 1e-3)])
-def test_precision_sweep_64cubed_4096_targets(dev, prec, med, mx):
+# Bars per precision: the scope's (force error <= 1e-6 median, <= 1e-4 max for
+# the FP32 forms; FP64 within 1e-12), and under them bars set at two to three
+# times the errors measured at this size (64^3, 4096 targets, MI355X: median /
+# max 4.8e-16 / 3.0e-15 FP64, 5.3e-8 / 7.5e-7 TwoSum and FP64 accumulation,
+# 1.37e-7 / 1.97e-6 plain FP32 accumulation).
+SWEEP_BARS = {"fp64": (1e-15, 1e-14), "mixed_twosum": (1e-7, 2e-6),
+              "mixed_f64acc": (1e-7, 2e-6), "fp32": (3e-7, 5e-6)}
+
+
+def test_precision_sweep_64cubed_4096_targets(dev):
     w = inputs.precision_sweep(64)
     t = w.extra["targets"]
     assert len(t) == 4096
     ref = oracle.forces_targets(w.x, w.m, t, w.eps, a=0.5)
-    acc = colatus.forces(to_dev(w.x, dev), to_dev(w.m, dev), w.eps, a=0.5, precision=prec)
-    got = acc.cpu().numpy()[:, t]
-    e = rel_err_per_particle(got, ref)
-    print(f"64^3 {prec}: median {np.median(e):.3e} max {e.max():.3e}", flush=True)
-    assert np.median(e) <= med and e.max() <= mx
+    xt, mt = to_dev(w.x, dev), to_dev(w.m, dev)
+    med = {}
+    for prec, (bmed, bmax) in SWEEP_BARS.items():
+        acc = colatus.forces(xt, mt, w.eps, a=0.5, precision=prec)
+        got = acc.cpu().numpy()[:, t]
+        e = rel_err_per_particle(got, ref)
+        med[prec] = np.median(e)
+        print(f"64^3 {prec}: median {np.median(e):.3e} max {e.max():.3e}", flush=True)
+        contract = (1e-12, 1e-12) if prec == "fp64" else (1e-6, 1e-4)
+        assert np.median(e) <= contract[0] and e.max() <= contract[1], prec
+        assert np.median(e) <= bmed and e.max() <= bmax, prec
+    # the compensated and FP64 accumulations of the 1024 tile partials per
+    # target are more accurate than the plain FP32 one
+    assert med["fp32"] >= 1.5 * med["mixed_twosum"]
+    assert med["fp32"] >= 1.5 * med["mixed_f64acc"]
 
 
 def _adjoint_setup(n_steps):
@@ -45,9 +63,17 @@ def _adjoint_setup(n_steps):
 
 
 def test_adjoint_32cubed_finite_differences(dev):
-    n_steps = 50  # the first quarter of the 200-step run: a from 0.2 to 0.3
+    """The adjoint workload in full: N = 32^3, 200 steps from a = 0.2 to 1,
+    checkpoints every 20; the gradient of the 64 tracers' summed squared
+    final velocity against central differences of the FP64 forward along the
+    16 seeded unit directions in (x, v).  A direction counts when the
+    differences at h = 1e-6 and 10 h agree to 1e-5 (outside that, chaotic
+    growth has left the linear regime and the direction is reported as
+    ill-conditioned); for those the FP64 adjoint must agree with the h = 1e-6
+    difference to 1e-5.  (Measured: all 16 directions counted, the largest
+    disagreement 3.1e-7.)"""
     w, v0 = _adjoint_setup(200)
-    a_end = w.a_begin * (w.a_end / w.a_begin) ** (n_steps / 200)
+    n_steps, a_end = w.n_steps, w.a_end
     tr = w.extra["tracers"]
     mt = to_dev(w.m, dev)
 
@@ -69,22 +95,25 @@ def test_adjoint_32cubed_finite_differences(dev):
         grads[prec] = (gx.cpu().numpy(), gv.cpu().numpy())
     gx, gv = grads["fp64"]
     dirs = w.extra["fd_directions"]
+    assert len(dirs) == 16
     ok = 0
-    for u in dirs:
+    for k, u in enumerate(dirs):
         ux, uv = u[0], u[1]
-        fd = []
-        for h in (1e-6, 5e-7):
+        fd = {}
+        for h in (1e-5, 1e-6):
             Lp = np.sum(forward(w.x + h * ux, v0 + h * uv)[:, tr] ** 2)
             Lm = np.sum(forward(w.x - h * ux, v0 - h * uv)[:, tr] ** 2)
-            fd.append((Lp - Lm) / (2 * h))
+            fd[h] = (Lp - Lm) / (2 * h)
         ad = np.sum(gx * ux) + np.sum(gv * uv)
-        linear = abs(fd[0] - fd[1]) <= 1e-4 * abs(fd[1])
-        print(f"direction: adjoint {ad:.10e} fd(h) {fd[0]:.10e} fd(h/2) {fd[1]:.10e}",
-              flush=True)
+        linear = abs(fd[1e-5] - fd[1e-6]) <= 1e-5 * abs(fd[1e-6])
+        print(f"direction {k}: adjoint {ad:.10e} fd(1e-6) {fd[1e-6]:.10e} fd(1e-5) "
+              f"{fd[1e-5]:.10e} rel {abs(ad - fd[1e-6]) / abs(fd[1e-6]):.2e}"
+              f"{'' if linear else ' (ill-conditioned)'}", flush=True)
         if linear:
             ok += 1
-            assert abs(ad - fd[1]) <= 1e-5 * abs(fd[1])
-    assert ok >= len(dirs) // 2, "too few directions in the linear regime"
+            assert abs(ad - fd[1e-6]) <= 1e-5 * abs(fd[1e-6]), k
+    print(f"{ok} of {len(dirs)} directions in the linear regime", flush=True)
+    assert ok >= 12, "too few directions in the linear regime"
     # the mixed-precision gradient is the gradient of a nearby map
     gmx, gmv = grads["mixed_twosum"]
     num = math.sqrt(np.sum((gmx - gx) ** 2) + np.sum((gmv - gv) ** 2))
@@ -98,13 +127,14 @@ def test_ftle_batched_equals_single_and_precisions_agree(dev):
     a_end = w.a_begin * (w.a_end / w.a_begin) ** (40 / 200)
     args = [to_dev(a, dev) for a in (w.x, v0, w.m)]
     tracers = list(w.extra["tracers"][:16])
-    lt64, ll64, phi64 = colatus.ftle(*args, w.eps, w.G, w.cosmo, w.a_begin, a_end, 40, tracers,
-                                     checkpoint_every=10, precision="fp64")
+    lt64, ll64, phi64 = (t.cpu().numpy() for t in colatus.ftle(
+        *args, w.eps, w.G, w.cosmo, w.a_begin, a_end, 40, tracers, checkpoint_every=10,
+        precision="fp64"))
     for t in tracers[:2]:
-        _, _, phi1 = colatus.ftle(*args, w.eps, w.G, w.cosmo, w.a_begin, a_end, 40, [t],
-                                  checkpoint_every=10, precision="fp64")
+        phi1 = colatus.ftle(*args, w.eps, w.G, w.cosmo, w.a_begin, a_end, 40, [t],
+                            checkpoint_every=10, precision="fp64")[2].cpu().numpy()
         assert np.allclose(phi1[0], phi64[tracers.index(t)], rtol=1e-12, atol=1e-14)
-    ltm, _, _ = colatus.ftle(*args, w.eps, w.G, w.cosmo, w.a_begin, a_end, 40, tracers,
-                             checkpoint_every=10, precision="mixed_twosum")
+    ltm = colatus.ftle(*args, w.eps, w.G, w.cosmo, w.a_begin, a_end, 40, tracers,
+                       checkpoint_every=10, precision="mixed_twosum")[0].cpu().numpy()
     print(f"FTLE fp64 {np.round(lt64[:4], 6)} mixed {np.round(ltm[:4], 6)}", flush=True)
     assert np.max(np.abs(ltm - lt64)) <= 1e-3 * max(1.0, np.abs(lt64).max())
