@@ -148,16 +148,18 @@ def main():
         return time.perf_counter() - t0
 
     # ---- roofline: pair-sweep launches timed with hipEvents ---------------
-    # Measured first, on a copy of the start state: 200 eagerly launched
-    # steps, each sweep and integrator launch bracketed by hipEvents on the
-    # launching stream.  Running it first also brings the GPU to its steady
-    # clock before the headline's warm-up steps.
-    R_STEPS = 200
+    # Measured first, on a copy of the start state: 100 untimed steps that
+    # bring the GPU to its steady clock, then 200 eagerly launched steps with
+    # each sweep and integrator launch bracketed by hipEvents on the
+    # launching stream.  (The GPU is therefore warm before the headline's own
+    # warm-up steps as well.)
+    R_WARM, R_STEPS = 100, 200
+    xr_, vr_, mr_ = state()
+    timed_run(xr_, vr_, mr_, 0, R_WARM, args.precision)
     colatus.set_option(colatus.OPT_TIMER, 1)
     colatus.timer_read(0, reset=True)
     colatus.timer_read(2, reset=True)
-    xr_, vr_, mr_ = state()
-    timed_run(xr_, vr_, mr_, 0, R_STEPS, args.precision)
+    timed_run(xr_, vr_, mr_, R_WARM, R_WARM + R_STEPS, args.precision)
     ms_tot, launches = colatus.timer_read(0, reset=True)
     int_ms, int_launches = colatus.timer_read(2, reset=True)
     colatus.set_option(colatus.OPT_TIMER, 0)
@@ -171,8 +173,8 @@ def main():
                 "flops_per_launch": FLOPS_PER_PAIR * pairs,
                 "note": "algorithmic: 20 flops per ordered pair, N^2 ordered pairs per "
                         "launch; the symmetric loop evaluates each unordered pair once "
-                        "and applies it to both particles; measured over the first "
-                        f"{R_STEPS} steps of the run, before the headline"}
+                        "and applies it to both particles; measured over steps "
+                        f"{R_WARM}-{R_WARM + R_STEPS} of the run, before the headline"}
     print(f"[bench] pair sweep {sweep_ms:.4f} ms/launch -> {achieved / 1e12:.2f} TFLOP/s",
           file=sys.stderr, flush=True)
 
@@ -246,6 +248,47 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
                        "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms_tot / launches * 1e-3)
                        / PEAK_FP64}
     print(f"[bench] fp64: {fp64_rate:.1f} Gpairs/s", file=sys.stderr, flush=True)
+
+    # the paper-scale run in full, 1000 steps from a = 1/51 to 1, in FP64 and
+    # mixed, each with per-step diagnostics (one call each, timed), and the
+    # chaos control of the Layzer-Irvine comparison: the FP64 run started
+    # from positions perturbed at the FP32 rounding level, x (1 + 2^-24 u)
+    u = np.random.default_rng(11).choice([-1.0, 1.0], size=w.x.shape)
+    full = {}
+    for key, prec, x0 in (("fp64", "fp64", w.x), (args.precision, args.precision, w.x),
+                          ("fp64_control", "fp64", w.x * (1 + 2.0 ** -24 * u))):
+        x = torch.from_numpy(np.ascontiguousarray(x0)).to(dev)
+        v = torch.from_numpy(v0.copy()).to(dev)
+        m = torch.from_numpy(w.m.copy()).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = colatus.run(x, v, m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, w.n_steps,
+                        precision=prec, diag=True)
+        torch.cuda.synchronize()
+        full[key] = (time.perf_counter() - t0, d)
+    ref = full["fp64"][1]
+    scale = float(np.abs(ref["U"]).max())
+
+    def departure(d, thr):
+        idx = np.nonzero(np.abs(d["LI"] - ref["LI"]) / scale > thr)[0]
+        return float(ref["a"][idx[0]]) if len(idx) else None
+
+    run1000 = {}
+    for key, (t, d) in full.items():
+        run1000[key] = {"seconds": t, "ms_per_step": 1e3 * t / w.n_steps,
+                        "gpairs_s": w.n_steps * pairs / t / 1e9,
+                        "LI_end_over_maxU": float(d["LI"][-1] / scale),
+                        "LI_max_over_maxU": float(np.abs(d["LI"]).max() / scale)}
+        if key != "fp64":
+            run1000[key]["max_dLI_vs_fp64_over_maxU"] = float(
+                np.abs(d["LI"] - ref["LI"]).max() / scale)
+            run1000[key]["a_where_dLI_exceeds"] = {f"{thr:g}": departure(d, thr)
+                                                   for thr in (1e-8, 1e-6, 1e-4)}
+    out["lcdm32_1000_steps_with_diagnostics"] = run1000
+    print(f"[bench] 1000-step runs: fp64 {run1000['fp64']['seconds']:.3f} s, "
+          f"{args.precision} {run1000[args.precision]['seconds']:.3f} s; LI end/max|U| "
+          f"{run1000['fp64']['LI_end_over_maxU']:.4f} / "
+          f"{run1000[args.precision]['LI_end_over_maxU']:.4f}", file=sys.stderr, flush=True)
 
     # mixed with per-step diagnostics (fused potential + energies + LI)
     x, v, m = state()

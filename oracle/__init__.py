@@ -79,6 +79,9 @@ def _load():
         [_d, _d, _i64, _i64, _i64, _p, _d, _p, _d, _p, _p, _i64, _p]
     lib.oracle_background_add.restype = None
     lib.oracle_background_add.argtypes = [_p, _i64, _d, _p, _p, _p]
+    lib.oracle_forces_periodic.restype = None
+    lib.oracle_forces_periodic.argtypes = [_p, _p, _i64, _d, _d, _d, _d, _d, ctypes.c_int,
+                                           ctypes.c_int, _p, _i64, _p, _p]
     lib.oracle_velocity_spectrum_bins.restype = None
     lib.oracle_velocity_spectrum_bins.argtypes = [_p, _i64, _i64, ctypes.c_int, _p, _i64, _p]
     lib.oracle_velocity_spectrum.restype = None
@@ -207,6 +210,71 @@ def forces_targets(x, m, targets, eps, G=1.0, a=1.0):
     _load().oracle_forces_targets(_ptr(x), _ptr(m), N, _ptr(t), t.shape[0],
                                   eps, G, a, _ptr(acc))
     return acc
+
+
+def periodic_cutoffs(L, alpha=None):
+    """Splitting parameter and cutoffs of the oracle's Ewald sums: alpha = 6/L
+    by default; the real-space images around the nearest one (|n_i| <= 1:
+    every omitted image lies 1.5 L away or more, erfc(1.5 alpha L) < 1e-35
+    for alpha L >= 6), and the reciprocal vectors |n| <= n_kmax with
+    exp(-pi^2 n^2 / (alpha L)^2) below 1e-18 beyond."""
+    if alpha is None:
+        alpha = 6.0 / L
+    aL = alpha * L
+    assert aL >= 4.0, "real-space images |n_i| <= 1 need alpha L >= 4"
+    n_kmax = int(np.ceil(aL * np.sqrt(18.0 * np.log(10.0)) / np.pi))
+    return alpha, 1, n_kmax
+
+
+def forces_periodic(x, m, eps, L, G=1.0, a=1.0, with_phi=False, targets=None, alpha=None):
+    """Periodic comoving field (Ewald summation in a box of side L, mean
+    density removed, nearest image Plummer-softened): acc (3, N) or
+    (3, n_targets), and phi if with_phi.  alpha: the Ewald splitting
+    parameter (the result does not depend on it)."""
+    x = _c(x)
+    m = _c(m)
+    N = m.shape[0]
+    assert x.shape == (3, N)
+    alpha, n_img, n_kmax = periodic_cutoffs(L, alpha)
+    t = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = N if t is None else t.shape[0]
+    acc = np.empty((3, nt))
+    phi = np.empty(nt) if with_phi else None
+    _load().oracle_forces_periodic(_ptr(x), _ptr(m), N, eps, G, a, L, alpha, n_img, n_kmax,
+                                   _ptr(t), nt, _ptr(acc), _ptr(phi))
+    return (acc, phi) if with_phi else acc
+
+
+def run_periodic(x, v, m, eps, G, cosmo, L, a_begin, a_end, n_steps, first_step=0,
+                 last_step=None):
+    """Kick-drift-kick steps [first_step, last_step) of the run's grid (the
+    same steps and coefficients as run()) with the periodic field, each
+    drift followed by the wrap of every position into [0, L).  Written
+    step by step in Python on top of the pinned periodic field and step
+    coefficients.  Returns (x, v)."""
+    if last_step is None:
+        last_step = n_steps
+    x = _c(x).copy()
+    v = _c(v).copy()
+    def grid_a(n):  # a_n = a_begin exp(n ln(a_end / a_begin) / n_steps), as run()
+        if cosmo["H0"] == 0:
+            return a_begin
+        if n == n_steps:
+            return a_end
+        return a_begin * np.exp(n * (np.log(a_end / a_begin) / n_steps))
+
+    a0 = grid_a(first_step)
+    p = a0 * a0 * v
+    g = forces_periodic(x, m, eps, L, G=G, a=1.0)
+    for n in range(first_step, last_step):
+        k1, d, k2, _ = step_coefficients(cosmo, a_begin, a_end, n_steps, n)
+        p = p + k1 * g
+        x = x + d * p
+        x = x - L * np.floor(x / L)
+        g = forces_periodic(x, m, eps, L, G=G, a=1.0)
+        p = p + k2 * g
+    a1 = grid_a(last_step)
+    return x, p / (a1 * a1)
 
 
 def potential(x, m, eps, G=1.0, attractor=None, background=None):

@@ -305,6 +305,169 @@ void oracle_force_vjp(const double *x, const double *m, int64_t N, double eps,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Periodic boundaries (Section II: the motion equations are solved in a   */
+/* periodic box), by Ewald summation.                                       */
+/* ------------------------------------------------------------------------ */
+/* The periodic comoving field in a box of side L, with the mean density
+ * removed (the images of every particle fill space; the uniform background
+ * of the same mean density is subtracted, so the field is that of the
+ * density contrast), is for particle k
+ *   g_k = G sum_{j != k} m_j E(x_j - x_k),
+ * E(d) = sum_{n in Z^3} (d + nL) / |d + nL|^3                (summed with
+ *        the background, i.e. Ewald's split):
+ *      = sum_n (d + nL) C(alpha |d + nL|) / |d + nL|^3
+ *        + (4 pi / L^3) sum_{q != 0} (q / q^2) exp(-q^2 / (4 alpha^2)) sin(q . d)
+ * with C(u) = erfc(u) + (2u / sqrt(pi)) exp(-u^2), q = 2 pi n / L over the
+ * integer vectors n != 0, for any splitting parameter alpha > 0.  The
+ * particle's own images pull it nowhere (they cancel in pairs), so j == k
+ * adds nothing.  Softening: the nearest image d* of each pair (minimum
+ * image) takes the Plummer law of Eq. (1) instead of the Newtonian one, i.e.
+ *   + d* [(|d*|^2 + eps^2)^{-3/2} - |d*|^{-3}]   (0 for d* = 0).
+ * The comoving potential (its negative gradient times m_k is m_k g_k):
+ *   phi_k = -G [ sum_{j != k} m_j Psi(x_j - x_k) + m_k Psi_self ],
+ *   Psi(d) = sum_n erfc(alpha r_n) / r_n + [(|d*|^2 + eps^2)^{-1/2} - 1/|d*|]
+ *            + (4 pi / L^3) sum_q exp(-q^2 / 4 alpha^2) / q^2 cos(q . d)
+ *            - pi / (alpha^2 L^3),
+ *   Psi_self = sum_{n != 0} erfc(alpha |n| L) / (|n| L) + (4 pi / L^3) sum_q
+ *            exp(-q^2 / 4 alpha^2) / q^2 - pi / (alpha^2 L^3) - 2 alpha / sqrt(pi)
+ * (the interaction with its own images and with the background; a
+ * constant: for one particle in a unit box Psi_self is the simple cubic
+ * lattice's Madelung constant).  For two coincident particles (d* = 0) the
+ * nearest-image potential is the limit 1/eps - 2 alpha / sqrt(pi).
+ * Real space: images n with |n_i| <= n_img around the nearest one; reciprocal
+ * space: |n| <= n_kmax.  Each term's definition above; the reciprocal sums
+ * are written with the structure factor S(q) = sum_j m_j exp(i q . x_j), so
+ * that sum_j m_j sin(q . (x_j - x_k)) = Im(exp(-i q . x_k) S(q)) and
+ * sum_j m_j cos(q . (x_j - x_k)) = Re(exp(-i q . x_k) S(q)) (j == k included:
+ * sin 0 = 0 for the force, cos 0 = 1 is the self part of the potential).
+ * targets: NULL (all particles, out [3][N]) or an index list (out
+ * [3][n_targets]); phi: NULL or [n_targets].  acc = g / a^3.              */
+static const double kPi = 3.14159265358979323846;
+
+static double ewald_c(double u)
+{
+    return erfc(u) + 2.0 / sqrt(kPi) * u * exp(-u * u);
+}
+
+void oracle_forces_periodic(const double *x, const double *m, int64_t N, double eps,
+                            double G, double a, double L, double alpha, int n_img,
+                            int n_kmax, const int64_t *targets, int64_t n_targets,
+                            double *acc, double *phi)
+{
+    const double *px = x, *py = x + N, *pz = x + 2 * N;
+    const double eps2 = eps * eps;
+    const double scale = G / (a * a * a);
+    const double vol = L * L * L;
+    const int64_t nt = targets ? n_targets : N;
+    /* reciprocal vectors and their structure factors */
+    int64_t nq = 0;
+    for (int i = -n_kmax; i <= n_kmax; ++i)
+        for (int j = -n_kmax; j <= n_kmax; ++j)
+            for (int l = -n_kmax; l <= n_kmax; ++l)
+                if ((i || j || l) && i * i + j * j + l * l <= n_kmax * n_kmax)
+                    ++nq;
+    double *qv = (double *)malloc((size_t)(nq > 0 ? nq : 1) * 6 * sizeof(double));
+    int64_t c = 0;
+    for (int i = -n_kmax; i <= n_kmax; ++i)
+        for (int j = -n_kmax; j <= n_kmax; ++j)
+            for (int l = -n_kmax; l <= n_kmax; ++l)
+                if ((i || j || l) && i * i + j * j + l * l <= n_kmax * n_kmax) {
+                    double *q = qv + 6 * c++;
+                    q[0] = 2.0 * kPi * i / L;
+                    q[1] = 2.0 * kPi * j / L;
+                    q[2] = 2.0 * kPi * l / L;
+                    const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+                    /* weight (4 pi / L^3) exp(-q^2 / 4 alpha^2) / q^2 */
+                    q[3] = 4.0 * kPi / vol * exp(-q2 / (4.0 * alpha * alpha)) / q2;
+                }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nq; ++t) {
+        double *q = qv + 6 * t;
+        ksum sr = {0, 0}, si = {0, 0};
+        for (int64_t j = 0; j < N; ++j) {
+            const double ph = q[0] * px[j] + q[1] * py[j] + q[2] * pz[j];
+            ksum_add(&sr, m[j] * cos(ph));
+            ksum_add(&si, m[j] * sin(ph));
+        }
+        q[4] = ksum_value(&sr);
+        q[5] = ksum_value(&si);
+    }
+    ksum mt = {0, 0};
+    for (int64_t j = 0; j < N; ++j)
+        ksum_add(&mt, m[j]);
+    const double M = ksum_value(&mt);
+    /* self part of the real-space potential (constant) */
+    ksum ss = {0, 0};
+    for (int i = -n_img; i <= n_img; ++i)
+        for (int j = -n_img; j <= n_img; ++j)
+            for (int l = -n_img; l <= n_img; ++l)
+                if (i || j || l) {
+                    const double r = L * sqrt((double)(i * i + j * j + l * l));
+                    ksum_add(&ss, erfc(alpha * r) / r);
+                }
+    const double psi_self_real = ksum_value(&ss) - 2.0 * alpha / sqrt(kPi);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t k = targets ? targets[t] : t;
+        ksum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, fp = {0, 0};
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == k)
+                continue;
+            double d[3] = {px[j] - px[k], py[j] - py[k], pz[j] - pz[k]};
+            for (int c3 = 0; c3 < 3; ++c3)
+                d[c3] -= L * nearbyint(d[c3] / L);  /* nearest image d* */
+            const double rs2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            for (int i = -n_img; i <= n_img; ++i)
+                for (int jj = -n_img; jj <= n_img; ++jj)
+                    for (int l = -n_img; l <= n_img; ++l) {
+                        const double e[3] = {d[0] + i * L, d[1] + jj * L, d[2] + l * L};
+                        const double r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+                        if (r2 == 0.0)
+                            continue; /* coincident pair: handled below */
+                        const double r = sqrt(r2);
+                        const double w = m[j] * ewald_c(alpha * r) / (r2 * r);
+                        ksum_add(&fx, w * e[0]);
+                        ksum_add(&fy, w * e[1]);
+                        ksum_add(&fz, w * e[2]);
+                        ksum_add(&fp, m[j] * erfc(alpha * r) / r);
+                    }
+            /* softening of the nearest image */
+            if (rs2 > 0.0) {
+                const double rs = sqrt(rs2);
+                const double sp = 1.0 / sqrt(rs2 + eps2);
+                const double w = m[j] * (sp * sp * sp - 1.0 / (rs2 * rs));
+                ksum_add(&fx, w * d[0]);
+                ksum_add(&fy, w * d[1]);
+                ksum_add(&fz, w * d[2]);
+                ksum_add(&fp, m[j] * (sp - 1.0 / rs));
+            } else {
+                ksum_add(&fp, m[j] * (1.0 / eps - 2.0 * alpha / sqrt(kPi)));
+            }
+        }
+        ksum_add(&fp, m[k] * psi_self_real);
+        for (int64_t u = 0; u < nq; ++u) {
+            const double *q = qv + 6 * u;
+            const double ph = q[0] * px[k] + q[1] * py[k] + q[2] * pz[k];
+            const double cs = cos(ph), sn = sin(ph);
+            /* Im(exp(-i q.x_k) S) and Re(exp(-i q.x_k) S) */
+            const double im = cs * q[5] - sn * q[4];
+            const double re = cs * q[4] + sn * q[5];
+            ksum_add(&fx, q[3] * q[0] * im);
+            ksum_add(&fy, q[3] * q[1] * im);
+            ksum_add(&fz, q[3] * q[2] * im);
+            ksum_add(&fp, q[3] * re);
+        }
+        ksum_add(&fp, -kPi * M / (alpha * alpha * vol));
+        acc[t] = scale * ksum_value(&fx);
+        acc[nt + t] = scale * ksum_value(&fy);
+        acc[2 * nt + t] = scale * ksum_value(&fz);
+        if (phi)
+            phi[t] = -G * ksum_value(&fp);
+    }
+    free(qv);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Deformation attractor of Eq. (10).                                       */
 /* ------------------------------------------------------------------------ */
 /* Eq. (10) adds to the gradient of Eq. (1) the term
