@@ -276,6 +276,47 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
                    const colatus_background *background, const colatus_tracks *tracks,
                    void *stream);
 
+/* Periodic boundaries (Section II solves the motion equations in a periodic
+ * box; the printed force loop is an open all-pairs sum, so the method is
+ * not given there): the periodic comoving field by Ewald summation, for one
+ * box of side `box` (comoving) holding all N particles, its images filling
+ * space and the mean density removed (the field of the density contrast):
+ *   acc_k = a^-3 G sum_{j != k} m_j E(x_j - x_k),
+ *   E(d)  = sum_n (d + nL) C(alpha |d + nL|) / |d + nL|^3
+ *           + (4 pi / L^3) sum_{q != 0} q / q^2 exp(-q^2 / 4 alpha^2) sin(q . d),
+ *   C(u)  = erfc(u) + (2u / sqrt(pi)) exp(-u^2),  q = 2 pi n / L,
+ * which does not depend on alpha; the nearest image d* of each pair takes
+ * the Plummer law of Eq. (1): + d* [(|d*|^2 + eps^2)^{-3/2} - |d*|^{-3}]
+ * (0 at d* = 0; at an exact half-box tie the image rint() picks).
+ *   phi_k = -G [sum_{j != k} m_j Psi(x_j - x_k) + m_k Psi_self], with Psi the
+ * matching potential (real part erfc(alpha r)/r, the nearest image's
+ * Plummer correction, reciprocal part exp(-q^2/4 alpha^2)/q^2 cos(q . d),
+ * constant -pi / (alpha^2 L^3)) and Psi_self the particle's own images and
+ * background (-2.8372974794806 / L for one particle: the simple cubic
+ * Madelung constant).  The library takes alpha and the cutoffs so that the
+ * neglected real-space images and reciprocal terms fall below 1e-15 (FP64)
+ * or 3e-9 (FP32 forms) of the kernel: real space on the nearest image only
+ * (the pair sweep's symmetric loop, in the given precision), reciprocal
+ * space in FP64 by structure factors.  No external terms; one box; 1 <= N
+ * <= 262144; box > 0 finite, else COLATUS_EINVAL.  Other arguments as
+ * colatus_forces.                                                         */
+int colatus_forces_periodic(const double *x, const double *m, int64_t N, double eps,
+                            double G, double a, double box, int precision, double *acc,
+                            double *phi, void *stream);
+
+/* Kick-drift-kick steps [first_step, last_step) of colatus_run's grid with
+ * the periodic field of colatus_forces_periodic; after every drift each
+ * coordinate is wrapped into [0, box).  diag: as colatus_run (U from the
+ * periodic potential; P is conserved, L is not, with periodic boundaries).
+ * Launched eagerly (one real-space sweep and the reciprocal-space kernels
+ * per step).  Arguments, limits and errors as colatus_run and
+ * colatus_forces_periodic.                                                 */
+int colatus_run_periodic(double *x, double *v, const double *m, int64_t N, double eps,
+                         double G, double H0, double Om_R, double Om_M, double Om_K,
+                         double Om_L, double box, double a_begin, double a_end,
+                         int64_t n_steps, int64_t first_step, int64_t last_step,
+                         int precision, colatus_diag *diag, void *stream);
+
 /* Velocity power spectrum of each tracer of a track (the power spectrum of
  * a single particle's velocity series that Section I names as the method's
  * goal): the periodogram over the track's rows,

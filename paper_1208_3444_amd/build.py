@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build", "colatus")
 LIB = os.path.join(HERE, "libcolatus.so")
 
-SOURCES = ["pair_sweep.hip", "integrator.hip", "spectrum.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["pair_sweep.hip", "integrator.hip", "spectrum.hip", "ewald.hip", "noalloc.hip",
+           "api.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -55,6 +55,9 @@ SIGNATURES = {
     "colatus_ftle": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64, _i64,
                           _i32, _p, _p, _p, _p, _i, _p, _p, _p, _p]),
     "colatus_cosmic_time": (_i, [_d, _d, _i64, _d, _d, _d, _d, _d, ctypes.POINTER(_d), _p]),
+    "colatus_forces_periodic": (_i, [_p, _p, _i64, _d, _d, _d, _d, _i, _p, _p, _p]),
+    "colatus_run_periodic": (_i, [_p, _p, _p, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d,
+                                  _i64, _i64, _i64, _i, _p, _p]),
     "colatus_force_vjp": (_i, [_p, _p, _i64, _d, _d, _i32, _p, _p, _i, _p, _p, _p]),
     "colatus_hubble": (_i, [_d, _d, _d, _d, _d, _d, ctypes.POINTER(_d)]),
     "colatus_strerror": (ctypes.c_char_p, [_i]),
@@ -236,6 +239,42 @@ def forces(x, m, eps, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False, ba
     del keep, keep_a, keep_b
     _check("colatus_forces", rc)
     return (acc, phi) if with_phi else acc
+
+
+def forces_periodic(x, m, eps, box, G=1.0, a=1.0, precision="mixed_twosum", with_phi=False):
+    """The periodic comoving field (Ewald summation, box side `box`, mean
+    density removed, nearest image Plummer-softened), times a^-3: acc (3, N),
+    and phi (N,) if with_phi (colatus_forces_periodic)."""
+    N = m.shape[0]
+    px, pm = _dev(x, "x", (3, N)), _dev(m, "m", (N,))
+    acc = torch.empty_like(x)
+    phi = torch.empty_like(m) if with_phi else None
+    rc = lib().colatus_forces_periodic(px, pm, N, float(eps), float(G), float(a), float(box),
+                                       _prec(precision), ctypes.c_void_p(acc.data_ptr()),
+                                       ctypes.c_void_p(phi.data_ptr()) if with_phi else None,
+                                       _stream(x))
+    _check("colatus_forces_periodic", rc)
+    return (acc, phi) if with_phi else acc
+
+
+def run_periodic(x, v, m, eps, G, cosmo, box, a_begin, a_end, n_steps, first_step=0,
+                 last_step=None, precision="mixed_twosum", diag=False):
+    """Kick-drift-kick steps with the periodic field, positions wrapped into
+    [0, box) after each drift, in place (colatus_run_periodic).  Returns the
+    diagnostics dict if diag, else None."""
+    if last_step is None:
+        last_step = n_steps
+    N = m.shape[0]
+    px, pv, pm = _dev(x, "x", (3, N)), _dev(v, "v", (3, N)), _dev(m, "m", (N,))
+    nr = last_step - first_step + 1
+    rows = (Diag * nr)() if diag else None
+    rc = lib().colatus_run_periodic(px, pv, pm, N, float(eps), float(G), *_cosmo(cosmo),
+                                    float(box), float(a_begin), float(a_end), int(n_steps),
+                                    int(first_step), int(last_step), _prec(precision),
+                                    ctypes.cast(rows, ctypes.c_void_p) if diag else None,
+                                    _stream(x))
+    _check("colatus_run_periodic", rc)
+    return _diag_dict(rows) if diag else None
 
 
 def _cosmo(c):

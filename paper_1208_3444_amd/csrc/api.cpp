@@ -206,6 +206,11 @@ struct Workspace {
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     Buffer part, part_phi, coef, p, diag_part, diag_out, counters, lam_x, lam_p, ckpt, seg,
         box_mass, att_acc, he_x, track_idx, track_slot, twiddle, ftle_idx;
+    // periodic boundaries: the reciprocal-space plan (vectors and weights for
+    // one box side and precision) and its work buffers
+    Buffer ew_segs, ew_coef, ew_skp, ew_S, ew_kpg, ew_kpp, ew_msum, ew_g, ew_p;
+    double ew_L = 0.0, ew_alpha = 0.0;
+    int ew_nmax = -1, ew_nsegs = 0, ew_K = 0;
     // work lists by (N, boxes, softenings, tile shape); fwd / adj: the lists
     // selected by the current call's forward and adjoint set-up
     std::vector<WorkList *> lists;
@@ -221,7 +226,9 @@ struct Workspace {
     {
         return {&part,     &part_phi,   &coef,  &p,        &diag_part,  &diag_out,
                 &counters, &lam_x,      &lam_p, &ckpt,     &seg,        &box_mass,
-                &att_acc,  &he_x,       &track_idx, &track_slot, &twiddle, &ftle_idx};
+                &att_acc,  &he_x,       &track_idx, &track_slot, &twiddle, &ftle_idx,
+                &ew_segs,  &ew_coef,    &ew_skp, &ew_S, &ew_kpg, &ew_kpp, &ew_msum, &ew_g,
+                &ew_p};
     }
 };
 
@@ -1224,6 +1231,147 @@ int resolve_external(const colatus_attractor *a, const colatus_background *bg, E
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Periodic boundaries (Ewald summation).
+// ---------------------------------------------------------------------------
+// The Ewald kernel's real-space part C(u) = erfc(u) + (2u/sqrt(pi)) e^{-u^2}
+// (u = alpha r) and the reciprocal weights exp(-pi^2 n^2 / (alpha L)^2)
+// both fall below the precision's resolution tol: alpha from C(alpha L / 2)
+// = tol (the nearest image is the only real-space term kept; the others lie
+// at least L / 2 away), n_max from the weight at tol.
+constexpr double kEwaldTolFP64 = 1e-15;
+constexpr double kEwaldTolFP32 = 3e-9;
+
+void ewald_parameters(double L, int precision, double &alpha, int &nmax)
+{
+    const double tol = precision == COLATUS_FP64 ? kEwaldTolFP64 : kEwaldTolFP32;
+    auto C = [](double u) { return std::erfc(u) + 1.1283791670955126 * u * std::exp(-u * u); };
+    double lo = 0.0, hi = 12.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (C(mid) > tol)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    alpha = 2.0 * hi / L;
+    nmax = (int)std::ceil(alpha * L / M_PI * std::sqrt(std::log(1.0 / tol)));
+}
+
+// The half-space reciprocal vectors n != 0, |n| <= nmax (n_x > 0, or n_x = 0
+// and n_y > 0, or n_x = n_y = 0 and n_z > 0), as column segments of up to
+// kEwaldSegLen consecutive n_z, with their weights 2 (4 pi / L^3)
+// exp(-k^2 / 4 alpha^2) / k^2; uploaded once per (L, precision).
+int ensure_ewald_plan(Workspace *ws, double L, int precision, hipStream_t s)
+{
+    double alpha = 0.0;
+    int nmax = 0;
+    ewald_parameters(L, precision, alpha, nmax);
+    if (ws->ew_L == L && ws->ew_alpha == alpha && ws->ew_nmax == nmax)
+        return COLATUS_OK;
+    ws->ew_nmax = -1;
+    std::vector<EwaldSeg> segs;
+    std::vector<double> coef;
+    const double vol = L * L * L;
+    for (int nx = 0; nx <= nmax; ++nx)
+        for (int ny = -nmax; ny <= nmax; ++ny) {
+            const int r2 = nx * nx + ny * ny;
+            if (r2 > nmax * nmax)
+                continue;
+            const int zm = (int)std::floor(std::sqrt((double)(nmax * nmax - r2)));
+            int z0 = -zm;
+            if (nx == 0 && ny < 0)
+                continue;
+            if (nx == 0 && ny == 0)
+                z0 = 1;
+            for (int zb = z0; zb <= zm; zb += kEwaldSegLen) {
+                EwaldSeg g;
+                g.nx = nx;
+                g.ny = ny;
+                g.z0 = zb;
+                g.cnt = std::min(kEwaldSegLen, zm - zb + 1);
+                g.k0 = (int)coef.size();
+                for (int q = 0; q < g.cnt; ++q) {
+                    const double kx = 2.0 * M_PI * nx / L, ky = 2.0 * M_PI * ny / L,
+                                 kz = 2.0 * M_PI * (zb + q) / L;
+                    const double k2 = kx * kx + ky * ky + kz * kz;
+                    coef.push_back(2.0 * 4.0 * M_PI / vol * std::exp(-k2 / (4.0 * alpha * alpha)) /
+                                   k2);
+                }
+                segs.push_back(g);
+            }
+        }
+    // the previous plan's buffers may still be read by queued work
+    CHECK_HIP(hipStreamSynchronize(s));
+    CHECK_RC(ensure(ws->ew_segs, std::max<size_t>(1, segs.size()) * sizeof(EwaldSeg)));
+    CHECK_RC(ensure(ws->ew_coef, std::max<size_t>(1, coef.size()) * sizeof(double)));
+    if (!segs.empty()) {
+        CHECK_HIP(hipMemcpyAsync(ws->ew_segs.ptr, segs.data(), segs.size() * sizeof(EwaldSeg),
+                                 hipMemcpyHostToDevice, s));
+        CHECK_HIP(hipMemcpyAsync(ws->ew_coef.ptr, coef.data(), coef.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+        CHECK_HIP(hipStreamSynchronize(s));  // the host tables are local
+    }
+    ws->ew_L = L;
+    ws->ew_alpha = alpha;
+    ws->ew_nsegs = (int)segs.size();
+    ws->ew_K = (int)coef.size();
+    ws->ew_nmax = nmax;
+    return COLATUS_OK;
+}
+
+// Work buffers of the reciprocal-space sums for N particles, and the
+// launch arguments.
+int ewald_args(Workspace *ws, const double *x, const double *m, int64_t N, EwaldArgs &A)
+{
+    const int n_sk = (int)std::max<int64_t>(1, std::min<int64_t>(128, N / 512));
+    const int64_t blocks = (N + 63) / 64;
+    const int n_kc = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4096 + blocks - 1) / blocks));
+    const size_t K = (size_t)std::max(1, ws->ew_K);
+    CHECK_RC(ensure(ws->ew_skp, (size_t)n_sk * K * 2 * sizeof(double)));
+    CHECK_RC(ensure(ws->ew_S, K * 2 * sizeof(double)));
+    CHECK_RC(ensure(ws->ew_kpg, (size_t)n_kc * 3 * (size_t)N * sizeof(double)));
+    CHECK_RC(ensure(ws->ew_kpp, (size_t)n_kc * (size_t)N * sizeof(double)));
+    CHECK_RC(ensure(ws->ew_msum, sizeof(double)));
+    CHECK_RC(ensure(ws->ew_g, 3 * (size_t)N * sizeof(double)));
+    CHECK_RC(ensure(ws->ew_p, (size_t)N * sizeof(double)));
+    A.x = x;
+    A.m = m;
+    A.N = N;
+    A.L = ws->ew_L;
+    A.alpha = ws->ew_alpha;
+    A.segs = static_cast<const EwaldSeg *>(ws->ew_segs.ptr);
+    A.n_segs = ws->ew_nsegs;
+    A.K = ws->ew_K;
+    A.coef = static_cast<const double *>(ws->ew_coef.ptr);
+    A.sk_part = static_cast<double2 *>(ws->ew_skp.ptr);
+    A.n_sk_chunks = n_sk;
+    A.S = static_cast<double2 *>(ws->ew_S.ptr);
+    A.n_k_chunks = n_kc;
+    A.kpart_g = static_cast<double *>(ws->ew_kpg.ptr);
+    A.kpart_p = static_cast<double *>(ws->ew_kpp.ptr);
+    A.msum = static_cast<double *>(ws->ew_msum.ptr);
+    A.gk = static_cast<double *>(ws->ew_g.ptr);
+    A.pk = static_cast<double *>(ws->ew_p.ptr);
+    return COLATUS_OK;
+}
+
+// The symmetric work list (parts of 256) of one box, whatever the tile
+// options say: the periodic real-space loop runs on it.
+int prepare_periodic_worklist(Workspace *ws, int64_t N, double eps, hipStream_t s)
+{
+    Boxes b;
+    b.off = {0, N};
+    b.eps = {eps};
+    b.max_n = N;
+    WorkList *wl = nullptr;
+    CHECK_RC(select_worklist(ws, b, N, symmetric_cfg(b, 4, 64), s, wl));
+    ws->fwd = wl;
+    return COLATUS_OK;
+}
+
+bool valid_box(double box) { return is_fin(box) && box > 0.0; }
+
 // The discrete adjoint of a kick-drift-kick run (colatus_adjoint and
 // colatus_ftle), on the calling entry point's workspace, lock held.
 struct AdjointParams {
@@ -1844,6 +1992,138 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps, d
                                      (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
                                      nullptr, slot_mode_of(wl, precision), x, m, N, G, G, ext, 1.0,
                                      g_cache, nullptr, s, p, v, coef));
+    return COLATUS_OK;
+}
+
+int colatus_forces_periodic(const double *x, const double *m, int64_t N, double eps, double G,
+                            double a, double box, int precision, double *acc, double *phi,
+                            void *stream)
+{
+    TraceRange trace("colatus_forces_periodic");
+    if (N < 1 || N > kSymMaxN || !valid_precision(precision) || !is_fin(G) || !is_fin(a) ||
+        a <= 0.0 || !is_fin(eps) || eps < 0.0 || !valid_box(box))
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, m, acc}));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(ensure_ewald_plan(ws, box, precision, s));
+    CHECK_RC(prepare_periodic_worklist(ws, N, eps, s));
+    const WorkList &wl = *ws->fwd;
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * 3 * N * sizeof(double)));
+    if (phi)
+        CHECK_RC(ensure(ws->part_phi, (size_t)wl.max_slices * N * sizeof(double)));
+    EwaldArgs E;
+    CHECK_RC(ewald_args(ws, x, m, N, E));
+    CHECK_HIP(launch_ewald_real(precision, phi != nullptr, x, m, N,
+                                static_cast<const WorkItem *>(wl.d_items.ptr), (int)wl.items.size(),
+                                static_cast<double *>(ws->part.ptr),
+                                phi ? static_cast<double *>(ws->part_phi.ptr) : nullptr, nullptr,
+                                box, ws->ew_alpha, s));
+    const ExtField none{};
+    CHECK_HIP(launch_forces_finalize(precision, nullptr,
+                                     static_cast<const IntBlock *>(wl.d_blocks.ptr),
+                                     (int)wl.blocks.size(), static_cast<const double *>(ws->part.ptr),
+                                     phi ? static_cast<const double *>(ws->part_phi.ptr) : nullptr,
+                                     slot_mode_of(wl, precision), x, m, N, G, G / (a * a * a),
+                                     none, 1.0 / (a * a * a), acc, phi, s));
+    CHECK_HIP(launch_ewald_kspace(E, s));
+    CHECK_HIP(launch_ewald_add(E.gk, E.pk, N, G, 1.0 / (a * a * a), acc, phi, s));
+    return COLATUS_OK;
+}
+
+int colatus_run_periodic(double *x, double *v, const double *m, int64_t N, double eps, double G,
+                         double H0, double Om_R, double Om_M, double Om_K, double Om_L,
+                         double box, double a_begin, double a_end, int64_t n_steps,
+                         int64_t first_step, int64_t last_step, int precision,
+                         colatus_diag *diag, void *stream)
+{
+    TraceRange trace("colatus_run_periodic");
+    if (N < 1 || N > kSymMaxN || !valid_precision(precision) || !is_fin(G) || !is_fin(eps) ||
+        eps < 0.0 || !valid_box(box))
+        return COLATUS_EINVAL;
+    if (n_steps < 1 || first_step < 0 || last_step <= first_step || last_step > n_steps)
+        return COLATUS_EINVAL;
+    CHECK_RC(check_ptrs({x, v, m}));
+    CHECK_RC(validate_cosmology(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace *ws = nullptr;
+    std::lock_guard<std::mutex> lock(g_mu);
+    CHECK_RC(get_workspace(s, ws));
+    CHECK_RC(ensure_ewald_plan(ws, box, precision, s));
+    CHECK_RC(prepare_periodic_worklist(ws, N, eps, s));
+    const WorkList &wl = *ws->fwd;
+    const int64_t nsteps = last_step - first_step;
+    const int64_t rows = nsteps + 1;
+    const size_t n3 = 3 * (size_t)N;
+    const bool with_diag = diag != nullptr;
+    CHECK_RC(ensure(ws->coef, (size_t)nsteps * sizeof(StepCoef)));
+    CHECK_RC(ensure(ws->p, n3 * sizeof(double)));
+    CHECK_RC(ensure(ws->part, (size_t)wl.max_slices * n3 * sizeof(double)));
+    if (with_diag) {
+        CHECK_RC(ensure(ws->part_phi, (size_t)wl.max_slices * N * sizeof(double)));
+        CHECK_RC(ensure(ws->diag_part, (size_t)rows * wl.blocks.size() * kDiagW * sizeof(double)));
+        CHECK_RC(ensure(ws->diag_out, (size_t)rows * sizeof(colatus_diag)));
+    }
+    EwaldArgs E;
+    CHECK_RC(ewald_args(ws, x, m, N, E));
+    StepCoef *coef = static_cast<StepCoef *>(ws->coef.ptr);
+    double *p = static_cast<double *>(ws->p.ptr);
+    CHECK_HIP(launch_coefficients(H0, Om_R, Om_M, Om_K, Om_L, a_begin, a_end, n_steps, first_step,
+                                  last_step, 0, coef, s));
+    CHECK_HIP(launch_convert(0, v, p, N, coef, 0, s));
+    CHECK_RC(set_step(ws, first_step, first_step, last_step, s));
+    auto sweep = [&](int64_t *step_inc) -> int {
+        CHECK_HIP(launch_ewald_real(precision, with_diag, x, m, N,
+                                    static_cast<const WorkItem *>(wl.d_items.ptr),
+                                    (int)wl.items.size(), static_cast<double *>(ws->part.ptr),
+                                    with_diag ? static_cast<double *>(ws->part_phi.ptr) : nullptr,
+                                    step_inc, box, ws->ew_alpha, s));
+        CHECK_HIP(launch_ewald_kspace(E, s));
+        return COLATUS_OK;
+    };
+    CHECK_RC(sweep(nullptr));
+    IntegrateArgs A;
+    A.x = x;
+    A.p = p;
+    A.m = m;
+    A.part = static_cast<const double *>(ws->part.ptr);
+    A.part_phi = with_diag ? static_cast<const double *>(ws->part_phi.ptr) : nullptr;
+    A.blocks = static_cast<const IntBlock *>(wl.d_blocks.ptr);
+    A.n_blocks = (int)wl.blocks.size();
+    A.N = N;
+    A.G = G;
+    A.coef = coef;
+    A.step = step_counter(ws);
+    A.work_counter = work_counter(ws);
+    A.diag_part = with_diag ? static_cast<double *>(ws->diag_part.ptr) : nullptr;
+    A.precision = precision;
+    A.box_mass = nullptr;  // the periodic slots hold their masses
+    A.slot_mode = slot_mode_of(wl, precision);
+    A.ext = ExtField{};
+    A.ewald_g = E.gk;
+    A.ewald_p = E.pk;
+    A.box = box;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        TraceRange step("step");
+        CHECK_RC(run_integrate(A, s));
+        CHECK_RC(sweep(step_counter(ws)));  // advances the step
+    }
+    CHECK_RC(run_integrate(A, s));  // closing half kick at a_last (+ diagnostics)
+    CHECK_HIP(launch_convert(1, p, v, N, coef, nsteps - 1, s));
+    if (with_diag) {
+        CHECK_HIP(launch_diag_reduce(static_cast<const double *>(ws->diag_part.ptr), (int)rows,
+                                     A.blocks, A.n_blocks, 1,
+                                     static_cast<const int32_t *>(wl.d_box_first.ptr), coef, H0,
+                                     static_cast<double *>(ws->diag_out.ptr), s));
+        CHECK_HIP(hipMemcpyAsync(diag, ws->diag_out.ptr, (size_t)rows * sizeof(colatus_diag),
+                                 hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        for (int64_t r = 0; r < rows; ++r)
+            if (diag[r].flags & 1u)
+                return COLATUS_ENONFINITE;
+    }
     return COLATUS_OK;
 }
 

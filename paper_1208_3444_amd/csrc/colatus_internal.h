@@ -228,6 +228,12 @@ struct IntegrateArgs {
     const int32_t *track_slot = nullptr; // [N]: tracer number of each particle or -1
     double *track = nullptr;   // [rows][2][3][n_tracers]: rows n > first are written here
     int32_t n_tracers = 0;
+    // periodic boundaries: the reciprocal-space field [3][N] and potential
+    // part [N] at x_n (launch_ewald_kspace), added to the slots' sums; after
+    // the drift every coordinate is wrapped into [0, box) (box > 0)
+    const double *ewald_g = nullptr;
+    const double *ewald_p = nullptr;
+    double box = 0.0;
 };
 // Finalise g(x_n) from the partials, then kick by k2_{n-1} (n > first),
 // record diagnostics of the state at a_n, and (n < last) kick by k1_n and
@@ -334,6 +340,48 @@ hipError_t launch_ftle_seed(double *lam, int64_t n, const int64_t *idx, int T, i
 hipError_t launch_ftle(const double *grad, const int64_t *idx, int T, int64_t N, double span_t,
                        double span_lna, double *lam_t, double *lam_lna, double *blocks,
                        hipStream_t stream);
+
+// ---- periodic boundaries (Ewald summation) -------------------------------
+// Real-space part: the symmetric work items (parts of 256, R = 4, one wave),
+// each pair's nearest image, Plummer pair less the smooth long-range part
+// (see pair_sweep.hip); slots as the symmetric loop's (FP32 for FP32 pairs,
+// FP64 otherwise), masses included (readers take no common mass).
+hipError_t launch_ewald_real(int precision, bool with_phi, const double *x, const double *m,
+                             int64_t N, const WorkItem *items, int n_items, double *part,
+                             double *part_phi, int64_t *step_inc, double L, double alpha,
+                             hipStream_t stream);
+
+// A run of consecutive n_z of one reciprocal-space column (nx, ny), its k
+// values stored from k0 on.
+constexpr int kEwaldSegLen = 8;
+struct EwaldSeg {
+    int nx, ny, z0, cnt, k0;
+};
+
+struct EwaldArgs {
+    const double *x, *m;
+    int64_t N;
+    double L, alpha;
+    const EwaldSeg *segs;  // [n_segs], k0 consecutive
+    int n_segs, K;
+    const double *coef;    // [K]: 2 (4 pi / L^3) exp(-k^2 / 4 alpha^2) / k^2
+    double2 *sk_part;      // [n_sk_chunks][K]
+    int n_sk_chunks;
+    double2 *S;            // [K]
+    int n_k_chunks;        // ranges of segments for the per-particle sums
+    double *kpart_g;       // [n_k_chunks][3][N]
+    double *kpart_p;       // [n_k_chunks][N]
+    double *msum;          // [1]: total mass
+    double *gk;            // [3][N] out: reciprocal field (no G)
+    double *pk;            // [N] out: reciprocal potential part + self and background terms
+};
+// The reciprocal-space field and potential part of every particle, with the
+// self and background constants (ewald.hip).
+hipError_t launch_ewald_kspace(const EwaldArgs &args, hipStream_t stream);
+
+// acc += G inv_a3 gk; phi += -G pk (phi may be null).
+hipError_t launch_ewald_add(const double *gk, const double *pk, int64_t N, double G,
+                            double inv_a3, double *acc, double *phi, hipStream_t stream);
 
 // p[0..n) = value (a fill kernel; graph-safe).
 hipError_t launch_fill(double *p, int64_t n, double value, hipStream_t stream);

@@ -447,6 +447,12 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
     for (int q = 0; q < kDiagW; ++q)
         v[q] = 0.0;
     if (lead && valid) {
+        if (A.ewald_g) {
+            for (int c = 0; c < 3; ++c)
+                gs[c] += A.ewald_g[c * N + i];
+            if (A.diag_part)
+                phs += A.ewald_p[i];
+        }
         double g[3] = {A.G * gs[0], A.G * gs[1], A.G * gs[2]};
         double p[3] = {A.p[i], A.p[N + i], A.p[2 * N + i]};
         double xx[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
@@ -491,6 +497,8 @@ __global__ __launch_bounds__(kFinalizeThreads) void integrate_kernel(IntegrateAr
             for (int c = 0; c < 3; ++c) {
                 p[c] += cf.k1 * g[c];
                 xx[c] += cf.d * p[c];
+                if (A.box > 0.0)
+                    xx[c] -= A.box * floor(xx[c] / A.box);
             }
             A.x[i] = xx[0];
             A.x[N + i] = xx[1];

@@ -1317,6 +1317,237 @@ hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const do
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Periodic boundaries: the real-space part of the Ewald sum, on the work
+// items of the symmetric loop (parts of 256, four targets per lane, one wave;
+// each unordered pair evaluated once and applied to both particles: the
+// term changes sign when the two particles swap).  Per pair, with d the
+// nearest image of x_j - x_k, r = |d|:
+//   w   = (r^2 + eps^2)^{-3/2} - P(alpha r) r^{-3},  P(u) = erf(u) - (2u / sqrt(pi)) e^{-u^2}
+//   psi = (r^2 + eps^2)^{-1/2} - erf(alpha r) / r
+// i.e. the Plummer pair of Eq. (1) less the smooth long-range part that the
+// reciprocal-space sum carries; the other images are negligible (alpha is
+// chosen so that the real-space kernel is below the precision's resolution
+// at half the box).  r == 0 (a part's own particle, or coincident
+// particles): w = 0 and psi = (eps^2)^{-1/2} (0 at eps == 0), the value the
+// open-box loop gives its self pair and the O(N) kernels remove.
+// Coordinates are taken relative to the item's first target, each wrapped to
+// its nearest image in FP64 before rounding, so that particles close across
+// the box's faces stay close; the pair's separation is wrapped once more in
+// the pair's precision.  Masses multiply every term (missing particles have
+// mass 0 at the reference point), and the slots hold them: readers are
+// given no common mass.
+// ---------------------------------------------------------------------------
+template <typename T> struct EwaldReal {
+    T L, invL, alpha, c2;  // c2 = 2 / sqrt(pi)
+};
+
+__device__ __forceinline__ float erfc_t(float u) { return erfcf(u); }
+__device__ __forceinline__ double erfc_t(double u) { return erfc(u); }
+__device__ __forceinline__ float exp_t(float u) { return expf(u); }
+__device__ __forceinline__ double exp_t(double u) { return exp(u); }
+__device__ __forceinline__ float rint_t(float u) { return rintf(u); }
+__device__ __forceinline__ double rint_t(double u) { return rint(u); }
+
+template <typename T, bool PHI>
+__device__ __forceinline__ void ewald_pair(T dx, T dy, T dz, T eps2, const EwaldReal<T> &E,
+                                           T &w, T &psi)
+{
+    const T r2 = fma_t(dx, dx, fma_t(dy, dy, dz * dz));
+    const T rs = rsqrt_t(r2 + eps2);
+    if (r2 > (T)0.0) {
+        const T ri = rsqrt_t(r2);
+        const T u = E.alpha * (r2 * ri);
+        const T erf_u = (T)1.0 - erfc_t(u);
+        const T P = erf_u - E.c2 * u * exp_t(-u * u);
+        w = rs * (rs * rs) - P * (ri * (ri * ri));
+        if constexpr (PHI)
+            psi = rs - erf_u * ri;
+    } else {
+        w = (T)0.0;
+        if constexpr (PHI)
+            psi = eps2 > (T)0.0 ? rs : (T)0.0;
+    }
+}
+
+__device__ __forceinline__ double wrap_image(double d, double L)
+{
+    return d - L * rint(d / L);
+}
+
+// 64 steps of one source chunk (sources travel around the wave as in
+// sym_chunk) against the lane's R targets.
+template <typename T, int R, bool REACT, bool PHI>
+__device__ __forceinline__ void ewald_chunk(T sx, T sy, T sz, T sm, T &qx, T &qy, T &qz, T &qp,
+                                            const T (&xi)[R], const T (&yi)[R],
+                                            const T (&zi)[R], const T (&mi)[R], T eps2,
+                                            const EwaldReal<T> &E, T (&ax)[R], T (&ay)[R],
+                                            T (&az)[R], T (&ap)[R])
+{
+    for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            T dx = sx - xi[r], dy = sy - yi[r], dz = sz - zi[r];
+            dx = fma_t(-E.L, rint_t(dx * E.invL), dx);
+            dy = fma_t(-E.L, rint_t(dy * E.invL), dy);
+            dz = fma_t(-E.L, rint_t(dz * E.invL), dz);
+            T w, psi;
+            ewald_pair<T, PHI>(dx, dy, dz, eps2, E, w, psi);
+            const T wt = sm * w;
+            ax[r] = fma_t(wt, dx, ax[r]);
+            ay[r] = fma_t(wt, dy, ay[r]);
+            az[r] = fma_t(wt, dz, az[r]);
+            if constexpr (PHI)
+                ap[r] = fma_t(sm, psi, ap[r]);
+            if constexpr (REACT) {
+                const T ws = mi[r] * w;
+                qx = fma_t(-ws, dx, qx);
+                qy = fma_t(-ws, dy, qy);
+                qz = fma_t(-ws, dz, qz);
+                if constexpr (PHI)
+                    qp = fma_t(mi[r], psi, qp);
+            }
+        }
+        sx = wave_rotate(sx);
+        sy = wave_rotate(sy);
+        sz = wave_rotate(sz);
+        sm = wave_rotate(sm);
+        if constexpr (REACT) {
+            qx = wave_rotate(qx);
+            qy = wave_rotate(qy);
+            qz = wave_rotate(qz);
+            if constexpr (PHI)
+                qp = wave_rotate(qp);
+        }
+    }
+}
+
+// One work item (kind 0: a pair of parts with the reaction; kind 1: a
+// 64-target piece of a diagonal part).  Slots as the symmetric loop's: FP32
+// sums stored as FP32 (FP32 pairs), FP64 otherwise; masses included.
+template <typename T, int R, bool REACT, bool PHI>
+__device__ __forceinline__ void ewald_item(const WorkItem &w, const double *__restrict__ X,
+                                           const double *__restrict__ Y,
+                                           const double *__restrict__ Z,
+                                           const double *__restrict__ m, int64_t N,
+                                           double *__restrict__ part,
+                                           double *__restrict__ part_phi, const double L,
+                                           const EwaldReal<T> &E)
+{
+    constexpr bool F32OUT = sizeof(T) == 4;
+    const int lane = threadIdx.x & 63;
+    // reference point: the item's first target (wave-uniform)
+    const double cx = X[w.i0], cy = Y[w.i0], cz = Z[w.i0];
+    T xi[R], yi[R], zi[R], mi[R];
+    T ax[R], ay[R], az[R], ap[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        valid[r] = i < w.i1;
+        if (valid[r]) {
+            xi[r] = (T)wrap_image(X[i] - cx, L);
+            yi[r] = (T)wrap_image(Y[i] - cy, L);
+            zi[r] = (T)wrap_image(Z[i] - cz, L);
+            mi[r] = (T)m[i];
+        } else {
+            xi[r] = yi[r] = zi[r] = mi[r] = (T)0.0;
+        }
+        ax[r] = ay[r] = az[r] = ap[r] = (T)0.0;
+    }
+    const T eps2 = (T)w.eps2;
+    const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t j = w.j0 + (int64_t)c * 64 + lane;
+        const bool jv = j < w.j1;
+        T sx = (T)0.0, sy = (T)0.0, sz = (T)0.0, sm = (T)0.0;
+        if (jv) {
+            sx = (T)wrap_image(X[j] - cx, L);
+            sy = (T)wrap_image(Y[j] - cy, L);
+            sz = (T)wrap_image(Z[j] - cz, L);
+            sm = (T)m[j];
+        }
+        T qx = (T)0.0, qy = (T)0.0, qz = (T)0.0, qp = (T)0.0;
+        ewald_chunk<T, R, REACT, PHI>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi, eps2, E,
+                                      ax, ay, az, ap);
+        if constexpr (REACT) {
+            if (jv) {
+                const int64_t rs = (int64_t)w.rslice;
+                if constexpr (F32OUT) {
+                    float *pf = reinterpret_cast<float *>(part);
+                    pf[(rs * 3 + 0) * N + j] = (float)qx;
+                    pf[(rs * 3 + 1) * N + j] = (float)qy;
+                    pf[(rs * 3 + 2) * N + j] = (float)qz;
+                    if constexpr (PHI)
+                        reinterpret_cast<float *>(part_phi)[rs * N + j] = (float)qp;
+                } else {
+                    part[(rs * 3 + 0) * N + j] = (double)qx;
+                    part[(rs * 3 + 1) * N + j] = (double)qy;
+                    part[(rs * 3 + 2) * N + j] = (double)qz;
+                    if constexpr (PHI)
+                        part_phi[rs * N + j] = (double)qp;
+                }
+            }
+        }
+    }
+    const int64_t slot = (int64_t)w.slice;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!valid[r])
+            continue;
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        if constexpr (F32OUT) {
+            float *pf = reinterpret_cast<float *>(part);
+            pf[(slot * 3 + 0) * N + i] = (float)ax[r];
+            pf[(slot * 3 + 1) * N + i] = (float)ay[r];
+            pf[(slot * 3 + 2) * N + i] = (float)az[r];
+            if constexpr (PHI)
+                reinterpret_cast<float *>(part_phi)[slot * N + i] = (float)ap[r];
+        } else {
+            part[(slot * 3 + 0) * N + i] = (double)ax[r];
+            part[(slot * 3 + 1) * N + i] = (double)ay[r];
+            part[(slot * 3 + 2) * N + i] = (double)az[r];
+            if constexpr (PHI)
+                part_phi[slot * N + i] = (double)ap[r];
+        }
+    }
+}
+
+template <typename T, bool PHI>
+__global__ __launch_bounds__(64) void ewald_real_kernel(
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
+    const WorkItem *__restrict__ items, int n_items, double *__restrict__ part,
+    double *__restrict__ part_phi, int64_t *__restrict__ step_inc, double L, double alpha)
+{
+    const double *X = x, *Y = x + N, *Z = x + 2 * N;
+    if (step_inc && blockIdx.x == 0 && threadIdx.x == 0)
+        *step_inc += 1;
+    const int it = (int)blockIdx.x;
+    if (it >= n_items)
+        return;
+    const WorkItem w = items[it];
+    EwaldReal<T> E;
+    E.L = (T)L;
+    E.invL = (T)(1.0 / L);
+    E.alpha = (T)alpha;
+    E.c2 = (T)1.1283791670955126;  // 2 / sqrt(pi)
+    if (w.kind == 0)
+        ewald_item<T, 4, true, PHI>(w, X, Y, Z, m, N, part, part_phi, L, E);
+    else
+        ewald_item<T, 1, false, PHI>(w, X, Y, Z, m, N, part, part_phi, L, E);
+}
+
+template <typename T, bool PHI>
+hipError_t launch_ewald_real_t(const double *x, const double *m, int64_t N,
+                               const WorkItem *items, int n_items, double *part,
+                               double *part_phi, int64_t *step_inc, double L, double alpha,
+                               hipStream_t stream)
+{
+    hipLaunchKernelGGL((ewald_real_kernel<T, PHI>), dim3(n_items), dim3(64), 0, stream, x, m, N,
+                       items, n_items, part, part_phi, step_inc, L, alpha);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_zero_counter(int *counter, hipStream_t stream)
@@ -1348,6 +1579,25 @@ hipError_t launch_pair_sweep(int precision, int form, const TileCfg &cfg, bool w
         return dispatch_fwd_form<float, kDirect>(form, cfg, with_phi, mask_self, a);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_ewald_real(int precision, bool with_phi, const double *x, const double *m,
+                             int64_t N, const WorkItem *items, int n_items, double *part,
+                             double *part_phi, int64_t *step_inc, double L, double alpha,
+                             hipStream_t stream)
+{
+    if (n_items <= 0)
+        return hipSuccess;
+    if (precision == kFP64)
+        return with_phi ? launch_ewald_real_t<double, true>(x, m, N, items, n_items, part,
+                                                            part_phi, step_inc, L, alpha, stream)
+                        : launch_ewald_real_t<double, false>(x, m, N, items, n_items, part,
+                                                             part_phi, step_inc, L, alpha,
+                                                             stream);
+    return with_phi ? launch_ewald_real_t<float, true>(x, m, N, items, n_items, part, part_phi,
+                                                       step_inc, L, alpha, stream)
+                    : launch_ewald_real_t<float, false>(x, m, N, items, n_items, part, part_phi,
+                                                        step_inc, L, alpha, stream);
 }
 
 // box_mass[b] = the common mass of box b, or NaN if its masses differ (or one

@@ -343,3 +343,30 @@ def test_ftle_and_cosmic_time_reject_bad_arguments_on_host():
     assert L.colatus_cosmic_time(-0.2, 1.0, 10, *LCDM, ctypes.byref(t), None) == EINVAL
     assert L.colatus_cosmic_time(0.3, 0.9, 10, 1.0, 0.0, 1.0, -2.0, 0.0, ctypes.byref(t),
                                  None) == EFRIEDMANN
+
+
+def test_periodic_entry_points_reject_bad_arguments_on_host():
+    L = colatus.lib()
+    f = L.colatus_forces_periodic
+
+    def forces(N=16, eps=0.01, a=1.0, box=1.0, prec=0, x=FAKE):
+        return f(x, FAKE, N, eps, 1.0, a, box, prec, FAKE, None, None)
+
+    assert forces(box=0.0) == EINVAL
+    assert forces(box=-1.0) == EINVAL
+    assert forces(box=float("inf")) == EINVAL
+    assert forces(N=0) == EINVAL
+    assert forces(N=262145) == EINVAL
+    assert forces(eps=-0.1) == EINVAL
+    assert forces(a=0.0) == EINVAL
+    assert forces(prec=9) == EINVAL
+    assert forces(x=None) == EINVAL
+    r = L.colatus_run_periodic
+
+    def run(box=1.0, first=0, last=4, n=4, cos=LCDM, a0=0.2, a1=1.0):
+        return r(FAKE, FAKE, FAKE, 16, 0.01, 1.0, *cos, box, a0, a1, n, first, last, 1, None, None)
+
+    assert run(box=0.0) == EINVAL
+    assert run(first=3, last=3) == EINVAL
+    assert run(last=5) == EINVAL
+    assert run(cos=(1.0, 0.0, 1.0, -2.0, 0.0), a0=0.3, a1=0.9) == EFRIEDMANN
