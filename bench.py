@@ -89,6 +89,9 @@ def parse():
     p.add_argument("--cpu-sample-steps", type=int, default=24)
     p.add_argument("--integrator-64-only", action="store_true",
                    help="run only the integrator measurement at 64^3 (5 launches per precision) and print it as one JSON object, for counter runs")
+    p.add_argument("--periodic-only", action="store_true",
+                   help="run only the periodic-boundary measurement at 32^3 and print it as one "
+                        "JSON object, for profiler runs")
     p.add_argument("--roctx", action="store_true",
                    help="roctx ranges around every library call (rocprofv3 --marker-trace)")
     p.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -130,6 +133,10 @@ def main():
     v0 = w.velocities(H_i)
     N = w.N
     pairs = float(N) * N
+    if args.periodic_only:
+        print(json.dumps({"periodic_32cubed": periodic_32cubed(w, v0, args, colatus, np, torch,
+                                                               dev)}), flush=True)
+        return
 
     def state():
         return (torch.from_numpy(w.x.copy()).to(dev), torch.from_numpy(v0.copy()).to(dev),
@@ -289,6 +296,24 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
           f"{args.precision} {run1000[args.precision]['seconds']:.3f} s; LI end/max|U| "
           f"{run1000['fp64']['LI_end_over_maxU']:.4f} / "
           f"{run1000[args.precision]['LI_end_over_maxU']:.4f}", file=sys.stderr, flush=True)
+
+    # the EdS 16^3 lattice run in full: 64 steps from a = 0.1 to 1, FP64 and
+    # mixed (launch-bound at this size: 4096 particles)
+    we = inputs.eds_lattice(16)
+    ve0 = we.velocities(colatus.hubble(we.a_begin, we.cosmo))
+    eds = {}
+    for prec in ("fp64", args.precision):
+        for rep in range(2):  # the second run of each is kept
+            xe_, ve_, me_ = (torch.from_numpy(a.copy()).to(dev) for a in (we.x, ve0, we.m))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            colatus.run(xe_, ve_, me_, we.eps, we.G, we.cosmo, we.a_begin, we.a_end, we.n_steps,
+                        precision=prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        eds[prec] = {"seconds_64_steps": t, "ms_per_step": 1e3 * t / we.n_steps,
+                     "gpairs_s": we.n_steps * float(we.N) ** 2 / t / 1e9}
+    out["eds_lattice_16cubed_64_steps"] = eds
 
     # mixed with per-step diagnostics (fused potential + energies + LI)
     x, v, m = state()
@@ -478,6 +503,9 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
           f"{out['adjoint_200_steps_all_positions_kept']['seconds']:.3f} s)",
           file=sys.stderr, flush=True)
 
+    per = periodic_32cubed(w, v0, args, colatus, np, torch, dev)
+    out["periodic_32cubed"] = per
+
     # single force evaluation at N = 64^3 in each precision
     ws3 = inputs.precision_sweep(64)
     x3, m3 = torch.from_numpy(ws3.x).to(dev), torch.from_numpy(ws3.m).to(dev)
@@ -561,6 +589,36 @@ def variants(w, v0, state, timed_run, args, colatus, inputs, np, torch, dev):
     print(f"[bench] ensemble: {ens['gpairs_s']:.1f} Gpairs/s "
           f"({ens['speedup_vs_per_box_loop']:.1f}x per-box loop)", file=sys.stderr, flush=True)
     return out
+
+
+def periodic_32cubed(w, v0, args, colatus, np, torch, dev):
+    """Periodic boundaries (Ewald summation) on the 32^3 positions in a unit
+    box: one force evaluation per precision (real-space pair sweep and
+    reciprocal-space sums), and 20 steps of the periodic run."""
+    per = {}
+    xp, mp = (torch.from_numpy(a.copy()).to(dev) for a in (w.x, w.m))
+    for prec in ("fp64", args.precision):
+        for _ in range(2):
+            colatus.forces_periodic(xp, mp, w.eps, 1.0, a=w.a_begin, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            colatus.forces_periodic(xp, mp, w.eps, 1.0, a=w.a_begin, precision=prec)
+        torch.cuda.synchronize()
+        per[prec] = {"force_ms": 1e3 * (time.perf_counter() - t0) / 5}
+    xr_, vr_ = (torch.from_numpy(a.copy()).to(dev) for a in (w.x, v0))
+    colatus.run_periodic(xr_, vr_, mp, w.eps, w.G, w.cosmo, 1.0, w.a_begin, w.a_end, w.n_steps,
+                         first_step=0, last_step=5, precision=args.precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    colatus.run_periodic(xr_, vr_, mp, w.eps, w.G, w.cosmo, 1.0, w.a_begin, w.a_end, w.n_steps,
+                         first_step=5, last_step=25, precision=args.precision)
+    torch.cuda.synchronize()
+    per[args.precision]["run_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / 20
+    print(f"[bench] periodic 32^3: force fp64 {per['fp64']['force_ms']:.3f} ms, "
+          f"{args.precision} {per[args.precision]['force_ms']:.3f} ms; run "
+          f"{per[args.precision]['run_ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    return per
 
 
 def integrator_64cubed(ws3, x3, m3, colatus, torch):

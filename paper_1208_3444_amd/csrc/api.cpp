@@ -1035,6 +1035,7 @@ std::vector<uint64_t> step_graph_key(const Workspace *ws, const RunParams &P,
     k.add((int64_t)A.ext.on); k.add(A.ext.S); k.add(A.ext.x); k.add(A.ext.y); k.add(A.ext.z);
     k.add((int64_t)A.ext.bg); k.add(A.ext.b); k.add(A.ext.cx); k.add(A.ext.cy); k.add(A.ext.cz);
     k.add(A.track_slot); k.add(A.track); k.add((int64_t)A.n_tracers);
+    k.add(A.ewald_g); k.add(A.ewald_p); k.add(A.box);
     // pair sweep
     k.add((int64_t)P.precision); k.add((int64_t)wl.cfg.R); k.add((int64_t)wl.cfg.tpb);
     k.add((int64_t)wl.cfg.slices); k.add((int64_t)wl.cfg.form); k.add((int64_t)(P.diag != nullptr));
@@ -1324,7 +1325,7 @@ int ensure_ewald_plan(Workspace *ws, double L, int precision, hipStream_t s)
 // launch arguments.
 int ewald_args(Workspace *ws, const double *x, const double *m, int64_t N, EwaldArgs &A)
 {
-    const int n_sk = (int)std::max<int64_t>(1, std::min<int64_t>(128, N / 512));
+    const int n_sk = (int)std::max<int64_t>(1, std::min<int64_t>(256, N / 256));
     const int64_t blocks = (N + 63) / 64;
     const int n_kc = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4096 + blocks - 1) / blocks));
     const size_t K = (size_t)std::max(1, ws->ew_K);
@@ -1353,6 +1354,7 @@ int ewald_args(Workspace *ws, const double *x, const double *m, int64_t N, Ewald
     A.msum = static_cast<double *>(ws->ew_msum.ptr);
     A.gk = static_cast<double *>(ws->ew_g.ptr);
     A.pk = static_cast<double *>(ws->ew_p.ptr);
+    A.mass_ready = false;
     return COLATUS_OK;
 }
 
@@ -2084,6 +2086,7 @@ int colatus_run_periodic(double *x, double *v, const double *m, int64_t N, doubl
         return COLATUS_OK;
     };
     CHECK_RC(sweep(nullptr));
+    E.mass_ready = true;  // the masses do not change during the run
     IntegrateArgs A;
     A.x = x;
     A.p = p;

@@ -353,7 +353,7 @@ hipError_t launch_ewald_real(int precision, bool with_phi, const double *x, cons
 
 // A run of consecutive n_z of one reciprocal-space column (nx, ny), its k
 // values stored from k0 on.
-constexpr int kEwaldSegLen = 8;
+constexpr int kEwaldSegLen = 16;
 struct EwaldSeg {
     int nx, ny, z0, cnt, k0;
 };
@@ -372,6 +372,7 @@ struct EwaldArgs {
     double *kpart_g;       // [n_k_chunks][3][N]
     double *kpart_p;       // [n_k_chunks][N]
     double *msum;          // [1]: total mass
+    bool mass_ready;       // msum already holds the masses' sum (a run's later steps)
     double *gk;            // [3][N] out: reciprocal field (no G)
     double *pk;            // [N] out: reciprocal potential part + self and background terms
 };

@@ -12,7 +12,7 @@
 //   psi^K  = sum_k c(k) Re(exp(-i k . x_i) S(k))            (potential part)
 // Phases start from sincospi of the exact phase at the first k of a short
 // run of consecutive n_z (a column segment) and advance by multiplying with
-// exp(+-i 2 pi z / L): at most seven FP64 products per segment.
+// exp(+-i 2 pi z / L): at most fifteen FP64 products per segment.
 #include "colatus_internal.h"
 
 #include <math.h>
@@ -194,16 +194,16 @@ __global__ void ewald_kreduce_kernel(const double *__restrict__ pg, const double
 }
 
 // Total mass, one block, fixed order (for the background constant).
-__global__ __launch_bounds__(256) void ewald_mass_kernel(const double *__restrict__ m, int64_t N,
-                                                         double *__restrict__ out)
+__global__ __launch_bounds__(1024) void ewald_mass_kernel(const double *__restrict__ m, int64_t N,
+                                                          double *__restrict__ out)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[1024];
     double t = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += 256)
+    for (int64_t i = threadIdx.x; i < N; i += 1024)
         t += m[i];
     sh[threadIdx.x] = t;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = 512; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off)
             sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
@@ -233,10 +233,12 @@ hipError_t launch_ewald_kspace(const EwaldArgs &A, hipStream_t stream)
     const double inv_L = 1.0 / A.L;
     const int64_t N = A.N;
     const int64_t chunk = (N + A.n_sk_chunks - 1) / A.n_sk_chunks;
-    hipLaunchKernelGGL(ewald_mass_kernel, dim3(1), dim3(256), 0, stream, A.m, N, A.msum);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
+    hipError_t e = hipSuccess;
+    if (!A.mass_ready) {
+        hipLaunchKernelGGL(ewald_mass_kernel, dim3(1), dim3(1024), 0, stream, A.m, N, A.msum);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
     const double pi = 3.14159265358979323846;
     const double self_c = -2.0 * A.alpha / sqrt(pi);
     const double bg_c = -pi / (A.alpha * A.alpha * A.L * A.L * A.L);

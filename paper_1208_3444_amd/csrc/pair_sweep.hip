@@ -1342,12 +1342,29 @@ template <typename T> struct EwaldReal {
     T L, invL, alpha, c2;  // c2 = 2 / sqrt(pi)
 };
 
-__device__ __forceinline__ float erfc_t(float u) { return erfcf(u); }
-__device__ __forceinline__ double erfc_t(double u) { return erfc(u); }
-__device__ __forceinline__ float exp_t(float u) { return expf(u); }
-__device__ __forceinline__ double exp_t(double u) { return exp(u); }
 __device__ __forceinline__ float rint_t(float u) { return rintf(u); }
 __device__ __forceinline__ double rint_t(double u) { return rint(u); }
+
+// erf(u) and exp(-u^2) for u >= 0.  FP64: the math library's erf and exp.
+// FP32: exp(-u^2) once, and erf(u) = 1 - t p(t) exp(-u^2), t = 1/(1 + 0.3275911 u),
+// p the fifth-degree polynomial of Hastings' approximation (Abramowitz and
+// Stegun 7.1.26; absolute error at most 1.5e-7, a few FP32 units of the
+// kernel it enters), sharing that exponential with the Gaussian term.
+__device__ __forceinline__ void erf_gauss(double u, double &erf_u, double &gauss)
+{
+    erf_u = erf(u);
+    gauss = exp(-u * u);
+}
+__device__ __forceinline__ void erf_gauss(float u, float &erf_u, float &gauss)
+{
+    gauss = __expf(-u * u);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+    const float p =
+        fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
+                     -0.284496736f),
+             0.254829592f);
+    erf_u = fmaf(-t * p, gauss, 1.0f);
+}
 
 template <typename T, bool PHI>
 __device__ __forceinline__ void ewald_pair(T dx, T dy, T dz, T eps2, const EwaldReal<T> &E,
@@ -1358,8 +1375,9 @@ __device__ __forceinline__ void ewald_pair(T dx, T dy, T dz, T eps2, const Ewald
     if (r2 > (T)0.0) {
         const T ri = rsqrt_t(r2);
         const T u = E.alpha * (r2 * ri);
-        const T erf_u = (T)1.0 - erfc_t(u);
-        const T P = erf_u - E.c2 * u * exp_t(-u * u);
+        T erf_u, gauss;
+        erf_gauss(u, erf_u, gauss);
+        const T P = erf_u - E.c2 * u * gauss;
         w = rs * (rs * rs) - P * (ri * (ri * ri));
         if constexpr (PHI)
             psi = rs - erf_u * ri;
