@@ -38,6 +38,7 @@ PEAK_HBM = 8.0e12            # bytes/s
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pair_sweep_lcdm32_pmc.md")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "pair_sweep_lcdm32_valu_pmc.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1208_3444_amd", "csrc", "pair_sweep.hip")
 
 
@@ -74,6 +75,23 @@ def pmc_traffic():
     if not m or not t or m.group(1) != src_hash:
         return None
     return float(t.group(1))
+
+
+def pmc_hw_flops():
+    """FP32 flops the sweep's instructions perform per launch (the counter
+    SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes) from the committed instruction-mix
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(VALU_SUMMARY):
+        return None
+    text = open(VALU_SUMMARY).read()
+    src_hash = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    m = re.search(r"source sha256 \(pair_sweep.hip\): ([0-9a-f]{64})", text)
+    f = re.search(r"hardware FP32 flops per launch: ([0-9.eE+-]+)", text)
+    if not m or not f or m.group(1) != src_hash:
+        return None
+    return float(f.group(1))
 
 
 def parse():
@@ -180,8 +198,12 @@ def main():
                 "flops_per_launch": FLOPS_PER_PAIR * pairs,
                 "note": "algorithmic: 20 flops per ordered pair, N^2 ordered pairs per "
                         "launch; the symmetric loop evaluates each unordered pair once "
-                        "and applies it to both particles; measured over steps "
+                        "and applies it to both particles (hw_frac: the FP32 flops its "
+                        "instructions perform, from the counters); measured over steps "
                         f"{R_WARM}-{R_WARM + R_STEPS} of the run, before the headline"}
+    hw = pmc_hw_flops()
+    roofline["hw_flops_per_launch"] = hw
+    roofline["hw_frac"] = None if hw is None else hw / (sweep_ms * 1e-3) / PEAK_FP32
     print(f"[bench] pair sweep {sweep_ms:.4f} ms/launch -> {achieved / 1e12:.2f} TFLOP/s",
           file=sys.stderr, flush=True)
 
