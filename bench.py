@@ -42,14 +42,34 @@ VALU_SUMMARY = os.path.join(ROOT, "profiles", "pair_sweep_lcdm32_valu_pmc.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1208_3444_amd", "csrc", "pair_sweep.hip")
 
 
+def slot_layout(N, precision):
+    """(slots per particle, bytes per slot, grouped) of the forward sweep the
+    library runs for one box of N: the symmetric form writes one slot per
+    part of R x threads particles (P parts), or ceil(P/2) + 1 in 2x2 groups
+    of part pairs (4 targets per lane, 64 threads, grouping on); FP32 slots
+    with FP32 pairs and parts of at most 256, else FP64."""
+    from paper_1208_3444_amd import colatus
+    R, tpb, slices, form = colatus.tile_config(N, precision)
+    grouped = (form == 2 and R == 4 and tpb == 64 and
+               colatus.get_option(colatus.OPT_PAIR_GROUP) == 1)
+    slots = ((slices + 1) // 2 + 1 if slices > 1 else 1) if grouped else slices
+    slot_bytes = 12.0 if form == 2 and precision != "fp64" and R * tpb <= 256 else 24.0
+    return slots, slot_bytes, grouped
+
+
 def sweep_kernel_name(N, precision):
     from paper_1208_3444_amd import colatus
-    R, tpb, slots, form = colatus.tile_config(N, precision)
+    R, tpb, slices, form = colatus.tile_config(N, precision)
     acc = {"mixed_twosum": "TwoSum", "mixed_f64acc": "FP64", "fp32": "FP32"}.get(precision,
                                                                                "FP64")
     if form == 2:
         t = "double" if precision == "fp64" else "float"
-        slot = "FP64" if precision == "fp64" or R * tpb > 256 else "FP32"
+        slots, slot_bytes, grouped = slot_layout(N, precision)
+        slot = "FP32" if slot_bytes == 12.0 else "FP64"
+        if grouped:
+            return (f"pair_sweep_sym_grp_kernel<{t}> (2x2 groups of part pairs, four waves "
+                    f"per workgroup; {slots} {slot} slots per particle, summed in {acc} by "
+                    f"the integrator)")
         return (f"pair_sweep_sym_kernel<{t}, R={R}, {tpb // 64} wave(s)> ({slots} {slot} "
                 f"slots per particle, summed in {acc} by the integrator)")
     return f"pair_sweep_kernel<{acc}, R={R}, {tpb} threads, form {form}>"
@@ -220,9 +240,7 @@ def main():
     # the O(N) integrator (finalise the slice partials, kick, drift): HBM-
     # bound; algorithmic bytes per particle = read S partial-sum slots (3
     # components, FP32 or FP64), x and p (48 B); write x and p (48 B)
-    R_, tpb_, slices, form_ = colatus.tile_config(N, args.precision)
-    # FP32 slots (symmetric loop, FP32 pairs, parts of <= 256): 12 B per slot
-    slot_bytes = 12.0 if form_ == 2 and args.precision != "fp64" and R_ * tpb_ <= 256 else 24.0
+    slices, slot_bytes, _ = slot_layout(N, args.precision)
     int_bytes = N * (slot_bytes * slices + 96.0)
     int_launch_ms = int_ms / int_launches
     integrator = {"bound": "hbm", "launch_us": 1e3 * int_launch_ms,
@@ -644,8 +662,9 @@ def periodic_32cubed(w, v0, args, colatus, np, torch, dev):
 
 
 def integrator_64cubed(ws3, x3, m3, colatus, torch):
-    """The integrator beyond the 256 MB Infinity Cache: at 64^3 its 1024 slots
-    per particle are 3.2 GB (FP32 slots) or 6.4 GB (FP64 pairs) per launch.
+    """The integrator beyond the 256 MB Infinity Cache: at 64^3 its 513 slots
+    per particle (1024 parts in 2x2 groups) are 1.6 GB (FP32 slots) or 3.2 GB
+    (FP64 pairs) per launch.
     A 4-step run per precision, its integrator launches timed with hipEvents."""
     v3 = torch.zeros_like(x3)
     integ = {}
@@ -657,8 +676,7 @@ def integrator_64cubed(ws3, x3, m3, colatus, torch):
         torch.cuda.synchronize()
         ms, launches = colatus.timer_read(2, reset=True)
         colatus.set_option(colatus.OPT_TIMER, 0)
-        R3, tpb3, s3, f3 = colatus.tile_config(ws3.N, prec)
-        sb = 12.0 if f3 == 2 and prec != "fp64" and R3 * tpb3 <= 256 else 24.0
+        s3, sb, _ = slot_layout(ws3.N, prec)
         nbytes = ws3.N * (sb * s3 + 96.0)
         integ[prec] = {"launch_ms": ms / launches, "bytes_per_launch": nbytes,
                        "achieved_GBs": nbytes / (ms / launches * 1e-3) / 1e9,

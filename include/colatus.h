@@ -377,7 +377,7 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m,
  * batch == NULL (one box); with the default options the two give the same
  * bits.  The call allocates nothing and copies nothing from the host: its
  * scratch (work items, blocks, the box's common mass, the partial-sum slots)
- * is one fixed device array of about 33.7 MB, which every device the library
+ * is one fixed device array of about 17.4 MB, which every device the library
  * runs on holds from the library's load until the process ends.  Limit:
  * 1 <= N <= 16384 in every precision (N > 16384: COLATUS_ESCRATCH, nothing
  * queued).  Every call on a device shares that device's array, which keeps
@@ -491,6 +491,15 @@ const char *colatus_strerror(int code);
                                      eagerly launched loops (graph-replayed steps
                                      fall inside their call's range), for
                                      rocprofv3 --marker-trace; 0 (default): none */
+#define COLATUS_OPT_PAIR_GROUP 10 /* 1 (default): the forward symmetric loop with 4
+                                     targets per lane and 64 threads runs 2x2 blocks
+                                     of part pairs in one workgroup of four waves,
+                                     adding the two partial sums of each target
+                                     part and of each source part before writing,
+                                     so every particle gets ceil(P/2) + 1 partial-sum
+                                     slots instead of P (P parts of 256 in its box);
+                                     0: one item per workgroup, P slots.  The sums
+                                     differ by the rounding of those additions  */
 int colatus_set_option(int key, int64_t value);
 int colatus_get_option(int key, int64_t *value);
 

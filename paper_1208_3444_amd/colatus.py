@@ -33,6 +33,7 @@ OPT_TILE_SLICES = 6
 OPT_PERSISTENT = 7
 OPT_PAIR_FORM = 8
 OPT_ROCTX = 9
+OPT_PAIR_GROUP = 10
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EFRIEDMANN", -3: "ENODEV", -4: "ENOMEM", -5: "EHIP",
           -6: "ENONFINITE", -7: "ESCRATCH"}

@@ -37,6 +37,7 @@ struct Options {
     std::atomic<int64_t> persistent{0};  // one-shot grid measured faster on gfx950
     std::atomic<int64_t> pair_form{-1};  // -1: heuristic or tuned
     std::atomic<int64_t> roctx{0};       // 1: roctx ranges around calls and eager steps
+    std::atomic<int64_t> pair_group{1};  // 1: 2x2 groups of part pairs (forward, form 2)
 };
 Options g_opt;
 std::mutex g_mu;  // guards the workspace map, tuned shapes and timers
@@ -174,7 +175,7 @@ struct WorkList {
                  const TileCfg &c) const
     {
         return N == n && off == o && eps == e && cfg.R == c.R && cfg.tpb == c.tpb &&
-               cfg.slices == c.slices && cfg.form == c.form;
+               cfg.slices == c.slices && cfg.form == c.form && cfg.group == c.group;
     }
 };
 
@@ -474,13 +475,25 @@ constexpr int64_t kSymMaxN = 262144;
 // cotangent); more share the geometry in the ordered form's chunks of 8.
 constexpr int kSymMaxCot = 3;
 
+// The forward symmetric form in 2x2 groups of part pairs (four waves per
+// workgroup), when COLATUS_OPT_PAIR_GROUP allows it.
+TileCfg grouped_cfg(const Boxes &b)
+{
+    TileCfg c = symmetric_cfg(b, 4, 64);
+    c.group = g_opt.pair_group != 0 ? 1 : 0;
+    return c;
+}
+
 // Built-in heuristic: forward sweeps use the symmetric form (each unordered
 // pair once, one wave per item, four targets per lane), measured at 32^3
-// 1.36x (FP32 pairs) and 1.41x (FP64) faster than the ordered form; so does
-// the adjoint with few cotangents (1.27x and 1.84x).
+// 1.36x (FP32 pairs) and 1.41x (FP64) faster than the ordered form, in 2x2
+// groups of part pairs that halve the slots per particle; the adjoint with
+// few cotangents uses the single-item symmetric form (1.27x and 1.84x).
 TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu, int n_cot = 1)
 {
-    if (b.max_n <= kSymMaxN && (kind == 0 || n_cot <= kSymMaxCot))
+    if (b.max_n <= kSymMaxN && kind == 0)
+        return grouped_cfg(b);
+    if (b.max_n <= kSymMaxN && n_cot <= kSymMaxCot)
         return symmetric_cfg(b, 4, 64);
     return ordered_cfg(b, precision, kind, n_cu);
 }
@@ -511,7 +524,7 @@ TileCfg apply_overrides(TileCfg c, int kind, int precision, const Boxes &b, int 
         want = 0;
     if (want >= 0 && want != c.form) {
         if (want == 2) {
-            c = symmetric_cfg(b, 4, 64);
+            c = kind == 0 ? grouped_cfg(b) : symmetric_cfg(b, 4, 64);
         } else {
             if (c.form == 2)
                 c = ordered_cfg(b, precision, kind, n_cu);
@@ -526,12 +539,20 @@ TileCfg apply_overrides(TileCfg c, int kind, int precision, const Boxes &b, int 
         c.slices = symmetric_cfg(b, c.R, c.tpb).slices;
     else if (g_opt.tile_slices > 0)
         c.slices = (int)g_opt.tile_slices;
+    // groups: the forward symmetric form with 4 targets per lane and 64
+    // threads only, and not when the option turns them off
+    if (kind != 0 || c.form != 2 || c.R != 4 || c.tpb != 64)
+        c.group = 0;
+    else if (g_opt.pair_group == 0)
+        c.group = 0;
     return c;
 }
 
 bool cfg_supported(const TileCfg &c, int kind, int precision)
 {
     const bool fp64 = precision == COLATUS_FP64;
+    if (c.group)
+        return kind == 0 && c.form == 2 && c.R == 4 && c.tpb == 64;
     if (kind == 0 && c.form == 2 && fp64)
         return (c.R == 4 && c.tpb == 64) || (c.R == 2 && c.tpb == 128);
     if (kind == 0 && c.form == 2)
@@ -616,12 +637,143 @@ void build_symmetric_items(const Boxes &b, const TileCfg &cfg, WorkList &wl)
                      [&cost](const WorkItem &a, const WorkItem &c) { return cost(a) > cost(c); });
 }
 
+// Grouped symmetric items (form 2, parts of 256, four waves per group).
+// Parts pair up into super-parts {2A, 2A+1} (the last alone when P is odd).
+// For super-parts A < B the group holds the 2x2 block of items (2A + a,
+// 2B + b) in wave 2a + b: targets in slot B, reactions in slot A; the two
+// waves with the same target part (or source part) add their partial sums
+// before the one write (tmate, rmate).  The pairs inside super-parts
+// (2A, 2A+1: slot A on both sides) and the diagonal pieces (slot
+// ceil(P/2), or slot A for a part alone in its super-part) have no partner
+// and are packed four to a group.  Every particle of a paired part gets
+// ceil(P/2) + 1 slots, one of a lone part ceil(P/2), each written exactly
+// once.  Groups are ordered by their longest item, largest first.
+void build_symmetric_groups(const Boxes &b, const TileCfg &cfg, WorkList &wl)
+{
+    const int64_t U = (int64_t)cfg.R * cfg.tpb;
+    const int nb = (int)b.eps.size();
+    struct Group {
+        WorkItem w[4];
+        int64_t cost;
+    };
+    auto cost = [U, &cfg](const WorkItem &w) -> int64_t {
+        if (w.kind < 0)
+            return 0;
+        const int64_t ns = w.j1 - w.j0;
+        return w.kind == 0 ? 4 * U * ns / 3 : (int64_t)cfg.tpb * ns;
+    };
+    WorkItem pad{};
+    pad.kind = -1;
+    std::vector<Group> groups;
+    std::vector<WorkItem> loose;
+    for (int box = 0; box < nb; ++box) {
+        const int64_t o0 = b.off[box], o1 = b.off[box + 1];
+        const int64_t P = (o1 - o0 + U - 1) / U;
+        const int64_t S2 = (P + 1) / 2;
+        const double eps2 = b.eps[box] * b.eps[box];
+        auto lo = [&](int64_t p) { return o0 + p * U; };
+        auto hi = [&](int64_t p) { return std::min(o0 + (p + 1) * U, o1); };
+        auto paired = [&](int64_t p) { return (p ^ 1) < P; };
+        wl.max_slices = std::max<int>(wl.max_slices, (int)(P > 1 ? S2 + 1 : S2));
+        for (int64_t A = 0; A < S2; ++A)
+            for (int64_t B = A + 1; B < S2; ++B) {
+                Group g;
+                for (WorkItem &w : g.w)
+                    w = pad;
+                g.cost = 0;
+                for (int a = 0; a < 2; ++a)
+                    for (int bb = 0; bb < 2; ++bb) {
+                        const int64_t p = 2 * A + a, q = 2 * B + bb;
+                        if (p >= P || q >= P)
+                            continue;
+                        WorkItem &w = g.w[2 * a + bb];
+                        w.i0 = lo(p);
+                        w.i1 = hi(p);
+                        w.j0 = lo(q);
+                        w.j1 = hi(q);
+                        w.eps2 = eps2;
+                        w.slice = (int32_t)B;
+                        w.rslice = (int32_t)A;
+                        w.box = box;
+                        w.kind = 0;
+                        w.tmate = (int8_t)(2 * B + (1 - bb) < P);
+                        w.rmate = (int8_t)(2 * A + (1 - a) < P);
+                        g.cost = std::max(g.cost, cost(w));
+                    }
+                groups.push_back(g);
+            }
+        for (int64_t p = 0; p < P; ++p) {
+            if ((p & 1) == 0 && paired(p)) {
+                WorkItem w{};
+                w.i0 = lo(p);
+                w.i1 = hi(p);
+                w.j0 = lo(p + 1);
+                w.j1 = hi(p + 1);
+                w.eps2 = eps2;
+                w.slice = (int32_t)(p / 2);
+                w.rslice = (int32_t)(p / 2);
+                w.box = box;
+                w.kind = 0;
+                loose.push_back(w);
+            }
+            const int32_t dslot = (int32_t)(paired(p) ? S2 : p / 2);
+            for (int64_t t0 = lo(p); t0 < hi(p); t0 += cfg.tpb) {
+                WorkItem w{};
+                w.i0 = t0;
+                w.i1 = std::min<int64_t>(t0 + cfg.tpb, hi(p));
+                w.j0 = lo(p);
+                w.j1 = hi(p);
+                w.eps2 = eps2;
+                w.slice = dslot;
+                w.rslice = dslot;
+                w.box = box;
+                w.kind = 1;
+                loose.push_back(w);
+            }
+        }
+        wl.box_first_block.push_back((int32_t)wl.blocks.size());
+        for (int64_t i0 = o0; i0 < o1; i0 += kIntBlock) {
+            const int64_t p = (i0 - o0) / U;
+            IntBlock ib;
+            ib.i0 = i0;
+            ib.i1 = std::min<int64_t>(i0 + kIntBlock, o1);
+            ib.eps = b.eps[box];
+            ib.box = box;
+            ib.n_slices = (int32_t)(paired(p) ? S2 + 1 : S2);
+            wl.blocks.push_back(ib);
+        }
+    }
+    wl.box_first_block.push_back((int32_t)wl.blocks.size());
+    std::stable_sort(loose.begin(), loose.end(), [&cost](const WorkItem &a, const WorkItem &c) {
+        return cost(a) > cost(c);
+    });
+    for (size_t k = 0; k < loose.size(); k += 4) {
+        Group g;
+        g.cost = 0;
+        for (size_t e = 0; e < 4; ++e) {
+            g.w[e] = k + e < loose.size() ? loose[k + e] : pad;
+            g.cost = std::max(g.cost, cost(g.w[e]));
+        }
+        groups.push_back(g);
+    }
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Group &a, const Group &c) { return a.cost > c.cost; });
+    wl.items.reserve(groups.size() * 4);
+    for (const Group &g : groups)
+        for (const WorkItem &w : g.w)
+            wl.items.push_back(w);
+}
+
 void build_worklist(const Boxes &b, int64_t N, const TileCfg &cfg, WorkList &wl)
 {
     wl.items.clear();
     wl.blocks.clear();
     wl.box_first_block.clear();
     wl.max_slices = 0;
+    if (cfg.form == 2 && cfg.group) {
+        build_symmetric_groups(b, cfg, wl);
+        return;
+    }
     if (cfg.form == 2) {
         build_symmetric_items(b, cfg, wl);
         return;
@@ -862,6 +1014,8 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
             if (kind == 0) {
                 const bool fp32 = precision != COLATUS_FP64;
                 if (b.max_n <= kSymMaxN) {
+                    if (g_opt.pair_group != 0)
+                        cand.push_back(grouped_cfg(b));
                     if (fp32)
                         for (auto rt : {std::make_pair(4, 64), std::make_pair(8, 64),
                                         std::make_pair(4, 128)})
@@ -1654,6 +1808,11 @@ int colatus_set_option(int key, int64_t value)
             return COLATUS_EINVAL;
         g_opt.pair_form = value;
         return COLATUS_OK;
+    case COLATUS_OPT_PAIR_GROUP:
+        if (value != 0 && value != 1)
+            return COLATUS_EINVAL;
+        g_opt.pair_group = value;
+        return COLATUS_OK;
     }
     return COLATUS_EINVAL;
 }
@@ -1673,6 +1832,7 @@ int colatus_get_option(int key, int64_t *value)
     case COLATUS_OPT_PERSISTENT: *value = g_opt.persistent; return COLATUS_OK;
     case COLATUS_OPT_PAIR_FORM: *value = g_opt.pair_form; return COLATUS_OK;
     case COLATUS_OPT_ROCTX: *value = g_opt.roctx; return COLATUS_OK;
+    case COLATUS_OPT_PAIR_GROUP: *value = g_opt.pair_group; return COLATUS_OK;
     }
     return COLATUS_EINVAL;
 }

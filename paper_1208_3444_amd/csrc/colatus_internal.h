@@ -13,8 +13,10 @@ namespace colatus {
 // writes its partial sums into slot `slice` of the partial-sum buffer.  In
 // the symmetric form (form 2) a box is cut into parts; kind 0 pairs part p
 // (targets) with part q > p (sources): p's partial from q goes to slot
-// `slice` (= q), q's reaction from p to slot `rslice` (= p); kind 1 is a
-// piece of one part's targets against that whole part (slot p, no reaction).
+// `slice`, q's reaction from p to slot `rslice`; kind 1 is a piece of one
+// part's targets against that whole part (no reaction).  One item per
+// workgroup: slice = q, rslice = p, diagonal slot p.  Grouped (four waves
+// per workgroup): slots numbered by super-part (build_symmetric_groups).
 struct WorkItem {
     int64_t i0, i1;   // targets [i0, i1)
     int64_t j0, j1;   // sources [j0, j1)
@@ -22,7 +24,12 @@ struct WorkItem {
     int32_t slice;    // partial-sum slot of the targets
     int32_t box;
     int32_t rslice;   // partial-sum slot of the sources' reaction (form 2)
-    int32_t kind;     // form 2: 0 = pair of parts, 1 = piece of a diagonal
+    int16_t kind;     // form 2: 0 = pair of parts, 1 = piece of a diagonal,
+                      // -1 = padding of a group (grouped form)
+    int8_t tmate;     // grouped form: 1 if the targets' partial sums are added
+                      // to those of wave (this wave ^ 1) of the group
+    int8_t rmate;     // grouped form: 1 if the reactions are added to those of
+                      // wave (this wave ^ 2) of the group
 };
 
 // Up to kIntBlock particles of one box, for the O(N) kernels (finalise,
@@ -111,6 +118,8 @@ struct TileCfg {
     int tpb;      // threads per block (= sources per LDS tile in forms 0, 1)
     int slices;   // source slices per box (form 2: parts of R * tpb particles)
     int form;     // FP32 pair-loop form (see launch_pair_sweep); 0 for FP64
+    int group = 0; // form 2 with R = 4, tpb = 64: 2x2 groups of part pairs
+                   // per workgroup of four waves (pair_sweep_sym_grp_kernel)
 };
 
 // How the readers add the slots a sweep of this shape writes (SlotMode).

@@ -6,8 +6,9 @@
 // on the device, so the call makes no allocation and no host-to-device copy.
 //
 // It runs the kernels of colatus_forces with the built-in tile shape (the
-// symmetric form: parts of 256 particles, four targets per lane), so with
-// the default options the two entry points give the same bits.
+// symmetric form: parts of 256 particles, four targets per lane, 2x2 groups
+// of part pairs per workgroup), so with the default options the two entry
+// points give the same bits.
 #include "colatus.h"
 #include "colatus_internal.h"
 
@@ -24,7 +25,11 @@ constexpr int64_t kNoAllocMaxN = 16384;
 constexpr int64_t kPart = 256;   // particles per part (4 targets x 64 lanes)
 constexpr int64_t kPiece = 64;   // targets per piece of a diagonal part
 constexpr int64_t kMaxParts = kNoAllocMaxN / kPart;
-constexpr int64_t kMaxItems = kMaxParts * (kMaxParts - 1) / 2 + kMaxParts * (kPart / kPiece);
+constexpr int64_t kMaxSupers = (kMaxParts + 1) / 2;  // super-parts of two parts
+constexpr int64_t kMaxLoose = kMaxParts / 2 + kMaxParts * (kPart / kPiece);
+constexpr int64_t kMaxItems =
+    4 * (kMaxSupers * (kMaxSupers - 1) / 2 + (kMaxLoose + 3) / 4);
+constexpr int64_t kMaxSlots = kMaxSupers + 1;  // partial-sum slots per particle
 constexpr int64_t kMaxBlocks = kNoAllocMaxN / kIntBlock;
 
 constexpr size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -35,10 +40,10 @@ constexpr size_t kOffBoxMass = 512;  // double: the box's common mass or NaN
 constexpr size_t kOffBlocks = 768;   // IntBlock[kMaxBlocks]
 constexpr size_t kOffItems = kOffBlocks + round256(kMaxBlocks * sizeof(IntBlock));
 constexpr size_t kOffPart = kOffItems + round256(kMaxItems * sizeof(WorkItem));
-constexpr size_t kPartBytes = (size_t)kMaxParts * 3 * kNoAllocMaxN * sizeof(double);
+constexpr size_t kPartBytes = (size_t)kMaxSlots * 3 * kNoAllocMaxN * sizeof(double);
 constexpr size_t kOffPhi = kOffPart + kPartBytes;
-constexpr size_t kPhiBytes = (size_t)kMaxParts * kNoAllocMaxN * sizeof(double);
-constexpr size_t kScratchBytes = kOffPhi + kPhiBytes;  // about 33.7 MB
+constexpr size_t kPhiBytes = (size_t)kMaxSlots * kNoAllocMaxN * sizeof(double);
+constexpr size_t kScratchBytes = kOffPhi + kPhiBytes;  // about 17.4 MB
 
 // The scratch array: one copy per device, held until the process ends.  Host
 // code never passes this name to a kernel (on the host it is only a handle);
@@ -68,19 +73,26 @@ int scratch_address(int dev, unsigned char *&out)
     return COLATUS_OK;
 }
 
-// Work items and blocks of one box [0, N) in the symmetric form, written by
-// one thread each: items [0, n_pairs) pair part p (targets, slot q) with part
-// q > p (sources, reaction in slot p), in row order of the (p, q) triangle;
-// items [n_pairs, n_items) are the 64-target pieces of the diagonal parts
-// (part j / 4, piece j % 4: every part but the last has four).  Also the box
-// offsets and the cleared work counter.  The order of the items does not
-// change the result (each writes its own slots).
-__global__ void noalloc_setup_kernel(int64_t N, double eps, int P, int n_pairs, int n_items,
-                                     int n_blocks, WorkItem *__restrict__ items,
-                                     IntBlock *__restrict__ blocks, int64_t *__restrict__ offsets,
-                                     int *__restrict__ counter)
+// Work items and blocks of one box [0, N) in the grouped symmetric form,
+// written by one thread each, four items per group.  Parts pair up into
+// super-parts {2A, 2A+1}; groups [0, n_blk) are the 2x2 blocks of super-parts
+// A < B in row order of the (A, B) triangle: wave 2a + b pairs part 2A + a
+// (targets, slot B) with part 2B + b (sources, reaction in slot A), and the
+// waves sharing a part add their partial sums (tmate, rmate); a missing part
+// leaves a padding item.  The remaining groups hold the loose items four at
+// a time: the pair inside each full super-part (slot A on both sides), then
+// the 64-target pieces of the diagonal parts (part j / 4, piece j % 4; slot
+// ceil(P/2), or A for a part alone in its super-part), then padding.  Every
+// particle gets ceil(P/2) + 1 slots (ceil(P/2) in a lone part).  Also the
+// box offsets and the cleared work counter.  The order of the groups does
+// not change the result (each slot is written by one group).
+__global__ void noalloc_setup_kernel(int64_t N, double eps, int P, int n_blk, int n_intra,
+                                     int n_pieces, int n_items, int n_blocks,
+                                     WorkItem *__restrict__ items, IntBlock *__restrict__ blocks,
+                                     int64_t *__restrict__ offsets, int *__restrict__ counter)
 {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int S2 = (P + 1) / 2;
     if (t == 0) {
         offsets[0] = 0;
         offsets[1] = N;
@@ -90,30 +102,50 @@ __global__ void noalloc_setup_kernel(int64_t N, double eps, int P, int n_pairs, 
         WorkItem w{};
         w.eps2 = eps * eps;
         w.box = 0;
-        if (t < n_pairs) {
-            int k = t, p = 0;
-            while (k >= P - 1 - p) {
-                k -= P - 1 - p;
-                ++p;
+        w.kind = -1;
+        const int g = t / 4, e = t % 4;
+        if (g < n_blk) {
+            int k = g, A = 0;
+            while (k >= S2 - 1 - A) {
+                k -= S2 - 1 - A;
+                ++A;
             }
-            const int q = p + 1 + k;
-            w.i0 = (int64_t)p * kPart;
-            w.i1 = min(w.i0 + kPart, N);
-            w.j0 = (int64_t)q * kPart;
-            w.j1 = min(w.j0 + kPart, N);
-            w.slice = q;
-            w.rslice = p;
-            w.kind = 0;
+            const int B = A + 1 + k;
+            const int a = e >> 1, b = e & 1;
+            const int p = 2 * A + a, q = 2 * B + b;
+            if (p < P && q < P) {
+                w.i0 = (int64_t)p * kPart;
+                w.i1 = min(w.i0 + kPart, N);
+                w.j0 = (int64_t)q * kPart;
+                w.j1 = min(w.j0 + kPart, N);
+                w.slice = B;
+                w.rslice = A;
+                w.kind = 0;
+                w.tmate = (int8_t)(2 * B + (1 - b) < P);
+                w.rmate = (int8_t)(2 * A + (1 - a) < P);
+            }
         } else {
-            const int j = t - n_pairs, p = j / (int)(kPart / kPiece), i = j % (int)(kPart / kPiece);
-            const int64_t p0 = (int64_t)p * kPart, p1 = min(p0 + kPart, N);
-            w.i0 = p0 + (int64_t)i * kPiece;
-            w.i1 = min(w.i0 + kPiece, p1);
-            w.j0 = p0;
-            w.j1 = p1;
-            w.slice = p;
-            w.rslice = p;
-            w.kind = 1;
+            const int l = (g - n_blk) * 4 + e;
+            if (l < n_intra) {
+                w.i0 = (int64_t)(2 * l) * kPart;
+                w.i1 = min(w.i0 + kPart, N);
+                w.j0 = (int64_t)(2 * l + 1) * kPart;
+                w.j1 = min(w.j0 + kPart, N);
+                w.slice = l;
+                w.rslice = l;
+                w.kind = 0;
+            } else if (l - n_intra < n_pieces) {
+                const int j = l - n_intra, p = j / (int)(kPart / kPiece),
+                          i = j % (int)(kPart / kPiece);
+                const int64_t p0 = (int64_t)p * kPart, p1 = min(p0 + kPart, N);
+                w.i0 = p0 + (int64_t)i * kPiece;
+                w.i1 = min(w.i0 + kPiece, p1);
+                w.j0 = p0;
+                w.j1 = p1;
+                w.slice = (p ^ 1) < P ? S2 : p / 2;
+                w.rslice = w.slice;
+                w.kind = 1;
+            }
         }
         items[t] = w;
     }
@@ -123,7 +155,8 @@ __global__ void noalloc_setup_kernel(int64_t N, double eps, int P, int n_pairs, 
         b.i1 = min(b.i0 + kIntBlock, N);
         b.eps = eps;
         b.box = 0;
-        b.n_slices = P;
+        const int p = (int)(b.i0 / kPart);
+        b.n_slices = (p ^ 1) < P ? S2 + 1 : S2;
         blocks[t] = b;
     }
 }
@@ -167,20 +200,25 @@ extern "C" int colatus_forces_noalloc(const double *x, const double *m, int64_t 
     double *part_phi = reinterpret_cast<double *>(base + kOffPhi);
 
     const int P = (int)((N + kPart - 1) / kPart);
-    const int n_pairs = P * (P - 1) / 2;
+    const int S2 = (P + 1) / 2;
+    const int n_blk = S2 * (S2 - 1) / 2;
+    const int n_intra = P / 2;
     const int64_t last_len = N - (int64_t)(P - 1) * kPart;
     const int n_pieces = (P - 1) * (int)(kPart / kPiece) + (int)((last_len + kPiece - 1) / kPiece);
-    const int n_items = n_pairs + n_pieces;
+    const int n_items = 4 * (n_blk + (n_intra + n_pieces + 3) / 4);
     const int n_blocks = (int)((N + kIntBlock - 1) / kIntBlock);
+    if (n_items > kMaxItems || n_blocks > kMaxBlocks)
+        return COLATUS_ESCRATCH;
     const int n_setup = n_items > n_blocks ? n_items : n_blocks;
     hipLaunchKernelGGL(noalloc_setup_kernel, dim3((unsigned)((n_setup + 255) / 256)), dim3(256),
-                       0, s, N, eps, P, n_pairs, n_items, n_blocks, items, blocks, offsets,
-                       counter);
+                       0, s, N, eps, P, n_blk, n_intra, n_pieces, n_items, n_blocks, items,
+                       blocks, offsets, counter);
     if (hipGetLastError() != hipSuccess)
         return COLATUS_EHIP;
     if (launch_box_mass(m, offsets, 1, N, box_mass, s) != hipSuccess)
         return COLATUS_EHIP;
-    const TileCfg cfg{4, 64, P, 2};
+    TileCfg cfg{4, 64, P, 2};
+    cfg.group = 1;
     if (launch_pair_sweep(precision, cfg.form, cfg, phi != nullptr, eps == 0.0, x, m, N, items,
                           n_items, counter, false, box_mass, part, phi ? part_phi : nullptr,
                           nullptr, s) != hipSuccess)

@@ -10,7 +10,10 @@
 // registers, four per lane, while part q's sources pass around the wave one
 // lane per step (DPP rotation) carrying their reaction accumulators.  Each
 // partial-sum slot (part p's pull on a particle) is written once; an O(N)
-// kernel adds the slots in a fixed order, so results are deterministic.
+// kernel adds the slots in a fixed order, so results are deterministic.  The
+// forward loop runs 2x2 blocks of part pairs in workgroups of four waves
+// that add the partial sums of a shared part in LDS before writing, halving
+// the slots.
 //
 // Ordered loops (forms 0 and 1; larger boxes, many-cotangent adjoints):
 //   * a work item is (block of target particles) x (slice of sources); the
@@ -668,6 +671,252 @@ pair_sweep_sym_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Grouped symmetric sweep: four waves per workgroup, each on its own work
+// item.  Parts pair up into super-parts {2A, 2A+1}; the group of two
+// super-parts A < B is the 2x2 block of part pairs {p0, p1} x {q0, q1}
+// (wave 2a + b: targets p_a, sources q_b).  The two waves with the same
+// target part add their targets' partial sums (wave 2a's + wave 2a+1's), the
+// two with the same source part their reactions (wave b's + wave b+2's),
+// through LDS, so the block writes one slot per particle where the single
+// items wrote two: a particle of a box of P parts gets ceil(P/2) + 1 slots
+// instead of P (slot B for super-part B != A, slot A for the pair inside
+// its super-part, the last for its diagonal; a part alone in its super-part
+// puts its diagonal in slot A).  Items without a partner (tmate / rmate 0),
+// and the groups of unrelated items (pairs inside super-parts, diagonal
+// pieces), write their slots directly; padding items (kind -1) only take
+// part in the barriers.  A combined slot is one addition (FP32 with FP32
+// pairs, FP64 with FP64 pairs) of two partial sums of at most 256 terms.
+// ---------------------------------------------------------------------------
+constexpr int kGroupWaves = 4;
+
+// Centre of the bounding box of one wave's valid targets, in every lane.
+template <int R>
+__device__ __forceinline__ void wave_centre(const double (&tx)[R], const double (&ty)[R],
+                                            const double (&tz)[R], const bool (&valid)[R],
+                                            double &cx, double &cy, double &cz)
+{
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (valid[r]) {
+            v[0] = fmin(v[0], tx[r]);
+            v[1] = fmin(v[1], ty[r]);
+            v[2] = fmin(v[2], tz[r]);
+            v[3] = fmax(v[3], tx[r]);
+            v[4] = fmax(v[4], ty[r]);
+            v[5] = fmax(v[5], tz[r]);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            v[q] = fmin(v[q], __shfl_xor(v[q], off, 64));
+            v[q + 3] = fmax(v[q + 3], __shfl_xor(v[q + 3], off, 64));
+        }
+    }
+    cx = uniform(0.5 * (v[0] + v[3]));
+    cy = uniform(0.5 * (v[1] + v[4]));
+    cz = uniform(0.5 * (v[2] + v[5]));
+}
+
+// One slot value of particle i: FP32 sums stored as FP32 without the box
+// mass; FP64 sums stored multiplied by it (scale, 1 when the masses differ).
+template <typename T, bool PHI>
+__device__ __forceinline__ void grp_store(double *__restrict__ part, double *__restrict__ part_phi,
+                                          int64_t N, int64_t slot, int64_t i, T vx, T vy, T vz,
+                                          T vp, double scale)
+{
+    if constexpr (sizeof(T) == 4) {
+        float *pf = reinterpret_cast<float *>(part);
+        pf[(slot * 3 + 0) * N + i] = vx;
+        pf[(slot * 3 + 1) * N + i] = vy;
+        pf[(slot * 3 + 2) * N + i] = vz;
+        if constexpr (PHI)
+            reinterpret_cast<float *>(part_phi)[slot * N + i] = vp;
+    } else {
+        part[(slot * 3 + 0) * N + i] = scale * vx;
+        part[(slot * 3 + 1) * N + i] = scale * vy;
+        part[(slot * 3 + 2) * N + i] = scale * vz;
+        if constexpr (PHI)
+            part_phi[slot * N + i] = scale * vp;
+    }
+}
+
+// The pair loop of one wave's item (R targets per lane; REACT: a pair of
+// parts with the reaction on the sources, else a diagonal piece).  The
+// targets' partial sums are left in (ax, ay, az, ap); the reactions go to
+// rst[NQ][256] (LDS, chunk c at 64 c + lane) when the item has a reaction
+// partner, else straight to slot rslice.
+template <typename T, int R, bool REACT, bool PHI, bool MASK>
+__device__ __forceinline__ void grp_item(const WorkItem &w, const double *__restrict__ X,
+                                         const double *__restrict__ Y,
+                                         const double *__restrict__ Z,
+                                         const double *__restrict__ m, int64_t N, double mbox,
+                                         double *__restrict__ part, double *__restrict__ part_phi,
+                                         T (*rst)[256], T (&ax)[R], T (&ay)[R], T (&az)[R],
+                                         T (&ap)[R], bool (&valid)[R])
+{
+    const int lane = threadIdx.x & 63;
+    const bool eqm = !isnan(mbox);
+    double tx[R], ty[R], tz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        valid[r] = i < w.i1;
+        const int64_t ii = valid[r] ? i : w.i0;
+        tx[r] = X[ii];
+        ty[r] = Y[ii];
+        tz[r] = Z[ii];
+    }
+    double cx, cy, cz;
+    wave_centre<R>(tx, ty, tz, valid, cx, cy, cz);
+    T xi[R], yi[R], zi[R], mi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        if (valid[r]) {
+            xi[r] = (T)(tx[r] - cx);
+            yi[r] = (T)(ty[r] - cy);
+            zi[r] = (T)(tz[r] - cz);
+            mi[r] = (T)m[i];
+        } else {
+            xi[r] = yi[r] = zi[r] = sym_pad<T>();
+            mi[r] = (T)0.0;
+        }
+        ax[r] = ay[r] = az[r] = ap[r] = (T)0.0;
+    }
+    const T eps2 = uniform((T)w.eps2);
+    const double scale = eqm ? mbox : 1.0;
+    const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t j = w.j0 + (int64_t)c * 64 + lane;
+        const bool jv = j < w.j1;
+        T sx = sym_pad<T>(), sy = sym_pad<T>(), sz = sym_pad<T>(), sm = (T)0.0;
+        if (jv) {
+            sx = (T)(X[j] - cx);
+            sy = (T)(Y[j] - cy);
+            sz = (T)(Z[j] - cz);
+            sm = (T)m[j];
+        }
+        T qx = (T)0.0, qy = (T)0.0, qz = (T)0.0, qp = (T)0.0;
+        if (eqm)
+            sym_chunk<T, R, REACT, true, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi,
+                                                 eps2, ax, ay, az, ap);
+        else
+            sym_chunk<T, R, REACT, false, PHI, MASK>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi,
+                                                  mi, eps2, ax, ay, az, ap);
+        if constexpr (REACT) {
+            if (rst) {
+                rst[0][c * 64 + lane] = qx;
+                rst[1][c * 64 + lane] = qy;
+                rst[2][c * 64 + lane] = qz;
+                if constexpr (PHI)
+                    rst[3][c * 64 + lane] = qp;
+            } else if (jv) {
+                grp_store<T, PHI>(part, part_phi, N, (int64_t)w.rslice, j, qx, qy, qz, qp, scale);
+            }
+        }
+    }
+}
+
+template <typename T, bool PHI, bool MASK>
+__global__ __launch_bounds__(64 * kGroupWaves)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void
+pair_sweep_sym_grp_kernel(
+    const double *__restrict__ x, const double *__restrict__ m, int64_t N,
+    const WorkItem *__restrict__ items, int n_groups, int *__restrict__ counter,
+    int persistent, const double *__restrict__ box_mass, double *__restrict__ part,
+    double *__restrict__ part_phi, int64_t *__restrict__ step_inc)
+{
+    constexpr int NQ = PHI ? 4 : 3;
+    // targets exported by the odd waves of a target pair; reactions of the
+    // waves with a reaction partner
+    __shared__ T tbuf[kGroupWaves / 2][NQ][256];
+    __shared__ T rbuf[kGroupWaves][NQ][256];
+    __shared__ int s_item;
+    const double *X = x, *Y = x + N, *Z = x + 2 * N;
+    // the wave index is uniform in the wave: the item loads to scalar registers
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (step_inc && blockIdx.x == 0 && threadIdx.x == 0)
+        *step_inc += 1;
+
+    for (int iter = 0;; ++iter) {
+        const int g = next_item(persistent, counter, &s_item, iter);
+        if (g >= n_groups)
+            break;
+        const WorkItem w = items[(int64_t)g * kGroupWaves + wave];
+        const double mbox = (w.kind >= 0 && box_mass) ? box_mass[w.box] : NAN;
+        const double scale = isnan(mbox) ? 1.0 : mbox;
+        T ax[4], ay[4], az[4], ap[4];
+        bool valid[4] = {false, false, false, false};
+        if (w.kind == 0) {
+            grp_item<T, 4, true, PHI, MASK>(w, X, Y, Z, m, N, mbox, part, part_phi,
+                                            w.rmate ? rbuf[wave] : nullptr, ax, ay, az, ap,
+                                            valid);
+            if (!w.tmate) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (valid[r])
+                        grp_store<T, PHI>(part, part_phi, N, (int64_t)w.slice,
+                                          w.i0 + (int64_t)(r * 64 + lane), ax[r], ay[r], az[r],
+                                          ap[r], scale);
+            } else if (wave & 1) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    tbuf[wave >> 1][0][r * 64 + lane] = ax[r];
+                    tbuf[wave >> 1][1][r * 64 + lane] = ay[r];
+                    tbuf[wave >> 1][2][r * 64 + lane] = az[r];
+                    if constexpr (PHI)
+                        tbuf[wave >> 1][3][r * 64 + lane] = ap[r];
+                }
+            }
+        } else if (w.kind == 1) {
+            T bx[1], by[1], bz[1], bp[1];
+            bool v1[1];
+            grp_item<T, 1, false, PHI, MASK>(w, X, Y, Z, m, N, mbox, part, part_phi, nullptr, bx,
+                                             by, bz, bp, v1);
+            if (v1[0])
+                grp_store<T, PHI>(part, part_phi, N, (int64_t)w.slice, w.i0 + lane, bx[0], by[0],
+                                  bz[0], bp[0], scale);
+        }
+        __syncthreads();
+        if (w.kind == 0 && w.tmate && !(wave & 1)) {
+            // targets: this wave's (sources q0) + the odd wave's (sources q1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (valid[r]) {
+                    const int e = r * 64 + lane;
+                    T vp = (T)0.0;
+                    if constexpr (PHI)
+                        vp = ap[r] + tbuf[wave >> 1][3][e];
+                    grp_store<T, PHI>(part, part_phi, N, (int64_t)w.slice, w.i0 + e,
+                                      ax[r] + tbuf[wave >> 1][0][e], ay[r] + tbuf[wave >> 1][1][e],
+                                      az[r] + tbuf[wave >> 1][2][e], vp, scale);
+                }
+        }
+        if (w.kind == 0 && w.rmate && wave < 2) {
+            // reactions on sources q_b: from targets p0 (wave b) + p1 (wave b + 2)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int e = c * 64 + lane;
+                const int64_t j = w.j0 + e;
+                if (j < w.j1) {
+                    T vp = (T)0.0;
+                    if constexpr (PHI)
+                        vp = rbuf[wave][3][e] + rbuf[wave + 2][3][e];
+                    grp_store<T, PHI>(part, part_phi, N, (int64_t)w.rslice, j,
+                                      rbuf[wave][0][e] + rbuf[wave + 2][0][e],
+                                      rbuf[wave][1][e] + rbuf[wave + 2][1][e],
+                                      rbuf[wave][2][e] + rbuf[wave + 2][2][e], vp, scale);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Symmetric adjoint sweep (form 2, FP32 pairs, one cotangent per launch).
 // The adjoint pair term M(d)(m_k lam_j - m_j lam_k), M(d) = r^-3 I -
 // 3 r^-5 d d^T, changes sign when k and j swap (M(-d) = M(d)), so each
@@ -1164,9 +1413,40 @@ hipError_t dispatch_sym_flags(bool phi, bool mask, const FwdArgs &a)
                 : launch_sym<T, ACC, R, W, false, false>(a);
 }
 
+// Grouped symmetric sweep: a.items holds kGroupWaves items per group.
+template <typename T, bool PHI, bool MASK>
+hipError_t launch_sym_grp(const FwdArgs &a)
+{
+    auto k = pair_sweep_sym_grp_kernel<T, PHI, MASK>;
+    const int n_groups = a.n_items / kGroupWaves;
+    const int tpb = 64 * kGroupWaves;
+    int grid = a.persistent ? persistent_grid(k, tpb, 0, n_groups) : n_groups;
+    if (grid <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(tpb), 0, a.s, a.x, a.m, a.N, a.items, n_groups,
+                       a.counter, a.persistent ? 1 : 0, a.box_mass, a.part, a.part_phi,
+                       a.step_inc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_sym_grp(bool phi, bool mask, const FwdArgs &a)
+{
+    if (a.n_items % kGroupWaves != 0)
+        return hipErrorInvalidValue;
+    if (phi)
+        return mask ? launch_sym_grp<T, true, true>(a) : launch_sym_grp<T, true, false>(a);
+    return mask ? launch_sym_grp<T, false, true>(a) : launch_sym_grp<T, false, false>(a);
+}
+
 template <typename T, int ACC>
 hipError_t dispatch_sym(const TileCfg &cfg, bool phi, bool mask, const FwdArgs &a)
 {
+    if (cfg.group) {
+        if (cfg.R != 4 || cfg.tpb != 64)
+            return hipErrorInvalidValue;
+        return dispatch_sym_grp<T>(phi, mask, a);
+    }
     if constexpr (sizeof(T) == 4) {
         if (cfg.R == 4 && cfg.tpb == 64)
             return dispatch_sym_flags<T, ACC, 4, 1>(phi, mask, a);

@@ -261,6 +261,12 @@ def test_options_and_tile_config():
     assert L.colatus_set_option(9, 5) == 0
     assert L.colatus_get_option(9, ctypes.byref(v)) == 0 and v.value == 1
     assert L.colatus_set_option(9, 0) == 0
+    # 2x2 groups of part pairs: on by default, 0 or 1 only
+    assert L.colatus_get_option(10, ctypes.byref(v)) == 0 and v.value == 1
+    assert L.colatus_set_option(10, 2) == EINVAL
+    assert L.colatus_set_option(10, 0) == 0
+    assert L.colatus_get_option(10, ctypes.byref(v)) == 0 and v.value == 0
+    assert L.colatus_set_option(10, 1) == 0
     # forward sweeps and the few-cotangent adjoint: symmetric form, parts of
     # 4 x 64 particles
     assert colatus.tile_config(32768, "mixed") == (4, 64, 128, 2)
