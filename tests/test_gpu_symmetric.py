@@ -11,9 +11,10 @@ Tolerances: the per-particle relative bars of the ordered loop (median 1e-6,
 max 1e-4) on the lattice and the 32^3 workload; on random clouds the
 conditioned error |a - a_ref| / sum_j |term_j| <= 5e-6.  Every partial sum
 here is one FP32 sum of at most 256 terms (a target's from one part, a
-source's reaction from one part), whose conditioned error is at most about
-(256 + 10) u = 1.6e-5 (u = 2^-24, 10 u for the pair term itself); the
-largest value observed is 3.7e-6.
+source's reaction from one part), or, in the forward loop's 2x2 groups
+(4 targets per lane, 64 threads), the FP32 sum of two such sums, whose
+conditioned error is at most about (257 + 10) u = 1.6e-5 (u = 2^-24, 10 u
+for the pair term itself); the largest value observed is 3.7e-6.
 """
 import numpy as np
 import pytest
