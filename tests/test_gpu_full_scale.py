@@ -138,3 +138,72 @@ def test_ftle_batched_equals_single_and_precisions_agree(dev):
                        checkpoint_every=10, precision="mixed_twosum")[0].cpu().numpy()
     print(f"FTLE fp64 {np.round(lt64[:4], 6)} mixed {np.round(ltm[:4], 6)}", flush=True)
     assert np.max(np.abs(ltm - lt64)) <= 1e-3 * max(1.0, np.abs(lt64).max())
+
+
+def test_ftle_32cubed_full_run_blocks_match_finite_differences(dev):
+    """The FTLE workload at full size: N = 32^3, the whole 200-step run from
+    a = 0.2 to 1 with checkpoints every 20.  For 4 of its 64 tracers the
+    library's 3x3 blocks B_t = d x_t(a_end) / d x_t(a_begin) (read off the
+    adjoint, FP64) are compared column by column with central differences of
+    the FP64 forward run, perturbing x_t(a_begin) by +-h e_c.  A column counts
+    when the differences at h = 1e-6 and 10 h agree to 1e-5 (else chaotic
+    growth has left the linear regime and the column is reported as
+    ill-conditioned); counted columns must agree with the h = 1e-6
+    difference to 1e-5 relative to the block's norm.  Then sigma_max and the
+    exponents of those tracers from the difference blocks (where all three
+    columns count) against the library's, and the mixed-precision FTLE of
+    the same tracers against the FP64 one."""
+    w, v0 = _adjoint_setup(200)
+    n_steps, a_end = w.n_steps, w.a_end
+    tracers = [int(t) for t in w.extra["tracers"][:4]]
+    mt = to_dev(w.m, dev)
+    args = [to_dev(w.x, dev), to_dev(v0, dev), mt]
+    lt, ll, B = (t.cpu().numpy() for t in colatus.ftle(
+        *args, w.eps, w.G, w.cosmo, w.a_begin, a_end, n_steps, tracers,
+        checkpoint_every=w.extra["checkpoint_every"], precision="fp64"))
+    ltm = colatus.ftle(*args, w.eps, w.G, w.cosmo, w.a_begin, a_end, n_steps, tracers,
+                       checkpoint_every=w.extra["checkpoint_every"],
+                       precision="mixed_twosum")[0].cpu().numpy()
+
+    def x_end(x):
+        xt, vt = to_dev(x, dev), to_dev(v0, dev)
+        colatus.run(xt, vt, mt, w.eps, w.G, w.cosmo, w.a_begin, a_end, n_steps, precision="fp64")
+        return xt.cpu().numpy()
+
+    counted = 0
+    full = []
+    for i, t in enumerate(tracers):
+        Bfd = np.zeros((3, 3))
+        cols_ok = 0
+        for c in range(3):
+            fd = {}
+            for h in (1e-5, 1e-6):
+                xp, xm = w.x.copy(), w.x.copy()
+                xp[c, t] += h
+                xm[c, t] -= h
+                fd[h] = (x_end(xp)[:, t] - x_end(xm)[:, t]) / (2 * h)
+            scale = np.linalg.norm(B[i])
+            linear = np.linalg.norm(fd[1e-5] - fd[1e-6]) <= 1e-5 * scale
+            err = np.linalg.norm(B[i][:, c] - fd[1e-6]) / scale
+            print(f"tracer {t} column {c}: |B - fd| / |B| {err:.2e}"
+                  f"{'' if linear else ' (ill-conditioned)'}", flush=True)
+            Bfd[:, c] = fd[1e-6]
+            if linear:
+                counted += 1
+                cols_ok += 1
+                assert err <= 1e-5, (t, c)
+        if cols_ok == 3:
+            full.append((i, Bfd))
+    print(f"{counted} of 12 columns in the linear regime", flush=True)
+    assert counted >= 9, "too few columns in the linear regime"
+    # exponents from the difference blocks, over the library's time span
+    for i, Bfd in full:
+        s_fd = np.linalg.svd(Bfd, compute_uv=False)[0]
+        s_lib = np.linalg.svd(B[i], compute_uv=False)[0]
+        span_lna = math.log(a_end / w.a_begin)
+        print(f"tracer {tracers[i]}: sigma_max fd {s_fd:.8e} library {s_lib:.8e}; exponent "
+              f"per ln a {math.log(s_fd) / span_lna:.8f} / {ll[i]:.8f}", flush=True)
+        assert abs(s_fd / s_lib - 1) <= 1e-5
+        assert abs(math.log(s_fd) / span_lna - ll[i]) <= 1e-5 * max(1.0, abs(ll[i]))
+    print(f"FTLE per unit time fp64 {lt} mixed {ltm}", flush=True)
+    assert np.max(np.abs(ltm - lt)) <= 1e-3 * max(1.0, np.abs(lt).max())
