@@ -1481,7 +1481,7 @@ int ewald_args(Workspace *ws, const double *x, const double *m, int64_t N, Ewald
 {
     const int n_sk = (int)std::max<int64_t>(1, std::min<int64_t>(256, N / 256));
     const int64_t blocks = (N + 63) / 64;
-    const int n_kc = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4096 + blocks - 1) / blocks));
+    const int n_kc = (int)std::max<int64_t>(1, std::min<int64_t>(64, (8192 + blocks - 1) / blocks));
     const size_t K = (size_t)std::max(1, ws->ew_K);
     CHECK_RC(ensure(ws->ew_skp, (size_t)n_sk * K * 2 * sizeof(double)));
     CHECK_RC(ensure(ws->ew_S, K * 2 * sizeof(double)));

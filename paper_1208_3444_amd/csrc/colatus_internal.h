@@ -376,7 +376,7 @@ struct EwaldArgs {
     const double *coef;    // [K]: 2 (4 pi / L^3) exp(-k^2 / 4 alpha^2) / k^2
     double2 *sk_part;      // [n_sk_chunks][K]
     int n_sk_chunks;
-    double2 *S;            // [K]
+    double2 *S;            // [K]: W(k) = coef(k) S(k), the weighted structure factor
     int n_k_chunks;        // ranges of segments for the per-particle sums
     double *kpart_g;       // [n_k_chunks][3][N]
     double *kpart_p;       // [n_k_chunks][N]

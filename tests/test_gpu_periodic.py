@@ -2,7 +2,7 @@
 colatus_run_periodic) against the oracle's Ewald sums.
 
 The library and the oracle split the sum differently (the library keeps
-only the nearest image in real space, alpha L about 11.8 in FP64 and 9.2 in
+only the nearest image in real space, alpha L = 12.08 in FP64 and 9.23 in
 the FP32 forms; the oracle 27 images at alpha L = 6), so agreement also
 checks that the split does not matter.  Errors are measured against the sum
 of the pair magnitudes, |d g_k| / (G sum_j m_j / |d*_jk|^2) (d* the nearest
