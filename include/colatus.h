@@ -511,8 +511,12 @@ int colatus_timer_read(int kind, double *total_ms, int64_t *launches, int reset)
 
 /* Tile shape the library would use (or has tuned) for N particles in one
  * box at the given precision: out[0] = targets per lane R, out[1] = threads
- * per block, out[2] = source slices, out[3] = pair-loop form (see
- * COLATUS_OPT_PAIR_FORM).  kind 0 = forward, 1 = adjoint.                 */
+ * per block, out[2] = source slices (form 2: the parts P of R x threads
+ * particles), out[3] = pair-loop form (see COLATUS_OPT_PAIR_FORM).  kind 0 =
+ * forward, 1 = adjoint.  A forward form 2 with R = 4 and 64 threads runs in
+ * 2x2 groups of part pairs while COLATUS_OPT_PAIR_GROUP is 1, and then
+ * writes ceil(P/2) + 1 partial-sum slots per particle (P = 1: one) instead
+ * of P.                                                                    */
 int colatus_tile_config(int64_t N, int precision, int kind, int32_t out[4]);
 
 /* Release all cached device scratch of every (device, stream) workspace,
