@@ -374,8 +374,12 @@ int colatus_adjoint(const double *x0, const double *v0, const double *m,
 /* colatus_forces without any allocation, for callers that cannot allocate
  * device memory: code under stream capture, tight serving loops, harnesses
  * that forbid hipMalloc.  Same arguments and results as colatus_forces with
- * batch == NULL (one box); with the default options the two give the same
- * bits.  The call allocates nothing and copies nothing from the host: its
+ * batch == NULL (one box).  It always runs the symmetric pair loop in 2x2
+ * groups: with COLATUS_OPT_PAIR_FORM = 2 (and the other options at their
+ * defaults) the two give the same bits; at the default pair form, boxes
+ * too small to fill the GPU with symmetric items (up to about 11 000
+ * particles) take the ordered loop in colatus_forces, and the two agree to
+ * the precision's rounding.  The call allocates nothing and copies nothing from the host: its
  * scratch (work items, blocks, the box's common mass, the partial-sum slots)
  * is one fixed device array of about 17.4 MB, which every device the library
  * runs on holds from the library's load until the process ends.  Limit:

@@ -5,10 +5,11 @@
 // lives in one file-scope device array; the items and blocks are generated
 // on the device, so the call makes no allocation and no host-to-device copy.
 //
-// It runs the kernels of colatus_forces with the built-in tile shape (the
-// symmetric form: parts of 256 particles, four targets per lane, 2x2 groups
-// of part pairs per workgroup), so with the default options the two entry
-// points give the same bits.
+// It runs the kernels of colatus_forces with the symmetric form's tile shape
+// (parts of 256 particles, four targets per lane, 2x2 groups of part pairs
+// per workgroup), so with that form selected the two entry points give the
+// same bits (colatus_forces takes the ordered loop for boxes too small to
+// fill the GPU with symmetric items, and then agrees to rounding).
 #include "colatus.h"
 #include "colatus_internal.h"
 

@@ -270,7 +270,12 @@ def test_options_and_tile_config():
     # forward sweeps and the few-cotangent adjoint: symmetric form, parts of
     # 4 x 64 particles
     assert colatus.tile_config(32768, "mixed") == (4, 64, 128, 2)
-    assert colatus.tile_config(1000, "fp32") == (4, 64, 4, 2)
+    # boxes too small to fill the GPU with symmetric items (fewer than 1024
+    # waves): the ordered loop, one target per lane, one source tile per slice
+    assert colatus.tile_config(1000, "fp32") == (1, 128, 8, 0)
+    assert colatus.tile_config(4096, "fp64") == (1, 128, 32, 0)
+    assert colatus.tile_config(8000, "mixed") == (1, 256, 32, 0)
+    assert colatus.tile_config(13824, "mixed") == (4, 64, 54, 2)
     assert colatus.tile_config(32768, "fp64") == (4, 64, 128, 2)
     assert colatus.tile_config(32768, "mixed", kind=1) == (4, 64, 128, 2)
     assert colatus.tile_config(262144, "mixed") == (4, 64, 1024, 2)

@@ -6,7 +6,9 @@ part and the two that share a source part before writing them, so every
 particle gets ceil(P/2) + 1 partial-sum slots instead of P.  The grouped
 and single-item forms evaluate the same pair terms in the same order; the
 grouped sums differ by one rounding per combined slot (FP32 with FP32
-pairs, FP64 with FP64 pairs).  Checked here:
+pairs, FP64 with FP64 pairs).  The symmetric form is forced at every size
+(COLATUS_OPT_PAIR_FORM = 2: boxes too small to fill the GPU take the
+ordered loop by default).  Checked here:
   * both forms against each other and against the oracle, for box sizes
     with an odd and an even number of parts, ragged last parts, a lone
     part, unequal masses, the potential and softening zero;
@@ -47,9 +49,13 @@ def _pot_scale(x, m, eps):
 
 @pytest.fixture
 def grouping():
+    # the symmetric form at every size (small boxes take the ordered loop by
+    # default)
+    colatus.set_option(colatus.OPT_PAIR_FORM, 2)
     yield
     colatus.set_option(colatus.OPT_PAIR_GROUP, 1)
     colatus.set_option(colatus.OPT_PERSISTENT, 0)
+    colatus.set_option(colatus.OPT_PAIR_FORM, -1)
 
 
 def _forces(x, m, eps, dev, prec, group, with_phi=False, batch=None, a=1.0):

@@ -3,8 +3,12 @@ both called through the C ABI on the same device buffers.
 
 Two calls in a row, the second with a smaller input (the scratch array keeps
 the first call's contents), in every precision, with and without the
-potential: the outputs must be bitwise equal (same kernels, same slots, same
-fixed-order slot sum).  The oversize case is rejected on the host.
+potential: the outputs must be bitwise equal to colatus_forces with the
+symmetric pair loop (COLATUS_OPT_PAIR_FORM = 2: same kernels, same slots,
+same fixed-order slot sum), and agree with colatus_forces at its default
+tile shape (the ordered loop for the smaller case, whose symmetric items
+would not fill the GPU) to the precision's tolerance.  The oversize case is
+rejected on the host.
 """
 import ctypes
 
@@ -54,13 +58,21 @@ def test_noalloc_equals_forces_two_calls(dev, prec, with_phi):
     cases = [(x1, m1, 0.004, 1.0, 0.7), (w2.x[:, :2900], w2.m[:2900], w2.eps, 1.0, 0.1)]
     for k, (x, m, eps, G, a) in enumerate(cases):
         xt, mt = to_dev(x, dev), to_dev(m, dev)
-        ref_acc, ref_phi = _call("colatus_forces", xt, mt, eps, G, a, prec, with_phi)
+        colatus.set_option(colatus.OPT_PAIR_FORM, 2)
+        try:
+            ref_acc, ref_phi = _call("colatus_forces", xt, mt, eps, G, a, prec, with_phi)
+        finally:
+            colatus.set_option(colatus.OPT_PAIR_FORM, -1)
         got_acc, got_phi = _call("colatus_forces_noalloc", xt, mt, eps, G, a, prec, with_phi)
+        dft_acc, _ = _call("colatus_forces", xt, mt, eps, G, a, prec, False)
+        e_dft = rel_err_per_particle(got_acc, dft_acc)
         print(f"call {k} N={m.shape[0]} {prec} phi={with_phi}: max |diff| "
-              f"{np.max(np.abs(got_acc - ref_acc)):.3e}", flush=True)
+              f"{np.max(np.abs(got_acc - ref_acc)):.3e}; against the default tile shape "
+              f"max relative {e_dft.max():.3e}", flush=True)
         assert np.array_equal(got_acc, ref_acc), (k, prec)
         if with_phi:
             assert np.array_equal(got_phi, ref_phi), (k, prec)
+        assert e_dft.max() <= (1e-12 if prec == "fp64" else 1e-4), (k, prec)
     # and the last call against the oracle, to the precision's tolerance
     ref = oracle.forces(cases[1][0], cases[1][1], cases[1][2], a=0.1)
     e = rel_err_per_particle(got_acc, ref)
