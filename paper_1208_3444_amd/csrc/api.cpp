@@ -496,30 +496,33 @@ int64_t symmetric_waves(const Boxes &b)
     return w;
 }
 
-// Forward sweeps whose symmetric items would give fewer waves than this in
-// all leave most of the GPU idle (one wave per CU at 16^3); they take the
+// Sweeps whose symmetric items would give fewer waves than this in all
+// leave most of the GPU idle (one wave per CU at 16^3); they take the
 // ordered loop with one target per lane and one source tile per slice
-// (small_boxes_cfg), measured faster in both precisions at 16^3 (4096
-// particles, 200 symmetric waves: 2.8x) and 20^3 (8000, 656 waves: 1.37x,
-// 1.19x in FP64) and slower from 24^3 (13824, 1700 waves).
+// (small_boxes_cfg).  Measured per step of a run: the forward 2.8x faster
+// in both precisions at 16^3 (4096 particles, 200 symmetric waves) and
+// 1.37x (1.19x in FP64) at 20^3 (8000, 656 waves); an adjoint step (its
+// forward and adjoint sweeps) 1.6x at 16^3 and 1.2x (1.06x) at 20^3; both
+// slower from 24^3 (13824, 1701 waves).
 constexpr int64_t kSmallSymWaves = 1024;
 
-TileCfg small_boxes_cfg(const Boxes &b)
+TileCfg small_boxes_cfg(const Boxes &b, int kind)
 {
-    const int tpb = b.max_n <= 6144 ? 128 : 256;
+    // the adjoint's ordered loop runs 256 threads per block
+    const int tpb = kind == 0 && b.max_n <= 6144 ? 128 : 256;
     return TileCfg{1, tpb, (int)std::max<int64_t>(1, (b.max_n + tpb - 1) / tpb), 0};
 }
 
 // Built-in heuristic: forward sweeps use the symmetric form (each unordered
 // pair once, one wave per item, four targets per lane), measured at 32^3
 // 1.36x (FP32 pairs) and 1.41x (FP64) faster than the ordered form, in 2x2
-// groups of part pairs that halve the slots per particle, unless the boxes
-// are too small to fill the GPU with its items; the adjoint with few
-// cotangents uses the single-item symmetric form (1.27x and 1.84x).
+// groups of part pairs that halve the slots per particle; the adjoint with
+// few cotangents uses the single-item symmetric form (1.27x and 1.84x);
+// both unless the boxes are too small to fill the GPU with its items.
 TileCfg heuristic_cfg(const Boxes &b, int precision, int kind, int n_cu, int n_cot = 1)
 {
-    if (kind == 0 && symmetric_waves(b) < kSmallSymWaves)
-        return small_boxes_cfg(b);
+    if (symmetric_waves(b) < kSmallSymWaves)
+        return small_boxes_cfg(b, kind);
     if (b.max_n <= kSymMaxN && kind == 0)
         return grouped_cfg(b);
     if (b.max_n <= kSymMaxN && n_cot <= kSymMaxCot)
@@ -1045,7 +1048,7 @@ int prepare_worklist(Workspace *ws, int kind, const Boxes &b, int64_t N, int pre
                 if (b.max_n <= kSymMaxN) {
                     if (g_opt.pair_group != 0)
                         cand.push_back(grouped_cfg(b));
-                    cand.push_back(small_boxes_cfg(b));
+                    cand.push_back(small_boxes_cfg(b, 0));
                     if (fp32)
                         for (auto rt : {std::make_pair(4, 64), std::make_pair(8, 64),
                                         std::make_pair(4, 128)})

@@ -276,6 +276,8 @@ def test_options_and_tile_config():
     assert colatus.tile_config(4096, "fp64") == (1, 128, 32, 0)
     assert colatus.tile_config(8000, "mixed") == (1, 256, 32, 0)
     assert colatus.tile_config(13824, "mixed") == (4, 64, 54, 2)
+    assert colatus.tile_config(4096, "mixed", kind=1) == (1, 256, 16, 0)
+    assert colatus.tile_config(13824, "mixed", kind=1) == (4, 64, 54, 2)
     assert colatus.tile_config(32768, "fp64") == (4, 64, 128, 2)
     assert colatus.tile_config(32768, "mixed", kind=1) == (4, 64, 128, 2)
     assert colatus.tile_config(262144, "mixed") == (4, 64, 1024, 2)

@@ -207,9 +207,14 @@ def test_force_vjp_symmetric_matches_oracle(dev, form2, N, C, spread, eps):
 
 
 def test_force_vjp_symmetric_is_the_default_for_few_cotangents(dev):
-    assert colatus.tile_config(700, "mixed_twosum", kind=1)[3] == 2
-    x, m = inputs.random_cloud(700, 9, scale=0.5)
-    lam = np.random.default_rng(1).standard_normal((1, 3, 700))
+    """Boxes large enough to fill the GPU with symmetric items (about 11 000
+    particles and more) take the symmetric adjoint loop by default, smaller
+    ones the ordered loop; both give the oracle's VJP."""
+    N = 12000
+    assert colatus.tile_config(N, "mixed_twosum", kind=1)[3] == 2
+    assert colatus.tile_config(700, "mixed_twosum", kind=1) == (1, 256, 3, 0)
+    x, m = inputs.random_cloud(N, 9, scale=0.5)
+    lam = np.random.default_rng(1).standard_normal((1, 3, N))
     xt, mt, lt = to_dev(x, dev), to_dev(m, dev), to_dev(lam, dev)
     a = colatus.force_vjp(xt, mt, lt, 0.02, 1.0, precision="mixed_twosum").cpu().numpy()
     colatus.set_option(colatus.OPT_PAIR_FORM, 0)
