@@ -207,3 +207,25 @@ def test_ftle_32cubed_full_run_blocks_match_finite_differences(dev):
         assert abs(math.log(s_fd) / span_lna - ll[i]) <= 1e-5 * max(1.0, abs(ll[i]))
     print(f"FTLE per unit time fp64 {lt} mixed {ltm}", flush=True)
     assert np.max(np.abs(ltm - lt)) <= 1e-3 * max(1.0, np.abs(lt).max())
+
+
+@pytest.mark.parametrize("N", [262144, 262145])
+def test_largest_symmetric_box_and_first_ordered_box(dev, N):
+    """The two sides of the switch between the pair loops: 2^18 particles
+    in one box is the largest the symmetric loop takes (1024 parts in 2x2
+    groups, 513 slots per particle); one more particle takes the ordered
+    loop.  256 sampled targets of a random cloud against the oracle, in
+    both precisions, to the per-particle bars of the 64^3 sweep."""
+    cfg = colatus.tile_config(N, "mixed_twosum")
+    assert (cfg[3] == 2) == (N <= 262144), cfg
+    x, m = inputs.random_cloud(N, 31, scale=1.0)
+    eps = 0.5 / 64
+    t = np.sort(np.random.Generator(np.random.PCG64(5)).choice(N, 256, replace=False))
+    ref = oracle.forces_targets(x, m, t, eps, a=0.5)
+    xt, mt = to_dev(x, dev), to_dev(m, dev)
+    for prec, med, mx in (("fp64", 1e-12, 1e-12), ("mixed_twosum", 1e-6, 1e-4)):
+        got = colatus.forces(xt, mt, eps, a=0.5, precision=prec).cpu().numpy()[:, t]
+        e = rel_err_per_particle(got, ref)
+        print(f"N={N} {prec} tile {colatus.tile_config(N, prec)}: median {np.median(e):.2e} "
+              f"max {e.max():.2e}", flush=True)
+        assert np.median(e) <= med and e.max() <= mx
