@@ -84,82 +84,115 @@ int scratch_address(int dev, unsigned char *&out)
 // a time: the pair inside each full super-part (slot A on both sides), then
 // the 64-target pieces of the diagonal parts (part j / 4, piece j % 4; slot
 // ceil(P/2), or A for a part alone in its super-part), then padding.  Every
-// particle gets ceil(P/2) + 1 slots (ceil(P/2) in a lone part).  Also the
-// box offsets and the cleared work counter.  The order of the groups does
-// not change the result (each slot is written by one group).
+// particle gets ceil(P/2) + 1 slots (ceil(P/2) in a lone part).  The order of
+// the groups does not change the result (each slot is written by one group).
+// The functions below are plain host-and-device code, so the list can be
+// checked on the host.
+//
+// Work item t (t < n_items) of that list.
+__host__ __device__ inline WorkItem noalloc_item(int t, int64_t N, double eps, int P, int n_blk,
+                                                 int n_intra, int n_pieces)
+{
+    const int S2 = (P + 1) / 2;
+    WorkItem w{};
+    w.eps2 = eps * eps;
+    w.box = 0;
+    w.kind = -1;
+    const int g = t / 4, e = t % 4;
+    if (g < n_blk) {
+        int k = g, A = 0;
+        while (k >= S2 - 1 - A) {
+            k -= S2 - 1 - A;
+            ++A;
+        }
+        const int B = A + 1 + k;
+        const int a = e >> 1, b = e & 1;
+        const int p = 2 * A + a, q = 2 * B + b;
+        if (p < P && q < P) {
+            w.i0 = (int64_t)p * kPart;
+            w.i1 = w.i0 + kPart < N ? w.i0 + kPart : N;
+            w.j0 = (int64_t)q * kPart;
+            w.j1 = w.j0 + kPart < N ? w.j0 + kPart : N;
+            w.slice = B;
+            w.rslice = A;
+            w.kind = 0;
+            w.tmate = (int8_t)(2 * B + (1 - b) < P);
+            w.rmate = (int8_t)(2 * A + (1 - a) < P);
+        }
+    } else {
+        const int l = (g - n_blk) * 4 + e;
+        if (l < n_intra) {
+            w.i0 = (int64_t)(2 * l) * kPart;
+            w.i1 = w.i0 + kPart < N ? w.i0 + kPart : N;
+            w.j0 = (int64_t)(2 * l + 1) * kPart;
+            w.j1 = w.j0 + kPart < N ? w.j0 + kPart : N;
+            w.slice = l;
+            w.rslice = l;
+            w.kind = 0;
+        } else if (l - n_intra < n_pieces) {
+            const int j = l - n_intra, p = j / (int)(kPart / kPiece), i = j % (int)(kPart / kPiece);
+            const int64_t p0 = (int64_t)p * kPart, p1 = p0 + kPart < N ? p0 + kPart : N;
+            w.i0 = p0 + (int64_t)i * kPiece;
+            w.i1 = w.i0 + kPiece < p1 ? w.i0 + kPiece : p1;
+            w.j0 = p0;
+            w.j1 = p1;
+            w.slice = (p ^ 1) < P ? S2 : p / 2;
+            w.rslice = w.slice;
+            w.kind = 1;
+        }
+    }
+    return w;
+}
+
+// IntBlock t (t < n_blocks): 64 particles, the slot count of their part.
+__host__ __device__ inline IntBlock noalloc_block(int t, int64_t N, double eps, int P)
+{
+    const int S2 = (P + 1) / 2;
+    IntBlock b;
+    b.i0 = (int64_t)t * kIntBlock;
+    b.i1 = b.i0 + kIntBlock < N ? b.i0 + kIntBlock : N;
+    b.eps = eps;
+    b.box = 0;
+    const int p = (int)(b.i0 / kPart);
+    b.n_slices = (p ^ 1) < P ? S2 + 1 : S2;
+    return b;
+}
+
+// The list's sizes for N particles (P parts of 256).
+struct NoAllocSizes {
+    int P, n_blk, n_intra, n_pieces, n_items, n_blocks;
+};
+__host__ __device__ inline NoAllocSizes noalloc_sizes(int64_t N)
+{
+    NoAllocSizes z;
+    z.P = (int)((N + kPart - 1) / kPart);
+    const int S2 = (z.P + 1) / 2;
+    z.n_blk = S2 * (S2 - 1) / 2;
+    z.n_intra = z.P / 2;
+    const int64_t last_len = N - (int64_t)(z.P - 1) * kPart;
+    z.n_pieces = (z.P - 1) * (int)(kPart / kPiece) + (int)((last_len + kPiece - 1) / kPiece);
+    z.n_items = 4 * (z.n_blk + (z.n_intra + z.n_pieces + 3) / 4);
+    z.n_blocks = (int)((N + kIntBlock - 1) / kIntBlock);
+    return z;
+}
+
+// One thread per item and block; also the box offsets and the cleared work
+// counter.
 __global__ void noalloc_setup_kernel(int64_t N, double eps, int P, int n_blk, int n_intra,
                                      int n_pieces, int n_items, int n_blocks,
                                      WorkItem *__restrict__ items, IntBlock *__restrict__ blocks,
                                      int64_t *__restrict__ offsets, int *__restrict__ counter)
 {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int S2 = (P + 1) / 2;
     if (t == 0) {
         offsets[0] = 0;
         offsets[1] = N;
         *counter = 0;
     }
-    if (t < n_items) {
-        WorkItem w{};
-        w.eps2 = eps * eps;
-        w.box = 0;
-        w.kind = -1;
-        const int g = t / 4, e = t % 4;
-        if (g < n_blk) {
-            int k = g, A = 0;
-            while (k >= S2 - 1 - A) {
-                k -= S2 - 1 - A;
-                ++A;
-            }
-            const int B = A + 1 + k;
-            const int a = e >> 1, b = e & 1;
-            const int p = 2 * A + a, q = 2 * B + b;
-            if (p < P && q < P) {
-                w.i0 = (int64_t)p * kPart;
-                w.i1 = min(w.i0 + kPart, N);
-                w.j0 = (int64_t)q * kPart;
-                w.j1 = min(w.j0 + kPart, N);
-                w.slice = B;
-                w.rslice = A;
-                w.kind = 0;
-                w.tmate = (int8_t)(2 * B + (1 - b) < P);
-                w.rmate = (int8_t)(2 * A + (1 - a) < P);
-            }
-        } else {
-            const int l = (g - n_blk) * 4 + e;
-            if (l < n_intra) {
-                w.i0 = (int64_t)(2 * l) * kPart;
-                w.i1 = min(w.i0 + kPart, N);
-                w.j0 = (int64_t)(2 * l + 1) * kPart;
-                w.j1 = min(w.j0 + kPart, N);
-                w.slice = l;
-                w.rslice = l;
-                w.kind = 0;
-            } else if (l - n_intra < n_pieces) {
-                const int j = l - n_intra, p = j / (int)(kPart / kPiece),
-                          i = j % (int)(kPart / kPiece);
-                const int64_t p0 = (int64_t)p * kPart, p1 = min(p0 + kPart, N);
-                w.i0 = p0 + (int64_t)i * kPiece;
-                w.i1 = min(w.i0 + kPiece, p1);
-                w.j0 = p0;
-                w.j1 = p1;
-                w.slice = (p ^ 1) < P ? S2 : p / 2;
-                w.rslice = w.slice;
-                w.kind = 1;
-            }
-        }
-        items[t] = w;
-    }
-    if (t < n_blocks) {
-        IntBlock b;
-        b.i0 = (int64_t)t * kIntBlock;
-        b.i1 = min(b.i0 + kIntBlock, N);
-        b.eps = eps;
-        b.box = 0;
-        const int p = (int)(b.i0 / kPart);
-        b.n_slices = (p ^ 1) < P ? S2 + 1 : S2;
-        blocks[t] = b;
-    }
+    if (t < n_items)
+        items[t] = noalloc_item(t, N, eps, P, n_blk, n_intra, n_pieces);
+    if (t < n_blocks)
+        blocks[t] = noalloc_block(t, N, eps, P);
 }
 
 }  // namespace
@@ -200,20 +233,14 @@ extern "C" int colatus_forces_noalloc(const double *x, const double *m, int64_t 
     double *part = reinterpret_cast<double *>(base + kOffPart);
     double *part_phi = reinterpret_cast<double *>(base + kOffPhi);
 
-    const int P = (int)((N + kPart - 1) / kPart);
-    const int S2 = (P + 1) / 2;
-    const int n_blk = S2 * (S2 - 1) / 2;
-    const int n_intra = P / 2;
-    const int64_t last_len = N - (int64_t)(P - 1) * kPart;
-    const int n_pieces = (P - 1) * (int)(kPart / kPiece) + (int)((last_len + kPiece - 1) / kPiece);
-    const int n_items = 4 * (n_blk + (n_intra + n_pieces + 3) / 4);
-    const int n_blocks = (int)((N + kIntBlock - 1) / kIntBlock);
+    const NoAllocSizes z = noalloc_sizes(N);
+    const int P = z.P, n_items = z.n_items, n_blocks = z.n_blocks;
     if (n_items > kMaxItems || n_blocks > kMaxBlocks)
         return COLATUS_ESCRATCH;
     const int n_setup = n_items > n_blocks ? n_items : n_blocks;
     hipLaunchKernelGGL(noalloc_setup_kernel, dim3((unsigned)((n_setup + 255) / 256)), dim3(256),
-                       0, s, N, eps, P, n_blk, n_intra, n_pieces, n_items, n_blocks, items,
-                       blocks, offsets, counter);
+                       0, s, N, eps, P, z.n_blk, z.n_intra, z.n_pieces, n_items, n_blocks,
+                       items, blocks, offsets, counter);
     if (hipGetLastError() != hipSuccess)
         return COLATUS_EHIP;
     if (launch_box_mass(m, offsets, 1, N, box_mass, s) != hipSuccess)

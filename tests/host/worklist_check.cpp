@@ -10,12 +10,20 @@
 //     (a combined partial sum counted once, by its writing wave);
 //   * single-item symmetric lists: the same with P slots per particle;
 //   * ordered lists: every (target, source slice) once, the slices of a box
-//     tiling its sources.
+//     tiling its sources;
+//   * the allocation-free call's list (generated on the device by the
+//     functions noalloc_list.cpp runs here): the grouped checks above for
+//     every N it accepts (all N to 1100, then a stride), within its fixed
+//     scratch, and the same items and partner pairings as the builder's
+//     grouped list for that box, so the two calls give the same sums.
 #include "api.cpp"
 
 #include <cstdio>
 #include <map>
 #include <random>
+
+bool noalloc_host_list(int64_t N, double eps, std::vector<colatus::WorkItem> &items,
+                       std::vector<colatus::IntBlock> &blocks, int &max_slots);
 
 namespace {
 
@@ -38,14 +46,15 @@ Boxes make_boxes(const std::vector<int64_t> &sizes)
 }
 
 // Simulated writes of a symmetric list (grouped or not) against its blocks.
-int check_symmetric(const std::vector<int64_t> &sizes, bool grouped)
+int check_list(const Boxes &b, const WorkList &wl, bool grouped)
 {
-    const Boxes b = make_boxes(sizes);
+    const std::vector<int64_t> sizes = [&b] {
+        std::vector<int64_t> v;
+        for (size_t k = 0; k + 1 < b.off.size(); ++k)
+            v.push_back(b.off[k + 1] - b.off[k]);
+        return v;
+    }();
     const int64_t N = b.off.back();
-    TileCfg cfg{4, 64, 1, 2};
-    cfg.group = grouped ? 1 : 0;
-    WorkList wl;
-    build_worklist(b, N, cfg, wl);
     const int64_t U = 256;
     const size_t G = grouped ? 4 : 1;
     if (wl.items.size() % G)
@@ -130,6 +139,63 @@ int check_symmetric(const std::vector<int64_t> &sizes, bool grouped)
     return 0;
 }
 
+int check_symmetric(const std::vector<int64_t> &sizes, bool grouped)
+{
+    const Boxes b = make_boxes(sizes);
+    TileCfg cfg{4, 64, 1, 2};
+    cfg.group = grouped ? 1 : 0;
+    WorkList wl;
+    build_worklist(b, b.off.back(), cfg, wl);
+    return check_list(b, wl, grouped);
+}
+
+// The combining structure of a grouped list: every pair item with its
+// partner flags, and the diagonal pieces, as a sorted multiset.
+std::vector<std::vector<int64_t>> signature(const std::vector<WorkItem> &items)
+{
+    std::vector<std::vector<int64_t>> sig;
+    for (size_t g = 0; g < items.size() / 4; ++g)
+        for (size_t e = 0; e < 4; ++e) {
+            const WorkItem &w = items[g * 4 + e];
+            if (w.kind < 0)
+                continue;
+            // a partner's part: the other target part of the group for a
+            // reaction partner, the other source part for a target partner
+            const int64_t tm = w.tmate ? items[g * 4 + (e ^ 1)].j0 : -1;
+            const int64_t rm = w.rmate ? items[g * 4 + (e ^ 2)].i0 : -1;
+            sig.push_back({w.kind, w.i0, w.i1, w.j0, w.j1, w.slice, w.rslice, tm, rm});
+        }
+    std::sort(sig.begin(), sig.end());
+    return sig;
+}
+
+int check_noalloc(int64_t N)
+{
+    std::vector<WorkItem> items;
+    std::vector<IntBlock> blocks;
+    int max_slots = 0;
+    if (!noalloc_host_list(N, 0.01, items, blocks, max_slots))
+        return fail("allocation-free list beyond its scratch", (long)N);
+    Boxes b = make_boxes({N});
+    WorkList wl;
+    wl.items = items;
+    wl.blocks = blocks;
+    wl.max_slices = max_slots;
+    if (check_list(b, wl, true))
+        return fail("allocation-free list", (long)N);
+    WorkList ref;
+    TileCfg cfg{4, 64, 1, 2};
+    cfg.group = 1;
+    build_worklist(b, N, cfg, ref);
+    if (signature(items) != signature(ref.items))
+        return fail("allocation-free list differs from the builder's", (long)N);
+    for (size_t k = 0; k < blocks.size(); ++k)
+        if (blocks[k].i0 != ref.blocks[k].i0 || blocks[k].i1 != ref.blocks[k].i1 ||
+            blocks[k].n_slices != ref.blocks[k].n_slices)
+            return fail("allocation-free blocks differ from the builder's", (long)N, (long)k);
+    return 0;
+}
+
 int check_ordered(const std::vector<int64_t> &sizes, int R, int tpb, int slices)
 {
     const Boxes b = make_boxes(sizes);
@@ -197,6 +263,12 @@ int main()
     bad |= check_ordered({32768}, 1, 256, 64);
     bad |= check_ordered({1000, 3, 70000}, 4, 128, 9);
     cases += 2;
+    for (int64_t n = 1; n <= 16384 && !bad; n += (n < 1100 ? 1 : 97)) {
+        bad |= check_noalloc(n);
+        ++cases;
+    }
+    bad |= check_noalloc(16384);
+    ++cases;
     std::printf(bad ? "FAILED (%d cases)\n" : "all ok (%d cases)\n", cases);
     return bad;
 }

@@ -6,8 +6,11 @@ links it against the built libcolatus.so for the kernel launchers it never
 calls, and runs it: for single boxes from 1 to 2^16 particles, random ragged
 batches and a 256-box ensemble it checks that the symmetric lists (grouped
 and single-item) meet every unordered pair of parts once and write every
-(particle, slot) their readers add exactly once, and that the ordered lists
-tile every box's sources.
+(particle, slot) their readers add exactly once, that the ordered lists
+tile every box's sources, and that the allocation-free call's list
+(generated on the device; here by the same functions, compiled for the
+host) passes the same checks for N up to its limit and matches the
+builder's grouped list item for item.
 """
 import os
 import shutil
@@ -24,7 +27,8 @@ def test_worklists_meet_every_pair_and_write_every_slot_once(tmp_path):
     rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
     cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "-I",
            os.path.join(ROOT, "include"), "-I", os.path.join(LIBDIR, "csrc"),
-           os.path.join(ROOT, "tests", "host", "worklist_check.cpp"), "-L", LIBDIR, "-lcolatus",
+           os.path.join(ROOT, "tests", "host", "worklist_check.cpp"),
+           os.path.join(ROOT, "tests", "host", "noalloc_list.cpp"), "-L", LIBDIR, "-lcolatus",
            "-Wl,-rpath," + LIBDIR, "-L", rocm_lib, "-lrocprofiler-sdk-roctx",
            "-Wl,-rpath," + rocm_lib, "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
