@@ -323,10 +323,12 @@ __global__ __launch_bounds__(TPB) void pair_sweep_kernel(
 // wave) and carries the accumulator of its reaction with it, so after 64
 // steps every source has met every target of the wave and is back in its
 // lane with its reaction complete.  The waves' reactions are added in a fixed
-// order.  Part p's partial sum from part q goes to slot q and part q's
-// reaction from part p to slot p: each (slot, particle) is written once, and
-// the O(N) kernels add the slots in a fixed order.  The diagonal item (p, p)
-// evaluates the ordered pairs of its part with the same loop and no reaction.
+// order.  Part p's partial sum from part q goes to the item's target slot
+// and part q's reaction from part p to its reaction slot (with one item per
+// workgroup slots q and p; the grouped form below numbers them by
+// super-part): each (slot, particle) is written once, and the O(N) kernels
+// add the slots in a fixed order.  The diagonal item (p, p) evaluates the
+// ordered pairs of its part with the same loop and no reaction.
 //
 // Per unordered pair with equal masses: 3 subtractions, 3 FMAs, one v_rsq,
 // 2 multiplies, 3 + 3 FMAs; per step and lane 6 rotations shared by R pairs.
