@@ -142,7 +142,7 @@ def parse():
     p.add_argument("--no-variants", action="store_true")
     p.add_argument("--no-ftle", action="store_true",
                    help="skip the 64-tracer FTLE (192 cotangents, 200 steps, about 13 s)")
-    p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--cpu-sample-steps", type=int, default=30)
     p.add_argument("--integrator-64-only", action="store_true",
                    help="run only the integrator measurement at 64^3 (5 launches per precision) and print it as one JSON object, for counter runs")
     p.add_argument("--periodic-only", action="store_true",
