@@ -238,10 +238,10 @@ int colatus_step(double *x, double *v, const double *m, int64_t N, double eps,
  * Requires n_steps >= 1, 0 <= first_step < last_step <= n_steps, a_begin > 0,
  * a_end > 0 (or > 0 elapsed time in the static limit), H^2 > 0 on the range
  * (else COLATUS_EFRIEDMANN).  The steps are launched on the stream as they
- * are queued; a call of 256 steps or more also captures 16 steps in a graph
- * that this and later calls with the same arguments and buffers replay (the
- * same kernels and arguments, so the same bits; COLATUS_OPT_GRAPH = 0 turns
- * this off).  attractor (or NULL): the Eq. (10) term joins g
+ * are queued; with COLATUS_OPT_GRAPH = 1, a call of 256 steps or more also
+ * captures 16 steps in a graph that this and later calls with the same
+ * arguments and buffers replay (the same kernels and arguments, so the same
+ * bits).  attractor (or NULL): the Eq. (10) term joins g
  * at every kick and its energy joins U; so does the Eq. (6) background
  * term (or NULL).  tracks (or NULL): see colatus_tracks; rows r >= 1 hold
  * v = p / a^2 as the final v does.                                          */
@@ -453,7 +453,9 @@ const char *colatus_strerror(int code);
 #define COLATUS_OPT_GRAPH      1  /* 1: colatus_run calls of 256 steps or more capture
                                      16 steps in a hipGraph, kept per (stream, kernel
                                      arguments) and replayed by later calls of 16
-                                     steps or more (default 1)                       */
+                                     steps or more; 0 (default): every step launched
+                                     eagerly (replay measured no faster on gfx950,
+                                     and the first capture costs a few ms)           */
 #define COLATUS_OPT_TIMER      2  /* 1: bracket every pair-sweep and integrator launch
                                      with hipEvents on its stream (default 0; the run
                                      then launches eagerly instead of from a graph)  */

@@ -28,7 +28,7 @@ constexpr int kMaxCot = 4096;
 // ---------------------------------------------------------------------------
 // Atomic: the roctx switch is read before an entry point takes the lock.
 struct Options {
-    std::atomic<int64_t> graph{1};
+    std::atomic<int64_t> graph{0};  // measured no faster than eager launches
     std::atomic<int64_t> timer{0};
     std::atomic<int64_t> autotune{0};
     std::atomic<int64_t> tile_r{0};

@@ -250,7 +250,7 @@ def test_hubble_host():
 def test_options_and_tile_config():
     L = colatus.lib()
     v = ctypes.c_int64()
-    assert L.colatus_get_option(1, ctypes.byref(v)) == 0 and v.value == 1
+    assert L.colatus_get_option(1, ctypes.byref(v)) == 0 and v.value == 0  # graphs off
     assert L.colatus_get_option(8, ctypes.byref(v)) == 0 and v.value == -1
     assert L.colatus_set_option(8, 3) == EINVAL
     assert L.colatus_set_option(4, 3) == EINVAL

@@ -58,11 +58,12 @@ def test_runs_with_diagnostics_tracks_and_external_terms(dev, graph, scheme):
                             background=bg, tracers=[0, 17, 300])
         return [_np(x), _np(v), d, _np(tr)]
 
+    prev = colatus.get_option(colatus.OPT_GRAPH)
     colatus.set_option(colatus.OPT_GRAPH, graph)
     try:
         _twice(go)
     finally:
-        colatus.set_option(colatus.OPT_GRAPH, 1)
+        colatus.set_option(colatus.OPT_GRAPH, prev)
 
 
 def test_ensemble_run(dev):

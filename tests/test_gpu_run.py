@@ -71,11 +71,12 @@ def test_run_resume_and_graph_modes_agree(dev):
     xh, vh, _ = _gpu_run(w, v0, dev, "mixed_twosum", last=17)
     xb, vb, _ = _gpu_run(w, vh, dev, "mixed_twosum", first=17, last=40, x=xh)
     assert np.max(np.abs(xb - xa)) <= 1e-12
-    colatus.set_option(colatus.OPT_GRAPH, 0)
+    prev = colatus.get_option(colatus.OPT_GRAPH)
+    colatus.set_option(colatus.OPT_GRAPH, 1 - prev)
     try:
         xe, ve, _ = _gpu_run(w, v0, dev, "mixed_twosum", last=40)
     finally:
-        colatus.set_option(colatus.OPT_GRAPH, 1)
+        colatus.set_option(colatus.OPT_GRAPH, prev)
     assert np.array_equal(xe, xa) and np.array_equal(ve, va)
     xr, vr, _ = _gpu_run(w, v0, dev, "mixed_twosum", last=40)
     assert np.array_equal(xr, xa) and np.array_equal(vr, va)
@@ -83,10 +84,11 @@ def test_run_resume_and_graph_modes_agree(dev):
 
 @pytest.mark.parametrize("diag", [False, True])
 def test_captured_step_graph_replays_equal_eager_steps(dev, diag):
-    """A run of 300 steps captures its step in a graph; a later, shorter call
-    on the same buffers replays the cached graph (16 steps per replay, the
-    rest launched eagerly).  Every replayed run equals the eager run bit for
-    bit, with eager work and synchronisations between the replays."""
+    """With graphs on (COLATUS_OPT_GRAPH = 1; off by default), a run of 300
+    steps captures its step in a graph; a later, shorter call on the same
+    buffers replays the cached graph (16 steps per replay, the rest launched
+    eagerly).  Every replayed run equals the eager run bit for bit, with
+    eager work and synchronisations between the replays."""
     w = inputs.eds_lattice(8, n_steps=300)
     v0 = _v0(w)
     xt, vt, mt = to_dev(w.x, dev), to_dev(v0, dev), to_dev(w.m, dev)
@@ -99,20 +101,23 @@ def test_captured_step_graph_replays_equal_eager_steps(dev, diag):
         torch.cuda.synchronize()
         return xt.cpu().numpy(), vt.cpu().numpy(), d
 
-    colatus.set_option(colatus.OPT_GRAPH, 0)
+    prev = colatus.get_option(colatus.OPT_GRAPH)
     try:
+        colatus.set_option(colatus.OPT_GRAPH, 0)
         eager = [run(0, 300), run(0, 40), run(7, 47)]
-    finally:
         colatus.set_option(colatus.OPT_GRAPH, 1)
-    for rep in range(3):
-        got = [run(0, 300), run(0, 40), run(7, 47)]
-        for (xe, ve, de), (xg, vg, dg) in zip(eager, got):
-            assert np.array_equal(xe, xg) and np.array_equal(ve, vg), rep
-            if diag:
-                for f in ("K", "U", "LI", "Px", "Lz", "t"):
-                    assert np.array_equal(de[f], dg[f]), (rep, f)
-        # eager library work on another state between the replays
-        _gpu_run(w, v0, dev, "mixed_twosum", last=3)
+        for rep in range(3):
+            got = [run(0, 300), run(0, 40), run(7, 47)]
+            for (xe, ve, de), (xg, vg, dg) in zip(eager, got):
+                assert np.array_equal(xe, xg) and np.array_equal(ve, vg), rep
+                if diag:
+                    for f in ("K", "U", "LI", "Px", "Lz", "t"):
+                        assert np.array_equal(de[f], dg[f]), (rep, f)
+            # eager library work on another state between the replays (3
+            # steps: below the replay length, launched eagerly)
+            _gpu_run(w, v0, dev, "mixed_twosum", last=3)
+    finally:
+        colatus.set_option(colatus.OPT_GRAPH, prev)
 
 
 def test_static_kepler_matches_oracle(dev):

@@ -26,13 +26,14 @@ def test_fp64_tracks_match_oracle(dev, scheme, graph):
     _, _, dr, tref = fn(w.x, v0, w.m, w.eps, w.G, w.cosmo, w.a_begin, w.a_end, 12, diag=True,
                         attractor=att, tracers=tr)
     x, v = to_dev(w.x, dev), to_dev(v0, dev)
+    prev = colatus.get_option(colatus.OPT_GRAPH)
     colatus.set_option(colatus.OPT_GRAPH, graph)
     try:
         d, track = colatus.run(x, v, to_dev(w.m, dev), w.eps, w.G, w.cosmo, w.a_begin, w.a_end,
                                12, precision="fp64", diag=True, attractor=att, scheme=scheme,
                                tracers=tr)
     finally:
-        colatus.set_option(colatus.OPT_GRAPH, 1)
+        colatus.set_option(colatus.OPT_GRAPH, prev)
     t = track.cpu().numpy()
     assert t.shape == (13, 2, 3, 5)
     assert np.max(np.abs(t[:, 0] - tref[:, 0])) <= 1e-12
