@@ -1649,12 +1649,11 @@ hipError_t dispatch_adj(const TileCfg &cfg, bool mask, const double *x, const do
 // at half the box).  r == 0 (a part's own particle, or coincident
 // particles): w = 0 and psi = (eps^2)^{-1/2} (0 at eps == 0), the value the
 // open-box loop gives its self pair and the O(N) kernels remove.
-// Coordinates are taken relative to the item's first target, each wrapped to
-// its nearest image in FP64 before rounding, so that particles close across
-// the box's faces stay close; the pair's separation is wrapped once more in
-// the pair's precision.  Masses multiply every term (missing particles have
-// mass 0 at the reference point), and the slots hold them: readers are
-// given no common mass.
+// FP64 pairs take coordinates relative to the item's first target, each
+// wrapped to its nearest image before the subtraction, and wrap the pair's
+// separation once more.  FP32 pairs take 32-bit fixed-point coordinates
+// (below).  Masses multiply every term (missing particles have mass 0), and
+// the slots hold them: readers are given no common mass.
 // ---------------------------------------------------------------------------
 template <typename T> struct EwaldReal {
     T L, invL, alpha, c2;  // c2 = 2 / sqrt(pi)
@@ -1663,25 +1662,11 @@ template <typename T> struct EwaldReal {
 __device__ __forceinline__ float rint_t(float u) { return rintf(u); }
 __device__ __forceinline__ double rint_t(double u) { return rint(u); }
 
-// erf(u) and exp(-u^2) for u >= 0.  FP64: the math library's erf and exp.
-// FP32: exp(-u^2) once, and erf(u) = 1 - t p(t) exp(-u^2), t = 1/(1 + 0.3275911 u),
-// p the fifth-degree polynomial of Hastings' approximation (Abramowitz and
-// Stegun 7.1.26; absolute error at most 1.5e-7, a few FP32 units of the
-// kernel it enters), sharing that exponential with the Gaussian term.
+// erf(u) and exp(-u^2) for u >= 0 (FP64 pairs): the math library's.
 __device__ __forceinline__ void erf_gauss(double u, double &erf_u, double &gauss)
 {
     erf_u = erf(u);
     gauss = exp(-u * u);
-}
-__device__ __forceinline__ void erf_gauss(float u, float &erf_u, float &gauss)
-{
-    gauss = __expf(-u * u);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
-    const float p =
-        fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
-                     -0.284496736f),
-             0.254829592f);
-    erf_u = fmaf(-t * p, gauss, 1.0f);
 }
 
 template <typename T, bool PHI>
@@ -1758,9 +1743,9 @@ __device__ __forceinline__ void ewald_chunk(T sx, T sy, T sz, T sm, T &qx, T &qy
     }
 }
 
-// One work item (kind 0: a pair of parts with the reaction; kind 1: a
-// 64-target piece of a diagonal part).  Slots as the symmetric loop's: FP32
-// sums stored as FP32 (FP32 pairs), FP64 otherwise; masses included.
+// One work item of FP64 pairs (kind 0: a pair of parts with the reaction;
+// kind 1: a 64-target piece of a diagonal part).  Slots as the symmetric
+// loop's, FP64, masses included.
 template <typename T, int R, bool REACT, bool PHI>
 __device__ __forceinline__ void ewald_item(const WorkItem &w, const double *__restrict__ X,
                                            const double *__restrict__ Y,
@@ -1770,7 +1755,7 @@ __device__ __forceinline__ void ewald_item(const WorkItem &w, const double *__re
                                            double *__restrict__ part_phi, const double L,
                                            const EwaldReal<T> &E)
 {
-    constexpr bool F32OUT = sizeof(T) == 4;
+    static_assert(sizeof(T) == 8, "FP32 pairs take ewald_item_fx");
     const int lane = threadIdx.x & 63;
     // reference point: the item's first target (wave-uniform)
     const double cx = X[w.i0], cy = Y[w.i0], cz = Z[w.i0];
@@ -1809,20 +1794,11 @@ __device__ __forceinline__ void ewald_item(const WorkItem &w, const double *__re
         if constexpr (REACT) {
             if (jv) {
                 const int64_t rs = (int64_t)w.rslice;
-                if constexpr (F32OUT) {
-                    float *pf = reinterpret_cast<float *>(part);
-                    pf[(rs * 3 + 0) * N + j] = (float)qx;
-                    pf[(rs * 3 + 1) * N + j] = (float)qy;
-                    pf[(rs * 3 + 2) * N + j] = (float)qz;
-                    if constexpr (PHI)
-                        reinterpret_cast<float *>(part_phi)[rs * N + j] = (float)qp;
-                } else {
-                    part[(rs * 3 + 0) * N + j] = (double)qx;
-                    part[(rs * 3 + 1) * N + j] = (double)qy;
-                    part[(rs * 3 + 2) * N + j] = (double)qz;
-                    if constexpr (PHI)
-                        part_phi[rs * N + j] = (double)qp;
-                }
+                part[(rs * 3 + 0) * N + j] = qx;
+                part[(rs * 3 + 1) * N + j] = qy;
+                part[(rs * 3 + 2) * N + j] = qz;
+                if constexpr (PHI)
+                    part_phi[rs * N + j] = qp;
             }
         }
     }
@@ -1832,20 +1808,194 @@ __device__ __forceinline__ void ewald_item(const WorkItem &w, const double *__re
         if (!valid[r])
             continue;
         const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
-        if constexpr (F32OUT) {
-            float *pf = reinterpret_cast<float *>(part);
-            pf[(slot * 3 + 0) * N + i] = (float)ax[r];
-            pf[(slot * 3 + 1) * N + i] = (float)ay[r];
-            pf[(slot * 3 + 2) * N + i] = (float)az[r];
+        part[(slot * 3 + 0) * N + i] = ax[r];
+        part[(slot * 3 + 1) * N + i] = ay[r];
+        part[(slot * 3 + 2) * N + i] = az[r];
+        if constexpr (PHI)
+            part_phi[slot * N + i] = ap[r];
+    }
+}
+
+// FP32 pairs on fixed-point coordinates.  Each coordinate is stored as
+// round(x 2^32 / L) modulo 2^32 (FP64 arithmetic, exact for |x| below
+// 2^21 L); the difference
+// of two such values, read as a signed 32-bit integer, is the nearest image
+// of the separation to 2^-32 L, with no wrap arithmetic, and one conversion
+// gives it in FP32.  Inside the loop lengths are in units of L / 2^32; the
+// stores scale the sums back (the force by (2^32 / L)^2, the potential by
+// 2^32 / L).
+struct EwaldFx {
+    float eps2;      // eps^2 in those units
+    float c_exp;     // -alpha^2 log2(e): exp(-alpha^2 r^2) = 2^(c_exp r^2)
+    float c_t;       // 0.3275911 alpha
+    float c_g;       // (2 / sqrt(pi)) alpha
+    float phi_self;  // the r = 0 potential term: (eps^2)^{-1/2}, 0 at eps = 0
+};
+
+__device__ __forceinline__ uint32_t fx_coord(double x, double scale)
+{
+    const double q = rint(x * scale);  // an integer; exact below 2^53
+    return (uint32_t)(q - 4294967296.0 * floor(q * 2.3283064365386963e-10));  // mod 2^32
+}
+
+__device__ __forceinline__ uint32_t wave_rotate_u(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
+}
+
+// One FP32 pair.  With u = alpha r, Hastings' approximation (Abramowitz and
+// Stegun 7.1.26; absolute error at most 1.5e-7, a few FP32 units of the
+// kernel it enters) gives erf(u) = 1 - t p(t) g, t = 1 / (1 + 0.3275911 u),
+// g = exp(-u^2), p of fourth degree, so that
+// P(u) = erf(u) - (2 / sqrt(pi)) u g = 1 - g (t p + c_g r).  (Folding c_g
+// into the exponent as 2^(c_exp r^2 + log2 c_g) would save the product c_g r
+// but raises the exponent's rounding error sixfold.)  At r = 0 the pair's
+// terms are selected (w = 0, psi = phi_self), not branched to, so that the
+// target rows interleave.
+template <bool PHI>
+__device__ __forceinline__ void ewald_pair_fx(float dx, float dy, float dz, const EwaldFx &E,
+                                              float &w, float &psi)
+{
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rs = __builtin_amdgcn_rsqf(r2 + E.eps2);
+    const float ri = __builtin_amdgcn_rsqf(r2);  // +inf at r = 0: not selected
+    const float r = r2 * ri;
+    const float g = __builtin_amdgcn_exp2f(E.c_exp * r2);
+    const float t = __builtin_amdgcn_rcpf(fmaf(E.c_t, r, 1.0f));
+    const float p =
+        fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
+                     -0.284496736f),
+             0.254829592f);
+    const float P = fmaf(-g, fmaf(t, p, E.c_g * r), 1.0f);
+    const bool nz = r2 > 0.0f;
+    w = nz ? fmaf(-P, ri * (ri * ri), rs * (rs * rs)) : 0.0f;
+    if constexpr (PHI) {
+        const float erf_u = fmaf(-t * p, g, 1.0f);
+        psi = nz ? fmaf(-erf_u, ri, rs) : E.phi_self;
+    }
+}
+
+template <int R, bool REACT, bool PHI>
+__device__ __forceinline__ void ewald_chunk_fx(uint32_t sx, uint32_t sy, uint32_t sz, float sm,
+                                               float &qx, float &qy, float &qz, float &qp,
+                                               const uint32_t (&xi)[R], const uint32_t (&yi)[R],
+                                               const uint32_t (&zi)[R], const float (&mi)[R],
+                                               const EwaldFx &E, float (&ax)[R], float (&ay)[R],
+                                               float (&az)[R], float (&ap)[R])
+{
+    for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float dx = (float)(int32_t)(sx - xi[r]);
+            const float dy = (float)(int32_t)(sy - yi[r]);
+            const float dz = (float)(int32_t)(sz - zi[r]);
+            float w, psi;
+            ewald_pair_fx<PHI>(dx, dy, dz, E, w, psi);
+            const float wt = sm * w;
+            ax[r] = fmaf(wt, dx, ax[r]);
+            ay[r] = fmaf(wt, dy, ay[r]);
+            az[r] = fmaf(wt, dz, az[r]);
             if constexpr (PHI)
-                reinterpret_cast<float *>(part_phi)[slot * N + i] = (float)ap[r];
-        } else {
-            part[(slot * 3 + 0) * N + i] = (double)ax[r];
-            part[(slot * 3 + 1) * N + i] = (double)ay[r];
-            part[(slot * 3 + 2) * N + i] = (double)az[r];
-            if constexpr (PHI)
-                part_phi[slot * N + i] = (double)ap[r];
+                ap[r] = fmaf(sm, psi, ap[r]);
+            if constexpr (REACT) {
+                const float ws = mi[r] * w;
+                qx = fmaf(-ws, dx, qx);
+                qy = fmaf(-ws, dy, qy);
+                qz = fmaf(-ws, dz, qz);
+                if constexpr (PHI)
+                    qp = fmaf(mi[r], psi, qp);
+            }
         }
+        sx = wave_rotate_u(sx);
+        sy = wave_rotate_u(sy);
+        sz = wave_rotate_u(sz);
+        sm = wave_rotate(sm);
+        if constexpr (REACT) {
+            qx = wave_rotate(qx);
+            qy = wave_rotate(qy);
+            qz = wave_rotate(qz);
+            if constexpr (PHI)
+                qp = wave_rotate(qp);
+        }
+    }
+}
+
+template <int R, bool REACT, bool PHI>
+__device__ __forceinline__ void ewald_item_fx(const WorkItem &w, const double *__restrict__ X,
+                                              const double *__restrict__ Y,
+                                              const double *__restrict__ Z,
+                                              const double *__restrict__ m, int64_t N,
+                                              double *__restrict__ part,
+                                              double *__restrict__ part_phi, const double L,
+                                              const double alpha)
+{
+    const int lane = threadIdx.x & 63;
+    const double sc = 4294967296.0 / L;  // fixed-point units per length
+    const double a_fx = alpha / sc;      // alpha in those units
+    EwaldFx E;
+    E.eps2 = (float)(w.eps2 * sc * sc);
+    E.c_exp = (float)(-a_fx * a_fx * 1.4426950408889634);
+    E.c_t = (float)(0.3275911 * a_fx);
+    E.c_g = (float)(1.1283791670955126 * a_fx);
+    E.phi_self = E.eps2 > 0.0f ? __builtin_amdgcn_rsqf(E.eps2) : 0.0f;
+    const double sf = sc * sc;  // force sums back to lengths
+    uint32_t xi[R], yi[R], zi[R];
+    float mi[R], ax[R], ay[R], az[R], ap[R];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        valid[r] = i < w.i1;
+        if (valid[r]) {
+            xi[r] = fx_coord(X[i], sc);
+            yi[r] = fx_coord(Y[i], sc);
+            zi[r] = fx_coord(Z[i], sc);
+            mi[r] = (float)m[i];
+        } else {
+            xi[r] = yi[r] = zi[r] = 0u;
+            mi[r] = 0.0f;
+        }
+        ax[r] = ay[r] = az[r] = ap[r] = 0.0f;
+    }
+    float *pf = reinterpret_cast<float *>(part);
+    float *pp = reinterpret_cast<float *>(part_phi);
+    const int n_chunks = (int)((w.j1 - w.j0 + 63) / 64);
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t j = w.j0 + (int64_t)c * 64 + lane;
+        const bool jv = j < w.j1;
+        uint32_t sx = 0u, sy = 0u, sz = 0u;
+        float sm = 0.0f;
+        if (jv) {
+            sx = fx_coord(X[j], sc);
+            sy = fx_coord(Y[j], sc);
+            sz = fx_coord(Z[j], sc);
+            sm = (float)m[j];
+        }
+        float qx = 0.0f, qy = 0.0f, qz = 0.0f, qp = 0.0f;
+        ewald_chunk_fx<R, REACT, PHI>(sx, sy, sz, sm, qx, qy, qz, qp, xi, yi, zi, mi, E, ax, ay,
+                                      az, ap);
+        if constexpr (REACT) {
+            if (jv) {
+                const int64_t rs = (int64_t)w.rslice;
+                pf[(rs * 3 + 0) * N + j] = (float)(sf * (double)qx);
+                pf[(rs * 3 + 1) * N + j] = (float)(sf * (double)qy);
+                pf[(rs * 3 + 2) * N + j] = (float)(sf * (double)qz);
+                if constexpr (PHI)
+                    pp[rs * N + j] = (float)(sc * (double)qp);
+            }
+        }
+    }
+    const int64_t slot = (int64_t)w.slice;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!valid[r])
+            continue;
+        const int64_t i = w.i0 + (int64_t)(r * 64 + lane);
+        pf[(slot * 3 + 0) * N + i] = (float)(sf * (double)ax[r]);
+        pf[(slot * 3 + 1) * N + i] = (float)(sf * (double)ay[r]);
+        pf[(slot * 3 + 2) * N + i] = (float)(sf * (double)az[r]);
+        if constexpr (PHI)
+            pp[slot * N + i] = (float)(sc * (double)ap[r]);
     }
 }
 
@@ -1862,15 +2012,22 @@ __global__ __launch_bounds__(64) void ewald_real_kernel(
     if (it >= n_items)
         return;
     const WorkItem w = items[it];
-    EwaldReal<T> E;
-    E.L = (T)L;
-    E.invL = (T)(1.0 / L);
-    E.alpha = (T)alpha;
-    E.c2 = (T)1.1283791670955126;  // 2 / sqrt(pi)
-    if (w.kind == 0)
-        ewald_item<T, 4, true, PHI>(w, X, Y, Z, m, N, part, part_phi, L, E);
-    else
-        ewald_item<T, 1, false, PHI>(w, X, Y, Z, m, N, part, part_phi, L, E);
+    if constexpr (sizeof(T) == 4) {
+        if (w.kind == 0)
+            ewald_item_fx<4, true, PHI>(w, X, Y, Z, m, N, part, part_phi, L, alpha);
+        else
+            ewald_item_fx<1, false, PHI>(w, X, Y, Z, m, N, part, part_phi, L, alpha);
+    } else {
+        EwaldReal<T> E;
+        E.L = (T)L;
+        E.invL = (T)(1.0 / L);
+        E.alpha = (T)alpha;
+        E.c2 = (T)1.1283791670955126;  // 2 / sqrt(pi)
+        if (w.kind == 0)
+            ewald_item<T, 4, true, PHI>(w, X, Y, Z, m, N, part, part_phi, L, E);
+        else
+            ewald_item<T, 1, false, PHI>(w, X, Y, Z, m, N, part, part_phi, L, E);
+    }
 }
 
 template <typename T, bool PHI>
