@@ -206,6 +206,28 @@ def test_force_vjp_symmetric_matches_oracle(dev, form2, N, C, spread, eps):
             assert e <= tol
 
 
+@pytest.mark.parametrize("spread", [False, True])
+def test_force_vjp_symmetric_scales_exactly_with_the_cotangent(dev, form2, spread):
+    """The sweep is linear in the cotangent and every operation on it is a
+    product or sum with cotangent-free factors, so scaling lam by 2^80 or
+    2^-60 scales the FP32 result exactly (no rounding changes, no overflow).
+    On a ragged box (parts of 256, 256, 188: chunks with padding lanes) this
+    also shows that no padding position (|d| ~ 1e18) meets an unscaled
+    cotangent: d.u would overflow FP32 at |u| ~ 1e20 and the sum turn NaN."""
+    N = 700
+    x, m = inputs.random_cloud(N, 41, scale=0.5, mass_spread=spread)
+    lam = np.random.default_rng(42).standard_normal((1, 3, N))
+    xt, mt = to_dev(x, dev), to_dev(m, dev)
+    for prec in ("mixed_twosum", "fp32"):
+        base = colatus.force_vjp(xt, mt, to_dev(lam, dev), 0.02, 1.3, precision=prec)
+        base = base.cpu().numpy()
+        assert np.all(np.isfinite(base))
+        for k in (80, -60):
+            got = colatus.force_vjp(xt, mt, to_dev(lam * 2.0 ** k, dev), 0.02, 1.3,
+                                    precision=prec).cpu().numpy()
+            assert np.array_equal(got, base * 2.0 ** k), (prec, k)
+
+
 def test_force_vjp_symmetric_is_the_default_for_few_cotangents(dev):
     """Boxes large enough to fill the GPU with symmetric items (about 11 000
     particles and more) take the symmetric adjoint loop by default, smaller
