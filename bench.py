@@ -745,6 +745,17 @@ def cpu_baseline(w, v0, args):
         npairs = float(ww.N) * (ww.N if tg is None else len(ww.extra[tg]))
         detail[name] = {"seconds_median_of_3": statistics.median(ts),
                         "gpairs_s": npairs / statistics.median(ts) / 1e9}
+    # ten steps of the 16^3 EdS lattice run (11 force sweeps)
+    w1 = _inputs().eds_lattice(16)
+    c1 = w1.cosmo
+    v1 = w1.velocities(oracle.hubble(w1.a_begin, c1["H0"], c1["Om_R"], c1["Om_M"], c1["Om_K"],
+                                     c1["Om_L"]))
+    t0 = time.perf_counter()
+    oracle.run(w1.x, v1, w1.m, w1.eps, w1.G, w1.cosmo, w1.a_begin, w1.a_end, w1.n_steps,
+               first_step=0, last_step=10)
+    t1 = time.perf_counter() - t0
+    detail["eds_lattice_16^3_10_steps"] = {"seconds": t1,
+                                           "gpairs_s": 11 * float(w1.N) ** 2 / t1 / 1e9}
     oracle.set_num_threads(1)
     t0 = time.perf_counter()
     oracle.forces(w.x, w.m, w.eps, G=w.G)
