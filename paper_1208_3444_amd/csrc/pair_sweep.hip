@@ -50,6 +50,20 @@ template <> struct V4<double> { using type = double4; };
 __device__ __forceinline__ float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
 __device__ __forceinline__ double rsqrt_t(double s) { return rsqrt_refined(s); }
 
+// s^{-3/2} for FP64 pairs that do not need s^{-1/2} itself: with
+// y = v_rsq_f64(s) (relative error below 6e-8) and e = 1 - s y^2,
+// s^{-3/2} = y^3 (1 - e)^{-3/2} = y^3 (1 + 3e/2 + O(e^2)).  The first-order
+// correction applied to y^3 leaves about (15/8) e^2 < 3e-14 relative, one
+// operation fewer than refining y (rsqrt_refined) and cubing it.
+__device__ __forceinline__ double rinv3_fp64(double s)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    const double y2 = y * y;
+    const double e = fma(-s, y2, 1.0);
+    const double y3 = y2 * y;
+    return fma(1.5 * e, y3, y3);
+}
+
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 
@@ -391,10 +405,17 @@ __device__ __forceinline__ void sym_chunk(T sx, T sy, T sz, T sm, T &qx, T &qy, 
             T s = fma_t(dx, dx, eps2);
             s = fma_t(dy, dy, s);
             s = fma_t(dz, dz, s);
-            T rinv = rsqrt_t(s);
-            if constexpr (MASK)
-                rinv = s > (T)0.0 ? rinv : (T)0.0;
-            const T w = rinv * (rinv * rinv);
+            T rinv, w;
+            if constexpr (sizeof(T) == 8 && !PHI) {
+                w = rinv3_fp64(s);
+                if constexpr (MASK)
+                    w = s > (T)0.0 ? w : (T)0.0;
+            } else {
+                rinv = rsqrt_t(s);
+                if constexpr (MASK)
+                    rinv = s > (T)0.0 ? rinv : (T)0.0;
+                w = rinv * (rinv * rinv);
+            }
             const T wt = EQM ? w : sm * w;
             ax[r] = fma_t(wt, dx, ax[r]);
             ay[r] = fma_t(wt, dy, ay[r]);
