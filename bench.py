@@ -279,7 +279,8 @@ def main():
 
     line = {
         "metric": METRIC, "value": value, "unit": "Gpairs/s", "n_gpus": 1, "steps": K,
-        "warmup": W, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": W, "ms_per_step": ms_per_step, "steps_per_s": 1e3 / ms_per_step,
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "lcdm_grf_32^3", "N": N, "cosmology": "LCDM Om_M=0.3 Om_L=0.7",
                    "a_begin": w.a_begin, "a_end": w.a_end, "n_steps_grid": w.n_steps,
@@ -294,6 +295,13 @@ def main():
     if not args.no_variants:
         line["variants"] = variants(w, v0, state, timed_run, args, colatus, inputs, np, torch,
                                     dev)
+        # mixed / FP64 throughput: the forward (headline against the FP64 call) and the
+        # forward + adjoint
+        var = line["variants"]
+        if args.precision != "fp64":
+            var["fp64_fwd"]["mixed_over_fp64"] = value / var["fp64_fwd"]["gpairs_s"]
+            var["fp64_fwd_adj"]["mixed_over_fp64"] = (var["mixed_fwd_adj"]["gpairs_s"]
+                                                      / var["fp64_fwd_adj"]["gpairs_s"])
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, v0, args)
