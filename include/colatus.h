@@ -296,7 +296,9 @@ int colatus_run_he(double *x, double *v, const double *m, int64_t N, double eps,
  * Madelung constant).  The library takes alpha and the cutoffs so that the
  * neglected real-space images and reciprocal terms fall below 1e-15 (FP64)
  * or 3e-9 (FP32 forms) of the kernel: real space on the nearest image only
- * (the pair sweep's symmetric loop, in the given precision), reciprocal
+ * (the pair sweep's symmetric loop, in the given precision; FP32 pairs
+ * take coordinates rounded to multiples of L / 2^32 and the nearest image
+ * of those, an exact tie along an axis giving -L/2), reciprocal
  * space in FP64 by structure factors.  No external terms; one box; 1 <= N
  * <= 262144; box > 0 finite, else COLATUS_EINVAL.  Other arguments as
  * colatus_forces.                                                         */
