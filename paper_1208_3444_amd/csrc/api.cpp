@@ -209,7 +209,7 @@ struct Workspace {
         box_mass, att_acc, he_x, track_idx, track_slot, twiddle, ftle_idx;
     // periodic boundaries: the reciprocal-space plan (vectors and weights for
     // one box side and precision) and its work buffers
-    Buffer ew_segs, ew_coef, ew_skp, ew_S, ew_kpg, ew_kpp, ew_msum, ew_g, ew_p;
+    Buffer ew_segs, ew_segs_sk, ew_coef, ew_skp, ew_S, ew_kpg, ew_kpp, ew_msum, ew_g, ew_p;
     double ew_L = 0.0, ew_alpha = 0.0;
     int ew_nmax = -1, ew_nsegs = 0, ew_K = 0;
     // work lists by (N, boxes, softenings, tile shape); fwd / adj: the lists
@@ -228,8 +228,8 @@ struct Workspace {
         return {&part,     &part_phi,   &coef,  &p,        &diag_part,  &diag_out,
                 &counters, &lam_x,      &lam_p, &ckpt,     &seg,        &box_mass,
                 &att_acc,  &he_x,       &track_idx, &track_slot, &twiddle, &ftle_idx,
-                &ew_segs,  &ew_coef,    &ew_skp, &ew_S, &ew_kpg, &ew_kpp, &ew_msum, &ew_g,
-                &ew_p};
+                &ew_segs,  &ew_segs_sk, &ew_coef, &ew_skp, &ew_S, &ew_kpg, &ew_kpp, &ew_msum,
+                &ew_g,     &ew_p};
     }
 };
 
@@ -1449,7 +1449,11 @@ void ewald_parameters(double L, int precision, double &alpha, int &nmax)
 // The half-space reciprocal vectors n != 0, |n| <= nmax (n_x > 0, or n_x = 0
 // and n_y > 0, or n_x = n_y = 0 and n_z > 0), as column segments of up to
 // kEwaldSegLen consecutive n_z, with their weights 2 (4 pi / L^3)
-// exp(-k^2 / 4 alpha^2) / k^2; uploaded once per (L, precision).
+// exp(-k^2 / 4 alpha^2) / k^2; uploaded once per (L, precision).  A second
+// copy of the segments, longest first, feeds the structure-factor kernel,
+// whose lanes each take a segment: a wave of equal counts runs its loop over
+// the k without idle lanes (its sums are stored by k, so the order changes
+// no result).
 int ensure_ewald_plan(Workspace *ws, double L, int precision, hipStream_t s)
 {
     double alpha = 0.0;
@@ -1489,13 +1493,19 @@ int ensure_ewald_plan(Workspace *ws, double L, int precision, hipStream_t s)
                 segs.push_back(g);
             }
         }
+    std::vector<EwaldSeg> segs_sk = segs;
+    std::stable_sort(segs_sk.begin(), segs_sk.end(),
+                     [](const EwaldSeg &a, const EwaldSeg &b) { return a.cnt > b.cnt; });
     // the previous plan's buffers may still be read by queued work
     CHECK_HIP(hipStreamSynchronize(s));
     CHECK_RC(ensure(ws->ew_segs, std::max<size_t>(1, segs.size()) * sizeof(EwaldSeg)));
+    CHECK_RC(ensure(ws->ew_segs_sk, std::max<size_t>(1, segs.size()) * sizeof(EwaldSeg)));
     CHECK_RC(ensure(ws->ew_coef, std::max<size_t>(1, coef.size()) * sizeof(double)));
     if (!segs.empty()) {
         CHECK_HIP(hipMemcpyAsync(ws->ew_segs.ptr, segs.data(), segs.size() * sizeof(EwaldSeg),
                                  hipMemcpyHostToDevice, s));
+        CHECK_HIP(hipMemcpyAsync(ws->ew_segs_sk.ptr, segs_sk.data(),
+                                 segs_sk.size() * sizeof(EwaldSeg), hipMemcpyHostToDevice, s));
         CHECK_HIP(hipMemcpyAsync(ws->ew_coef.ptr, coef.data(), coef.size() * sizeof(double),
                                  hipMemcpyHostToDevice, s));
         CHECK_HIP(hipStreamSynchronize(s));  // the host tables are local
@@ -1529,6 +1539,7 @@ int ewald_args(Workspace *ws, const double *x, const double *m, int64_t N, Ewald
     A.L = ws->ew_L;
     A.alpha = ws->ew_alpha;
     A.segs = static_cast<const EwaldSeg *>(ws->ew_segs.ptr);
+    A.segs_sk = static_cast<const EwaldSeg *>(ws->ew_segs_sk.ptr);
     A.n_segs = ws->ew_nsegs;
     A.K = ws->ew_K;
     A.coef = static_cast<const double *>(ws->ew_coef.ptr);

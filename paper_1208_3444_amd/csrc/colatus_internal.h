@@ -372,6 +372,7 @@ struct EwaldArgs {
     int64_t N;
     double L, alpha;
     const EwaldSeg *segs;  // [n_segs], k0 consecutive
+    const EwaldSeg *segs_sk;  // [n_segs] the same segments, longest first (structure factors)
     int n_segs, K;
     const double *coef;    // [K]: 2 (4 pi / L^3) exp(-k^2 / 4 alpha^2) / k^2
     double2 *sk_part;      // [n_sk_chunks][K]

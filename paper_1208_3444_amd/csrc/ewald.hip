@@ -295,8 +295,8 @@ hipError_t launch_ewald_kspace(const EwaldArgs &A, hipStream_t stream)
         hipLaunchKernelGGL(ewald_sk_kernel,
                            dim3((unsigned)((A.n_segs + kSegThreads - 1) / kSegThreads),
                                 (unsigned)A.n_sk_chunks),
-                           dim3(kSegThreads * kSkWaves), 0, stream, A.x, A.m, N, chunk, A.segs,
-                           A.n_segs, A.K, inv_L, A.sk_part);
+                           dim3(kSegThreads * kSkWaves), 0, stream, A.x, A.m, N, chunk,
+                           A.segs_sk, A.n_segs, A.K, inv_L, A.sk_part);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         hipLaunchKernelGGL(ewald_sk_reduce_kernel, dim3((unsigned)((A.K + kRedK - 1) / kRedK)),
