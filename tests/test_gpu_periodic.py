@@ -48,10 +48,13 @@ def _cloud(N, seed, L):
     return x, m
 
 
-@pytest.mark.parametrize("N", [1500, 300])
+@pytest.mark.parametrize("N,L", [(1500, 1.0), (300, 1.0), (1500, 2.5), (300, 0.37)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_twosum", "mixed_f64acc", "fp32"])
-def test_periodic_forces_match_oracle(dev, N, prec):
-    L, eps, G, a = 1.0, 0.01, 1.3, 0.7
+def test_periodic_forces_match_oracle(dev, N, L, prec):
+    """Box sides that are not powers of two as well (the FP32 pairs' fixed-point
+    scale 2^32 / L is then inexact, and the softening and Ewald constants
+    change units with it)."""
+    eps, G, a = 0.01 * L, 1.3, 0.7
     x, m = _cloud(N, 600 + N, L)
     ref, pref = oracle.forces_periodic(x, m, eps, L, G=G, a=a, with_phi=True)
     acc, phi = colatus.forces_periodic(to_dev(x, dev), to_dev(m, dev), eps, L, G=G, a=a,
@@ -60,7 +63,7 @@ def test_periodic_forces_match_oracle(dev, N, prec):
     fs, ps = _scales(x, m, L, eps)
     e = np.linalg.norm(acc - ref, axis=0) / (G / a ** 3 * fs)
     ep = np.abs(phi - pref) / (G * ps)
-    print(f"N={N} {prec}: field median {np.median(e):.3e} max {e.max():.3e}; potential "
+    print(f"N={N} L={L} {prec}: field median {np.median(e):.3e} max {e.max():.3e}; potential "
           f"median {np.median(ep):.3e} max {ep.max():.3e}", flush=True)
     if prec == "fp64":
         assert e.max() <= 1e-12 and ep.max() <= 1e-12
