@@ -1855,8 +1855,11 @@ struct EwaldFx {
 
 __device__ __forceinline__ uint32_t fx_coord(double x, double scale)
 {
-    const double q = rint(x * scale);  // an integer; exact below 2^53
-    return (uint32_t)(q - 4294967296.0 * floor(q * 2.3283064365386963e-10));  // mod 2^32
+    double q = rint(x * scale);  // an integer; exact below 2^53
+    q -= 4294967296.0 * floor(q * 2.3283064365386963e-10);  // mod 2^32
+    // a non-finite coordinate (or one beyond 2^21 L) takes 0 here, a defined
+    // conversion; a NaN still reaches every field through the reciprocal sums
+    return q >= 0.0 && q < 4294967296.0 ? (uint32_t)q : 0u;
 }
 
 __device__ __forceinline__ uint32_t wave_rotate_u(uint32_t v)

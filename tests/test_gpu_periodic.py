@@ -186,3 +186,17 @@ def test_periodic_fp32_close_pairs_across_the_faces(dev, prec):
     print(f"{prec}: conditioned error, cluster median {np.median(e[1::2]):.3e} max "
           f"{e[1::2].max():.3e}; others max {e[0::2].max():.3e}", flush=True)
     assert e.max() <= 2e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_twosum"])
+def test_periodic_nan_position_reaches_the_field(dev, prec):
+    """A NaN coordinate is not validated on entry; it must not vanish into a
+    finite field.  The FP32 pairs' fixed-point conversion maps it to 0 (a
+    defined value), and the reciprocal-space sums, over every particle, carry
+    the NaN to every particle's field and potential."""
+    x, m = inputs.random_cloud(300, 5, scale=1.0)
+    x[1, 17] = np.nan
+    acc, phi = colatus.forces_periodic(to_dev(x, dev), to_dev(m, dev), 0.01, 1.0,
+                                       precision=prec, with_phi=True)
+    acc, phi = acc.cpu().numpy(), phi.cpu().numpy()
+    assert np.isnan(acc).all() and np.isnan(phi).all()
