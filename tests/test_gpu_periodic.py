@@ -200,3 +200,40 @@ def test_periodic_nan_position_reaches_the_field(dev, prec):
                                        precision=prec, with_phi=True)
     acc, phi = acc.cpu().numpy(), phi.cpu().numpy()
     assert np.isnan(acc).all() and np.isnan(phi).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_twosum"])
+@pytest.mark.parametrize("N", [1, 2, 3, 257])
+def test_periodic_degenerate_sizes(dev, prec, N):
+    """One particle: no force (its images pull evenly) and the simple cubic
+    lattice's Madelung potential -G m 2.8372974794806 / L (with the removed
+    background); two, three and 257 particles (a full part of 256 and one
+    more) against the oracle, at the bars of the random-cloud test."""
+    L, eps, G = 1.7, 0.02, 1.3
+    x, m = inputs.random_cloud(N, 70 + N, scale=L)
+    acc, phi = colatus.forces_periodic(to_dev(x, dev), to_dev(m, dev), eps, L, G=G,
+                                       precision=prec, with_phi=True)
+    acc, phi = acc.cpu().numpy(), phi.cpu().numpy()
+    if N == 1:
+        want = -G * m[0] * MADELUNG_SC / L
+        print(f"{prec}: |acc| / (G m / L^2) {np.abs(acc).max() / (G * m[0] / L ** 2):.3e}; "
+              f"phi rel {abs(phi[0] / want - 1):.3e}", flush=True)
+        # FP32 pairs: the real-space slot holds the self term m / eps, formed
+        # in fixed-point units and scaled back; the epilogue removes m / eps
+        # as the open-box loop rounds it.  The two can differ by a few units
+        # 2^-24 of m / eps (by 4.8e-6 of this potential at L = 2.5, by
+        # nothing at this L), and m / eps is (L / eps) / 2.837 = 30 times the
+        # potential here
+        ptol = 1e-12 if prec == "fp64" else 30 * 4 * 2.0 ** -24
+        assert np.abs(acc).max() <= (1e-12 if prec == "fp64" else 1e-6) * G * m[0] / L ** 2
+        assert abs(phi[0] / want - 1) <= ptol
+        return
+    ref, pref = oracle.forces_periodic(x, m, eps, L, G=G, with_phi=True)
+    fs, ps = _scales(x, m, L, eps)
+    e = np.linalg.norm(acc - ref, axis=0) / (G * fs)
+    ep = np.abs(phi - pref) / (G * ps)
+    print(f"N={N} {prec}: field max {e.max():.3e}; potential max {ep.max():.3e}", flush=True)
+    if prec == "fp64":
+        assert e.max() <= 1e-12 and ep.max() <= 1e-12
+    else:
+        assert e.max() <= 1e-4 and ep.max() <= 1e-4
