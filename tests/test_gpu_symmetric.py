@@ -298,3 +298,24 @@ def test_fp64_symmetric_vjp(dev, form2, N, C):
                             precision="fp64").cpu().numpy()
     for c in range(C):
         assert _rel(got[c], oracle.force_vjp(x, m, lam[c], 0.02, G=1.3)) <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-30])
+def test_fp64_symmetric_pair_law_over_twelve_decades(dev, form2, eps):
+    """FP64 pairs that need no potential take r^-3 from v_rsq_f64 with a
+    first-order correction of its cube (relative error below 3e-14 for
+    v_rsq_f64's 6e-8).  Two particles at +-r/2 (the separation exact in
+    FP64), r from 1e-8 to 1e4: each acceleration is G m / r^2 along the pair
+    to 5e-14; eps = 0 takes the coincident-pair mask, eps = 1e-30 does not."""
+    G, mass = 1.3, 0.7
+    for r in np.logspace(-8, 4, 49):
+        x = np.zeros((3, 2))
+        x[0] = [-r / 2, r / 2]
+        x[1] = [0.25 * r, -0.25 * r]
+        d = x[:, 1] - x[:, 0]
+        rr = np.sqrt((d ** 2).sum())
+        acc = colatus.forces(to_dev(x, dev), to_dev(np.full(2, mass), dev), eps, G=G,
+                             precision="fp64").cpu().numpy()
+        want = G * mass * d / rr ** 3
+        e = max(np.abs(acc[:, 0] - want).max(), np.abs(acc[:, 1] + want).max())
+        assert e <= 5e-14 * np.abs(want).max(), (r, e / np.abs(want).max())
